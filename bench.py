@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark: encoded-shot FWI gradient + Langevin update on one MI355X.
+
+Workload (one "step" = one Langevin refinement of every posterior sample): 2D
+400 x 150 grid at 20 m (440 x 190 with the 20-cell sponge), 80 surface shots of a 6 Hz
+Ricker wavelet and 400 receivers, 2000 recorded samples at 2 ms from 4000 internal
+steps of 1 ms; 16 posterior samples, each drawing 10 supergathers of 8 shots with
++-1 polarity per step (160 simulations in one launch per time step).  Per step: draw
+encodings (host), encode observed data, forward + misfit + adjoint-state gradient,
+Langevin update.  Inputs are seeded synthetic (folded-layer thrust model, smoothed
+start, 1 % Gaussian noise) and resident in HBM before the timed region.
+
+Prints one JSON line.  Metric: physical cell-steps of the complete forward + adjoint
+gradient per second (Gcell-steps/s).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fwi_kernels.hip", "fwi_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2512_12797_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, grid, wav, nt_sample, R, vstart):
+    """Time the oracle (as it stands) on one sample's supergathers for nt_sample steps."""
+    import oracle
+    sims = [s for s in range(batch.nsim) if batch.sample_of[s] == 0]
+    og = oracle.Grid(nz=grid.nz, nx=grid.nx, dz=grid.dz, dx=grid.dx, nb=grid.nb, v_ref=grid.v_ref)
+    sp = np.zeros(len(sims) + 1, dtype=np.int32)
+    rp = np.zeros(len(sims) + 1, dtype=np.int32)
+    sc, sw, rc = [], [], []
+    for i, s in enumerate(sims):
+        a, b = batch.src_ptr[s], batch.src_ptr[s + 1]
+        sc.extend(batch.src_cell[a:b]); sw.extend(batch.src_w[a:b])
+        sp[i + 1] = sp[i] + (b - a)
+        a, b = batch.rec_ptr[s], batch.rec_ptr[s + 1]
+        rc.extend(batch.rec_cell[a:b])
+        rp[i + 1] = rp[i] + (b - a)
+    r = np.random.default_rng(99)
+    dobs = [r.standard_normal((nt_sample // R, rp[i + 1] - rp[i])) for i in range(len(sims))]
+    threads = min(len(sims), int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    oracle.gradient_batch([og] * len(sims), [vstart.ravel()] * len(sims), 1e-3, nt_sample, R, sp,
+                          np.array(sc, dtype=np.int32), np.array(sw, dtype=np.float64), wav[:nt_sample].astype(np.float64),
+                          rp, np.array(rc, dtype=np.int32), dobs, 1.0)
+    dt = time.perf_counter() - t0
+    cells = len(sims) * grid.nphys * nt_sample
+    return {"value": cells / dt / 1e9, "unit": "Gcell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle gradient (forward + misfit + adjoint + imaging) of one posterior sample's "
+                      "%d supergathers over the first %d of the %d internal steps, OpenMP over supergathers; "
+                      "%.1f s wall" % (len(sims), nt_sample, 4000, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=0, help="override internal steps (profiling runs only)")
+    ap.add_argument("--ckpt", default="auto", help="auto | 0 (keep all imaging operands) | K (checkpoint)")
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
+              "(see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_12797_amd import fwi, problems
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = W.C2
+    nt = args.nt or cfg.nt
+    R = cfg.rec_every
+    nt_rec = nt // R
+    grid = problems.grid_of(cfg)
+    wav = W.ricker(cfg.freq, cfg.dt, nt)
+    vtrue = W.thrust_2d(cfg.nz, cfg.nx, seed=args.seed)
+    vstart = np.clip(W.smooth(vtrue, 16.0), cfg.vmin, cfg.vmax)
+    shots = problems.shot_cells(cfg, grid)
+
+    # ---- observed data: forward of the true model, one simulation per shot (setup)
+    t_setup = time.perf_counter()
+    obs_batch = problems.single_shot_batch(cfg, grid, shots, wav)
+    tf = fwi.time_axis(cfg.dt, nt, R, -1)
+    ws_obs = fwi.alloc_workspace(obs_batch, tf)
+    d_shots = torch.empty(cfg.nshot, nt_rec, len(problems.receiver_cells(cfg, grid)), device=dev)
+    fwi.fwi_forward(obs_batch, tf, torch.tensor(vtrue.ravel(), dtype=torch.float32, device=dev), d_shots, ws_obs)
+    fwi.fwi_poll_status(ws_obs)
+    del ws_obs
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    rms = float(d_shots.pow(2).mean().sqrt())
+    sigma = 0.01 * rms
+    d_shots += sigma * torch.randn(d_shots.shape, generator=gen, device=dev)
+    inv_sigma2 = 1.0 / sigma ** 2
+
+    # ---- the sampler state
+    batch0, groups0 = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, args.seed, 0)
+    v = torch.tensor(np.tile(vstart.ravel(), cfg.nsample), dtype=torch.float32, device=dev)
+    nsim = batch0.nsim
+    d_enc = torch.empty(nsim, nt_rec, d_shots.shape[2], device=dev)
+    grad = torch.empty(batch0.model_size, device=dev)
+    gnorm = torch.empty(cfg.nsample, device=dev)
+    misfit = torch.empty(nsim, dtype=torch.float64, device=dev)
+
+    free, total = torch.cuda.mem_get_info()
+    if args.ckpt == "auto":
+        need = fwi.fwi_workspace_size(batch0, fwi.time_axis(cfg.dt, nt, R, 0))
+        ckpt = 0 if need < free - (8 << 30) else 10
+    else:
+        ckpt = int(args.ckpt)
+    time_ax = fwi.time_axis(cfg.dt, nt, R, ckpt)
+    ws = fwi.alloc_workspace(batch0, time_ax)
+    log("setup %.1f s; workspace %.1f GB (ckpt_every=%d); free %.1f of %.1f GB" % (
+        time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, free / 1e9, total / 1e9))
+
+    eta = [1e-3]
+    v_lo, v_hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+
+    def step(t):
+        batch, groups = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, args.seed, t)
+        ptr, shot, w = problems.encode_tables(groups, cfg.shots_per_group)
+        gp = torch.from_numpy(ptr).to(dev, non_blocking=True)
+        gs = torch.from_numpy(shot).to(dev, non_blocking=True)
+        gw = torch.from_numpy(w).to(dev, non_blocking=True)
+        fwi.fwi_encode(d_shots, gp, gs, gw, d_enc)
+        kappa = [g[2] for g in groups]
+        fwi.fwi_gradient(batch, time_ax, v, d_enc, inv_sigma2, kappa, None, misfit, grad, gnorm, ws)
+        fwi.fwi_langevin(batch.model_off, v, grad, None, args.seed, t, eta[0], math.sqrt(2 * eta[0]), v_lo, v_hi)
+
+    for t in range(args.warmup):
+        step(t)
+        if t == 0:
+            gmax = float(grad.abs().max())
+            eta[0] = 10.0 / gmax if gmax > 0 else 1e-3  # ~10 m/s per refinement step
+    fwi.fwi_poll_status(ws)
+    torch.cuda.synchronize()
+
+    fwi.fwi_timing_enable(True)
+    fwi.fwi_timing_read(0, True)
+    fwi.fwi_timing_read(1, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup, args.warmup + args.steps):
+        step(t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwi.fwi_timing_enable(False)
+    fwd_ms, fwd_n = fwi.fwi_timing_read(0, True)
+    adj_ms, adj_n = fwi.fwi_timing_read(1, True)
+    fwi.fwi_poll_status(ws)
+    elapsed = t1 - t0
+
+    phys_cells = nsim * cfg.nz * cfg.nx
+    pad_cells = nsim * (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    samp_cells = cfg.nsample * (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    cell_steps = phys_cells * nt * args.steps
+    value = cell_steps / elapsed / 1e9
+    log("step %.1f ms; %.1f Gcell-steps/s physical, %.1f padded; fwd kernel %.1f us x %d, adj kernel %.1f us x %d" % (
+        1e3 * elapsed / args.steps, value, pad_cells * nt * args.steps / elapsed / 1e9,
+        1e3 * fwd_ms / max(fwd_n, 1), fwd_n, 1e3 * adj_ms / max(adj_n, 1), adj_n))
+
+    # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
+    # adjoint + imaging step: lt^{k+1}, lt^{k+2} read, lt^k write, W^{k-1} read, FP64
+    # accumulator read+write = 32 B per simulation cell, plus c once per sample cell.
+    # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
+    # 16 B per simulation cell (12 B when recomputing from checkpoints without a store),
+    # plus c once per sample cell.
+    fwd_bytes = pad_cells * 16 + samp_cells * 4
+    adj_bytes = pad_cells * 32 + samp_cells * 4
+    if adj_ms >= fwd_ms:
+        name, nbytes, ms, n = "adjoint+imaging step (k_step2d<bz,true>)", adj_bytes, adj_ms, adj_n
+    else:
+        name, nbytes, ms, n = "forward step (k_step2d<bz,false>)", fwd_bytes, fwd_ms, fwd_n
+    avg_s = ms / max(n, 1) / 1e3
+    achieved = nbytes / avg_s / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            if tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name:
+                traffic = tj.get("bytes_per_launch")
+        except (ValueError, OSError):
+            traffic = None
+
+    # ---- copy probe: achievable bandwidth for context
+    n4 = 1 << 28  # 1 GiB per buffer
+    a = torch.empty(n4, device=dev)
+    b = torch.empty(n4, device=dev)
+    fwi.fwi_copy_probe(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        fwi.fwi_copy_probe(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * 4 * n4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+
+    res = {
+        "metric": "Gcell-steps/s fwd+adjoint FWI gradient",
+        "value": round(value, 3),
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2d-400x150-thrust-80shot-s8: 16 samples x 10 supergathers (+-1), "
+                               "%d steps of 1 ms, gradient + Langevin" % nt,
+                   "grid": [cfg.nz, cfg.nx], "padded": [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
+                   "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
+                   "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
+                   "padded_gcell_steps_per_s": round(pad_cells * nt * args.steps / elapsed / 1e9, 3),
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+                     "copy_probe_GBs": round(copy_gbs, 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        res["cpu_baseline"] = cpu_baseline(batch0, grid, wav, min(args.cpu_steps, nt), R, vstart)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,889 @@
+// fwi_host.cpp -- host side of the C ABI: validation, batch tables, workspace layout and
+// the time-stepping schedule (forward, residual/misfit, adjoint with checkpoint
+// recomputation, finalization), all enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fwi.h"
+#include "fwi_internal.h"
+#include "fwi_launch.h"
+
+using namespace fwi;
+
+namespace {
+
+thread_local std::string g_err;
+
+fwi_status fail(fwi_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(FWI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// 8th-order central weights of the second derivative (Fornberg 1988)
+const double kC8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+// stability: largest |eigenvalue| of L8 is (2048/315) sum h^-2; leapfrog needs
+// dt^2 v^2 (2048/315) sum h^-2 <= 4, i.e. v dt sqrt(sum h^-2) <= sqrt(315/512)
+const double kCflLimit = 0.78436482084846;  // sqrt(315/512)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
+
+int env_int(const char *name, int dflt)
+{
+    const char *s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atoi(s);
+}
+
+// ---------------------------------------------------------------- validation
+
+fwi_status check_grid(const fwi_grid &g, int i)
+{
+    if (g.ndim != 2 && g.ndim != 3) return fail(FWI_E_ARG, "grid %d: ndim must be 2 or 3", i);
+    if (g.nz < 1 || g.nx < 1 || g.ny < 1) return fail(FWI_E_ARG, "grid %d: dims must be >= 1", i);
+    if (g.ndim == 2 && g.ny != 1) return fail(FWI_E_ARG, "grid %d: ny must be 1 in 2D", i);
+    if (!(g.dz > 0) || !(g.dx > 0) || (g.ndim == 3 && !(g.dy > 0)))
+        return fail(FWI_E_ARG, "grid %d: spacings must be > 0", i);
+    if (g.nb < 0) return fail(FWI_E_ARG, "grid %d: nb must be >= 0", i);
+    if (g.nb > 0 && !(g.v_ref > 0)) return fail(FWI_E_ARG, "grid %d: v_ref must be > 0", i);
+    if (g.nb > 0 && !(g.refl > 0 && g.refl < 1)) return fail(FWI_E_ARG, "grid %d: refl must be in (0,1)", i);
+    if (!(g.v_max > 0) || !std::isfinite(g.v_max)) return fail(FWI_E_ARG, "grid %d: v_max must be > 0", i);
+    const int64_t N = (int64_t)(g.nz + 2 * g.nb) * (g.ndim == 3 ? g.ny + 2 * g.nb : 1) * (g.nx + 2 * g.nb);
+    if (N >= (int64_t)1 << 31) return fail(FWI_E_UNSUPPORTED, "grid %d: more than 2^31 padded cells", i);
+    return FWI_OK;
+}
+
+double courant(const fwi_grid &g, double dt)
+{
+    double s = 1.0 / (g.dz * g.dz) + 1.0 / (g.dx * g.dx);
+    if (g.ndim == 3) s += 1.0 / (g.dy * g.dy);
+    return g.v_max * dt * std::sqrt(s);
+}
+
+fwi_status check_all(const fwi_batch *b, const fwi_time *t, double *worst)
+{
+    if (!b || !t) return fail(FWI_E_ARG, "null batch or time");
+    if (!(t->dt > 0) || !std::isfinite(t->dt)) return fail(FWI_E_ARG, "dt must be > 0");
+    if (t->nt < 1) return fail(FWI_E_ARG, "nt must be >= 1");
+    if (t->rec_every < 1 || t->nt % t->rec_every != 0) return fail(FWI_E_ARG, "nt must be a multiple of rec_every >= 1");
+    if (t->ckpt_every < -1) return fail(FWI_E_ARG, "ckpt_every must be >= -1");
+    if (b->nsim < 1 || b->nsample < 1) return fail(FWI_E_ARG, "nsim and nsample must be >= 1");
+    if (b->nsim > 65535 || b->nsample > 65535) return fail(FWI_E_UNSUPPORTED, "more than 65535 sims or samples");
+    if (!b->grid || !b->model_off || !b->sample_of || !b->src_ptr || !b->rec_ptr || !b->wavelet)
+        return fail(FWI_E_ARG, "null array in batch");
+    int ndim = b->grid[0].ndim;
+    double cmax = 0;
+    for (int i = 0; i < b->nsample; ++i) {
+        fwi_status s = check_grid(b->grid[i], i);
+        if (s) return s;
+        if (b->grid[i].ndim != ndim) return fail(FWI_E_UNSUPPORTED, "mixed 2D/3D grids in one batch");
+        int64_t nphys = (int64_t)b->grid[i].nz * b->grid[i].ny * b->grid[i].nx;
+        if (b->model_off[i + 1] - b->model_off[i] != nphys)
+            return fail(FWI_E_ARG, "model_off[%d+1]-model_off[%d] != physical cells of its grid", i, i);
+        if (b->model_off[i] < 0) return fail(FWI_E_ARG, "model_off must be >= 0");
+        cmax = std::max(cmax, courant(b->grid[i], t->dt));
+    }
+    if (worst) *worst = cmax;
+    if (cmax > kCflLimit)
+        return fail(FWI_E_CFL, "Courant number %.6f exceeds the 8th-order leapfrog limit %.6f", cmax, kCflLimit);
+    int prev = -1;
+    std::vector<int> cnt(b->nsample, 0);
+    for (int s = 0; s < b->nsim; ++s) {
+        int k = b->sample_of[s];
+        if (k < 0 || k >= b->nsample) return fail(FWI_E_ARG, "sample_of[%d] out of range", s);
+        if (k < prev) return fail(FWI_E_ARG, "sims must be grouped by increasing sample");
+        if (k != prev && prev >= 0 && cnt[k] > 0) return fail(FWI_E_ARG, "sims of a sample must be contiguous");
+        prev = k;
+        cnt[k]++;
+    }
+    for (int k = 0; k < b->nsample; ++k)
+        if (cnt[k] == 0) return fail(FWI_E_ARG, "sample %d has no simulation", k);
+    if (b->src_ptr[0] != 0 || b->rec_ptr[0] != 0) return fail(FWI_E_ARG, "src_ptr[0] and rec_ptr[0] must be 0");
+    for (int s = 0; s < b->nsim; ++s) {
+        if (b->src_ptr[s + 1] < b->src_ptr[s]) return fail(FWI_E_ARG, "src_ptr not monotonic");
+        if (b->rec_ptr[s + 1] < b->rec_ptr[s]) return fail(FWI_E_ARG, "rec_ptr not monotonic");
+    }
+    if (b->src_ptr[b->nsim] > 0 && (!b->src_cell || !b->src_w)) return fail(FWI_E_ARG, "null source arrays");
+    if (b->rec_ptr[b->nsim] > 0 && !b->rec_cell) return fail(FWI_E_ARG, "null receiver array");
+    std::vector<int32_t> tmp;
+    for (int s = 0; s < b->nsim; ++s) {
+        const fwi_grid &g = b->grid[b->sample_of[s]];
+        int64_t nphys = (int64_t)g.nz * g.ny * g.nx;
+        for (int i = b->src_ptr[s]; i < b->src_ptr[s + 1]; ++i) {
+            if (b->src_cell[i] < 0 || b->src_cell[i] >= nphys)
+                return fail(FWI_E_ARG, "sim %d: source cell %d outside the grid", s, b->src_cell[i]);
+            if (!std::isfinite(b->src_w[i])) return fail(FWI_E_ARG, "sim %d: non-finite source weight", s);
+        }
+        tmp.assign(b->rec_cell + b->rec_ptr[s], b->rec_cell + b->rec_ptr[s + 1]);
+        for (int32_t c : tmp)
+            if (c < 0 || c >= nphys) return fail(FWI_E_ARG, "sim %d: receiver cell %d outside the grid", s, c);
+        std::sort(tmp.begin(), tmp.end());
+        if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end())
+            return fail(FWI_E_ARG, "sim %d: duplicate receiver cell", s);
+    }
+    for (int n = 0; n < t->nt; ++n)
+        if (!std::isfinite(b->wavelet[n])) return fail(FWI_E_ARG, "non-finite wavelet sample %d", n);
+    return FWI_OK;
+}
+
+// ---------------------------------------------------------------- the plan
+
+struct Plan {
+    int ndim = 2;
+    int bz = 32, ty = 8;
+    std::vector<SimDesc> sims;
+    std::vector<SampleDesc> samples;
+    std::vector<Tile> tiles;
+    std::vector<EvRow> evrows;
+    std::vector<int32_t> evvec;
+    std::vector<SrcPos> src;
+    int64_t cells = 0;       // one field level, all sims
+    int64_t coefs = 0;       // all samples' padded cells
+    int64_t data = 0;        // all sims' data
+    int64_t max_cell = 0;    // largest padded sample grid
+    int nt_rec = 0;
+    int per_xcd = 0;
+    // layout
+    int nlev = 2, K = 0, nseg = 1;
+    bool fwd_only = false;  // ckpt_every == -1: no adjoint state is kept
+    int64_t wst_levels = 0, ck_slots = 0;
+    int nchunk_res = 1, nchunk_fin = 1;
+    size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_evrows = 0, t_evvec = 0, t_src = 0, t_bytes = 0;
+    size_t o_status = 0, o_tables = 0, o_cf = 0, o_fields = 0, o_wst = 0, o_ck = 0, o_gacc = 0, o_rho = 0,
+           o_part = 0, o_npart = 0, o_mis = 0, total = 0;
+};
+
+void stencil_weights(const fwi_grid &g, float w[3][5], double gmax[3], float &inv_vol)
+{
+    const double h[3] = {g.dz, g.ndim == 3 ? g.dy : 1.0, g.dx};
+    for (int a = 0; a < 3; ++a) {
+        bool on = g.ndim == 3 || a != 1;
+        for (int m = 0; m < 5; ++m) w[a][m] = on ? (float)(kC8[m] / (h[a] * h[a])) : 0.0f;
+        gmax[a] = (on && g.nb > 0) ? 3.0 * g.v_ref * std::log(1.0 / g.refl) / (2.0 * g.nb * h[a]) : 0.0;
+    }
+    double vol = g.dz * g.dx * (g.ndim == 3 ? g.dy : 1.0);
+    inv_vol = (float)(1.0 / vol);
+}
+
+void pick_tiles(Plan &p, const fwi_batch *b)
+{
+    // default: the tallest tile that still gives >= 4 tiles per CU (256 CUs)
+    auto count = [&](int bz, int ty) {
+        int64_t n = 0;
+        for (int s = 0; s < b->nsim; ++s) {
+            const fwi_grid &g = b->grid[b->sample_of[s]];
+            int64_t Nx = g.nx + 2 * g.nb, Nz = g.nz + 2 * g.nb, Ny = p.ndim == 3 ? g.ny + 2 * g.nb : 1;
+            n += ((Nx + kTileX - 1) / kTileX) * ((Nz + bz - 1) / bz) * (p.ndim == 3 ? (Ny + ty - 1) / ty : 1);
+        }
+        return n;
+    };
+    if (p.ndim == 2) {
+        int bz = 8;
+        for (int c : {64, 32, 16, 8})
+            if (count(c, 1) >= 1024) {
+                bz = c;
+                break;
+            }
+        p.bz = env_int("FWI_TILE_BZ", bz);
+        p.ty = 1;
+        if (p.bz != 8 && p.bz != 16 && p.bz != 32 && p.bz != 64) p.bz = bz;
+    } else {
+        int ty = env_int("FWI_TILE_TY", 8);
+        if (ty != 8 && ty != 16) ty = 8;
+        int bz = 16;
+        for (int c : {64, 32, 16})
+            if (count(c, ty) >= 1024) {
+                bz = c;
+                break;
+            }
+        p.bz = env_int("FWI_TILE_BZ", bz);
+        if (p.bz != 16 && p.bz != 32 && p.bz != 64) p.bz = bz;
+        p.ty = ty;
+    }
+}
+
+fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p)
+{
+    p.ndim = b->grid[0].ndim;
+    pick_tiles(p, b);
+    p.nt_rec = t->nt / t->rec_every;
+    const int TYt = p.ndim == 3 ? p.ty : 1;
+    // samples
+    p.samples.resize(b->nsample);
+    for (int k = 0; k < b->nsample; ++k) {
+        const fwi_grid &g = b->grid[k];
+        SampleDesc &S = p.samples[k];
+        memset(&S, 0, sizeof S);
+        S.m_off = b->model_off[k];
+        S.c_off = p.coefs;
+        S.N[0] = g.nz + 2 * g.nb;
+        S.N[1] = g.ndim == 3 ? g.ny + 2 * g.nb : 1;
+        S.N[2] = g.nx + 2 * g.nb;
+        S.n[0] = g.nz;
+        S.n[1] = g.ny;
+        S.n[2] = g.nx;
+        S.nb = g.nb;
+        S.ndim = g.ndim;
+        float w[3][5];
+        float iv;
+        stencil_weights(g, w, S.gmax, iv);
+        S.dt = t->dt;
+        S.v_max = g.v_max;
+        S.kappa = kappa ? kappa[k] : 1.0;
+        S.nphys = (int64_t)g.nz * g.ny * g.nx;
+        S.ncell = (int64_t)S.N[0] * S.N[1] * S.N[2];
+        S.sim_beg = -1;
+        p.coefs += S.ncell;
+        p.max_cell = std::max(p.max_cell, S.ncell);
+    }
+    // sims, tiles, receiver events, sources
+    p.sims.resize(b->nsim);
+    struct Ev {
+        int32_t tile, z, slot, r;
+    };
+    std::vector<Ev> evs;
+    for (int s = 0; s < b->nsim; ++s) {
+        const int k = b->sample_of[s];
+        const fwi_grid &g = b->grid[k];
+        SampleDesc &Sm = p.samples[k];
+        if (Sm.sim_beg < 0) Sm.sim_beg = s;
+        Sm.sim_cnt++;
+        SimDesc &S = p.sims[s];
+        memset(&S, 0, sizeof S);
+        S.u_off = p.cells;
+        S.c_off = Sm.c_off;
+        S.d_off = p.data;
+        S.m_off = Sm.m_off;
+        for (int a = 0; a < 3; ++a) {
+            S.N[a] = Sm.N[a];
+            S.n[a] = Sm.n[a];
+        }
+        S.nb = g.nb;
+        S.ndim = g.ndim;
+        S.nrec = b->rec_ptr[s + 1] - b->rec_ptr[s];
+        S.src_beg = b->src_ptr[s];
+        S.src_cnt = b->src_ptr[s + 1] - b->src_ptr[s];
+        S.sample = k;
+        stencil_weights(g, S.w, S.gmax, S.inv_vol);
+        S.dt = t->dt;
+        p.cells += Sm.ncell;
+        p.data += (int64_t)p.nt_rec * S.nrec;
+        // tiles: z block, then y block, then x strip
+        const int ntx = (S.N[2] + kTileX - 1) / kTileX;
+        const int nty = (S.N[1] + TYt - 1) / TYt;
+        const int ntz = (S.N[0] + p.bz - 1) / p.bz;
+        const int tile0 = (int)p.tiles.size();
+        for (int iz = 0; iz < ntz; ++iz)
+            for (int iy = 0; iy < nty; ++iy)
+                for (int ix = 0; ix < ntx; ++ix) {
+                    Tile T;
+                    memset(&T, 0, sizeof T);
+                    T.sim = s;
+                    T.x0 = ix * kTileX;
+                    T.y0 = iy * TYt;
+                    T.z0 = iz * p.bz;
+                    p.tiles.push_back(T);
+                }
+        const int nby = g.ndim == 3 ? g.nb : 0;
+        for (int r = 0; r < S.nrec; ++r) {
+            const int32_t c = b->rec_cell[b->rec_ptr[s] + r];
+            const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
+            const int px = ix + g.nb, py = iy + nby, pz = iz + g.nb;
+            const int tl = tile0 + ((pz / p.bz) * nty + py / TYt) * ntx + px / kTileX;
+            evs.push_back({tl, pz, (py % TYt) * kTileX + px % kTileX, r});
+        }
+    }
+    for (int s = 0; s < b->nsim; ++s) {
+        const fwi_grid &g = b->grid[b->sample_of[s]];
+        const int nby = g.ndim == 3 ? g.nb : 0;
+        for (int i = b->src_ptr[s]; i < b->src_ptr[s + 1]; ++i) {
+            const int32_t c = b->src_cell[i];
+            SrcPos sp;
+            sp.x = c % g.nx + g.nb;
+            sp.y = (c / g.nx) % g.ny + nby;
+            sp.z = c / (g.nx * g.ny) + g.nb;
+            sp.w = b->src_w[i];
+            p.src.push_back(sp);
+        }
+    }
+    std::sort(evs.begin(), evs.end(), [](const Ev &a, const Ev &b) {
+        return a.tile != b.tile ? a.tile < b.tile : a.z < b.z;
+    });
+    const int vec = kTileX * TYt;
+    for (size_t i = 0; i < evs.size();) {
+        size_t j = i;
+        EvRow row{evs[i].z, (int32_t)p.evvec.size()};
+        p.evvec.resize(p.evvec.size() + vec, -1);
+        Tile &T = p.tiles[evs[i].tile];
+        if (T.ev_cnt == 0) T.ev_beg = (int32_t)p.evrows.size();
+        while (j < evs.size() && evs[j].tile == evs[i].tile && evs[j].z == evs[i].z) {
+            p.evvec[row.vec_off + evs[j].slot] = evs[j].r;
+            ++j;
+        }
+        p.evrows.push_back(row);
+        T.ev_cnt++;
+        i = j;
+    }
+    if (p.tiles.size() >= (size_t)1 << 30) return fail(FWI_E_UNSUPPORTED, "too many tiles");
+    p.per_xcd = (int)((p.tiles.size() + 7) / 8);
+    // table layout
+    size_t o = 0;
+    p.t_sims = o;
+    o = align_up(o + p.sims.size() * sizeof(SimDesc));
+    p.t_samples = o;
+    o = align_up(o + p.samples.size() * sizeof(SampleDesc));
+    p.t_tiles = o;
+    o = align_up(o + p.tiles.size() * sizeof(Tile));
+    p.t_evrows = o;
+    o = align_up(o + std::max<size_t>(1, p.evrows.size()) * sizeof(EvRow));
+    p.t_evvec = o;
+    o = align_up(o + std::max<size_t>(1, p.evvec.size()) * sizeof(int32_t));
+    p.t_src = o;
+    o = align_up(o + std::max<size_t>(1, p.src.size()) * sizeof(SrcPos));
+    p.t_bytes = o;
+    // workspace layout
+    p.fwd_only = t->ckpt_every < 0;
+    p.K = p.fwd_only ? 0 : t->ckpt_every;
+    if (p.K > t->nt) p.K = t->nt;
+    p.nseg = p.K > 0 ? (t->nt + p.K - 1) / p.K : 1;
+    p.nlev = p.K > 0 ? 4 : 2;
+    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.K : t->nt);
+    p.ck_slots = p.K > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
+    int64_t maxdata = 0;
+    for (auto &S : p.sims) maxdata = std::max(maxdata, (int64_t)p.nt_rec * S.nrec);
+    p.nchunk_res = (int)std::min<int64_t>(64, std::max<int64_t>(1, maxdata / 4096));
+    int64_t maxphys = 0;
+    for (auto &S : p.samples) maxphys = std::max(maxphys, S.nphys);
+    p.nchunk_fin = (int)std::min<int64_t>(256, std::max<int64_t>(1, maxphys / 2048));
+    size_t w = 0;
+    p.o_status = w;
+    w = align_up(w + 64);
+    p.o_tables = w;
+    w = align_up(w + p.t_bytes);
+    p.o_cf = w;
+    w = align_up(w + (size_t)p.coefs * 4);
+    p.o_fields = w;
+    w = align_up(w + (size_t)p.nlev * p.cells * 4);
+    p.o_wst = w;
+    w = align_up(w + (size_t)p.wst_levels * p.cells * 4);
+    p.o_ck = w;
+    w = align_up(w + (size_t)p.ck_slots * p.cells * 4);
+    p.o_gacc = w;
+    w = align_up(w + (p.fwd_only ? 0 : (size_t)p.cells * 8));
+    p.o_rho = w;
+    w = align_up(w + (size_t)std::max<int64_t>(1, p.data) * 4);
+    p.o_part = w;
+    w = align_up(w + (size_t)b->nsim * p.nchunk_res * 8);
+    p.o_npart = w;
+    w = align_up(w + (size_t)b->nsample * p.nchunk_fin * 8);
+    p.o_mis = w;
+    w = align_up(w + (size_t)b->nsim * 8);
+    p.total = w;
+    return FWI_OK;
+}
+
+// ----------------------------------------------------------- host staging
+
+struct Stager {
+    std::mutex m;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+Stager g_stage;
+
+fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_stage.m);
+    if (g_stage.pending) HIP_TRY(hipEventSynchronize(g_stage.ev));
+    g_stage.pending = false;
+    if (g_stage.cap < p.t_bytes) {
+        if (g_stage.host) HIP_TRY(hipHostFree(g_stage.host));
+        g_stage.host = nullptr;
+        g_stage.cap = 0;
+        HIP_TRY(hipHostMalloc(&g_stage.host, p.t_bytes, hipHostMallocDefault));
+        g_stage.cap = p.t_bytes;
+    }
+    uint8_t *h = (uint8_t *)g_stage.host;
+    memset(h, 0, p.t_bytes);
+    memcpy(h + p.t_sims, p.sims.data(), p.sims.size() * sizeof(SimDesc));
+    memcpy(h + p.t_samples, p.samples.data(), p.samples.size() * sizeof(SampleDesc));
+    memcpy(h + p.t_tiles, p.tiles.data(), p.tiles.size() * sizeof(Tile));
+    if (!p.evrows.empty()) memcpy(h + p.t_evrows, p.evrows.data(), p.evrows.size() * sizeof(EvRow));
+    if (!p.evvec.empty()) memcpy(h + p.t_evvec, p.evvec.data(), p.evvec.size() * sizeof(int32_t));
+    if (!p.src.empty()) memcpy(h + p.t_src, p.src.data(), p.src.size() * sizeof(SrcPos));
+    HIP_TRY(hipMemcpyAsync(dst, h, p.t_bytes, hipMemcpyHostToDevice, st));
+    if (!g_stage.ev) HIP_TRY(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(g_stage.ev, st));
+    g_stage.pending = true;
+    return FWI_OK;
+}
+
+// ------------------------------------------------------------ kernel timing
+
+// When enabled, every time-step launch is bracketed by a pair of HIP events recorded on
+// the launch's stream; fwi_timing_read turns the pairs into per-kind totals.
+struct Timing {
+    std::mutex m;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Pair {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Pair> pending;
+    double total_ms[2] = {0, 0};
+    int64_t count[2] = {0, 0};
+};
+Timing g_timing;
+
+hipError_t timed_step(const StepArgs &a, const Plan &p, bool adjoint, hipStream_t st)
+{
+    if (!g_timing.on) return launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
+    std::lock_guard<std::mutex> lk(g_timing.m);
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+        if (g_timing.pool.empty()) {
+            hipError_t e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) return e;
+        } else {
+            ev[i] = g_timing.pool.back();
+            g_timing.pool.pop_back();
+        }
+    }
+    hipError_t e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    g_timing.pending.push_back({ev[0], ev[1], adjoint ? 1 : 0});
+    return e;
+}
+
+// ------------------------------------------------------------- the schedule
+
+struct Dev {
+    uint8_t *base;
+    int *status;
+    const SimDesc *sims;
+    const SampleDesc *samples;
+    const Tile *tiles;
+    const EvRow *evrows;
+    const int32_t *evvec;
+    const SrcPos *src;
+    float *cf;
+    float *lev[4];
+    float *wst;
+    float *ck;
+    double *gacc;
+    float *rho;
+    double *part;
+    double *npart;
+    double *mis;
+};
+
+Dev carve(const Plan &p, void *ws)
+{
+    Dev d;
+    d.base = (uint8_t *)ws;
+    d.status = (int *)(d.base + p.o_status);
+    uint8_t *tb = d.base + p.o_tables;
+    d.sims = (const SimDesc *)(tb + p.t_sims);
+    d.samples = (const SampleDesc *)(tb + p.t_samples);
+    d.tiles = (const Tile *)(tb + p.t_tiles);
+    d.evrows = (const EvRow *)(tb + p.t_evrows);
+    d.evvec = (const int32_t *)(tb + p.t_evvec);
+    d.src = (const SrcPos *)(tb + p.t_src);
+    d.cf = (float *)(d.base + p.o_cf);
+    for (int l = 0; l < 4; ++l) d.lev[l] = l < p.nlev ? (float *)(d.base + p.o_fields) + (size_t)l * p.cells : nullptr;
+    d.wst = (float *)(d.base + p.o_wst);
+    d.ck = (float *)(d.base + p.o_ck);
+    d.gacc = (double *)(d.base + p.o_gacc);
+    d.rho = (float *)(d.base + p.o_rho);
+    d.part = (double *)(d.base + p.o_part);
+    d.npart = (double *)(d.base + p.o_npart);
+    d.mis = (double *)(d.base + p.o_mis);
+    return d;
+}
+
+StepArgs base_args(const Plan &p, const Dev &d)
+{
+    StepArgs a;
+    memset(&a, 0, sizeof a);
+    a.sims = d.sims;
+    a.tiles = d.tiles;
+    a.evrows = d.evrows;
+    a.evvec = d.evvec;
+    a.src = d.src;
+    a.cf = d.cf;
+    a.ntiles = (int32_t)p.tiles.size();
+    a.per_xcd = p.per_xcd;
+    a.rec_j = -1;
+    return a;
+}
+
+fwi_status prologue(const fwi_batch *b, const fwi_time *t, const double *kappa, void *ws, size_t ws_bytes, Plan &p)
+{
+    fwi_status s = check_all(b, t, nullptr);
+    if (s) return s;
+    s = build_plan(b, t, kappa, p);
+    if (s) return s;
+    if (!ws) return fail(FWI_E_WORKSPACE, "null workspace");
+    if ((uintptr_t)ws % kAlign) return fail(FWI_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < p.total) return fail(FWI_E_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, p.total);
+    return FWI_OK;
+}
+
+// forward sweep n = 0..nt-1; records data into `dat`; stores imaging operands (store-all)
+// or checkpoints (K >= 1)
+fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fwi_time *t, const float *v,
+                       float *dat, hipStream_t st)
+{
+    // a forward pass starts a new evaluation: clear the device flags first (the workspace
+    // is caller memory whose initial content is unknown)
+    HIP_TRY(launch_fill_i32(d.status, 1, 0, st));
+    HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, st));
+    HIP_TRY(launch_fill_f32(d.lev[0], 2 * p.cells, 0.0f, st));
+    StepArgs a = base_args(p, d);
+    a.dat = dat;
+    float *cur = d.lev[0], *prev = d.lev[1];
+    for (int n = 0; n < t->nt; ++n) {
+        a.cur = cur;
+        a.prev = prev;
+        a.next = prev;  // in place over u^{n-1}
+        a.fn = b->wavelet[n];
+        a.rec_j = (n + 1) % t->rec_every == 0 ? (n + 1) / t->rec_every - 1 : -1;
+        a.wst = (p.K == 0 && !p.fwd_only) ? d.wst + (size_t)n * p.cells : nullptr;
+        a.cka = a.ckb = nullptr;
+        if (p.K > 0 && (n + 1) % p.K == 0 && (n + 1) / p.K < p.nseg) {
+            const int slot = (n + 1) / p.K;
+            a.cka = d.ck + (size_t)(2 * (slot - 1)) * p.cells;
+            a.ckb = d.ck + (size_t)(2 * (slot - 1) + 1) * p.cells;
+        }
+        HIP_TRY(timed_step(a, p, false, st));
+        std::swap(cur, prev);
+    }
+    return FWI_OK;
+}
+
+// adjoint sweep k = nt..1 with imaging, then finalization into grad / grad_norm
+fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fwi_time *t, const float *v,
+                       const float *rho, float *grad, float *grad_norm, hipStream_t st)
+{
+    HIP_TRY(launch_fill_f64(d.gacc, p.cells, 0.0, st));
+    float *L0 = p.K == 0 ? d.lev[0] : d.lev[2];
+    float *L1 = p.K == 0 ? d.lev[1] : d.lev[3];
+    HIP_TRY(launch_fill_f32(L0, p.cells, 0.0f, st));
+    HIP_TRY(launch_fill_f32(L1, p.cells, 0.0f, st));
+    StepArgs a = base_args(p, d);
+    a.rho = rho;
+    a.gacc = d.gacc;
+    float *lcur = L0, *lprev = L1;
+    auto adj_step = [&](int k, const float *wimg) -> fwi_status {
+        a.cur = lcur;
+        a.prev = lprev;
+        a.next = lprev;
+        a.wimg = wimg;
+        a.rec_j = k % t->rec_every == 0 ? k / t->rec_every - 1 : -1;
+        HIP_TRY(timed_step(a, p, true, st));
+        std::swap(lcur, lprev);
+        return FWI_OK;
+    };
+    if (p.K == 0) {
+        for (int k = t->nt; k >= 1; --k) {
+            fwi_status s = adj_step(k, d.wst + (size_t)(k - 1) * p.cells);
+            if (s) return s;
+        }
+    } else {
+        float *P0 = d.lev[0], *P1 = d.lev[1];
+        StepArgs f = base_args(p, d);
+        for (int sg = p.nseg - 1; sg >= 0; --sg) {
+            const int ns = sg * p.K, ne = std::min(ns + p.K, t->nt);
+            const float *cur, *prev;
+            if (sg == 0) {
+                HIP_TRY(launch_fill_f32(P0, 2 * p.cells, 0.0f, st));
+                cur = P0;
+                prev = P1;
+            } else {
+                cur = d.ck + (size_t)(2 * (sg - 1)) * p.cells;
+                prev = d.ck + (size_t)(2 * (sg - 1) + 1) * p.cells;
+            }
+            for (int n = ns; n < ne; ++n) {
+                float *next;
+                if (prev == P0 || prev == P1)
+                    next = const_cast<float *>(prev);
+                else
+                    next = cur == P0 ? P1 : P0;
+                f.cur = cur;
+                f.prev = prev;
+                f.next = next;
+                f.fn = b->wavelet[n];
+                f.wst = d.wst + (size_t)(n - ns) * p.cells;
+                HIP_TRY(timed_step(f, p, false, st));
+                prev = cur;
+                cur = next;
+            }
+            for (int k = ne; k >= ns + 1; --k) {
+                fwi_status s = adj_step(k, d.wst + (size_t)(k - 1 - ns) * p.cells);
+                if (s) return s;
+            }
+        }
+    }
+    HIP_TRY(launch_finalize(d.samples, d.sims, b->nsample, d.gacc, v, grad, d.npart, p.nchunk_fin, d.status, st));
+    if (grad_norm) HIP_TRY(launch_norm_final(d.npart, p.nchunk_fin, b->nsample, grad_norm, st));
+    return FWI_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char *fwi_status_string(fwi_status s)
+{
+    switch (s) {
+    case FWI_OK: return "ok";
+    case FWI_E_ARG: return "invalid argument";
+    case FWI_E_CFL: return "time step violates the stability limit";
+    case FWI_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case FWI_E_HIP: return "HIP runtime error";
+    case FWI_E_NONFINITE: return "non-finite value or model above v_max found on the device";
+    case FWI_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+const char *fwi_last_error(void) { return g_err.c_str(); }
+
+fwi_status fwi_check(const fwi_batch *b, const fwi_time *t, double *worst_courant)
+{
+    return check_all(b, t, worst_courant);
+}
+
+fwi_status fwi_workspace_size(const fwi_batch *b, const fwi_time *t, size_t *bytes)
+{
+    if (!bytes) return fail(FWI_E_ARG, "null bytes");
+    fwi_status s = check_all(b, t, nullptr);
+    if (s) return s;
+    Plan p;
+    s = build_plan(b, t, nullptr, p);
+    if (s) return s;
+    *bytes = p.total;
+    return FWI_OK;
+}
+
+fwi_status fwi_forward(const fwi_batch *b, const fwi_time *t, const float *v, float *d_pred, void *ws,
+                       size_t ws_bytes, void *stream)
+{
+    Plan p;
+    fwi_status s = prologue(b, t, nullptr, ws, ws_bytes, p);
+    if (s) return s;
+    if (!v) return fail(FWI_E_ARG, "null model");
+    hipStream_t st = (hipStream_t)stream;
+    Dev d = carve(p, ws);
+    s = upload_tables(p, d.base + p.o_tables, st);
+    if (s) return s;
+    return run_forward(p, d, b, t, v, d_pred ? d_pred : d.rho, st);
+}
+
+fwi_status fwi_adjoint(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_res,
+                       const double *kappa, float *grad, float *grad_norm, void *ws, size_t ws_bytes, void *stream)
+{
+    Plan p;
+    fwi_status s = prologue(b, t, kappa, ws, ws_bytes, p);
+    if (s) return s;
+    if (!v || !d_res || !grad) return fail(FWI_E_ARG, "null model, residual or gradient");
+    if (p.fwd_only) return fail(FWI_E_ARG, "ckpt_every = -1 keeps no adjoint state");
+    hipStream_t st = (hipStream_t)stream;
+    Dev d = carve(p, ws);
+    s = upload_tables(p, d.base + p.o_tables, st);
+    if (s) return s;
+    HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, st));
+    return run_adjoint(p, d, b, t, v, d_res, grad, grad_norm, st);
+}
+
+fwi_status fwi_gradient(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_obs,
+                        float inv_sigma2, const double *kappa, float *d_pred, double *misfit, float *grad,
+                        float *grad_norm, void *ws, size_t ws_bytes, void *stream)
+{
+    Plan p;
+    fwi_status s = prologue(b, t, kappa, ws, ws_bytes, p);
+    if (s) return s;
+    if (!v || !d_obs || !grad) return fail(FWI_E_ARG, "null model, observed data or gradient");
+    if (p.fwd_only) return fail(FWI_E_ARG, "ckpt_every = -1 keeps no adjoint state");
+    if (!std::isfinite(inv_sigma2) || !(inv_sigma2 > 0)) return fail(FWI_E_ARG, "inv_sigma2 must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    Dev d = carve(p, ws);
+    s = upload_tables(p, d.base + p.o_tables, st);
+    if (s) return s;
+    float *dat = d_pred ? d_pred : d.rho;
+    s = run_forward(p, d, b, t, v, dat, st);
+    if (s) return s;
+    HIP_TRY(launch_residual(d.sims, b->nsim, p.nt_rec, dat, d_obs, d.rho, inv_sigma2, d.part, p.nchunk_res,
+                            d.status, st));
+    HIP_TRY(launch_misfit_final(d.part, p.nchunk_res, b->nsim, 0.5 * (double)inv_sigma2, misfit ? misfit : d.mis,
+                                st));
+    return run_adjoint(p, d, b, t, v, d.rho, grad, grad_norm, st);
+}
+
+fwi_status fwi_encode(const float *d_shots, int32_t nshot, int64_t n_per_shot, int32_t ngrp, const int32_t *grp_ptr,
+                      const int32_t *grp_shot, const float *grp_w, int32_t n_entries, float *d_enc, void *stream)
+{
+    if (!d_shots || !grp_ptr || !grp_shot || !grp_w || !d_enc) return fail(FWI_E_ARG, "null pointer");
+    if (nshot < 1 || n_per_shot < 1 || ngrp < 1 || n_entries < 0) return fail(FWI_E_ARG, "sizes must be >= 1");
+    if (ngrp > 65535) return fail(FWI_E_UNSUPPORTED, "more than 65535 groups");
+    HIP_TRY(launch_encode(d_shots, nshot, n_per_shot, ngrp, grp_ptr, grp_shot, grp_w, n_entries, d_enc,
+                          (hipStream_t)stream));
+    return FWI_OK;
+}
+
+// Philox4x64-10 (Salmon et al., SC 2011), host copy for the encoding draw.
+static void philox4x64_host(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)M0 * c[0];
+        const unsigned __int128 p1 = (unsigned __int128)M1 * c[2];
+        const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c[1] ^ k0;
+        const uint64_t n2 = (uint64_t)(p0 >> 64) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint64_t)p1;
+        c[2] = n2;
+        c[3] = (uint64_t)p0;
+    }
+}
+
+fwi_status fwi_draw_encoding(uint64_t seed, uint64_t step, uint64_t sample, int32_t nshot, int32_t s, int32_t G,
+                             int32_t *grp_shot, float *grp_w, double *kappa)
+{
+    if (!grp_shot || !grp_w || !kappa) return fail(FWI_E_ARG, "null output");
+    if (nshot < 1 || s < 1 || s > nshot || G < 1) return fail(FWI_E_ARG, "need 1 <= s <= nshot and G >= 1");
+    // word j of the stream: word (j mod 4) of Philox({j/4, step, sample, 0}, {seed, 0x454E43})
+    auto word = [&](uint64_t j) {
+        uint64_t c[4] = {j >> 2, step, sample, 0};
+        philox4x64_host(c, seed, 0x454E43ULL);
+        return c[j & 3];
+    };
+    const int per = nshot / s;
+    const int P = (G + per - 1) / per;
+    std::vector<int32_t> perm(nshot);
+    for (int g = 0; g < G; ++g) {
+        const int part = g / per, slot = g % per;
+        if (slot == 0) {
+            for (int i = 0; i < nshot; ++i) perm[i] = i;
+            for (int i = nshot - 1; i >= 1; --i) {
+                const uint64_t w = word((uint64_t)part * nshot + (uint64_t)(nshot - 1 - i));
+                const int j = (int)(w % (uint64_t)(i + 1));
+                std::swap(perm[i], perm[j]);
+            }
+        }
+        for (int m = 0; m < s; ++m) {
+            grp_shot[g * s + m] = perm[slot * s + m];
+            const uint64_t w = word((uint64_t)P * nshot + (uint64_t)g * s + m);
+            grp_w[g * s + m] = (w >> 63) ? -1.0f : 1.0f;
+        }
+    }
+    *kappa = (double)nshot / ((double)G * s);
+    return FWI_OK;
+}
+
+fwi_status fwi_langevin(int32_t nsample, const int64_t *model_off, float *v, const float *grad, const float *xi,
+                        uint64_t seed, uint64_t step, float eta, float nu, float v_lo, float v_hi, void *stream)
+{
+    if (nsample < 1 || !model_off || !v || !grad) return fail(FWI_E_ARG, "null argument or nsample < 1");
+    if (!(eta >= 0) || !(nu >= 0) || !std::isfinite(eta) || !std::isfinite(nu))
+        return fail(FWI_E_ARG, "eta and nu must be finite and >= 0");
+    if (!(v_lo <= v_hi)) return fail(FWI_E_ARG, "v_lo must be <= v_hi");
+    for (int k = 0; k < nsample; ++k)
+        if (model_off[k] < 0 || model_off[k + 1] < model_off[k]) return fail(FWI_E_ARG, "model_off not monotonic");
+    hipStream_t st = (hipStream_t)stream;
+    for (int k = 0; k < nsample; ++k) {
+        const int64_t o = model_off[k], n = model_off[k + 1] - model_off[k];
+        HIP_TRY(launch_langevin(n, v + o, grad + o, xi ? xi + o : nullptr, seed, step, (uint64_t)k, (double)eta,
+                                (double)nu, (double)v_lo, (double)v_hi, st));
+    }
+    return FWI_OK;
+}
+
+fwi_status fwi_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_timing.m);
+    g_timing.on = on != 0;
+    return FWI_OK;
+}
+
+fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, int32_t reset)
+{
+    if (kind < 0 || kind > 1 || !total_ms || !launches) return fail(FWI_E_ARG, "bad kind or null output");
+    std::lock_guard<std::mutex> lk(g_timing.m);
+    for (auto &pr : g_timing.pending) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventSynchronize(pr.b));
+        HIP_TRY(hipEventElapsedTime(&ms, pr.a, pr.b));
+        g_timing.total_ms[pr.kind] += ms;
+        g_timing.count[pr.kind] += 1;
+        g_timing.pool.push_back(pr.a);
+        g_timing.pool.push_back(pr.b);
+    }
+    g_timing.pending.clear();
+    *total_ms = g_timing.total_ms[kind];
+    *launches = g_timing.count[kind];
+    if (reset) {
+        g_timing.total_ms[kind] = 0;
+        g_timing.count[kind] = 0;
+    }
+    return FWI_OK;
+}
+
+fwi_status fwi_copy_probe(const float *src, float *dst, int64_t n, void *stream)
+{
+    if (!src || !dst || n < 0 || n % 4) return fail(FWI_E_ARG, "need non-null buffers and n % 4 == 0");
+    if (((uintptr_t)src | (uintptr_t)dst) % 16) return fail(FWI_E_ARG, "buffers must be 16-byte aligned");
+    HIP_TRY(launch_copy(src, dst, n, (hipStream_t)stream));
+    return FWI_OK;
+}
+
+fwi_status fwi_poll_status(void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ws || ws_bytes < 64) return fail(FWI_E_WORKSPACE, "null or too small workspace");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    int flags = 0;
+    HIP_TRY(hipMemcpy(&flags, ws, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags) {
+        const int zero = 0;
+        HIP_TRY(hipMemcpy(ws, &zero, sizeof zero, hipMemcpyHostToDevice));
+        return fail(FWI_E_NONFINITE, "device flags 0x%x: %s%s%s", flags,
+                    (flags & 1) ? "[model non-finite, <= 0 or above v_max] " : "",
+                    (flags & 2) ? "[non-finite predicted data] " : "", (flags & 4) ? "[non-finite gradient]" : "");
+    }
+    return FWI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// fwi_internal.h -- descriptors shared by the host scheduler and the gfx950 kernels.
+//
+// Layout of the batch on the device: every simulation ("sim") owns one padded grid
+// (physical grid plus nb sponge cells on every face) per field level, packed one after
+// the other at SimDesc::u_off.  Per-sample arrays (the leapfrog coefficient c = dt^2 v^2 /
+// (1 + gamma dt)) are packed at SampleDesc::c_off.  x is the fastest axis, then y, then z.
+#pragma once
+#include <stdint.h>
+
+namespace fwi {
+
+constexpr int kTileX = 64;   // one wavefront spans 64 consecutive x cells
+constexpr int kTileY3 = 8;   // 3D tile: 64 x 8 cells per xy plane
+constexpr int kHalo = 4;     // 8th-order stencil radius
+
+struct SimDesc {
+    int64_t u_off;      // element offset of this sim in every field level
+    int64_t c_off;      // element offset of its sample in the coefficient array
+    int64_t d_off;      // element offset of its data [nt_rec][nrec]
+    int64_t m_off;      // element offset of its sample's physical model
+    int32_t N[3];       // padded dims (z, y, x); y = 1 in 2D
+    int32_t n[3];       // physical dims
+    int32_t nb;         // sponge cells
+    int32_t nrec;       // receivers of this sim
+    int32_t src_beg;    // first source (index into the batch source table)
+    int32_t src_cnt;    // number of sources
+    int32_t sample;     // owning sample
+    int32_t ndim;
+    float w[3][5];      // stencil weights C_k / h_a^2, axes (z, y, x); zero for an unused axis
+    float inv_vol;      // 1 / prod h
+    float pad0;
+    double gmax[3];     // sponge gmax per axis (z, y, x); zero for an unused axis
+    double dt;
+};
+
+struct SampleDesc {
+    int64_t m_off;      // physical model / gradient offset
+    int64_t c_off;      // padded coefficient offset
+    int32_t N[3];
+    int32_t n[3];
+    int32_t nb;
+    int32_t sim_beg;    // first sim of this sample
+    int32_t sim_cnt;    // its number of sims
+    int32_t ndim;
+    double gmax[3];
+    double dt;
+    double v_max;
+    double kappa;
+    int64_t nphys;      // physical cells
+    int64_t ncell;      // padded cells
+};
+
+struct Tile {
+    int32_t sim;
+    int32_t x0, y0, z0; // padded coordinates of the tile origin
+    int32_t ev_beg;     // first receiver event row of this tile
+    int32_t ev_cnt;     // number of event rows
+    int32_t pad0, pad1;
+};
+
+// One row (2D: a grid row; 3D: an xy plane) of a tile that holds receivers.  vec_off
+// points at kTileX * ty entries of receiver indices (local to the sim) or -1.
+struct EvRow {
+    int32_t z;
+    int32_t vec_off;
+};
+
+struct SrcPos {
+    int32_t z, y, x;    // padded coordinates
+    float w;            // encoding weight
+};
+
+// Arguments of one time step (forward, recompute or adjoint).
+struct StepArgs {
+    const SimDesc *sims;
+    const Tile *tiles;
+    const EvRow *evrows;
+    const int32_t *evvec;
+    const SrcPos *src;
+    const float *cur;       // u^n (or lt^{k+1})
+    const float *prev;      // u^{n-1} (or lt^{k+2})
+    float *next;            // u^{n+1} (or lt^k); may alias prev
+    const float *cf;        // per-sample c
+    float *wst;             // imaging operand W^n = L u^n + q^n for this step (nullable)
+    const float *wimg;      // adjoint: W^{k-1} to image with
+    float *cka, *ckb;       // checkpoint slots for u^{n+1}, u^n (nullable)
+    float *dat;             // forward: recorded data (nullable)
+    const float *rho;       // adjoint: residual
+    double *gacc;           // adjoint: per-sim imaging accumulator
+    int32_t ntiles;
+    int32_t per_xcd;        // tiles per XCD chunk (grid = 8 * per_xcd)
+    int32_t rec_j;          // recording slot j, or -1
+    float fn;               // wavelet sample f[n] (forward)
+};
+
+}  // namespace fwi

@@ -1,0 +1,787 @@
+// fwi_kernels.hip -- gfx950 (CDNA4) kernels of the encoded-shot FWI gradient.
+//
+// Time stepping (both dims) streams each tile along z with a 9-deep register queue for
+// the z-derivative of the 8th-order Laplacian; the x (and y) neighbours come from an LDS
+// row/plane.  One wavefront covers 64 consecutive x cells, so every global access of a
+// row is a coalesced 256-byte segment.  One launch per time step covers every tile of
+// every simulation of the batch (grids may differ in size); the block -> tile map gives
+// each of the 8 XCDs a contiguous chunk of tiles so neighbouring tiles share an L2.
+//
+// Scheme (per padded cell): u^{n+1} = a u^n - b u^{n-1} + c (L u^n + q^n), with
+// a = 2/(1+gamma dt), b = (1-gamma dt)/(1+gamma dt) computed from the cell index in
+// FP64 and rounded once, and c precomputed per sample in FP64 and rounded once.
+// The scaled adjoint lt = c lambda obeys the same recursion backward in time with
+// c-weighted receiver injection; the imaging term lt^k (L u^{k-1} + q^{k-1}) is summed
+// in FP64 per sim.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fwi_internal.h"
+#include "fwi_launch.h"
+
+namespace fwi {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int xcd_tile(int bid, int per_xcd) { return (bid & 7) * per_xcd + (bid >> 3); }
+
+// gamma contribution of one axis: gmax * (d/nb)^2 with d the cells into the sponge.
+// Evaluated with contraction off so it rounds exactly like a plain FP64 expression.
+__device__ __forceinline__ double sponge_axis(int p, int n, int nb, double gmax)
+{
+#pragma clang fp contract(off)
+    if (nb == 0) return 0.0;
+    int d = p < nb ? nb - p : (p > nb + n - 1 ? p - (nb + n - 1) : 0);
+    double r = (double)d / (double)nb;
+    return gmax * r * r;
+}
+
+__device__ __forceinline__ void sponge_ab(double gam, double dt, float &a, float &b)
+{
+#pragma clang fp contract(off)
+    if (gam == 0.0) {
+        a = 2.0f;
+        b = 1.0f;
+        return;
+    }
+    double gd = gam * dt;
+    a = (float)(2.0 / (1.0 + gd));
+    b = (float)((1.0 - gd) / (1.0 + gd));
+}
+
+__device__ __forceinline__ double coef_c(double v, double gam, double dt)
+{
+#pragma clang fp contract(off)
+    double gd = gam * dt;
+    return dt * dt * v * v / (1.0 + gd);
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ p, int64_t n, T val)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = val;
+}
+
+// ------------------------------------------------------------- coefficients
+
+// c = dt^2 v_pad^2 / (1 + gamma dt) for every padded cell of every sample; flags
+// non-finite, non-positive or above-v_max velocities.
+__global__ void k_prep(const SampleDesc *__restrict__ smp, const float *__restrict__ v, float *__restrict__ cf,
+                       int *__restrict__ status)
+{
+    const SampleDesc S = smp[blockIdx.y];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int Nx = S.N[2], Ny = S.N[1];
+    const int nby = S.ndim == 3 ? S.nb : 0;
+    int bad = 0;
+    for (; i < S.ncell; i += stride) {
+        int px = (int)(i % Nx);
+        int64_t r = i / Nx;
+        int py = (int)(r % Ny);
+        int pz = (int)(r / Ny);
+        int ix = min(max(px - S.nb, 0), S.n[2] - 1);
+        int iy = min(max(py - nby, 0), S.n[1] - 1);
+        int iz = min(max(pz - S.nb, 0), S.n[0] - 1);
+        float vv = v[S.m_off + ((int64_t)iz * S.n[1] + iy) * S.n[2] + ix];
+        if (!(vv > 0.0f) || !(vv <= (float)S.v_max) || !isfinite(vv)) bad = 1;
+        double gam = 0.0;
+        gam = gam + sponge_axis(pz, S.n[0], S.nb, S.gmax[0]);
+        if (S.ndim == 3) gam = gam + sponge_axis(py, S.n[1], S.nb, S.gmax[1]);
+        gam = gam + sponge_axis(px, S.n[2], S.nb, S.gmax[2]);
+        cf[S.c_off + i] = (float)coef_c((double)vv, gam, S.dt);
+    }
+    if (bad) atomicOr(status, 1);
+}
+
+// ------------------------------------------------------------ 2D stepping
+
+// Per-lane source bookkeeping for one tile: the row of the lane's source (or -1) and
+// the summed weight; `multi` when a lane holds sources on more than one row.
+struct LaneSrc {
+    int z;
+    float w;
+    bool multi;
+};
+
+__device__ __forceinline__ LaneSrc scan_sources_2d(const SrcPos *__restrict__ src, int beg, int cnt, int x,
+                                                   int z0, int z1)
+{
+    LaneSrc r{-1, 0.0f, false};
+    for (int s = 0; s < cnt; ++s) {
+        const SrcPos p = src[beg + s];
+        if (p.x == x && p.z >= z0 && p.z < z1) {
+            if (r.z < 0 || r.z == p.z) {
+                r.z = p.z;
+                r.w += p.w;
+            } else {
+                r.multi = true;
+            }
+        }
+    }
+    return r;
+}
+
+// Laplacian of the centre row held in `row` (x neighbours, offset 4) and queue q (z).
+__device__ __forceinline__ float lap2d(const float *row, int lane, const float (&q)[9], const float (&wz)[5],
+                                       const float (&wx)[5])
+{
+    float lx = wx[0] * q[4];
+    lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+    lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+    lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+    lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+    float lz = wz[0] * q[4];
+    lz += wz[1] * (q[3] + q[5]);
+    lz += wz[2] * (q[2] + q[6]);
+    lz += wz[3] * (q[1] + q[7]);
+    lz += wz[4] * (q[0] + q[8]);
+    return lz + lx;
+}
+
+template <int BZ, bool ADJ>
+__global__ __launch_bounds__(64) void k_step2d(const StepArgs A)
+{
+    const int t = xcd_tile(blockIdx.x, A.per_xcd);
+    if (t >= A.ntiles) return;
+    const Tile T = A.tiles[t];
+    const SimDesc &S = A.sims[T.sim];
+    const int Nx = S.N[2], Nz = S.N[0];
+    const int lane = threadIdx.x;
+    const int x = T.x0 + lane;
+    const bool xin = x < Nx;
+    const int z0 = T.z0;
+    const int z1 = min(z0 + BZ, Nz);
+    const float *__restrict__ U = A.cur + S.u_off;
+    const float *Up = A.prev + S.u_off;
+    float *Un = A.next + S.u_off;
+    const float *__restrict__ Cf = A.cf + S.c_off;
+
+    float wz[5], wx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        wz[k] = S.w[0][k];
+        wx[k] = S.w[2][k];
+    }
+    __shared__ float row[kTileX + 2 * kHalo];
+
+    // sponge: x part per lane (z part per row), parameters of the nb-cell profile
+    const double gx = sponge_axis(x, S.n[2], S.nb, S.gmax[2]);
+    const double dt = S.dt;
+
+    LaneSrc src{-1, 0.0f, false};
+    bool multi = false;
+    float famp = 0.0f;
+    if (!ADJ) {
+        src = scan_sources_2d(A.src, S.src_beg, S.src_cnt, x, z0, z1);
+        multi = __any(src.multi);
+        famp = A.fn * S.inv_vol;
+    }
+
+    // halo lanes: 0..3 -> x0-4..x0-1, 4..7 -> x0+64..x0+67
+    const int hx = lane < 4 ? T.x0 - kHalo + lane : T.x0 + kTileX - 4 + lane;
+    const bool hl = lane < 8 && hx >= 0 && hx < Nx;
+
+    float q[9];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int zz = z0 - kHalo + k;
+        q[k] = (xin && zz >= 0 && zz < Nz) ? U[(int64_t)zz * Nx + x] : 0.0f;
+    }
+    int ev = T.ev_beg;
+    const int ev_end = T.ev_beg + T.ev_cnt;
+    const bool rec = A.rec_j >= 0;
+
+    for (int z = z0; z < z1; ++z) {
+        const int64_t rowoff = (int64_t)z * Nx;
+        {
+            int zz = z + kHalo;
+            q[8] = (xin && zz < Nz) ? U[rowoff + (int64_t)kHalo * Nx + x] : 0.0f;
+        }
+        const float h = hl ? U[rowoff + hx] : 0.0f;
+        row[lane + kHalo] = q[4];
+        if (lane < 4)
+            row[lane] = h;
+        else if (lane < 8)
+            row[kTileX + lane] = h;
+        __syncthreads();
+        float wv = lap2d(row, lane, q, wz, wx);
+
+        float a, b;
+        {
+            double gam = 0.0;
+            gam = gam + sponge_axis(z, S.n[0], S.nb, S.gmax[0]);
+            gam = gam + gx;
+            sponge_ab(gam, dt, a, b);
+        }
+        // receiver of this lane on this row (event rows are sorted by z, one per row)
+        int rid = -1;
+        if (rec) {
+            while (ev < ev_end && A.evrows[ev].z < z) ++ev;
+            if (ev < ev_end && A.evrows[ev].z == z) rid = A.evvec[A.evrows[ev].vec_off + lane];
+        }
+        if (!ADJ) {
+            if (z == src.z) wv += src.w * famp;
+            if (multi) {
+                // a lane holds sources on several rows of this tile: add all at (z, x)
+                float extra = 0.0f;
+                if (src.multi)
+                    for (int s = 0; s < S.src_cnt; ++s) {
+                        const SrcPos p = A.src[S.src_beg + s];
+                        if (p.x == x && p.z == z && z != src.z) extra += p.w;
+                    }
+                wv += extra * famp;
+            }
+        } else if (rid >= 0) {
+            // c-weighted injection of the residual at receivers recorded at this step
+            wv += A.rho[S.d_off + (int64_t)A.rec_j * S.nrec + rid];
+        }
+        if (xin) {
+            const int64_t o = rowoff + x;
+            const float c = Cf[o];
+            const float up = Up[o];
+            const float un = a * q[4] - b * up + c * wv;
+            Un[o] = un;
+            if (!ADJ) {
+                if (A.wst) __builtin_nontemporal_store(wv, A.wst + S.u_off + o);
+                if (A.cka) {
+                    A.cka[S.u_off + o] = un;
+                    A.ckb[S.u_off + o] = q[4];
+                }
+                if (rid >= 0 && A.dat) A.dat[S.d_off + (int64_t)A.rec_j * S.nrec + rid] = un;
+            } else {
+                const float wi = __builtin_nontemporal_load(A.wimg + S.u_off + o);
+                A.gacc[S.u_off + o] += (double)un * (double)wi;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
+    }
+}
+
+// ------------------------------------------------------------ 3D stepping
+
+// Block: 64 x 4 threads; tile 64 x TY cells in (x, y); each thread owns RPT = TY/4 rows
+// y = y0 + ty + 4 r.  The plane buffer holds the tile plus a 4-cell halo in x and y.
+template <int TY>
+struct Plane {
+    float v[TY + 2 * kHalo][kTileX + 2 * kHalo];
+};
+
+template <int BZ, int TY, bool ADJ>
+__global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
+{
+    constexpr int RPT = TY / 4;
+    const int t = xcd_tile(blockIdx.x, A.per_xcd);
+    if (t >= A.ntiles) return;
+    const Tile T = A.tiles[t];
+    const SimDesc &S = A.sims[T.sim];
+    const int Nx = S.N[2], Ny = S.N[1], Nz = S.N[0];
+    const int64_t plane = (int64_t)Nx * Ny;
+    const int lane = threadIdx.x & 63;
+    const int ty = threadIdx.x >> 6;
+    const int x = T.x0 + lane;
+    const int z0 = T.z0;
+    const int z1 = min(z0 + BZ, Nz);
+    const float *__restrict__ U = A.cur + S.u_off;
+    const float *Up = A.prev + S.u_off;
+    float *Un = A.next + S.u_off;
+    const float *__restrict__ Cf = A.cf + S.c_off;
+    __shared__ Plane<TY> P;
+
+    float wz[5], wy[5], wx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        wz[k] = S.w[0][k];
+        wy[k] = S.w[1][k];
+        wx[k] = S.w[2][k];
+    }
+    const double dt = S.dt;
+    const double gx = sponge_axis(x, S.n[2], S.nb, S.gmax[2]);
+
+    int yr[RPT];
+    bool in[RPT];
+    double gy[RPT];
+    int64_t col[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        yr[r] = T.y0 + ty + 4 * r;
+        in[r] = x < Nx && yr[r] < Ny;
+        gy[r] = sponge_axis(yr[r], S.n[1], S.nb, S.gmax[1]);
+        col[r] = (int64_t)yr[r] * Nx + x;
+    }
+
+    // sources
+    int sz[RPT];
+    float sw[RPT];
+    bool smulti = false;
+    float famp = 0.0f;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        sz[r] = -1;
+        sw[r] = 0.0f;
+    }
+    if (!ADJ) {
+        famp = A.fn * S.inv_vol;
+        for (int s = 0; s < S.src_cnt; ++s) {
+            const SrcPos p = A.src[S.src_beg + s];
+            if (p.x != x || p.z < z0 || p.z >= z1) continue;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (p.y == yr[r]) {
+                    if (sz[r] < 0 || sz[r] == p.z) {
+                        sz[r] = p.z;
+                        sw[r] += p.w;
+                    } else {
+                        smulti = true;
+                    }
+                }
+        }
+    }
+    const bool multi = __syncthreads_or(smulti);
+
+    float q[RPT][9];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int zz = z0 - kHalo + k;
+            q[r][k] = (in[r] && zz >= 0 && zz < Nz) ? U[(int64_t)zz * plane + col[r]] : 0.0f;
+        }
+
+    // y-halo: LDS rows 0..3 (y0-4..y0-1) and TY+4..TY+7 (y0+TY..y0+TY+3); thread (ty, lane)
+    // loads row ty and row TY+4+ty.  x-halo: 8 columns x TY rows by the first TY*8 threads.
+    const int hy0 = T.y0 - kHalo + ty, hy1 = T.y0 + TY + ty;
+    const bool hyl0 = x < Nx && hy0 >= 0, hyl1 = x < Nx && hy1 < Ny;
+    const int xh_t = threadIdx.x;                 // < TY * 8 participates
+    const int xh_row = xh_t >> 3, xh_c = xh_t & 7;
+    const int xh_col = xh_c < 4 ? xh_c : kTileX + xh_c;       // LDS column
+    const int xh_x = T.x0 - kHalo + xh_col;                   // global x
+    const int xh_y = T.y0 + xh_row;
+    const bool xhl = xh_t < TY * 8 && xh_x >= 0 && xh_x < Nx && xh_y < Ny;
+
+    int ev = T.ev_beg;
+    const int ev_end = T.ev_beg + T.ev_cnt;
+    const bool rec = A.rec_j >= 0;
+
+    for (int z = z0; z < z1; ++z) {
+        const int64_t zoff = (int64_t)z * plane;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            int zz = z + kHalo;
+            q[r][8] = (in[r] && zz < Nz) ? U[zoff + (int64_t)kHalo * plane + col[r]] : 0.0f;
+            P.v[ty + 4 * r + kHalo][lane + kHalo] = q[r][4];
+        }
+        P.v[ty][lane + kHalo] = hyl0 ? U[zoff + (int64_t)hy0 * Nx + x] : 0.0f;
+        P.v[TY + kHalo + ty][lane + kHalo] = hyl1 ? U[zoff + (int64_t)hy1 * Nx + x] : 0.0f;
+        if (xh_t < TY * 8) P.v[xh_row + kHalo][xh_col] = xhl ? U[zoff + (int64_t)xh_y * Nx + xh_x] : 0.0f;
+        __syncthreads();
+
+        const double gz = sponge_axis(z, S.n[0], S.nb, S.gmax[0]);
+        // receiver event row of this plane (uniform)
+        int evoff = -1;
+        if (rec) {
+            while (ev < ev_end && A.evrows[ev].z < z) ++ev;
+            if (ev < ev_end && A.evrows[ev].z == z) evoff = A.evrows[ev].vec_off;
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int ly = ty + 4 * r + kHalo;
+            const int lx = lane + kHalo;
+            float sx = wx[0] * q[r][4];
+            sx += wx[1] * (P.v[ly][lx - 1] + P.v[ly][lx + 1]);
+            sx += wx[2] * (P.v[ly][lx - 2] + P.v[ly][lx + 2]);
+            sx += wx[3] * (P.v[ly][lx - 3] + P.v[ly][lx + 3]);
+            sx += wx[4] * (P.v[ly][lx - 4] + P.v[ly][lx + 4]);
+            float sy = wy[0] * q[r][4];
+            sy += wy[1] * (P.v[ly - 1][lx] + P.v[ly + 1][lx]);
+            sy += wy[2] * (P.v[ly - 2][lx] + P.v[ly + 2][lx]);
+            sy += wy[3] * (P.v[ly - 3][lx] + P.v[ly + 3][lx]);
+            sy += wy[4] * (P.v[ly - 4][lx] + P.v[ly + 4][lx]);
+            float sz_ = wz[0] * q[r][4];
+            sz_ += wz[1] * (q[r][3] + q[r][5]);
+            sz_ += wz[2] * (q[r][2] + q[r][6]);
+            sz_ += wz[3] * (q[r][1] + q[r][7]);
+            sz_ += wz[4] * (q[r][0] + q[r][8]);
+            float wv = sz_ + sy + sx;
+            float a, b;
+            {
+                double gam = 0.0;
+                gam = gam + gz;
+                gam = gam + gy[r];
+                gam = gam + gx;
+                sponge_ab(gam, dt, a, b);
+            }
+            const int rid = evoff >= 0 ? A.evvec[evoff + (ty + 4 * r) * kTileX + lane] : -1;
+            if (!ADJ) {
+                if (z == sz[r]) wv += sw[r] * famp;
+                if (multi) {
+                    float extra = 0.0f;
+                    if (in[r])
+                        for (int s = 0; s < S.src_cnt; ++s) {
+                            const SrcPos p = A.src[S.src_beg + s];
+                            if (p.x == x && p.y == yr[r] && p.z == z && z != sz[r]) extra += p.w;
+                        }
+                    wv += extra * famp;
+                }
+            } else if (rid >= 0) {
+                wv += A.rho[S.d_off + (int64_t)A.rec_j * S.nrec + rid];
+            }
+            if (in[r]) {
+                const int64_t o = zoff + col[r];
+                const float c = Cf[o];
+                const float up = Up[o];
+                const float un = a * q[r][4] - b * up + c * wv;
+                Un[o] = un;
+                if (!ADJ) {
+                    if (A.wst) __builtin_nontemporal_store(wv, A.wst + S.u_off + o);
+                    if (A.cka) {
+                        A.cka[S.u_off + o] = un;
+                        A.ckb[S.u_off + o] = q[r][4];
+                    }
+                    if (rid >= 0 && A.dat) A.dat[S.d_off + (int64_t)A.rec_j * S.nrec + rid] = un;
+                } else {
+                    const float wi = __builtin_nontemporal_load(A.wimg + S.u_off + o);
+                    A.gacc[S.u_off + o] += (double)un * (double)wi;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) q[r][k] = q[r][k + 1];
+    }
+}
+
+// ---------------------------------------------------------- misfit/residual
+
+// Block (chunk, sim): rho = (d - d_obs) inv_sigma2 and a partial sum of (d - d_obs)^2.
+__global__ __launch_bounds__(256) void k_residual(const SimDesc *__restrict__ sims, int nt_rec,
+                                                  const float *d, const float *__restrict__ dobs,
+                                                  float *rho, float inv_sigma2,
+                                                  double *__restrict__ partial, int nchunk,
+                                                  int *__restrict__ status)
+{
+    const SimDesc &S = sims[blockIdx.y];
+    const int64_t n = (int64_t)nt_rec * S.nrec;
+    const int64_t per = (n + nchunk - 1) / nchunk;
+    const int64_t beg = (int64_t)blockIdx.x * per;
+    const int64_t end = min(beg + per, n);
+    double acc = 0.0;
+    int bad = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const float r = d[S.d_off + i] - dobs[S.d_off + i];
+        if (!isfinite(r)) bad = 1;
+        rho[S.d_off + i] = r * inv_sigma2;
+        acc += (double)r * (double)r;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * nchunk + blockIdx.x] = red[0];
+    if (bad) atomicOr(status, 2);
+}
+
+__global__ void k_misfit_final(const double *__restrict__ partial, int nchunk, int nsim, double half_is2,
+                               double *__restrict__ misfit)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsim) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += partial[(int64_t)s * nchunk + c];
+    misfit[s] = half_is2 * acc;
+}
+
+// ------------------------------------------------------------- finalize
+
+// grad[s][cell] = kappa_s (2 / v) sum_{sims of s} sum_{padded cells replicating cell} g;
+// block (chunk, sample) also leaves a partial sum of grad^2.
+__global__ __launch_bounds__(256) void k_finalize(const SampleDesc *__restrict__ smp, const SimDesc *__restrict__ sims,
+                                                  const double *__restrict__ gacc, const float *__restrict__ v,
+                                                  float *__restrict__ grad, double *__restrict__ partial,
+                                                  int nchunk, int *__restrict__ status)
+{
+    const SampleDesc S = smp[blockIdx.y];
+    const int nx = S.n[2], ny = S.n[1], nz = S.n[0];
+    const int Nx = S.N[2], Ny = S.N[1];
+    const int nby = S.ndim == 3 ? S.nb : 0;
+    const int64_t per = (S.nphys + nchunk - 1) / nchunk;
+    const int64_t beg = (int64_t)blockIdx.x * per;
+    const int64_t end = min(beg + per, S.nphys);
+    double acc2 = 0.0;
+    int bad = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const int ix = (int)(i % nx);
+        const int64_t rr = i / nx;
+        const int iy = (int)(rr % ny);
+        const int iz = (int)(rr / ny);
+        const int xl = ix == 0 ? 0 : ix + S.nb, xh = ix == nx - 1 ? Nx - 1 : ix + S.nb;
+        const int yl = iy == 0 ? 0 : iy + nby, yh = iy == ny - 1 ? Ny - 1 : iy + nby;
+        const int zl = iz == 0 ? 0 : iz + S.nb, zh = iz == nz - 1 ? S.N[0] - 1 : iz + S.nb;
+        double sum = 0.0;
+        for (int s = 0; s < S.sim_cnt; ++s) {
+            const double *g = gacc + sims[S.sim_beg + s].u_off;
+            for (int pz = zl; pz <= zh; ++pz)
+                for (int py = yl; py <= yh; ++py) {
+                    const int64_t base = ((int64_t)pz * Ny + py) * Nx;
+                    for (int px = xl; px <= xh; ++px) sum += g[base + px];
+                }
+        }
+        const double val = S.kappa * (2.0 / (double)v[S.m_off + i]) * sum;
+        const float gv = (float)val;
+        if (!isfinite(gv)) bad = 1;
+        grad[S.m_off + i] = gv;
+        acc2 += (double)gv * (double)gv;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * nchunk + blockIdx.x] = red[0];
+    if (bad) atomicOr(status, 4);
+}
+
+__global__ void k_norm_final(const double *__restrict__ partial, int nchunk, int nsample, float *__restrict__ norm)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsample) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += partial[(int64_t)s * nchunk + c];
+    norm[s] = (float)sqrt(acc);
+}
+
+// ----------------------------------------------------------------- encode
+
+__global__ __launch_bounds__(256) void k_encode(const float *__restrict__ d, int nshot, int64_t nper,
+                                                const int32_t *__restrict__ gp, const int32_t *__restrict__ gs,
+                                                const float *__restrict__ gw, int n_entries, float *__restrict__ out)
+{
+    const int g = blockIdx.y;
+    const int b = gp[g], e = gp[g + 1];
+    // a malformed group table poisons the group's output instead of reading out of bounds
+    bool ok = b >= 0 && e >= b && e <= n_entries;
+    for (int k = b; ok && k < e; ++k) ok = gs[k] >= 0 && gs[k] < nshot;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nper; i += stride) {
+        float acc = ok ? 0.0f : __builtin_nanf("");
+        if (ok)
+            for (int k = b; k < e; ++k) acc += gw[k] * d[(int64_t)gs[k] * nper + i];
+        out[(int64_t)g * nper + i] = acc;
+    }
+}
+
+// --------------------------------------------------------------- Langevin
+
+// Philox4x64-10 (Salmon et al., SC 2011).
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+// One thread per group of 4 cells of one sample's model (n cells at v, g, xi).
+__global__ __launch_bounds__(256) void k_langevin(int64_t n, float *__restrict__ v, const float *__restrict__ g,
+                                                  const float *__restrict__ xi, uint64_t seed, uint64_t step,
+                                                  uint64_t sample, double eta, double nu, double lo, double hi)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (4 * m >= n) return;
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (xi == nullptr) {
+        uint64_t c[4] = {(uint64_t)m, step, sample, 0};
+        philox4x64(c, seed, 0x4C414E47ULL);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const double r = sqrt(-2.0 * log(u01(c[2 * p])));
+            const double th = 6.283185307179586476925 * u01(c[2 * p + 1]);
+            z[2 * p] = r * cos(th);
+            z[2 * p + 1] = r * sin(th);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = 4 * m + j;
+        if (i >= n) break;
+        const double xv = xi ? (double)xi[i] : z[j];
+        double y = (double)v[i] - eta * (double)g[i] + nu * xv;
+        y = y < lo ? lo : y;
+        y = y > hi ? hi : y;
+        v[i] = (float)y;
+    }
+}
+
+// ------------------------------------------------------------- copy probe
+
+// Plain streaming copy (16-byte vectors): the achievable-bandwidth reference and the
+// calibration kernel for hardware byte counters.
+__global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ s, float4 *__restrict__ d, int64_t n4)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n4; i += stride) d[i] = s[i];
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline int blocks_for(int64_t n, int bs, int cap)
+{
+    int64_t b = (n + bs - 1) / bs;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+hipError_t launch_copy(const float *src, float *dst, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_copy<<<blocks_for(n / 4, 256, 256 * 8 * 8), 256, 0, st>>>((const float4 *)src, (float4 *)dst, n / 4);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill<float><<<blocks_for(n, 256, 65536), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill<double><<<blocks_for(n, 256, 65536), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill<int><<<blocks_for(n, 256, 65536), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const SampleDesc *smp, int nsample, int64_t max_cell, const float *v, float *cf, int *status,
+                       hipStream_t st)
+{
+    dim3 grid(blocks_for(max_cell, 256, 4096), nsample);
+    k_prep<<<grid, 256, 0, st>>>(smp, v, cf, status);
+    return hipGetLastError();
+}
+
+template <bool ADJ>
+static hipError_t step2d_dispatch(const StepArgs &a, int bz, hipStream_t st)
+{
+    dim3 grid(8 * a.per_xcd);
+    switch (bz) {
+    case 8: k_step2d<8, ADJ><<<grid, 64, 0, st>>>(a); break;
+    case 16: k_step2d<16, ADJ><<<grid, 64, 0, st>>>(a); break;
+    case 32: k_step2d<32, ADJ><<<grid, 64, 0, st>>>(a); break;
+    case 64: k_step2d<64, ADJ><<<grid, 64, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool ADJ>
+static hipError_t step3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
+{
+    dim3 grid(8 * a.per_xcd);
+    if (ty == 8) {
+        switch (bz) {
+        case 16: k_step3d<16, 8, ADJ><<<grid, 256, 0, st>>>(a); break;
+        case 32: k_step3d<32, 8, ADJ><<<grid, 256, 0, st>>>(a); break;
+        case 64: k_step3d<64, 8, ADJ><<<grid, 256, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (ty == 16) {
+        switch (bz) {
+        case 16: k_step3d<16, 16, ADJ><<<grid, 256, 0, st>>>(a); break;
+        case 32: k_step3d<32, 16, ADJ><<<grid, 256, 0, st>>>(a); break;
+        case 64: k_step3d<64, 16, ADJ><<<grid, 256, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty, hipStream_t st)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    if (ndim == 2) return adjoint ? step2d_dispatch<true>(a, bz, st) : step2d_dispatch<false>(a, bz, st);
+    return adjoint ? step3d_dispatch<true>(a, bz, ty, st) : step3d_dispatch<false>(a, bz, ty, st);
+}
+
+hipError_t launch_residual(const SimDesc *sims, int nsim, int nt_rec, const float *d, const float *dobs, float *rho,
+                           float inv_sigma2, double *partial, int nchunk, int *status, hipStream_t st)
+{
+    dim3 grid(nchunk, nsim);
+    k_residual<<<grid, 256, 0, st>>>(sims, nt_rec, d, dobs, rho, inv_sigma2, partial, nchunk, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit_final(const double *partial, int nchunk, int nsim, double half_is2, double *misfit,
+                               hipStream_t st)
+{
+    k_misfit_final<<<(nsim + 255) / 256, 256, 0, st>>>(partial, nchunk, nsim, half_is2, misfit);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SampleDesc *smp, const SimDesc *sims, int nsample, const double *gacc,
+                           const float *v, float *grad, double *partial, int nchunk, int *status, hipStream_t st)
+{
+    dim3 grid(nchunk, nsample);
+    k_finalize<<<grid, 256, 0, st>>>(smp, sims, gacc, v, grad, partial, nchunk, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_final(const double *partial, int nchunk, int nsample, float *norm, hipStream_t st)
+{
+    k_norm_final<<<(nsample + 255) / 256, 256, 0, st>>>(partial, nchunk, nsample, norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const float *d, int nshot, int64_t nper, int ngrp, const int32_t *gp, const int32_t *gs,
+                         const float *gw, int n_entries, float *out, hipStream_t st)
+{
+    dim3 grid(blocks_for(nper, 256, 2048), ngrp);
+    k_encode<<<grid, 256, 0, st>>>(d, nshot, nper, gp, gs, gw, n_entries, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_langevin(int64_t n, float *v, const float *g, const float *xi, uint64_t seed, uint64_t step,
+                           uint64_t sample, double eta, double nu, double lo, double hi, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_langevin<<<blocks_for((n + 3) / 4, 256, 1 << 30), 256, 0, st>>>(n, v, g, xi, seed, step, sample, eta, nu,
+                                                                      lo, hi);
+    return hipGetLastError();
+}
+
+}  // namespace fwi

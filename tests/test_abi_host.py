@@ -1,0 +1,121 @@
+"""C ABI checks that need no GPU: symbols, host validation, workspace sizing, encoding draw."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2512_12797_amd import fwi
+    if not os.path.exists(fwi.LIB_PATH):
+        pytest.skip("library not built")
+    fwi.lib()
+    return fwi
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fwi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fwi_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(F):
+    names = declared_symbols()
+    assert len(names) >= 11
+    L = C.CDLL(F.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def small(F, **kw):
+    g = F.Grid(nz=20, nx=30, dz=10.0, dx=10.0, nb=4, v_ref=3000.0, v_max=3000.0)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    rec = np.arange(30, dtype=np.int32) + 30
+    wav = W.ricker(10.0, 1e-3, 100)
+    return g, rec, wav
+
+
+def expect(F, status, fn, *a):
+    with pytest.raises(F.FwiError) as e:
+        fn(*a)
+    assert e.value.status == status, str(e.value)
+
+
+def test_validation_errors(F):
+    g, rec, wav = small(F)
+    b = F.Batch([g], [0], [([31], [1.0])], [rec], wav)
+    t = F.time_axis(1e-3, 100, 2, 0)
+    assert 0 < F.fwi_check(b, t) < 0.79
+    # stability limit: v_max dt sqrt(2)/h must stay below sqrt(315/512)
+    lim = np.sqrt(315 / 512) / np.sqrt(2) * 10.0 / 3000.0
+    expect(F, F.FWI_E_CFL, F.fwi_check, b, F.time_axis(lim * 1.01, 100, 1, 0))
+    F.fwi_check(b, F.time_axis(lim * 0.99, 100, 1, 0))
+    expect(F, F.FWI_E_ARG, F.fwi_check, b, F.time_axis(1e-3, 101, 2, 0))
+    expect(F, F.FWI_E_ARG, F.fwi_check, b, F.time_axis(1e-3, 100, 1, -2))
+    gbad, _, _ = small(F, ny=2)
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([gbad], [0], [([31], [1.0])], [rec], wav), t)
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g], [0], [([600], [1.0])], [rec], wav), t)
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g], [0], [([31], [1.0])], [np.r_[rec, rec[:1]]], wav), t)
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g, g], [1, 0], [([31], [1.0])] * 2, [rec] * 2, wav), t)
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g, g], [0, 0], [([31], [1.0])] * 2, [rec] * 2, wav), t)
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g], [0], [([31], [np.nan])], [rec], wav), t)
+    g3 = F.Grid(nz=4, ny=4, nx=4, dz=10, dy=10, dx=10, nb=1, v_ref=2000, v_max=2000, ndim=3)
+    expect(F, F.FWI_E_UNSUPPORTED, F.fwi_check, F.Batch([g, g3], [0, 1], [([31], [1.0]), ([1], [1.0])],
+                                                        [rec, np.array([2], dtype=np.int32)], wav), t)
+
+
+def test_workspace_sizes(F):
+    g, rec, wav = small(F)
+    b = F.Batch([g], [0, 0], [([31], [1.0]), ([40], [-1.0])], [rec, rec], wav)
+    cells = 2 * (28 * 38)
+    full = F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, 0))
+    ck = F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, 10))
+    assert full >= 100 * cells * 4
+    assert ck < full
+    assert ck >= (10 + 2 * 9) * cells * 4
+
+
+def test_null_workspace_rejected_before_any_device_work(F):
+    g, rec, wav = small(F)
+    b = F.Batch([g], [0], [([31], [1.0])], [rec], wav)
+    t = F.time_axis(1e-3, 100, 2, 0)
+    L = F.lib()
+    st = L.fwi_forward(b.c, C.byref(t), C.c_void_p(1 << 20), None, None, 0, None)
+    assert st == F.FWI_E_WORKSPACE
+    st = L.fwi_gradient(b.c, C.byref(t), C.c_void_p(1 << 20), C.c_void_p(1 << 20), C.c_float(-1.0), None, None,
+                        None, C.c_void_p(1 << 20), None, C.c_void_p(1 << 21), 1 << 40, None)
+    assert st == F.FWI_E_ARG  # inv_sigma2 <= 0
+    assert b"inv_sigma2" in L.fwi_last_error()
+
+
+@pytest.mark.parametrize("nshot,s,G", [(80, 8, 10), (80, 16, 10), (8, 1, 8), (50, 8, 1), (7, 3, 5)])
+def test_draw_encoding_bit_exact_vs_oracle(F, nshot, s, G):
+    for step in (0, 1, 99):
+        for sample in (0, 5):
+            a = F.fwi_draw_encoding(2024, step, sample, nshot, s, G)
+            b = oracle.draw_encoding(2024, step, sample, nshot, s, G)
+            assert np.array_equal(a[0], b[0])
+            assert np.array_equal(a[1].astype(np.float64), b[1])
+            assert a[2] == b[2]
+
+
+def test_langevin_argument_checks(F):
+    L = F.lib()
+    off = np.array([0, 10], dtype=np.int64)
+    p = C.c_void_p(1 << 20)
+    st = L.fwi_langevin(1, off.ctypes.data_as(C.POINTER(C.c_int64)), p, p, None, 0, 0, C.c_float(-1.0),
+                        C.c_float(1.0), C.c_float(0.0), C.c_float(1.0), None)
+    assert st == F.FWI_E_ARG
+    st = L.fwi_langevin(1, off.ctypes.data_as(C.POINTER(C.c_int64)), p, p, None, 0, 0, C.c_float(1.0),
+                        C.c_float(1.0), C.c_float(2.0), C.c_float(1.0), None)
+    assert st == F.FWI_E_ARG
+    assert F.lib().fwi_status_string(F.FWI_E_CFL)
