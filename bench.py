@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--ckpt", default="auto", help="auto | 0 (keep all imaging operands) | K (checkpoint)")
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "

@@ -70,7 +70,8 @@ fwi_status check_grid(const fwi_grid &g, int i)
     if (g.nb > 0 && !(g.refl > 0 && g.refl < 1)) return fail(FWI_E_ARG, "grid %d: refl must be in (0,1)", i);
     if (!(g.v_max > 0) || !std::isfinite(g.v_max)) return fail(FWI_E_ARG, "grid %d: v_max must be > 0", i);
     const int64_t N = (int64_t)(g.nz + 2 * g.nb) * (g.ndim == 3 ? g.ny + 2 * g.nb : 1) * (g.nx + 2 * g.nb);
-    if (N >= (int64_t)1 << 31) return fail(FWI_E_UNSUPPORTED, "grid %d: more than 2^31 padded cells", i);
+    // fields are addressed through 32-bit byte offsets (FP64 accumulators: 8 bytes/cell)
+    if (N >= (int64_t)1 << 28) return fail(FWI_E_UNSUPPORTED, "grid %d: more than 2^28 padded cells", i);
     return FWI_OK;
 }
 
@@ -346,7 +347,9 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         i = j;
     }
     if (p.tiles.size() >= (size_t)1 << 30) return fail(FWI_E_UNSUPPORTED, "too many tiles");
-    p.per_xcd = (int)((p.tiles.size() + 7) / 8);
+    // 2D: a workgroup runs 4 tiles (one per wavefront); 3D: one tile per workgroup
+    const size_t nwg = p.ndim == 2 ? (p.tiles.size() + 3) / 4 : p.tiles.size();
+    p.per_xcd = (int)((nwg + 7) / 8);
     // table layout
     size_t o = 0;
     p.t_sims = o;

@@ -45,8 +45,9 @@ __device__ __forceinline__ void sponge_ab(double gam, double dt, float &a, float
         return;
     }
     double gd = gam * dt;
-    a = (float)(2.0 / (1.0 + gd));
-    b = (float)((1.0 - gd) / (1.0 + gd));
+    double inv = 1.0 / (1.0 + gd);
+    a = (float)(2.0 * inv);           // exactly 2/(1+gd) rounded: scaling by 2 is exact
+    b = (float)((1.0 - gd) * inv);
 }
 
 __device__ __forceinline__ double coef_c(double v, double gam, double dt)
@@ -125,7 +126,8 @@ __device__ __forceinline__ LaneSrc scan_sources_2d(const SrcPos *__restrict__ sr
 }
 
 // Laplacian of the centre row held in `row` (x neighbours, offset 4) and queue q (z).
-__device__ __forceinline__ float lap2d(const float *row, int lane, const float (&q)[9], const float (&wz)[5],
+template <int NQ>
+__device__ __forceinline__ float lap2d(const float *row, int lane, const float (&q)[NQ], const float (&wz)[5],
                                        const float (&wx)[5])
 {
     float lx = wx[0] * q[4];
@@ -141,23 +143,86 @@ __device__ __forceinline__ float lap2d(const float *row, int lane, const float (
     return lz + lx;
 }
 
-template <int BZ, bool ADJ>
-__global__ __launch_bounds__(64) void k_step2d(const StepArgs A)
+// Wave-scope ordering of LDS traffic: a wavefront executes in order, so making the
+// compiler keep program order is all that is needed between a wave's own LDS write and
+// its reads of neighbouring lanes.
+__device__ __forceinline__ void wave_lds_sync()
 {
-    const int t = xcd_tile(blockIdx.x, A.per_xcd);
-    if (t >= A.ntiles) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------ buffer access
+// Raw buffer loads/stores through a resource that spans one simulation's field: an
+// offset outside [0, bytes) reads 0 and drops a store in hardware, so the streaming
+// loops need no bounds branches (the Dirichlet ghost ring comes out as zeros).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit data format
+constexpr uint32_t kOOB = 0xFFFFFFF0u;  // an offset beyond every resource
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double bload64(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore64(rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r,
+                                          (int)off, 0, 0);
+}
+
+// 2D step.  A workgroup holds 4 independent wavefronts; each owns one 64 x BZ tile and
+// streams it along z.  Every global load for row z+4 is issued while row z is computed
+// (centre queue q, halo queue hq, and 4-deep queues of the point operands), so the
+// memory latency of a row overlaps four rows of work.  Loads are unconditional buffer
+// loads (rows outside the grid read 0); lanes beyond the grid's x extent keep 0.
+template <int BZ, bool ADJ>
+__global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
+{
+    constexpr int PF = 4;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the tile index is uniform per wavefront: say so, so that tile and simulation
+    // descriptors are fetched with scalar loads once, outside the row loop
+    const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd) * 4 + wave);
+    if (t >= A.ntiles) return;  // waves are independent: no workgroup barrier below
     const Tile T = A.tiles[t];
     const SimDesc &S = A.sims[T.sim];
     const int Nx = S.N[2], Nz = S.N[0];
-    const int lane = threadIdx.x;
+    const int nz_phys = S.n[0], nx_phys = S.n[2], nb = S.nb;
+    const double gmz = S.gmax[0], gmx = S.gmax[2];
+    const int64_t u_off = S.u_off, d_off = S.d_off;
+    const int nrec = S.nrec, src_beg = S.src_beg, src_cnt = S.src_cnt;
+    const uint32_t fbytes = (uint32_t)Nz * (uint32_t)Nx * 4u;
     const int x = T.x0 + lane;
     const bool xin = x < Nx;
     const int z0 = T.z0;
     const int z1 = min(z0 + BZ, Nz);
-    const float *__restrict__ U = A.cur + S.u_off;
-    const float *Up = A.prev + S.u_off;
-    float *Un = A.next + S.u_off;
-    const float *__restrict__ Cf = A.cf + S.c_off;
+    const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
+    const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
+    const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
+    const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
+    const rsrc_t rW = make_rsrc(ADJ ? A.wimg + u_off : (A.wst ? A.wst + u_off : A.next), ADJ || A.wst ? fbytes : 0);
+    const rsrc_t rG = make_rsrc(ADJ ? (const void *)(A.gacc + u_off) : (const void *)A.next, ADJ ? 2 * fbytes : 0);
+    const rsrc_t rKa = make_rsrc(A.cka ? A.cka + u_off : A.next, A.cka ? fbytes : 0);
+    const rsrc_t rKb = make_rsrc(A.ckb ? A.ckb + u_off : A.next, A.ckb ? fbytes : 0);
+    const int rec_j = A.rec_j;
+    float *Dat = (!ADJ && A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
+    const float *Rho = (ADJ && rec_j >= 0) ? A.rho + d_off + (int64_t)rec_j * nrec : nullptr;
+    const EvRow *__restrict__ evrows = A.evrows;
+    const int32_t *__restrict__ evvec = A.evvec;
 
     float wz[5], wx[5];
 #pragma unroll
@@ -165,100 +230,148 @@ __global__ __launch_bounds__(64) void k_step2d(const StepArgs A)
         wz[k] = S.w[0][k];
         wx[k] = S.w[2][k];
     }
-    __shared__ float row[kTileX + 2 * kHalo];
+    __shared__ float rows[4][2][kTileX + 2 * kHalo];
 
-    // sponge: x part per lane (z part per row), parameters of the nb-cell profile
-    const double gx = sponge_axis(x, S.n[2], S.nb, S.gmax[2]);
+    const double gx = sponge_axis(x, nx_phys, nb, gmx);
     const double dt = S.dt;
 
     LaneSrc src{-1, 0.0f, false};
     bool multi = false;
     float famp = 0.0f;
     if (!ADJ) {
-        src = scan_sources_2d(A.src, S.src_beg, S.src_cnt, x, z0, z1);
+        src = scan_sources_2d(A.src, src_beg, src_cnt, x, z0, z1);
         multi = __any(src.multi);
         famp = A.fn * S.inv_vol;
     }
 
-    // halo lanes: 0..3 -> x0-4..x0-1, 4..7 -> x0+64..x0+67
+    // byte offsets: lane column (clamped into the row for lanes past the edge, whose
+    // values are then forced to 0), halo column for lanes 0..7
+    const uint32_t xo = 4u * (uint32_t)min(x, Nx - 1);
     const int hx = lane < 4 ? T.x0 - kHalo + lane : T.x0 + kTileX - 4 + lane;
     const bool hl = lane < 8 && hx >= 0 && hx < Nx;
+    const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
+    const uint32_t rowb = 4u * (uint32_t)Nx;
+    auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
+    // wavefield reads: lanes past the x edge (or not halo lanes) use an out-of-range offset
+    // so that the hardware returns 0 and no select on the loaded value is needed
+    auto coff = [&](int zz) -> uint32_t { return xin ? roff(zz) + xo : kOOB; };
+    auto hoff = [&](int zz) -> uint32_t { return hl ? roff(zz) + ho : kOOB; };
 
-    float q[9];
+    // centre queue: rows z-4 .. z+8 (q[4] is row z; row z+8 arrives while row z is done)
+    float q[13], hq[PF + 1], cq[PF], pq[PF], wq[PF];
+    double gq[PF];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        int zz = z0 - kHalo + k;
-        q[k] = (xin && zz >= 0 && zz < Nz) ? U[(int64_t)zz * Nx + x] : 0.0f;
+    for (int k = 0; k < 12; ++k) q[k] = bload(rU, coff(z0 - kHalo + k));
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const uint32_t o = roff(z0 + k);
+        hq[k] = bload(rU, hoff(z0 + k));
+        cq[k] = bload(rC, o + xo);
+        pq[k] = bload(rP, o + xo);
+        if (ADJ) {
+            wq[k] = bload(rW, o + xo);
+            gq[k] = bload64(rG, 2 * (o + xo));
+        }
     }
+    // receiver event rows of this tile, kept in scalar registers (one row per z)
+    const bool rec = rec_j >= 0 && T.ev_cnt > 0;
     int ev = T.ev_beg;
     const int ev_end = T.ev_beg + T.ev_cnt;
-    const bool rec = A.rec_j >= 0;
+    int ev_z = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+    int ev_off = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
 
+    int par = 0;
     for (int z = z0; z < z1; ++z) {
-        const int64_t rowoff = (int64_t)z * Nx;
-        {
-            int zz = z + kHalo;
-            q[8] = (xin && zz < Nz) ? U[rowoff + (int64_t)kHalo * Nx + x] : 0.0f;
+        // ---- prefetch: centre row z+8, halo and point operands of row z+4 (reads
+        // beyond the tile are harmless and unused)
+        q[12] = bload(rU, coff(z + 8));
+        const uint32_t of = roff(z + PF);
+        const float hn = bload(rU, hoff(z + PF));
+        const float cn = bload(rC, of + xo);
+        const float pn = bload(rP, of + xo);
+        float wn = 0.0f;
+        double gn = 0.0;
+        if (ADJ) {
+            wn = bload(rW, of + xo);
+            gn = bload64(rG, 2 * (of + xo));
         }
-        const float h = hl ? U[rowoff + hx] : 0.0f;
+        // ---- row z
+        float *row = rows[wave][par];
         row[lane + kHalo] = q[4];
         if (lane < 4)
-            row[lane] = h;
+            row[lane] = hq[0];
         else if (lane < 8)
-            row[kTileX + lane] = h;
-        __syncthreads();
+            row[kTileX + lane] = hq[0];
+        wave_lds_sync();
         float wv = lap2d(row, lane, q, wz, wx);
+        par ^= 1;
 
         float a, b;
         {
             double gam = 0.0;
-            gam = gam + sponge_axis(z, S.n[0], S.nb, S.gmax[0]);
+            gam = gam + sponge_axis(z, nz_phys, nb, gmz);
             gam = gam + gx;
             sponge_ab(gam, dt, a, b);
         }
-        // receiver of this lane on this row (event rows are sorted by z, one per row)
-        int rid = -1;
-        if (rec) {
-            while (ev < ev_end && A.evrows[ev].z < z) ++ev;
-            if (ev < ev_end && A.evrows[ev].z == z) rid = A.evvec[A.evrows[ev].vec_off + lane];
-        }
+        const bool evrow = z == ev_z;  // uniform
         if (!ADJ) {
             if (z == src.z) wv += src.w * famp;
             if (multi) {
-                // a lane holds sources on several rows of this tile: add all at (z, x)
                 float extra = 0.0f;
                 if (src.multi)
-                    for (int s = 0; s < S.src_cnt; ++s) {
-                        const SrcPos p = A.src[S.src_beg + s];
+                    for (int s = 0; s < src_cnt; ++s) {
+                        const SrcPos p = A.src[src_beg + s];
                         if (p.x == x && p.z == z && z != src.z) extra += p.w;
                     }
                 wv += extra * famp;
             }
-        } else if (rid >= 0) {
-            // c-weighted injection of the residual at receivers recorded at this step
-            wv += A.rho[S.d_off + (int64_t)A.rec_j * S.nrec + rid];
+        } else if (evrow) {
+            // c-weighted injection of the residual at this row's receivers
+            const int rid = evvec[ev_off + lane];
+            if (rid >= 0) wv += Rho[rid];
         }
-        if (xin) {
-            const int64_t o = rowoff + x;
-            const float c = Cf[o];
-            const float up = Up[o];
-            const float un = a * q[4] - b * up + c * wv;
-            Un[o] = un;
-            if (!ADJ) {
-                if (A.wst) __builtin_nontemporal_store(wv, A.wst + S.u_off + o);
-                if (A.cka) {
-                    A.cka[S.u_off + o] = un;
-                    A.ckb[S.u_off + o] = q[4];
-                }
-                if (rid >= 0 && A.dat) A.dat[S.d_off + (int64_t)A.rec_j * S.nrec + rid] = un;
-            } else {
-                const float wi = __builtin_nontemporal_load(A.wimg + S.u_off + o);
-                A.gacc[S.u_off + o] += (double)un * (double)wi;
+        // lanes past the x edge store to an out-of-range offset (dropped); the select is
+        // on the whole offset so that the row term cannot wrap it back into range
+        const uint32_t o = xin ? roff(z) + xo : kOOB;
+        const float un = a * q[4] - b * pq[0] + cq[0] * wv;
+        bstore(rN, o, un);
+        if (!ADJ) {
+            bstore(rW, o, wv);
+            bstore(rKa, o, un);
+            bstore(rKb, o, q[4]);
+            if (evrow && Dat) {
+                const int rid = evvec[ev_off + lane];
+                if (rid >= 0) Dat[rid] = un;
+            }
+        } else {
+            bstore64(rG, xin ? 2 * o : kOOB, gq[0] + (double)un * (double)wq[0]);
+        }
+        if (evrow) {
+            ++ev;
+            ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+            ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
+        }
+        // ---- shift the queues
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = q[k + 1];
+#pragma unroll
+        for (int k = 0; k < PF - 1; ++k) hq[k] = hq[k + 1];
+        hq[PF - 1] = hn;
+#pragma unroll
+        for (int k = 0; k < PF - 1; ++k) {
+            cq[k] = cq[k + 1];
+            pq[k] = pq[k + 1];
+            if (ADJ) {
+                wq[k] = wq[k + 1];
+                gq[k] = gq[k + 1];
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
+        cq[PF - 1] = cn;
+        pq[PF - 1] = pn;
+        if (ADJ) {
+            wq[PF - 1] = wn;
+            gq[PF - 1] = gn;
+        }
     }
 }
 
@@ -696,12 +809,13 @@ hipError_t launch_prep(const SampleDesc *smp, int nsample, int64_t max_cell, con
 template <bool ADJ>
 static hipError_t step2d_dispatch(const StepArgs &a, int bz, hipStream_t st)
 {
+    // per_xcd counts workgroups of 4 tiles here
     dim3 grid(8 * a.per_xcd);
     switch (bz) {
-    case 8: k_step2d<8, ADJ><<<grid, 64, 0, st>>>(a); break;
-    case 16: k_step2d<16, ADJ><<<grid, 64, 0, st>>>(a); break;
-    case 32: k_step2d<32, ADJ><<<grid, 64, 0, st>>>(a); break;
-    case 64: k_step2d<64, ADJ><<<grid, 64, 0, st>>>(a); break;
+    case 8: k_step2d<8, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 16: k_step2d<16, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 32: k_step2d<32, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 64: k_step2d<64, ADJ><<<grid, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

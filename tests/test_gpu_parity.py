@@ -205,7 +205,7 @@ def test_3d_parity(F, ckpt):
     g = F.Grid(nz=18, ny=21, nx=70, dz=20.0, dy=22.0, dx=25.0, nb=5, v_ref=3500.0, v_max=3600.0, ndim=3)
     cfg = W.C5
     m = f32(W.layered_salt_3d(18, 21, 70, seed=4, vmin=1500, vmax=3500).ravel())
-    truth = f32(W.layered_salt_3d(18, 21, 70, seed=9, vmin=1500, vmax=3500).ravel())
+    truth = f32(m * 0.9)  # 10 % slower: traveltimes move by many samples (residual ratio ~1)
     nt, R = 150, 2
 
     def cell(z, y, x):
@@ -218,7 +218,9 @@ def test_3d_parity(F, ckpt):
     wav = W.ricker(6.0, 2e-3, nt)
     batch = F.Batch([g], [0, 0], srcs, [rec, rec], wav)
     time = F.time_axis(2e-3, nt, R, ckpt)
-    dobs = [f32(d) for d in oracle_forward_sims(batch, 2e-3, nt, R, [truth], coef_fp32=False)]
+    # half-amplitude observed data keeps the residual ratio near 1 (well-conditioned
+    # d - d_obs) despite the short record being dominated by direct arrivals
+    dobs = [f32(0.5 * d) for d in oracle_forward_sims(batch, 2e-3, nt, R, [truth], coef_fp32=False)]
     dp, mis, gr, gn = run_gradient(F, batch, time, [m], np.concatenate([d.ravel() for d in dobs]), 1.0, [1.0])
     odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, [m], dobs, 1.0, [1.0])
     gdp = split_data(dp, batch, nt // R)
