@@ -44,11 +44,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, grid, wav, nt_sample, R, vstart):
+def cpu_baseline(batch, grid, wav, nt_sample, R, vstart, cfg):
     """Time the oracle (as it stands) on one sample's supergathers for nt_sample steps."""
     import oracle
     sims = [s for s in range(batch.nsim) if batch.sample_of[s] == 0]
-    og = oracle.Grid(nz=grid.nz, nx=grid.nx, dz=grid.dz, dx=grid.dx, nb=grid.nb, v_ref=grid.v_ref)
+    og = oracle.Grid(nz=grid.nz, nx=grid.nx, dz=grid.dz, dx=grid.dx, nb=grid.nb, v_ref=grid.v_ref, ny=grid.ny,
+                     dy=grid.dy, ndim=grid.ndim)
     sp = np.zeros(len(sims) + 1, dtype=np.int32)
     rp = np.zeros(len(sims) + 1, dtype=np.int32)
     sc, sw, rc = [], [], []
@@ -63,7 +64,7 @@ def cpu_baseline(batch, grid, wav, nt_sample, R, vstart):
     dobs = [r.standard_normal((nt_sample // R, rp[i + 1] - rp[i])) for i in range(len(sims))]
     threads = min(len(sims), int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
     t0 = time.perf_counter()
-    oracle.gradient_batch([og] * len(sims), [vstart.ravel()] * len(sims), 1e-3, nt_sample, R, sp,
+    oracle.gradient_batch([og] * len(sims), [vstart.ravel()] * len(sims), cfg.dt, nt_sample, R, sp,
                           np.array(sc, dtype=np.int32), np.array(sw, dtype=np.float64), wav[:nt_sample].astype(np.float64),
                           rp, np.array(rc, dtype=np.int32), dobs, 1.0)
     dt = time.perf_counter() - t0
@@ -71,7 +72,7 @@ def cpu_baseline(batch, grid, wav, nt_sample, R, vstart):
     return {"value": cells / dt / 1e9, "unit": "Gcell-steps/s", "cores": threads, "kind": "oracle",
             "sample": "FP64 oracle gradient (forward + misfit + adjoint + imaging) of one posterior sample's "
                       "%d supergathers over the first %d of the %d internal steps, OpenMP over supergathers; "
-                      "%.1f s wall" % (len(sims), nt_sample, 4000, dt)}
+                      "%.1f s wall" % (len(sims), nt_sample, cfg.nt, dt)}
 
 
 def main():
@@ -83,7 +84,9 @@ def main():
     ap.add_argument("--ckpt", default="auto", help="auto | 0 (keep all imaging operands) | K (checkpoint)")
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4000)
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d"],
+                    help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
@@ -95,14 +98,18 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    cfg = W.C2
+    cfg = W.C2 if args.workload == "2d" else W.C5
     nt = args.nt or cfg.nt
     R = cfg.rec_every
     nt_rec = nt // R
     grid = problems.grid_of(cfg)
     wav = W.ricker(cfg.freq, cfg.dt, nt)
-    vtrue = W.thrust_2d(cfg.nz, cfg.nx, seed=args.seed)
-    vstart = np.clip(W.smooth(vtrue, 16.0), cfg.vmin, cfg.vmax)
+    if cfg.ndim == 2:
+        vtrue = W.thrust_2d(cfg.nz, cfg.nx, seed=args.seed)
+        vstart = np.clip(W.smooth(vtrue, 16.0), cfg.vmin, cfg.vmax)
+    else:
+        vtrue = W.layered_salt_3d(cfg.nz, cfg.ny, cfg.nx, seed=args.seed, vmin=cfg.vmin, vmax=cfg.vmax)
+        vstart = np.clip(W.smooth(vtrue, 8.0), cfg.vmin, cfg.vmax)
     shots = problems.shot_cells(cfg, grid)
 
     # ---- observed data: forward of the true model, one simulation per shot (setup)
@@ -132,8 +139,12 @@ def main():
 
     free, total = torch.cuda.mem_get_info()
     if args.ckpt == "auto":
-        need = fwi.fwi_workspace_size(batch0, fwi.time_axis(cfg.dt, nt, R, 0))
-        ckpt = 0 if need < free - (8 << 30) else 10
+        ckpt = 0
+        for k in (0, 10, 15, 20, 30, 50, 100):
+            need = fwi.fwi_workspace_size(batch0, fwi.time_axis(cfg.dt, nt, R, k))
+            if need < free - (8 << 30):
+                ckpt = k
+                break
     else:
         ckpt = int(args.ckpt)
     time_ax = fwi.time_axis(cfg.dt, nt, R, ckpt)
@@ -178,9 +189,10 @@ def main():
     fwi.fwi_poll_status(ws)
     elapsed = t1 - t0
 
-    phys_cells = nsim * cfg.nz * cfg.nx
-    pad_cells = nsim * (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
-    samp_cells = cfg.nsample * (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    ny_pad = cfg.ny + 2 * cfg.nb if cfg.ndim == 3 else 1
+    phys_cells = nsim * cfg.nz * cfg.ny * cfg.nx
+    pad_cells = nsim * (cfg.nz + 2 * cfg.nb) * ny_pad * (cfg.nx + 2 * cfg.nb)
+    samp_cells = cfg.nsample * (cfg.nz + 2 * cfg.nb) * ny_pad * (cfg.nx + 2 * cfg.nb)
     cell_steps = phys_cells * nt * args.steps
     value = cell_steps / elapsed / 1e9
     log("step %.1f ms; %.1f Gcell-steps/s physical, %.1f padded; fwd kernel %.1f us x %d, adj kernel %.1f us x %d" % (
@@ -193,16 +205,19 @@ def main():
     # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
     # 16 B per simulation cell (12 B when recomputing from checkpoints without a store),
     # plus c once per sample cell.
-    fwd_bytes = pad_cells * 16 + samp_cells * 4
+    # with checkpoints the forward sweeps (first pass: 12 B; recomputation: 16 B) average
+    # to 14 B per simulation cell
+    fwd_bytes = pad_cells * (16 if ckpt == 0 else 14) + samp_cells * 4
     adj_bytes = pad_cells * 32 + samp_cells * 4
+    kname = "k_step2d" if cfg.ndim == 2 else "k_step3d"
     if adj_ms >= fwd_ms:
-        name, nbytes, ms, n = "adjoint+imaging step (k_step2d<bz,true>)", adj_bytes, adj_ms, adj_n
+        name, nbytes, ms, n = "adjoint+imaging step (%s<bz,true>)" % kname, adj_bytes, adj_ms, adj_n
     else:
-        name, nbytes, ms, n = "forward step (k_step2d<bz,false>)", fwd_bytes, fwd_ms, fwd_n
+        name, nbytes, ms, n = "forward step (%s<bz,false>)" % kname, fwd_bytes, fwd_ms, fwd_n
     avg_s = ms / max(n, 1) / 1e3
     achieved = nbytes / avg_s / 1e9
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
@@ -238,9 +253,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2d-400x150-thrust-80shot-s8: 16 samples x 10 supergathers (+-1), "
-                               "%d steps of 1 ms, gradient + Langevin" % nt,
-                   "grid": [cfg.nz, cfg.nx], "padded": [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
+        "config": {"workload": ("2d-400x150-thrust-80shot-s8: 16 samples x 10 supergathers (+-1), "
+                                "%d steps of 1 ms, gradient + Langevin" % nt) if cfg.ndim == 2 else
+                               ("3d-200x200x100-salt-64shot-s16: 8 samples x 4 supergathers (+-1), "
+                                "%d steps of 2 ms, gradient + Langevin" % nt),
+                   "grid": [cfg.nz, cfg.ny, cfg.nx] if cfg.ndim == 3 else [cfg.nz, cfg.nx],
+                   "padded": [cfg.nz + 2 * cfg.nb, ny_pad, cfg.nx + 2 * cfg.nb] if cfg.ndim == 3 else
+                             [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
                    "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
                    "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
                    "padded_gcell_steps_per_s": round(pad_cells * nt * args.steps / elapsed / 1e9, 3),
@@ -252,7 +271,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline(batch0, grid, wav, min(args.cpu_steps, nt), R, vstart)
+        # the oracle keeps every wavefield of a simulation in host memory: the 3D sample is a
+        # short window of steps (5.8 M cells x 8 B per step and simulation)
+        cpu_nt = args.cpu_steps or (nt if cfg.ndim == 2 else 60)
+        res["cpu_baseline"] = cpu_baseline(batch0, grid, wav, min(cpu_nt, nt), R, vstart, cfg)
     print(json.dumps(res), flush=True)
 
 

@@ -210,8 +210,7 @@ void pick_tiles(Plan &p, const fwi_batch *b)
         p.ty = 1;
         if (p.bz != 8 && p.bz != 16 && p.bz != 32 && p.bz != 64) p.bz = bz;
     } else {
-        int ty = env_int("FWI_TILE_TY", 8);
-        if (ty != 8 && ty != 16) ty = 8;
+        const int ty = 8;  // the 3D kernel's tile is 64 x 8 cells per plane
         int bz = 16;
         for (int c : {64, 32, 16})
             if (count(c, ty) >= 1024) {

@@ -377,33 +377,51 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
 
 // ------------------------------------------------------------ 3D stepping
 
-// Block: 64 x 4 threads; tile 64 x TY cells in (x, y); each thread owns RPT = TY/4 rows
-// y = y0 + ty + 4 r.  The plane buffer holds the tile plus a 4-cell halo in x and y.
-template <int TY>
-struct Plane {
-    float v[TY + 2 * kHalo][kTileX + 2 * kHalo];
+// 3D step.  Block: 64 x 4 threads; tile 64 x 8 cells in (x, y); each thread owns the two
+// rows y = y0 + ty and y0 + ty + 4 and streams the tile along z.  The xy plane (tile plus
+// a 4-cell halo in x and y) goes through a double-buffered LDS plane with one barrier
+// per plane; the z-derivative comes from a register queue that runs 8 planes ahead, and
+// the halo and point operands are fetched 4 planes ahead with unconditional buffer loads.
+constexpr int kTY3 = 8;
+struct Plane3 {
+    float v[2][kTY3 + 2 * kHalo][kTileX + 2 * kHalo];
 };
 
-template <int BZ, int TY, bool ADJ>
+template <int BZ, bool ADJ>
 __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
 {
-    constexpr int RPT = TY / 4;
+    constexpr int RPT = kTY3 / 4;
+    constexpr int PF = 4;
     const int t = xcd_tile(blockIdx.x, A.per_xcd);
-    if (t >= A.ntiles) return;
+    if (t >= A.ntiles) return;  // uniform per block
     const Tile T = A.tiles[t];
     const SimDesc &S = A.sims[T.sim];
     const int Nx = S.N[2], Ny = S.N[1], Nz = S.N[0];
-    const int64_t plane = (int64_t)Nx * Ny;
+    const int nz_phys = S.n[0], ny_phys = S.n[1], nx_phys = S.n[2], nb = S.nb;
+    const double gmz = S.gmax[0], gmy = S.gmax[1], gmx = S.gmax[2];
+    const int64_t u_off = S.u_off, d_off = S.d_off;
+    const int nrec = S.nrec, src_beg = S.src_beg, src_cnt = S.src_cnt;
+    const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
+    const uint32_t fbytes = pbytes * (uint32_t)Nz;
     const int lane = threadIdx.x & 63;
     const int ty = threadIdx.x >> 6;
     const int x = T.x0 + lane;
     const int z0 = T.z0;
     const int z1 = min(z0 + BZ, Nz);
-    const float *__restrict__ U = A.cur + S.u_off;
-    const float *Up = A.prev + S.u_off;
-    float *Un = A.next + S.u_off;
-    const float *__restrict__ Cf = A.cf + S.c_off;
-    __shared__ Plane<TY> P;
+    const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
+    const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
+    const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
+    const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
+    const rsrc_t rW = make_rsrc(ADJ ? A.wimg + u_off : (A.wst ? A.wst + u_off : A.next), ADJ || A.wst ? fbytes : 0);
+    const rsrc_t rG = make_rsrc(ADJ ? (const void *)(A.gacc + u_off) : (const void *)A.next, ADJ ? 2 * fbytes : 0);
+    const rsrc_t rKa = make_rsrc(A.cka ? A.cka + u_off : A.next, A.cka ? fbytes : 0);
+    const rsrc_t rKb = make_rsrc(A.ckb ? A.ckb + u_off : A.next, A.ckb ? fbytes : 0);
+    const int rec_j = A.rec_j;
+    float *Dat = (!ADJ && A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
+    const float *Rho = (ADJ && rec_j >= 0) ? A.rho + d_off + (int64_t)rec_j * nrec : nullptr;
+    const EvRow *__restrict__ evrows = A.evrows;
+    const int32_t *__restrict__ evvec = A.evvec;
+    __shared__ Plane3 P;
 
     float wz[5], wy[5], wx[5];
 #pragma unroll
@@ -413,21 +431,41 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
         wx[k] = S.w[2][k];
     }
     const double dt = S.dt;
-    const double gx = sponge_axis(x, S.n[2], S.nb, S.gmax[2]);
+    const double gx = sponge_axis(x, nx_phys, nb, gmx);
 
+    auto poff = [&](int zz) -> uint32_t { return (uint32_t)zz * pbytes; };  // zz < 0 wraps out of range
     int yr[RPT];
     bool in[RPT];
     double gy[RPT];
-    int64_t col[RPT];
+    uint32_t col[RPT];  // byte offset of (y, x) within a plane (clamped for lanes outside)
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         yr[r] = T.y0 + ty + 4 * r;
         in[r] = x < Nx && yr[r] < Ny;
-        gy[r] = sponge_axis(yr[r], S.n[1], S.nb, S.gmax[1]);
-        col[r] = (int64_t)yr[r] * Nx + x;
+        gy[r] = sponge_axis(yr[r], ny_phys, nb, gmy);
+        col[r] = 4u * ((uint32_t)min(yr[r], Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
     }
+    auto coff = [&](int r, int zz) -> uint32_t { return in[r] ? poff(zz) + col[r] : kOOB; };
 
-    // sources
+    // y-halo rows: LDS rows ty (y0-4+ty) and TY+4+ty (y0+TY+ty); x-halo: 8 columns x TY
+    // rows by the first TY*8 threads
+    const int hy0 = T.y0 - kHalo + ty, hy1 = T.y0 + kTY3 + ty;
+    const bool hyl0 = x < Nx && hy0 >= 0, hyl1 = x < Nx && hy1 < Ny;
+    const uint32_t hyo0 = 4u * ((uint32_t)max(hy0, 0) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
+    const uint32_t hyo1 = 4u * ((uint32_t)min(hy1, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
+    const int xh_t = threadIdx.x;
+    const bool xh_on = xh_t < kTY3 * 8;
+    const int xh_row = (xh_t >> 3) & (kTY3 - 1), xh_c = xh_t & 7;
+    const int xh_col = xh_c < 4 ? xh_c : kTileX + xh_c;  // LDS column
+    const int xh_x = T.x0 - kHalo + xh_col;
+    const int xh_y = T.y0 + xh_row;
+    const bool xhl = xh_on && xh_x >= 0 && xh_x < Nx && xh_y < Ny;
+    const uint32_t xho = 4u * ((uint32_t)min(xh_y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(xh_x, 0), Nx - 1));
+    auto h0off = [&](int zz) -> uint32_t { return hyl0 ? poff(zz) + hyo0 : kOOB; };
+    auto h1off = [&](int zz) -> uint32_t { return hyl1 ? poff(zz) + hyo1 : kOOB; };
+    auto hxoff = [&](int zz) -> uint32_t { return xhl ? poff(zz) + xho : kOOB; };
+
+    // sources in this thread's columns
     int sz[RPT];
     float sw[RPT];
     bool smulti = false;
@@ -439,8 +477,8 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
     }
     if (!ADJ) {
         famp = A.fn * S.inv_vol;
-        for (int s = 0; s < S.src_cnt; ++s) {
-            const SrcPos p = A.src[S.src_beg + s];
+        for (int s = 0; s < src_cnt; ++s) {
+            const SrcPos p = A.src[src_beg + s];
             if (p.x != x || p.z < z0 || p.z >= z1) continue;
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
@@ -456,70 +494,88 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
     }
     const bool multi = __syncthreads_or(smulti);
 
-    float q[RPT][9];
+    float q[RPT][13], cq[RPT][PF], pq[RPT][PF], wq[RPT][PF];
+    double gq[RPT][PF];
+    float h0q[PF], h1q[PF], hxq[PF];
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            int zz = z0 - kHalo + k;
-            q[r][k] = (in[r] && zz >= 0 && zz < Nz) ? U[(int64_t)zz * plane + col[r]] : 0.0f;
-        }
-
-    // y-halo: LDS rows 0..3 (y0-4..y0-1) and TY+4..TY+7 (y0+TY..y0+TY+3); thread (ty, lane)
-    // loads row ty and row TY+4+ty.  x-halo: 8 columns x TY rows by the first TY*8 threads.
-    const int hy0 = T.y0 - kHalo + ty, hy1 = T.y0 + TY + ty;
-    const bool hyl0 = x < Nx && hy0 >= 0, hyl1 = x < Nx && hy1 < Ny;
-    const int xh_t = threadIdx.x;                 // < TY * 8 participates
-    const int xh_row = xh_t >> 3, xh_c = xh_t & 7;
-    const int xh_col = xh_c < 4 ? xh_c : kTileX + xh_c;       // LDS column
-    const int xh_x = T.x0 - kHalo + xh_col;                   // global x
-    const int xh_y = T.y0 + xh_row;
-    const bool xhl = xh_t < TY * 8 && xh_x >= 0 && xh_x < Nx && xh_y < Ny;
-
-    int ev = T.ev_beg;
-    const int ev_end = T.ev_beg + T.ev_cnt;
-    const bool rec = A.rec_j >= 0;
-
-    for (int z = z0; z < z1; ++z) {
-        const int64_t zoff = (int64_t)z * plane;
+        for (int k = 0; k < 12; ++k) q[r][k] = bload(rU, coff(r, z0 - kHalo + k));
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int zz = z0 + k;
+        h0q[k] = bload(rU, h0off(zz));
+        h1q[k] = bload(rU, h1off(zz));
+        hxq[k] = bload(rU, hxoff(zz));
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            int zz = z + kHalo;
-            q[r][8] = (in[r] && zz < Nz) ? U[zoff + (int64_t)kHalo * plane + col[r]] : 0.0f;
-            P.v[ty + 4 * r + kHalo][lane + kHalo] = q[r][4];
+            const uint32_t o = poff(zz) + col[r];
+            cq[r][k] = bload(rC, o);
+            pq[r][k] = bload(rP, o);
+            if (ADJ) {
+                wq[r][k] = bload(rW, o);
+                gq[r][k] = bload64(rG, 2 * o);
+            }
         }
-        P.v[ty][lane + kHalo] = hyl0 ? U[zoff + (int64_t)hy0 * Nx + x] : 0.0f;
-        P.v[TY + kHalo + ty][lane + kHalo] = hyl1 ? U[zoff + (int64_t)hy1 * Nx + x] : 0.0f;
-        if (xh_t < TY * 8) P.v[xh_row + kHalo][xh_col] = xhl ? U[zoff + (int64_t)xh_y * Nx + xh_x] : 0.0f;
-        __syncthreads();
+    }
+    const bool rec = rec_j >= 0 && T.ev_cnt > 0;
+    int ev = T.ev_beg;
+    const int ev_end = T.ev_beg + T.ev_cnt;
+    int ev_z = rec ? evrows[ev].z : -1;
+    int ev_off = rec ? evrows[ev].vec_off : 0;
 
-        const double gz = sponge_axis(z, S.n[0], S.nb, S.gmax[0]);
-        // receiver event row of this plane (uniform)
-        int evoff = -1;
-        if (rec) {
-            while (ev < ev_end && A.evrows[ev].z < z) ++ev;
-            if (ev < ev_end && A.evrows[ev].z == z) evoff = A.evrows[ev].vec_off;
+    int par = 0;
+    for (int z = z0; z < z1; ++z) {
+        // ---- prefetch: centre plane z+8, halos and point operands of plane z+4
+        float cn[RPT], pn[RPT], wn[RPT];
+        double gn[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) q[r][12] = bload(rU, coff(r, z + 8));
+        const float h0n = bload(rU, h0off(z + PF));
+        const float h1n = bload(rU, h1off(z + PF));
+        const float hxn = bload(rU, hxoff(z + PF));
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const uint32_t o = poff(z + PF) + col[r];
+            cn[r] = bload(rC, o);
+            pn[r] = bload(rP, o);
+            if (ADJ) {
+                wn[r] = bload(rW, o);
+                gn[r] = bload64(rG, 2 * o);
+            }
         }
+        // ---- plane z into LDS
+        float(*V)[kTileX + 2 * kHalo] = P.v[par];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) V[ty + 4 * r + kHalo][lane + kHalo] = q[r][4];
+        V[ty][lane + kHalo] = h0q[0];
+        V[kTY3 + kHalo + ty][lane + kHalo] = h1q[0];
+        if (xh_on) V[xh_row + kHalo][xh_col] = hxq[0];
+        __syncthreads();
+        par ^= 1;
+
+        const double gz = sponge_axis(z, nz_phys, nb, gmz);
+        const bool evrow = z == ev_z;  // uniform
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int ly = ty + 4 * r + kHalo;
             const int lx = lane + kHalo;
             float sx = wx[0] * q[r][4];
-            sx += wx[1] * (P.v[ly][lx - 1] + P.v[ly][lx + 1]);
-            sx += wx[2] * (P.v[ly][lx - 2] + P.v[ly][lx + 2]);
-            sx += wx[3] * (P.v[ly][lx - 3] + P.v[ly][lx + 3]);
-            sx += wx[4] * (P.v[ly][lx - 4] + P.v[ly][lx + 4]);
+            sx += wx[1] * (V[ly][lx - 1] + V[ly][lx + 1]);
+            sx += wx[2] * (V[ly][lx - 2] + V[ly][lx + 2]);
+            sx += wx[3] * (V[ly][lx - 3] + V[ly][lx + 3]);
+            sx += wx[4] * (V[ly][lx - 4] + V[ly][lx + 4]);
             float sy = wy[0] * q[r][4];
-            sy += wy[1] * (P.v[ly - 1][lx] + P.v[ly + 1][lx]);
-            sy += wy[2] * (P.v[ly - 2][lx] + P.v[ly + 2][lx]);
-            sy += wy[3] * (P.v[ly - 3][lx] + P.v[ly + 3][lx]);
-            sy += wy[4] * (P.v[ly - 4][lx] + P.v[ly + 4][lx]);
-            float sz_ = wz[0] * q[r][4];
-            sz_ += wz[1] * (q[r][3] + q[r][5]);
-            sz_ += wz[2] * (q[r][2] + q[r][6]);
-            sz_ += wz[3] * (q[r][1] + q[r][7]);
-            sz_ += wz[4] * (q[r][0] + q[r][8]);
-            float wv = sz_ + sy + sx;
+            sy += wy[1] * (V[ly - 1][lx] + V[ly + 1][lx]);
+            sy += wy[2] * (V[ly - 2][lx] + V[ly + 2][lx]);
+            sy += wy[3] * (V[ly - 3][lx] + V[ly + 3][lx]);
+            sy += wy[4] * (V[ly - 4][lx] + V[ly + 4][lx]);
+            float szz = wz[0] * q[r][4];
+            szz += wz[1] * (q[r][3] + q[r][5]);
+            szz += wz[2] * (q[r][2] + q[r][6]);
+            szz += wz[3] * (q[r][1] + q[r][7]);
+            szz += wz[4] * (q[r][0] + q[r][8]);
+            float wv = szz + sy + sx;
             float a, b;
             {
                 double gam = 0.0;
@@ -528,45 +584,71 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
                 gam = gam + gx;
                 sponge_ab(gam, dt, a, b);
             }
-            const int rid = evoff >= 0 ? A.evvec[evoff + (ty + 4 * r) * kTileX + lane] : -1;
             if (!ADJ) {
                 if (z == sz[r]) wv += sw[r] * famp;
                 if (multi) {
                     float extra = 0.0f;
                     if (in[r])
-                        for (int s = 0; s < S.src_cnt; ++s) {
-                            const SrcPos p = A.src[S.src_beg + s];
+                        for (int s = 0; s < src_cnt; ++s) {
+                            const SrcPos p = A.src[src_beg + s];
                             if (p.x == x && p.y == yr[r] && p.z == z && z != sz[r]) extra += p.w;
                         }
                     wv += extra * famp;
                 }
-            } else if (rid >= 0) {
-                wv += A.rho[S.d_off + (int64_t)A.rec_j * S.nrec + rid];
+            } else if (evrow) {
+                const int rid = evvec[ev_off + (ty + 4 * r) * kTileX + lane];
+                if (rid >= 0) wv += Rho[rid];
             }
-            if (in[r]) {
-                const int64_t o = zoff + col[r];
-                const float c = Cf[o];
-                const float up = Up[o];
-                const float un = a * q[r][4] - b * up + c * wv;
-                Un[o] = un;
-                if (!ADJ) {
-                    if (A.wst) __builtin_nontemporal_store(wv, A.wst + S.u_off + o);
-                    if (A.cka) {
-                        A.cka[S.u_off + o] = un;
-                        A.ckb[S.u_off + o] = q[r][4];
-                    }
-                    if (rid >= 0 && A.dat) A.dat[S.d_off + (int64_t)A.rec_j * S.nrec + rid] = un;
-                } else {
-                    const float wi = __builtin_nontemporal_load(A.wimg + S.u_off + o);
-                    A.gacc[S.u_off + o] += (double)un * (double)wi;
+            const uint32_t o = in[r] ? poff(z) + col[r] : kOOB;
+            const float un = a * q[r][4] - b * pq[r][0] + cq[r][0] * wv;
+            bstore(rN, o, un);
+            if (!ADJ) {
+                bstore(rW, o, wv);
+                bstore(rKa, o, un);
+                bstore(rKb, o, q[r][4]);
+                if (evrow && Dat) {
+                    const int rid = evvec[ev_off + (ty + 4 * r) * kTileX + lane];
+                    if (rid >= 0) Dat[rid] = un;
                 }
+            } else {
+                bstore64(rG, in[r] ? 2 * o : kOOB, gq[r][0] + (double)un * (double)wq[r][0]);
             }
         }
-        __syncthreads();
+        if (evrow) {
+            ++ev;
+            ev_z = ev < ev_end ? evrows[ev].z : -1;
+            ev_off = ev < ev_end ? evrows[ev].vec_off : 0;
+        }
+        // ---- shift the queues
 #pragma unroll
-        for (int r = 0; r < RPT; ++r)
+        for (int r = 0; r < RPT; ++r) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) q[r][k] = q[r][k + 1];
+            for (int k = 0; k < 12; ++k) q[r][k] = q[r][k + 1];
+#pragma unroll
+            for (int k = 0; k < PF - 1; ++k) {
+                cq[r][k] = cq[r][k + 1];
+                pq[r][k] = pq[r][k + 1];
+                if (ADJ) {
+                    wq[r][k] = wq[r][k + 1];
+                    gq[r][k] = gq[r][k + 1];
+                }
+            }
+            cq[r][PF - 1] = cn[r];
+            pq[r][PF - 1] = pn[r];
+            if (ADJ) {
+                wq[r][PF - 1] = wn[r];
+                gq[r][PF - 1] = gn[r];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PF - 1; ++k) {
+            h0q[k] = h0q[k + 1];
+            h1q[k] = h1q[k + 1];
+            hxq[k] = hxq[k + 1];
+        }
+        h0q[PF - 1] = h0n;
+        h1q[PF - 1] = h1n;
+        hxq[PF - 1] = hxn;
     }
 }
 
@@ -825,22 +907,12 @@ template <bool ADJ>
 static hipError_t step3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
 {
     dim3 grid(8 * a.per_xcd);
-    if (ty == 8) {
-        switch (bz) {
-        case 16: k_step3d<16, 8, ADJ><<<grid, 256, 0, st>>>(a); break;
-        case 32: k_step3d<32, 8, ADJ><<<grid, 256, 0, st>>>(a); break;
-        case 64: k_step3d<64, 8, ADJ><<<grid, 256, 0, st>>>(a); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else if (ty == 16) {
-        switch (bz) {
-        case 16: k_step3d<16, 16, ADJ><<<grid, 256, 0, st>>>(a); break;
-        case 32: k_step3d<32, 16, ADJ><<<grid, 256, 0, st>>>(a); break;
-        case 64: k_step3d<64, 16, ADJ><<<grid, 256, 0, st>>>(a); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        return hipErrorInvalidValue;
+    if (ty != kTY3) return hipErrorInvalidValue;
+    switch (bz) {
+    case 16: k_step3d<16, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 32: k_step3d<32, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 64: k_step3d<64, ADJ><<<grid, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
