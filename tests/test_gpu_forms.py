@@ -1,0 +1,177 @@
+"""GPU tests of the autograd form and of full-size sampled parity.
+
+* autograd (torch.autograd.Function over fwi_forward / fwi_adjoint) on an uneven batch
+  of three grid sizes with checkpoints every 10 steps: gradient vs the FP64 oracle and
+  vs central differences of the loss;
+* full-size sampled parity on the uneven 32-sample configuration (2000 steps, K = 10)
+  and on the 400x150 / 160-simulation configuration the benchmark times, comparing the
+  outputs of one sample (all of its simulations) with the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import workloads as W
+from helpers import f32, ogrid, oracle_batch_gradient, oracle_forward_sims, rel, split_data, split_model
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12797_amd import fwi
+    fwi.lib()
+    return fwi
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def uneven_problem(F, sizes, nsample, nt, ckpt, h=10.0, nb=8, seed=0, s=2):
+    """Salt models on grids of several sizes, samples round-robin over sizes, one
+    supergather of s shots per sample (G = 1)."""
+    from paper_2512_12797_amd import problems
+    cfg = W.C3
+    grids = [F.Grid(nz=sizes[k % len(sizes)][0], nx=sizes[k % len(sizes)][1], dz=h, dx=h, nb=nb,
+                    v_ref=cfg.vmax, v_max=cfg.vmax * 1.1) for k in range(nsample)]
+    wav = W.ricker(cfg.freq, cfg.dt, nt)
+    batch, groups = problems.encoded_batch(cfg, grids, wav, seed=seed, step=0, s=s, G=1,
+                                           nshot_of=lambda g: max(s, g.nx // 16))
+    models = [f32(W.salt_2d(g.nz, g.nx, seed=seed + k).ravel()) for k, g in enumerate(grids)]
+    start = [f32(W.smooth(m.reshape(g.nz, g.nx), 3.0).ravel()) for m, g in zip(models, grids)]
+    time = F.time_axis(cfg.dt, nt, 1, ckpt)
+    return batch, groups, time, models, start
+
+
+def test_autograd_uneven_vs_oracle_and_fd(F):
+    from paper_2512_12797_amd.autograd import FwiOperator
+    sizes = [(24, 40), (30, 64), (30, 100)]
+    batch, groups, time, truth, start = uneven_problem(F, sizes, 6, 300, 10)
+    say("case autograd uneven 3 sizes, ckpt 10")
+    dobs = [f32(d) for d in oracle_forward_sims(batch, time.dt, time.nt, 1, [m for m in truth], coef_fp32=False)]
+    dobs_t = dev(np.concatenate([d.ravel() for d in dobs]))
+    op = FwiOperator(batch, time)
+    v = dev(np.concatenate(start)).requires_grad_(True)
+    d = op(v)
+    loss = 0.5 * ((d - dobs_t).double() ** 2).sum()
+    loss.backward()
+    g = v.grad.double().cpu().numpy()
+    _, omis, ogr = oracle_batch_gradient(batch, time.dt, time.nt, 1, start, dobs, 1.0, [1.0] * batch.nsample)
+    gg = split_model(g, batch)
+    for k in range(batch.nsample):
+        e = rel(gg[k], ogr[k])
+        say("  sample %d (%dx%d) autograd gradient rel %.2e" % (k, batch.grids[k].nz, batch.grids[k].nx, e))
+        assert e < TOL
+    assert abs(loss.item() / omis.sum() - 1) < TOL
+    # central differences of the FP32 loss along a smooth direction
+    r = np.random.default_rng(3)
+    dv = dev(np.concatenate([W.smooth(r.standard_normal((gr.nz, gr.nx)), 2.0).ravel() * 30.0
+                             for gr in batch.grids]))
+    eps = 0.5
+
+    def L(x):
+        with torch.no_grad():
+            return float(0.5 * ((op(x) - dobs_t).double() ** 2).sum())
+
+    fd = (L(v.detach() + eps * dv) - L(v.detach() - eps * dv)) / (2 * eps)
+    an = float((v.grad.double() * dv.double()).sum())
+    say("  FD %.6e  autograd %.6e  rel %.2e" % (fd, an, abs(fd - an) / abs(an)))
+    assert abs(fd - an) <= 2e-3 * abs(an)
+
+
+def test_uneven_full_size_sampled(F):
+    # the uneven configuration at full size: 32 samples on 256x128, 512x200, 800x200
+    # (10 m, 20-cell sponge), 2000 steps, checkpoints every 10, one launch per step over
+    # all 32 simulations; sample 0 (the 256x128 grid) is recomputed by the oracle
+    from paper_2512_12797_amd.autograd import FwiOperator
+    sizes = list(W.C3_SIZES)
+    batch, groups, time, truth, start = uneven_problem(F, sizes, 32, 2000, 10, nb=20, s=8)
+    say("case uneven full size: %d sims, padded cells %d" % (batch.nsim, sum(
+        (g.nz + 40) * (g.nx + 40) for g in batch.grids)))
+    r = np.random.default_rng(9)
+    nt_rec = time.nt
+    # observed data: the oracle for sample 0's simulation, seeded noise elsewhere
+    d0 = oracle_forward_sims(_sub_batch(F, batch, [0]), time.dt, time.nt, 1, [truth[0]], coef_fp32=False)[0]
+    dobs = [f32(d0)] + [f32(1e-6 * r.standard_normal((nt_rec, batch.nrec[s]))) for s in range(1, batch.nsim)]
+    op = FwiOperator(batch, time)
+    v = dev(np.concatenate(start)).requires_grad_(True)
+    d = op(v)
+    loss = 0.5 * ((d - dev(np.concatenate([x.ravel() for x in dobs]))).double() ** 2).sum()
+    loss.backward()
+    g0 = split_model(v.grad.double().cpu().numpy(), batch)[0]
+    sb = _sub_batch(F, batch, [0])
+    odp, _, ogr = oracle_batch_gradient(sb, time.dt, time.nt, 1, [start[0]], [dobs[0]], 1.0, [1.0])
+    e_d = rel(split_data(d.detach().double().cpu().numpy(), batch, nt_rec)[0], odp[0])
+    e_g = rel(g0, ogr[0])
+    say("  sample 0: data rel %.2e, gradient rel %.2e" % (e_d, e_g))
+    assert e_d < TOL and e_g < TOL
+
+
+def _sub_batch(F, batch, sims):
+    """The simulations `sims` of a batch as their own batch (one sample each)."""
+    sources, receivers, grids = [], [], []
+    for s in sims:
+        a, b = batch.src_ptr[s], batch.src_ptr[s + 1]
+        sources.append((batch.src_cell[a:b], batch.src_w[a:b]))
+        receivers.append(batch.rec_cell[batch.rec_ptr[s]:batch.rec_ptr[s + 1]])
+        grids.append(batch.grids[batch.sample_of[s]])
+    return F.Batch(grids, list(range(len(sims))), sources, receivers, batch.wavelet)
+
+
+def test_bench_configuration_full_size_sampled(F):
+    # the benchmark's configuration and launch shape: 400x150, 160 simulations (16
+    # samples x 10 supergathers of 8), 4000 internal steps recorded every 2, keep-all
+    # schedule; sample 0's 10 supergathers are recomputed by the oracle
+    from paper_2512_12797_amd import problems
+    cfg = W.C2
+    grid = problems.grid_of(cfg)
+    wav = W.ricker(cfg.freq, cfg.dt, cfg.nt)
+    batch, groups = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, seed=1000, step=0)
+    vtrue = f32(W.thrust_2d(cfg.nz, cfg.nx, seed=1000).ravel())
+    vstart = f32(np.clip(W.smooth(vtrue.reshape(cfg.nz, cfg.nx), 16.0), cfg.vmin, cfg.vmax).ravel())
+    time = F.time_axis(cfg.dt, cfg.nt, cfg.rec_every, 0)
+    nt_rec = cfg.nt_rec
+    s0 = [s for s in range(batch.nsim) if batch.sample_of[s] == 0]
+    say("case bench configuration full size (oracle on %d simulations)" % len(s0))
+    sb = _sub_batch(F, batch, s0)
+    dobs0 = [f32(x) for x in oracle_forward_sims(sb, cfg.dt, cfg.nt, cfg.rec_every, [vtrue] * len(s0),
+                                                 coef_fp32=False)]
+    r = np.random.default_rng(1)
+    dobs = dobs0 + [f32(1e-3 * r.standard_normal((nt_rec, batch.nrec[s]))) for s in range(len(s0), batch.nsim)]
+    v = dev(np.tile(vstart, cfg.nsample))
+    dpred = torch.zeros(batch.data_size(nt_rec), device="cuda")
+    mis = torch.zeros(batch.nsim, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(batch.model_size, device="cuda")
+    ws = F.alloc_workspace(batch, time)
+    kappa = [g[2] for g in groups]
+    F.fwi_gradient(batch, time, v, dev(np.concatenate([x.ravel() for x in dobs])), 1.0, kappa, dpred, mis, grad,
+                   None, ws)
+    F.fwi_poll_status(ws)
+    del ws
+    torch.cuda.empty_cache()
+    odp, omis, ogr = oracle_batch_gradient(sb, cfg.dt, cfg.nt, cfg.rec_every, [vstart] * len(s0), dobs0, 1.0,
+                                           [kappa[0]] * len(s0))
+    gdp = split_data(dpred.double().cpu().numpy(), batch, nt_rec)
+    gm = mis.cpu().numpy()
+    for i, s in enumerate(s0):
+        e = rel(gdp[s], odp[i])
+        ratio = np.linalg.norm(odp[i] - dobs0[i]) / np.linalg.norm(dobs0[i])
+        say("  sim %d data rel %.2e residual ratio %.2f misfit rel %.2e" % (s, e, ratio, abs(gm[s] / omis[i] - 1)))
+        assert e < TOL and abs(gm[s] / omis[i] - 1) < TOL
+    g0 = grad.double().cpu().numpy()[:grid.nphys]
+    ref = sum(ogr)  # each oracle "sample" here is one simulation, already scaled by kappa
+    e = rel(g0, ref)
+    say("  sample 0 gradient rel %.2e" % e)
+    assert e < TOL
