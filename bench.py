@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--ckpt", default="auto", help="auto | 0 (keep all imaging operands) | K (checkpoint)")
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graphs", type=int, default=1, help="replay each gradient as a captured HIP graph")
+    ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
     ap.add_argument("--workload", default="2d", choices=["2d", "3d"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations")
@@ -152,6 +154,13 @@ def main():
     log("setup %.1f s; workspace %.1f GB (ckpt_every=%d); free %.1f of %.1f GB" % (
         time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, free / 1e9, total / 1e9))
 
+    tuned = None
+    if args.tune:
+        tuned = fwi.fwi_tune(batch0, time_ax, v, ws, os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+        log("tuner: tile height %d, %.3f ms per gradient time step" % tuned)
+    stream = torch.cuda.Stream()  # graphs need a non-default stream
+    torch.cuda.set_stream(stream)
+    fwi.fwi_graphs_enable(bool(args.graphs))
     eta = [1e-3]
     v_lo, v_hi = cfg.vmin * 0.9, cfg.vmax * 1.1
 
@@ -174,9 +183,12 @@ def main():
     fwi.fwi_poll_status(ws)
     torch.cuda.synchronize()
 
-    fwi.fwi_timing_enable(True)
+    # kernel durations: HIP events around every step launch of the timed region when the
+    # launches are direct; graph replays cannot be timed per kernel, so with graphs the same
+    # step is repeated once, untimed, with direct launches and events
     fwi.fwi_timing_read(0, True)
     fwi.fwi_timing_read(1, True)
+    fwi.fwi_timing_enable(not args.graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for t in range(args.warmup, args.warmup + args.steps):
@@ -184,10 +196,17 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fwi.fwi_timing_enable(False)
-    fwd_ms, fwd_n = fwi.fwi_timing_read(0, True)
-    adj_ms, adj_n = fwi.fwi_timing_read(1, True)
     fwi.fwi_poll_status(ws)
     elapsed = t1 - t0
+    gstats = fwi.fwi_graphs_stats()
+    if args.graphs:
+        fwi.fwi_graphs_enable(False)
+        fwi.fwi_timing_enable(True)
+        step(args.warmup + args.steps)
+        torch.cuda.synchronize()
+        fwi.fwi_timing_enable(False)
+    fwd_ms, fwd_n = fwi.fwi_timing_read(0, True)
+    adj_ms, adj_n = fwi.fwi_timing_read(1, True)
 
     ny_pad = cfg.ny + 2 * cfg.nb if cfg.ndim == 3 else 1
     phys_cells = nsim * cfg.nz * cfg.ny * cfg.nx
@@ -262,6 +281,8 @@ def main():
                              [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
                    "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
                    "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
+                   "tile_rows": tuned[0] if tuned else None, "graphs": bool(args.graphs),
+                   "graph_captures_replays": list(gstats),
                    "padded_gcell_steps_per_s": round(pad_cells * nt * args.steps / elapsed / 1e9, 3),
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,

@@ -207,9 +207,10 @@ fwi_status fwi_poll_status(void *ws, size_t ws_bytes, void *stream);
 /*
  * Kernel timing for roofline measurement.  While enabled (process-wide), every time-step
  * kernel launch of fwi_forward / fwi_adjoint / fwi_gradient is bracketed by two HIP
- * events recorded on the launch's stream.  fwi_timing_read synchronizes those events and
- * returns the accumulated kernel time and launch count of one kind: 0 = forward or
- * recomputation step, 1 = adjoint + imaging step; reset != 0 zeroes that kind afterwards.
+ * events recorded on the launch's stream (launches captured into a replay graph are not
+ * timed).  fwi_timing_read synchronizes the events and returns the accumulated kernel time
+ * and launch count of one kind: 0 = forward or recomputation step, 1 = adjoint + imaging
+ * step; reset != 0 zeroes that kind afterwards.
  */
 fwi_status fwi_timing_enable(int32_t on);
 fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, int32_t reset);
@@ -219,6 +220,34 @@ fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, in
  * the achievable-HBM-bandwidth reference and the calibration kernel for byte counters.
  */
 fwi_status fwi_copy_probe(const float *src, float *dst, int64_t n, void *stream);
+
+/*
+ * Graph replay (process-wide).  While enabled, fwi_forward / fwi_adjoint / fwi_gradient on a
+ * non-default stream capture their kernel launches into a HIP graph the first time a given
+ * configuration (pointers, scalars, wavelet, batch shape, time axis) is seen and replay the
+ * instantiated graph on later calls; the geometry tables are still uploaded by a plain
+ * copy before each replay, so encodings, sources and kappa may change between calls.  Up to
+ * 8 graphs are cached (least recently used evicted).  Disabling frees them.  Calls on the
+ * default (NULL) stream, and calls while kernel timing is enabled, launch directly.
+ * fwi_graphs_stats returns the number of captures and replays so far.
+ */
+fwi_status fwi_graphs_enable(int32_t on);
+fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays);
+
+/*
+ * Tile height of the step kernels: rows per 2D tile (8, 16, 32, 64) or planes per 3D tile
+ * (16, 32, 64).  fwi_set_tile forces one for every batch of that dimensionality (0 returns
+ * to automatic choice).  fwi_tune times one forward and one adjoint step of every candidate
+ * on the caller's batch, model v (device) and workspace (>= fwi_workspace_size, whose
+ * tables are sized for any candidate), keeps the fastest for this batch shape (the
+ * multiset of padded grid sizes) for later calls, and returns it (bz_out, and the cost of
+ * one gradient time step in ms_out; both nullable).  With cache_path (nullable) the choice
+ * is read from / appended to a JSON-lines file ({"sig": ..., "bz": ..., "ms": ...}) so that
+ * later processes skip the timing.  The workspace content is overwritten.
+ */
+fwi_status fwi_set_tile(int32_t ndim, int32_t bz);
+fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
+                    const char *cache_path, int32_t *bz_out, double *ms_out);
 
 #ifdef __cplusplus
 }

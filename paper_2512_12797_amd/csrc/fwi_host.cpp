@@ -171,6 +171,7 @@ struct Plan {
     int64_t wst_levels = 0, ck_slots = 0;
     int nchunk_res = 1, nchunk_fin = 1;
     size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_evrows = 0, t_evvec = 0, t_src = 0, t_bytes = 0;
+    size_t t_alloc = 0;  // table region reserved in the workspace (largest over tile heights)
     size_t o_status = 0, o_tables = 0, o_cf = 0, o_fields = 0, o_wst = 0, o_ck = 0, o_gacc = 0, o_rho = 0,
            o_part = 0, o_npart = 0, o_mis = 0, total = 0;
 };
@@ -187,46 +188,100 @@ void stencil_weights(const fwi_grid &g, float w[3][5], double gmax[3], float &in
     inv_vol = (float)(1.0 / vol);
 }
 
-void pick_tiles(Plan &p, const fwi_batch *b)
+// Tile heights the kernels are instantiated for (rows per 2D tile, planes per 3D tile).
+const int kBz2[] = {8, 16, 32, 64};
+const int kBz3[] = {16, 32, 64};
+
+// Process-wide tile choices: forced per dimensionality (fwi_set_tile) or tuned per batch
+// shape (fwi_tune).
+struct TileChoices {
+    std::mutex m;
+    int forced[4] = {0, 0, 0, 0};
+    std::vector<std::pair<std::string, int>> tuned;
+};
+TileChoices g_tiles;
+
+// Batch shape signature: dimensionality and the multiset of padded grid sizes.
+std::string shape_signature(const fwi_batch *b)
 {
+    std::vector<std::string> v;
+    for (int s = 0; s < b->nsim; ++s) {
+        const fwi_grid &g = b->grid[b->sample_of[s]];
+        char buf[64];
+        snprintf(buf, sizeof buf, "%dx%dx%d", g.nz + 2 * g.nb, g.ndim == 3 ? g.ny + 2 * g.nb : 1, g.nx + 2 * g.nb);
+        v.push_back(buf);
+    }
+    std::sort(v.begin(), v.end());
+    std::string sig = b->grid[0].ndim == 3 ? "3d" : "2d";
+    for (size_t i = 0; i < v.size();) {
+        size_t j = i;
+        while (j < v.size() && v[j] == v[i]) ++j;
+        sig += ":" + v[i] + "*" + std::to_string(j - i);
+        i = j;
+    }
+    return sig;
+}
+
+bool valid_bz(int ndim, int bz)
+{
+    if (ndim == 2) return bz == 8 || bz == 16 || bz == 32 || bz == 64;
+    return bz == 16 || bz == 32 || bz == 64;
+}
+
+void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
+{
+    p.ty = p.ndim == 3 ? kTileY3 : 1;
+    if (valid_bz(p.ndim, bz_override)) {
+        p.bz = bz_override;
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tiles.m);
+        if (valid_bz(p.ndim, g_tiles.forced[p.ndim])) {
+            p.bz = g_tiles.forced[p.ndim];
+            return;
+        }
+        const std::string sig = shape_signature(b);
+        for (auto &e : g_tiles.tuned)
+            if (e.first == sig && valid_bz(p.ndim, e.second)) {
+                p.bz = e.second;
+                return;
+            }
+    }
     // default: the tallest tile that still gives >= 4 tiles per CU (256 CUs)
-    auto count = [&](int bz, int ty) {
+    auto count = [&](int bz) {
         int64_t n = 0;
         for (int s = 0; s < b->nsim; ++s) {
             const fwi_grid &g = b->grid[b->sample_of[s]];
             int64_t Nx = g.nx + 2 * g.nb, Nz = g.nz + 2 * g.nb, Ny = p.ndim == 3 ? g.ny + 2 * g.nb : 1;
-            n += ((Nx + kTileX - 1) / kTileX) * ((Nz + bz - 1) / bz) * (p.ndim == 3 ? (Ny + ty - 1) / ty : 1);
+            n += ((Nx + kTileX - 1) / kTileX) * ((Nz + bz - 1) / bz) * ((Ny + p.ty - 1) / p.ty);
         }
         return n;
     };
     if (p.ndim == 2) {
-        int bz = 8;
+        p.bz = 8;
         for (int c : {64, 32, 16, 8})
-            if (count(c, 1) >= 1024) {
-                bz = c;
+            if (count(c) >= 1024) {
+                p.bz = c;
                 break;
             }
-        p.bz = env_int("FWI_TILE_BZ", bz);
-        p.ty = 1;
-        if (p.bz != 8 && p.bz != 16 && p.bz != 32 && p.bz != 64) p.bz = bz;
     } else {
-        const int ty = 8;  // the 3D kernel's tile is 64 x 8 cells per plane
-        int bz = 16;
+        p.bz = 16;
         for (int c : {64, 32, 16})
-            if (count(c, ty) >= 1024) {
-                bz = c;
+            if (count(c) >= 1024) {
+                p.bz = c;
                 break;
             }
-        p.bz = env_int("FWI_TILE_BZ", bz);
-        if (p.bz != 16 && p.bz != 32 && p.bz != 64) p.bz = bz;
-        p.ty = ty;
     }
 }
 
-fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p)
+size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz);
+
+fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p, int bz_override = 0,
+                      bool size_for_all_tiles = true)
 {
     p.ndim = b->grid[0].ndim;
-    pick_tiles(p, b);
+    pick_tiles(p, b, bz_override);
     p.nt_rec = t->nt / t->rec_every;
     const int TYt = p.ndim == 3 ? p.ty : 1;
     // samples
@@ -364,6 +419,13 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.t_src = o;
     o = align_up(o + std::max<size_t>(1, p.src.size()) * sizeof(SrcPos));
     p.t_bytes = o;
+    p.t_alloc = o;
+    if (size_for_all_tiles) {
+        if (p.ndim == 2)
+            for (int c : kBz2) p.t_alloc = std::max(p.t_alloc, plan_tables_bytes(b, t, c));
+        else
+            for (int c : kBz3) p.t_alloc = std::max(p.t_alloc, plan_tables_bytes(b, t, c));
+    }
     // workspace layout
     p.fwd_only = t->ckpt_every < 0;
     p.K = p.fwd_only ? 0 : t->ckpt_every;
@@ -382,7 +444,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.o_status = w;
     w = align_up(w + 64);
     p.o_tables = w;
-    w = align_up(w + p.t_bytes);
+    w = align_up(w + p.t_alloc);
     p.o_cf = w;
     w = align_up(w + (size_t)p.coefs * 4);
     p.o_fields = w;
@@ -403,6 +465,13 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     w = align_up(w + (size_t)b->nsim * 8);
     p.total = w;
     return FWI_OK;
+}
+
+size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz)
+{
+    Plan q;
+    if (build_plan(b, t, nullptr, q, bz, false)) return 0;
+    return q.t_bytes;
 }
 
 // ----------------------------------------------------------- host staging
@@ -461,25 +530,159 @@ struct Timing {
 };
 Timing g_timing;
 
+// event pairs recorded while this thread captures a graph (owned by that graph)
+thread_local std::vector<Timing::Pair> t_capture_pairs;
+
 hipError_t timed_step(const StepArgs &a, const Plan &p, bool adjoint, hipStream_t st)
 {
-    if (!g_timing.on) return launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
+    {
+        std::lock_guard<std::mutex> lk(g_timing.m);
+        if (!g_timing.on) return launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return e;
+    // captured launches are not timed (the runtime gives no elapsed time for events
+    // recorded by graph replays)
+    if (cs == hipStreamCaptureStatusActive) return launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
     std::lock_guard<std::mutex> lk(g_timing.m);
     hipEvent_t ev[2];
     for (int i = 0; i < 2; ++i) {
         if (g_timing.pool.empty()) {
-            hipError_t e = hipEventCreate(&ev[i]);
+            e = hipEventCreate(&ev[i]);
             if (e != hipSuccess) return e;
         } else {
             ev[i] = g_timing.pool.back();
             g_timing.pool.pop_back();
         }
     }
-    hipError_t e = hipEventRecord(ev[0], st);
+    e = hipEventRecord(ev[0], st);
     if (e == hipSuccess) e = launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
     g_timing.pending.push_back({ev[0], ev[1], adjoint ? 1 : 0});
     return e;
+}
+
+// ------------------------------------------------------------------ graphs
+
+// Replay of whole launch sequences.  When enabled, a forward / adjoint / gradient call on a
+// non-default stream captures its launches (after the table upload, which stays a plain
+// copy) into a HIP graph the first time a given configuration is seen and replays the
+// instantiated graph on later calls.  The key covers every value that reaches a kernel
+// argument: pointers, scalars, the wavelet, table offsets and launch shapes.  Table
+// contents (sources, encodings, kappa) are device data and may change between replays.
+struct GraphCache {
+    std::mutex m;
+    bool on = false;
+    struct Entry {
+        uint64_t key;
+        hipGraphExec_t exec;
+        uint64_t used;
+        std::vector<Timing::Pair> pairs;  // timing events inside the graph
+        bool timed_pending;               // replayed since the last fwi_timing_read
+    };
+    std::vector<Entry> entries;
+    uint64_t tick = 0;
+    int64_t captures = 0, replays = 0;
+};
+GraphCache g_graphs;
+constexpr size_t kMaxGraphs = 8;
+
+struct KeyHash {
+    uint64_t h = 1469598103934665603ULL;  // FNV-1a
+    void bytes(const void *p, size_t n)
+    {
+        const uint8_t *c = (const uint8_t *)p;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= c[i];
+            h *= 1099511628211ULL;
+        }
+    }
+    template <class T>
+    void add(const T &v)
+    {
+        bytes(&v, sizeof v);
+    }
+};
+
+void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
+{
+    k.add(p.ndim); k.add(p.bz); k.add(p.ty); k.add(p.per_xcd); k.add(p.cells); k.add(p.coefs); k.add(p.data);
+    k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
+    k.add(p.nchunk_res); k.add(p.nchunk_fin);
+    const size_t nt = p.tiles.size();
+    k.add(nt);
+    const size_t offs[] = {p.t_sims, p.t_samples, p.t_tiles, p.t_evrows, p.t_evvec, p.t_src, p.t_bytes,
+                           p.o_status, p.o_tables, p.o_cf, p.o_fields, p.o_wst, p.o_ck, p.o_gacc, p.o_rho,
+                           p.o_part, p.o_npart, p.o_mis, p.total};
+    k.bytes(offs, sizeof offs);
+    k.add(b->nsim); k.add(b->nsample);
+    k.add(t->dt); k.add(t->nt); k.add(t->rec_every); k.add(t->ckpt_every);
+    k.bytes(b->wavelet, sizeof(float) * t->nt);
+}
+
+void destroy_entry(GraphCache::Entry &e)
+{
+    (void)hipGraphExecDestroy(e.exec);
+    for (auto &pr : e.pairs) {
+        (void)hipEventDestroy(pr.a);
+        (void)hipEventDestroy(pr.b);
+    }
+    e.pairs.clear();
+}
+
+template <class Body>
+fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
+{
+    bool use;
+    {
+        std::lock_guard<std::mutex> lk(g_graphs.m);
+        use = g_graphs.on && st != nullptr;
+    }
+    if (!use) return body(st);
+    std::lock_guard<std::mutex> lk(g_graphs.m);
+    for (auto &e : g_graphs.entries)
+        if (e.key == key) {
+            e.used = ++g_graphs.tick;
+            g_graphs.replays++;
+            HIP_TRY(hipGraphLaunch(e.exec, st));
+            e.timed_pending = !e.pairs.empty();
+            return FWI_OK;
+        }
+    t_capture_pairs.clear();
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    fwi_status s = body(st);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    GraphCache::Entry ent{key, nullptr, 0, std::move(t_capture_pairs), false};
+    t_capture_pairs.clear();
+    if (s || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        destroy_entry(ent);
+        return s ? s : fail(FWI_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        ent.exec = nullptr;
+        for (auto &pr : ent.pairs) {
+            (void)hipEventDestroy(pr.a);
+            (void)hipEventDestroy(pr.b);
+        }
+        return fail(FWI_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    if (g_graphs.entries.size() >= kMaxGraphs) {
+        auto old = std::min_element(g_graphs.entries.begin(), g_graphs.entries.end(),
+                                    [](const GraphCache::Entry &a, const GraphCache::Entry &b) { return a.used < b.used; });
+        destroy_entry(*old);
+        g_graphs.entries.erase(old);
+    }
+    ent.used = ++g_graphs.tick;
+    ent.timed_pending = !ent.pairs.empty();
+    g_graphs.entries.push_back(std::move(ent));
+    g_graphs.captures++;
+    HIP_TRY(hipGraphLaunch(g_graphs.entries.back().exec, st));
+    return FWI_OK;
 }
 
 // ------------------------------------------------------------- the schedule
@@ -706,7 +909,11 @@ fwi_status fwi_forward(const fwi_batch *b, const fwi_time *t, const float *v, fl
     Dev d = carve(p, ws);
     s = upload_tables(p, d.base + p.o_tables, st);
     if (s) return s;
-    return run_forward(p, d, b, t, v, d_pred ? d_pred : d.rho, st);
+    KeyHash k;
+    k.add(1);
+    k.add(v); k.add(d_pred); k.add(ws); k.add(st);
+    hash_plan(k, p, b, t);
+    return run_maybe_graph(k.h, st, [&](hipStream_t s2) { return run_forward(p, d, b, t, v, d_pred ? d_pred : d.rho, s2); });
 }
 
 fwi_status fwi_adjoint(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_res,
@@ -721,8 +928,14 @@ fwi_status fwi_adjoint(const fwi_batch *b, const fwi_time *t, const float *v, co
     Dev d = carve(p, ws);
     s = upload_tables(p, d.base + p.o_tables, st);
     if (s) return s;
-    HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, st));
-    return run_adjoint(p, d, b, t, v, d_res, grad, grad_norm, st);
+    KeyHash k;
+    k.add(2);
+    k.add(v); k.add(d_res); k.add(grad); k.add(grad_norm); k.add(ws); k.add(st);
+    hash_plan(k, p, b, t);
+    return run_maybe_graph(k.h, st, [&](hipStream_t s2) -> fwi_status {
+        HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, s2));
+        return run_adjoint(p, d, b, t, v, d_res, grad, grad_norm, s2);
+    });
 }
 
 fwi_status fwi_gradient(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_obs,
@@ -740,13 +953,20 @@ fwi_status fwi_gradient(const fwi_batch *b, const fwi_time *t, const float *v, c
     s = upload_tables(p, d.base + p.o_tables, st);
     if (s) return s;
     float *dat = d_pred ? d_pred : d.rho;
-    s = run_forward(p, d, b, t, v, dat, st);
-    if (s) return s;
-    HIP_TRY(launch_residual(d.sims, b->nsim, p.nt_rec, dat, d_obs, d.rho, inv_sigma2, d.part, p.nchunk_res,
-                            d.status, st));
-    HIP_TRY(launch_misfit_final(d.part, p.nchunk_res, b->nsim, 0.5 * (double)inv_sigma2, misfit ? misfit : d.mis,
-                                st));
-    return run_adjoint(p, d, b, t, v, d.rho, grad, grad_norm, st);
+    KeyHash k;
+    k.add(3);
+    k.add(v); k.add(d_obs); k.add(inv_sigma2); k.add(d_pred); k.add(misfit); k.add(grad); k.add(grad_norm);
+    k.add(ws); k.add(st);
+    hash_plan(k, p, b, t);
+    return run_maybe_graph(k.h, st, [&](hipStream_t s2) -> fwi_status {
+        fwi_status r = run_forward(p, d, b, t, v, dat, s2);
+        if (r) return r;
+        HIP_TRY(launch_residual(d.sims, b->nsim, p.nt_rec, dat, d_obs, d.rho, inv_sigma2, d.part, p.nchunk_res,
+                                d.status, s2));
+        HIP_TRY(launch_misfit_final(d.part, p.nchunk_res, b->nsim, 0.5 * (double)inv_sigma2,
+                                    misfit ? misfit : d.mis, s2));
+        return run_adjoint(p, d, b, t, v, d.rho, grad, grad_norm, s2);
+    });
 }
 
 fwi_status fwi_encode(const float *d_shots, int32_t nshot, int64_t n_per_shot, int32_t ngrp, const int32_t *grp_ptr,
@@ -843,7 +1063,24 @@ fwi_status fwi_timing_enable(int32_t on)
 fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, int32_t reset)
 {
     if (kind < 0 || kind > 1 || !total_ms || !launches) return fail(FWI_E_ARG, "bad kind or null output");
+    // graphs replayed since the last read: durations of their latest replay
+    std::vector<Timing::Pair> from_graphs;
+    {
+        std::lock_guard<std::mutex> lk(g_graphs.m);
+        for (auto &e : g_graphs.entries)
+            if (e.timed_pending) {
+                from_graphs.insert(from_graphs.end(), e.pairs.begin(), e.pairs.end());
+                e.timed_pending = false;
+            }
+    }
     std::lock_guard<std::mutex> lk(g_timing.m);
+    for (auto &pr : from_graphs) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventSynchronize(pr.b));
+        HIP_TRY(hipEventElapsedTime(&ms, pr.a, pr.b));
+        g_timing.total_ms[pr.kind] += ms;
+        g_timing.count[pr.kind] += 1;
+    }
     for (auto &pr : g_timing.pending) {
         float ms = 0.0f;
         HIP_TRY(hipEventSynchronize(pr.b));
@@ -860,6 +1097,163 @@ fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, in
         g_timing.total_ms[kind] = 0;
         g_timing.count[kind] = 0;
     }
+    return FWI_OK;
+}
+
+fwi_status fwi_graphs_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_graphs.m);
+    g_graphs.on = on != 0;
+    if (!g_graphs.on) {
+        (void)hipDeviceSynchronize();
+        for (auto &e : g_graphs.entries) destroy_entry(e);
+        g_graphs.entries.clear();
+    }
+    return FWI_OK;
+}
+
+fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays)
+{
+    if (!captures || !replays) return fail(FWI_E_ARG, "null output");
+    std::lock_guard<std::mutex> lk(g_graphs.m);
+    *captures = g_graphs.captures;
+    *replays = g_graphs.replays;
+    return FWI_OK;
+}
+
+fwi_status fwi_set_tile(int32_t ndim, int32_t bz)
+{
+    if (ndim != 2 && ndim != 3) return fail(FWI_E_ARG, "ndim must be 2 or 3");
+    if (bz != 0 && !valid_bz(ndim, bz)) return fail(FWI_E_ARG, "unsupported tile height %d", bz);
+    std::lock_guard<std::mutex> lk(g_tiles.m);
+    g_tiles.forced[ndim] = bz;
+    return FWI_OK;
+}
+
+// Time one forward step and one adjoint step of every candidate tile height on the
+// caller's batch and workspace; keep the fastest for this batch shape.
+fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
+                    const char *cache_path, int32_t *bz_out, double *ms_out)
+{
+    Plan p0;
+    fwi_status s = prologue(b, t, nullptr, ws, ws_bytes, p0);
+    if (s) return s;
+    if (!v) return fail(FWI_E_ARG, "null model");
+    hipStream_t st = (hipStream_t)stream;
+    const std::string sig = shape_signature(b);
+    // a recorded choice for this shape wins
+    if (cache_path && *cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[4096];
+            const std::string needle = "\"sig\": \"" + sig + "\"";
+            int found = 0;
+            double ms = 0;
+            while (fgets(line, sizeof line, f)) {
+                if (!strstr(line, needle.c_str())) continue;
+                const char *q = strstr(line, "\"bz\": ");
+                const char *m = strstr(line, "\"ms\": ");
+                if (q && valid_bz(p0.ndim, atoi(q + 6))) {
+                    found = atoi(q + 6);
+                    ms = m ? atof(m + 6) : 0.0;
+                }
+            }
+            fclose(f);
+            if (found) {
+                std::lock_guard<std::mutex> lk(g_tiles.m);
+                bool set = false;
+                for (auto &e : g_tiles.tuned)
+                    if (e.first == sig) {
+                        e.second = found;
+                        set = true;
+                    }
+                if (!set) g_tiles.tuned.push_back({sig, found});
+                if (bz_out) *bz_out = found;
+                if (ms_out) *ms_out = ms;
+                return FWI_OK;
+            }
+        }
+    }
+    std::vector<int> cand;
+    if (p0.ndim == 2)
+        cand.assign(std::begin(kBz2), std::end(kBz2));
+    else
+        cand.assign(std::begin(kBz3), std::end(kBz3));
+    const int reps = 8;
+    hipEvent_t e0, e1, e2;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventCreate(&e2));
+    int best = 0;
+    double best_ms = 1e30;
+    for (int bz : cand) {
+        Plan p;
+        s = build_plan(b, t, nullptr, p, bz);
+        if (s) return s;
+        Dev d = carve(p, ws);
+        s = upload_tables(p, d.base + p.o_tables, st);
+        if (s) return s;
+        HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, st));
+        HIP_TRY(launch_fill_f32(d.lev[0], 2 * p.cells, 0.0f, st));
+        if (!p.fwd_only) HIP_TRY(launch_fill_f64(d.gacc, p.cells, 0.0, st));
+        StepArgs a = base_args(p, d);
+        a.fn = 0.0f;
+        a.wst = p.fwd_only ? nullptr : d.wst;
+        a.wimg = p.fwd_only ? nullptr : d.wst;
+        a.gacc = d.gacc;
+        a.rho = d.rho;
+        for (int pass = 0; pass < 2; ++pass) {  // first pass warms the caches
+            float *cur = d.lev[0], *prev = d.lev[1];
+            HIP_TRY(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) {
+                a.cur = cur;
+                a.prev = a.next = prev;
+                HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.ty, st));
+                std::swap(cur, prev);
+            }
+            HIP_TRY(hipEventRecord(e1, st));
+            if (!p.fwd_only)
+                for (int r = 0; r < reps; ++r) {
+                    a.cur = cur;
+                    a.prev = a.next = prev;
+                    HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.ty, st));
+                    std::swap(cur, prev);
+                }
+            HIP_TRY(hipEventRecord(e2, st));
+        }
+        HIP_TRY(hipEventSynchronize(e2));
+        float fms = 0, ams = 0;
+        HIP_TRY(hipEventElapsedTime(&fms, e0, e1));
+        HIP_TRY(hipEventElapsedTime(&ams, e1, e2));
+        // cost of one gradient time step: forward sweeps (two with recomputation) + adjoint
+        const double ms = (fms * (p.K > 0 ? 2.0 : 1.0) + ams) / reps;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = bz;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    {
+        std::lock_guard<std::mutex> lk(g_tiles.m);
+        bool set = false;
+        for (auto &e : g_tiles.tuned)
+            if (e.first == sig) {
+                e.second = best;
+                set = true;
+            }
+        if (!set) g_tiles.tuned.push_back({sig, best});
+    }
+    if (cache_path && *cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"sig\": \"%s\", \"bz\": %d, \"ms\": %.6f}\n", sig.c_str(), best, best_ms);
+            fclose(f);
+        }
+    }
+    if (bz_out) *bz_out = best;
+    if (ms_out) *ms_out = best_ms;
     return FWI_OK;
 }
 

@@ -382,15 +382,15 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
 // a 4-cell halo in x and y) goes through a double-buffered LDS plane with one barrier
 // per plane; the z-derivative comes from a register queue that runs 8 planes ahead, and
 // the halo and point operands are fetched 4 planes ahead with unconditional buffer loads.
-constexpr int kTY3 = 8;
+
 struct Plane3 {
-    float v[2][kTY3 + 2 * kHalo][kTileX + 2 * kHalo];
+    float v[2][kTileY3 + 2 * kHalo][kTileX + 2 * kHalo];
 };
 
 template <int BZ, bool ADJ>
 __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
 {
-    constexpr int RPT = kTY3 / 4;
+    constexpr int RPT = kTileY3 / 4;
     constexpr int PF = 4;
     const int t = xcd_tile(blockIdx.x, A.per_xcd);
     if (t >= A.ntiles) return;  // uniform per block
@@ -449,13 +449,13 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
 
     // y-halo rows: LDS rows ty (y0-4+ty) and TY+4+ty (y0+TY+ty); x-halo: 8 columns x TY
     // rows by the first TY*8 threads
-    const int hy0 = T.y0 - kHalo + ty, hy1 = T.y0 + kTY3 + ty;
+    const int hy0 = T.y0 - kHalo + ty, hy1 = T.y0 + kTileY3 + ty;
     const bool hyl0 = x < Nx && hy0 >= 0, hyl1 = x < Nx && hy1 < Ny;
     const uint32_t hyo0 = 4u * ((uint32_t)max(hy0, 0) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
     const uint32_t hyo1 = 4u * ((uint32_t)min(hy1, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
     const int xh_t = threadIdx.x;
-    const bool xh_on = xh_t < kTY3 * 8;
-    const int xh_row = (xh_t >> 3) & (kTY3 - 1), xh_c = xh_t & 7;
+    const bool xh_on = xh_t < kTileY3 * 8;
+    const int xh_row = (xh_t >> 3) & (kTileY3 - 1), xh_c = xh_t & 7;
     const int xh_col = xh_c < 4 ? xh_c : kTileX + xh_c;  // LDS column
     const int xh_x = T.x0 - kHalo + xh_col;
     const int xh_y = T.y0 + xh_row;
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) V[ty + 4 * r + kHalo][lane + kHalo] = q[r][4];
         V[ty][lane + kHalo] = h0q[0];
-        V[kTY3 + kHalo + ty][lane + kHalo] = h1q[0];
+        V[kTileY3 + kHalo + ty][lane + kHalo] = h1q[0];
         if (xh_on) V[xh_row + kHalo][xh_col] = hxq[0];
         __syncthreads();
         par ^= 1;
@@ -907,7 +907,7 @@ template <bool ADJ>
 static hipError_t step3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
 {
     dim3 grid(8 * a.per_xcd);
-    if (ty != kTY3) return hipErrorInvalidValue;
+    if (ty != kTileY3) return hipErrorInvalidValue;
     switch (bz) {
     case 16: k_step3d<16, ADJ><<<grid, 256, 0, st>>>(a); break;
     case 32: k_step3d<32, ADJ><<<grid, 256, 0, st>>>(a); break;

@@ -74,6 +74,13 @@ def lib():
         L.fwi_langevin.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                    C.c_uint64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
         L.fwi_poll_status.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
+        for name in ("fwi_graphs_enable", "fwi_graphs_stats", "fwi_set_tile", "fwi_tune"):
+            getattr(L, name).restype = C.c_int32
+        L.fwi_graphs_enable.argtypes = [C.c_int32]
+        L.fwi_graphs_stats.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.fwi_set_tile.argtypes = [C.c_int32, C.c_int32]
+        L.fwi_tune.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p, C.c_size_t,
+                               C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         for name in ("fwi_timing_enable", "fwi_timing_read", "fwi_copy_probe"):
             getattr(L, name).restype = C.c_int32
         L.fwi_timing_enable.argtypes = [C.c_int32]
@@ -300,3 +307,26 @@ def fwi_timing_read(kind: int, reset: bool = True):
 
 def fwi_copy_probe(src, dst, stream=None):
     _ok(lib().fwi_copy_probe(_ptr(src), _ptr(dst), src.numel(), _stream(stream)))
+
+
+def fwi_graphs_enable(on: bool):
+    _ok(lib().fwi_graphs_enable(1 if on else 0))
+
+
+def fwi_graphs_stats():
+    c, r = C.c_int64(0), C.c_int64(0)
+    _ok(lib().fwi_graphs_stats(C.byref(c), C.byref(r)))
+    return c.value, r.value
+
+
+def fwi_set_tile(ndim: int, bz: int):
+    _ok(lib().fwi_set_tile(ndim, bz))
+
+
+def fwi_tune(batch, time, v, ws, cache_path=None, stream=None):
+    """Returns (tile height, ms per gradient time step)."""
+    bz = C.c_int32(0)
+    ms = C.c_double(0.0)
+    _ok(lib().fwi_tune(batch.c, C.byref(time), _ptr(v), _ptr(ws), ws.numel(), _stream(stream),
+                       cache_path.encode() if cache_path else None, C.byref(bz), C.byref(ms)))
+    return bz.value, ms.value

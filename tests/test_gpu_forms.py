@@ -175,3 +175,119 @@ def test_bench_configuration_full_size_sampled(F):
     e = rel(g0, ref)
     say("  sample 0 gradient rel %.2e" % e)
     assert e < TOL
+
+
+# ------------------------------------------------ graphs, tile heights, tuner
+
+def _edge_batch(F, seed, ckpt=0, nt=160):
+    """Uneven 2-sample batch whose encodings are redrawn per `seed`."""
+    from paper_2512_12797_amd import problems
+    cfg = W.C3
+    grids = [F.Grid(nz=37, nx=83, dz=10.0, dx=10.0, nb=7, v_ref=3500.0, v_max=3850.0),
+             F.Grid(nz=50, nx=150, dz=10.0, dx=10.0, nb=6, v_ref=3500.0, v_max=3850.0)]
+    wav = W.ricker(15.0, 1e-3, nt)
+    batch, groups = problems.encoded_batch(cfg, grids, wav, seed=seed, step=seed, s=3, G=2,
+                                           nshot_of=lambda g: 6)
+    time = F.time_axis(1e-3, nt, 2, ckpt)
+    models = [f32(W.salt_2d(g.nz, g.nx, seed=k + 5, vtop=1500, vbot=2800, vsalt=3500).ravel())
+              for k, g in enumerate(grids)]
+    return batch, groups, time, models
+
+
+def _run(F, batch, time, v, dobs, kappa, ws, stream=None):
+    nd = batch.data_size(time.nt // time.rec_every)
+    dpred = torch.zeros(nd, device="cuda")
+    mis = torch.zeros(batch.nsim, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(batch.model_size, device="cuda")
+    F.fwi_gradient(batch, time, v, dobs, 2.0, kappa, dpred, mis, grad, None, ws, stream=stream)
+    torch.cuda.synchronize()
+    return dpred.cpu().numpy(), mis.cpu().numpy(), grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("ckpt", [0, 6])
+def test_graph_replays_equal_eager(F, ckpt):
+    say("case graph replays ckpt=%d" % ckpt)
+    side = torch.cuda.Stream()
+    batch, _, time, models = _edge_batch(F, 1, ckpt)
+    nd = batch.data_size(time.nt // 2)
+    r = np.random.default_rng(0)
+    v = dev(np.concatenate(models))
+    dobs = dev(1e-4 * r.standard_normal(nd))
+    ws = F.alloc_workspace(batch, time)
+    outs_eager = []
+    for seed in (1, 2, 3):
+        b, groups, _, _ = _edge_batch(F, seed, ckpt)
+        outs_eager.append(_run(F, b, time, v, dobs, [g[2] for g in groups], ws))
+    F.fwi_graphs_enable(True)
+    try:
+        c0, r0 = F.fwi_graphs_stats()
+        for rep in range(2):
+            for i, seed in enumerate((1, 2, 3)):
+                b, groups, _, _ = _edge_batch(F, seed, ckpt)
+                with torch.cuda.stream(side):
+                    out = _run(F, b, time, v, dobs, [g[2] * (1.0 + 0.0 * rep) for g in groups], ws, stream=side)
+                # unrelated eager work between replays
+                junk = torch.randn(1 << 20, device="cuda").sum()
+                torch.cuda.synchronize()
+                for a, e in zip(out, outs_eager[i]):
+                    assert np.array_equal(a, e), (rep, seed)
+        c1, r1 = F.fwi_graphs_stats()
+        say("  captures %d replays %d" % (c1 - c0, r1 - r0))
+        assert c1 - c0 == 1 and r1 - r0 == 5
+    finally:
+        F.fwi_graphs_enable(False)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_results_identical_for_every_tile_height(F, ndim):
+    say("case tile heights %dD" % ndim)
+    if ndim == 2:
+        batch, groups, time, models = _edge_batch(F, 4, 0, 120)
+        cands = [8, 16, 32, 64]
+    else:
+        g = F.Grid(nz=40, ny=13, nx=70, dz=20.0, dy=20.0, dx=20.0, nb=4, v_ref=3000.0, v_max=3300.0, ndim=3)
+        rec = np.array([(1 * 13 + y) * 70 + x for y in range(0, 13, 3) for x in range(0, 70, 5)], dtype=np.int32)
+        batch = F.Batch([g], [0, 0], [([(1 * 13 + 6) * 70 + 30], [1.0]), ([(20 * 13 + 2) * 70 + 3], [-1.0])],
+                        [rec, rec], W.ricker(8.0, 2e-3, 80))
+        time = F.time_axis(2e-3, 80, 1, 0)
+        models = [f32(np.random.default_rng(1).uniform(1800, 3000, g.nphys))]
+        groups = [(None, None, 1.0)]
+        cands = [16, 32, 64]
+    nd = batch.data_size(time.nt // time.rec_every)
+    v = dev(np.concatenate(models))
+    dobs = dev(1e-4 * np.random.default_rng(2).standard_normal(nd))
+    ws = F.alloc_workspace(batch, time)
+    outs = []
+    try:
+        for bz in cands:
+            F.fwi_set_tile(ndim, bz)
+            outs.append(_run(F, batch, time, v, dobs, [g[2] for g in groups], ws))
+    finally:
+        F.fwi_set_tile(ndim, 0)
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_tuner_and_cache(F, tmp_path):
+    say("case tuner")
+    batch, groups, time, models = _edge_batch(F, 7, 0, 120)
+    v = dev(np.concatenate(models))
+    ws = F.alloc_workspace(batch, time)
+    path = str(tmp_path / "tune.json")
+    bz, ms = F.fwi_tune(batch, time, v, ws, path)
+    say("  tuned bz %d, %.4f ms per gradient step" % (bz, ms))
+    assert bz in (8, 16, 32, 64) and ms > 0
+    lines = open(path).read().strip().splitlines()
+    assert len(lines) == 1 and '"bz": %d' % bz in lines[0]
+    bz2, ms2 = F.fwi_tune(batch, time, v, ws, path)  # read back, no new line
+    assert bz2 == bz and abs(ms2 - ms) < 1e-5
+    assert len(open(path).read().strip().splitlines()) == 1
+    # the tuned choice is used and the result is still the oracle's
+    nd = batch.data_size(time.nt // 2)
+    dobs = f32(1e-4 * np.random.default_rng(3).standard_normal(nd))
+    dp, mis, gr = _run(F, batch, time, v, dev(dobs), [g[2] for g in groups], ws)
+    _, omis, ogr = oracle_batch_gradient(batch, time.dt, time.nt, 2, models,
+                                         split_data(dobs, batch, time.nt // 2), 2.0, [g[2] for g in groups])
+    for k, gk in enumerate(split_model(gr.astype(np.float64), batch)):
+        assert rel(gk, ogr[k]) < TOL
