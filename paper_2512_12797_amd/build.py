@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwi_mi355.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["fwi_kernels.hip", "fwi_host.cpp"]
+SOURCES = ["fwi_kernels.hip", "fwi_host.cpp", "nn_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code (toolchain notes)
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
