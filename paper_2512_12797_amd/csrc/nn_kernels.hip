@@ -40,8 +40,10 @@ __device__ __forceinline__ float dsilu(float z)
 
 // ------------------------------------------------------------------ conv3x3
 
-// Block = 4 wavefronts in a 2 x 2 arrangement covering 64 pixels x 64 output channels;
-// each wavefront accumulates a 32 x 32 tile.
+// Block = 4 wavefronts in a 2 x 2 arrangement; each wavefront accumulates MT x NT tiles of
+// 32 pixels x 32 output channels (each loaded fragment feeds NT or MT matrix operations)
+// and fetches the fragments of the next K step while the current ones are multiplied.
+template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x, int N, int H, int W, int Cin,
                                                  const uint16_t *__restrict__ w, int Cout,
                                                  const float *__restrict__ bias, const float *__restrict__ aux,
@@ -50,103 +52,168 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x,
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t P = (int64_t)N * H * W;
-    const int64_t p0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
-    const int co0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int64_t p0 = (int64_t)blockIdx.x * (64 * MT) + (wave & 1) * (32 * MT);
+    const int co0 = blockIdx.y * (64 * NT) + (wave >> 1) * (32 * NT);
     if (co0 >= Cout || p0 >= P) return;  // uniform per wavefront; no barriers below
-    const int64_t p = p0 + (lane & 31);
-    const bool pin = p < P;
-    int n = 0, y = 0, xx = 0;
-    if (pin) {
-        xx = (int)(p % W);
-        const int64_t t = p / W;
-        y = (int)(t % H);
-        n = (int)(t / H);
-    }
     const int kh = (lane >> 5) * 8;
-    const int co = co0 + (lane & 31);
-    const uint16_t *wrow = w + (int64_t)co * 9 * Cin + kh;
-    f32x16 acc = {};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
-        const bool v = pin && yy >= 0 && yy < H && xs >= 0 && xs < W;
-        const uint16_t *xp = x + (((int64_t)n * H + (v ? yy : 0)) * W + (v ? xs : 0)) * Cin + kh;
-        const uint16_t *wp = wrow + tap * Cin;
-        for (int c0 = 0; c0 < Cin; c0 += 16) {
-            uint4 av = make_uint4(0u, 0u, 0u, 0u);
-            if (v) av = *(const uint4 *)(xp + c0);
-            const uint4 bv = *(const uint4 *)(wp + c0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                          __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
-        }
-    }
-    const int c = co0 + (lane & 31);
-    const float b = bias ? bias[c] : 0.0f;
+    int py[MT], px[MT], pn[MT];
+    bool pin[MT];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t pr = p0 + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
-        if (pr >= P) continue;
-        float val = acc[r] + b;
-        const int64_t o = pr * Cout + c;
-        if (aux) val *= dsilu(aux[o]);
-        if (res && c == 0) val += res[pr];
-        if (of32) of32[o] = val;
-        if (obf) obf[o] = f2bf(act ? silu(val) : val);
+    for (int i = 0; i < MT; ++i) {
+        const int64_t p = p0 + 32 * i + (lane & 31);
+        pin[i] = p < P;
+        px[i] = pin[i] ? (int)(p % W) : 0;
+        const int64_t t = pin[i] ? p / W : 0;
+        py[i] = (int)(t % H);
+        pn[i] = (int)(t / H);
+    }
+    const uint16_t *wrow[NT];
+    bool cin_[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = co0 + 32 * j + (lane & 31);
+        cin_[j] = co < Cout;
+        wrow[j] = w + (int64_t)(cin_[j] ? co : 0) * 9 * Cin + kh;
+    }
+    const int csteps = Cin / 16;
+    const int ksteps = 9 * csteps;
+    auto load_a = [&](int ks, uint4 (&a)[MT]) {
+        const int tap = ks / csteps, c0 = (ks - tap * csteps) * 16;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const int yy = py[i] + dy, xs = px[i] + dx;
+            const bool v = pin[i] && yy >= 0 && yy < H && xs >= 0 && xs < W;
+            a[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (v) a[i] = *(const uint4 *)(x + (((int64_t)pn[i] * H + yy) * W + xs) * Cin + kh + c0);
+        }
+    };
+    auto load_b = [&](int ks, uint4 (&b)[NT]) {
+        const int tap = ks / csteps, c0 = (ks - tap * csteps) * 16;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) b[j] = *(const uint4 *)(wrow[j] + tap * Cin + c0);
+    };
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = f32x16{};
+    uint4 a[MT], b[NT], an[MT], bn[NT];
+    load_a(0, a);
+    load_b(0, b);
+    for (int ks = 0; ks < ksteps; ++ks) {
+        if (ks + 1 < ksteps) {
+            load_a(ks + 1, an);
+            load_b(ks + 1, bn);
+        }
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[i]),
+                                                                    __builtin_bit_cast(bf16x8, b[j]), acc[i][j], 0, 0,
+                                                                    0);
+#pragma unroll
+        for (int i = 0; i < MT; ++i) a[i] = an[i];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) b[j] = bn[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int c = co0 + 32 * j + (lane & 31);
+        if (!cin_[j]) continue;
+        const float bb = bias ? bias[c] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t pr = p0 + 32 * i + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
+                if (pr >= P) continue;
+                float val = acc[i][j][r] + bb;
+                const int64_t o = pr * Cout + c;
+                if (aux) val *= dsilu(aux[o]);
+                if (res && c == 0) val += res[pr];
+                if (of32) of32[o] = val;
+                if (obf) obf[o] = f2bf(act ? silu(val) : val);
+            }
     }
 }
 
 // ------------------------------------------------------------------- wgrad
 
-// One wavefront per (32 output channels, 32 input channels, tap, pixel chunk):
-// partial dw over the chunk's pixels with M = co, N = ci, K = pixels.
+// One wavefront per (32 output channels, 32 input channels, pixel chunk), all 9 taps:
+// M = co, N = ci, K = pixels in steps of 16.  Each step loads the 16-pixel x 32-channel
+// tiles of dz (once) and of x at the 9 shifted positions with one coalesced 16-byte load
+// per lane, stages them in LDS and reads them back in the matrix-operand layout.
 __global__ __launch_bounds__(64) void k_wgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
                                               int N, int H, int W, int Cin, int Cout, int64_t per_chunk,
                                               float *__restrict__ work)
 {
+    __shared__ uint16_t ta[16][32];
+    __shared__ uint16_t tb[16][32];
     const int lane = threadIdx.x;
-    const int nco = Cout / 32, nci = Cin / 32 > 0 ? (Cin + 31) / 32 : 1;
-    int t = blockIdx.x;
-    const int tap = t % 9;
-    t /= 9;
-    const int cit = t % nci;
-    const int cot = t / nci;
+    const int nci = (Cin + 31) / 32;
+    const int cit = blockIdx.x % nci, cot = blockIdx.x / nci;
     const int chunk = blockIdx.y;
     const int64_t P = (int64_t)N * H * W;
     const int64_t pb = (int64_t)chunk * per_chunk;
     const int64_t pe = std::min<int64_t>(pb + per_chunk, P);
-    const int co = cot * 32 + (lane & 31);
-    const int ci = cit * 32 + (lane & 31);
-    const bool ciin = ci < Cin;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const int ks = (lane >> 5) * 8;
-    f32x16 acc = {};
+    const int lr = lane >> 2, lc = (lane & 3) * 8;  // loader role: tile row (pixel) lr, 8 channels from lc
+    const int co_ld = cot * 32 + lc, ci_ld = cit * 32 + lc;
+    const int kr = 8 * (lane >> 5), mc = lane & 31;  // operand role: rows kr..kr+7, column mc
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
     for (int64_t pk = pb; pk < pe; pk += 16) {
-        bf16x8 a, b;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t pp = pk + ks + j;
-            uint16_t av = 0, bv = 0;
-            if (pp < pe) {
-                av = dz[pp * Cout + co];
-                const int xx = (int)(pp % W);
-                const int64_t tt = pp / W;
-                const int y = (int)(tt % H);
-                const int n = (int)(tt / H);
-                const int yy = y + dy, xs = xx + dx;
-                if (ciin && yy >= 0 && yy < H && xs >= 0 && xs < W) bv = x[(((int64_t)n * H + yy) * W + xs) * Cin + ci];
-            }
-            a[j] = __builtin_bit_cast(__bf16, av);
-            b[j] = __builtin_bit_cast(__bf16, bv);
+        const int64_t pp = pk + lr;
+        const bool pv = pp < pe;
+        uint4 av = make_uint4(0u, 0u, 0u, 0u);
+        if (pv) av = *(const uint4 *)(dz + pp * Cout + co_ld);
+        int y = 0, xx = 0, n = 0;
+        if (pv) {
+            xx = (int)(pp % W);
+            const int64_t tt = pp / W;
+            y = (int)(tt % H);
+            n = (int)(tt / H);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-    // acc[r]: row (co) 8*(r/4) + 4*(lane/32) + r%4, column (ci) lane%32
-    float *wk = work + (int64_t)chunk * Cout * 9 * Cin;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        *(uint4 *)&ta[lr][lc] = av;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bf16x8 a;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int cor = cot * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
-        const int cic = cit * 32 + (lane & 31);
-        if (cic < Cin) wk[((int64_t)cor * 9 + tap) * Cin + cic] = acc[r];
+        for (int j = 0; j < 8; ++j) a[j] = __builtin_bit_cast(__bf16, ta[kr + j][mc]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
+            uint4 bv = make_uint4(0u, 0u, 0u, 0u);
+            if (pv && ci_ld < Cin && yy >= 0 && yy < H && xs >= 0 && xs < W)
+                bv = *(const uint4 *)(x + (((int64_t)n * H + yy) * W + xs) * Cin + ci_ld);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            *(uint4 *)&tb[lr][lc] = bv;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = __builtin_bit_cast(__bf16, tb[kr + j][mc]);
+            acc[tap] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[tap], 0, 0, 0);
+        }
     }
+    // acc[tap][r]: row (co) 8*(r/4) + 4*(lane/32) + r%4, column (ci) lane%32
+    float *wk = work + (int64_t)chunk * Cout * 9 * Cin;
+    const int cic = cit * 32 + (lane & 31);
+    if (cic < Cin)
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int cor = cot * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
+                wk[((int64_t)cor * 9 + tap) * Cin + cic] = acc[tap][r];
+            }
 }
 
 __global__ void k_sum_chunks(const float *__restrict__ work, int nchunk, int64_t n, float *__restrict__ out)
@@ -158,15 +225,29 @@ __global__ void k_sum_chunks(const float *__restrict__ work, int nchunk, int64_t
     out[i] = s;
 }
 
-// db partials: block = pixel chunk, threads over channels
+// db partials: block = pixel chunk; the 256 threads form (256/C) pixel lanes x C channels
+// (C <= 256, a power of two up to the padding) so that every load row is coalesced; the
+// pixel lanes are then summed in a fixed-order LDS tree.
 __global__ __launch_bounds__(256) void k_bias_partial(const float *__restrict__ dz, int64_t P, int C, int64_t per_chunk,
                                                       float *__restrict__ work)
 {
+    __shared__ float red[256];
     const int64_t pb = (int64_t)blockIdx.x * per_chunk, pe = std::min<int64_t>(pb + per_chunk, P);
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    for (int c0 = 0; c0 < C; c0 += 256) {
+        const int cw = std::min(256, C - c0);           // channels in this pass
+        const int lanes = 256 / cw;                     // pixel lanes
+        const int c = threadIdx.x % cw, pl = threadIdx.x / cw;
         float s = 0.0f;
-        for (int64_t p = pb; p < pe; ++p) s += dz[p * C + c];
-        work[(int64_t)blockIdx.x * C + c] = s;
+        if (pl < lanes)
+            for (int64_t p = pb + pl; p < pe; p += lanes) s += dz[p * C + c0 + c];
+        red[threadIdx.x] = pl < lanes ? s : 0.0f;
+        __syncthreads();
+        if (threadIdx.x < cw) {
+            float t = 0.0f;
+            for (int l = 0; l < lanes; ++l) t += red[l * cw + threadIdx.x];
+            work[(int64_t)blockIdx.x * C + c0 + threadIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -416,9 +497,18 @@ fwi_status fwi_nn_conv3x3(const uint16_t *x, fwi_nn_shape in, const uint16_t *w,
         return nn_fail(FWI_E_ARG, "conv3x3: need input channels %% 16 == 0 and output channels %% 32 == 0");
     if (!out_f32 && !out_bf16) return nn_fail(FWI_E_ARG, "conv3x3: no output");
     const int64_t P = (int64_t)in.n * in.h * in.w;
-    dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
-    k_conv3x3<<<grid, 256, 0, (hipStream_t)stream>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32,
-                                                     out_bf16);
+    hipStream_t st = (hipStream_t)stream;
+    // 64 x 64 wavefront tiles where the output channels allow it and the grid stays large
+    if (cout % 64 == 0 && P >= 64 * 1024) {
+        dim3 grid((unsigned)((P + 127) / 128), (unsigned)((cout + 127) / 128));
+        k_conv3x3<2, 2><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, out_bf16);
+    } else if (P >= 64 * 1024) {
+        dim3 grid((unsigned)((P + 127) / 128), (unsigned)((cout + 63) / 64));
+        k_conv3x3<2, 1><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, out_bf16);
+    } else {
+        dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
+        k_conv3x3<1, 1><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, out_bf16);
+    }
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -439,7 +529,7 @@ fwi_status fwi_nn_wgrad(const uint16_t *dz, const float *dz_f32, const uint16_t 
     const int nch = wgrad_chunks(in, cout);
     const int64_t per = (P + nch - 1) / nch;
     const int nci = (in.c + 31) / 32;
-    dim3 grid((unsigned)((cout / 32) * nci * 9), (unsigned)nch);
+    dim3 grid((unsigned)((cout / 32) * nci), (unsigned)nch);
     k_wgrad<<<grid, 64, 0, st>>>(dz, x, in.n, in.h, in.w, in.c, cout, per, work);
     NN_TRY(hipGetLastError());
     const int64_t nw = (int64_t)cout * 9 * in.c;

@@ -56,7 +56,8 @@ def f64(t, N=None):
     return t.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("n,h,w,ci,co", [(2, 9, 13, 16, 32), (1, 16, 16, 32, 64), (3, 8, 6, 96, 96)])
+@pytest.mark.parametrize("n,h,w,ci,co", [(2, 9, 13, 16, 32), (1, 16, 16, 32, 64), (3, 8, 6, 96, 96),
+                                         (1, 256, 256, 32, 64), (2, 181, 183, 16, 96), (1, 256, 257, 64, 32)])
 def test_conv_fwd_dgrad_wgrad(N, n, h, w, ci, co):
     say("case conv %s" % ((n, h, w, ci, co),))
     r = np.random.default_rng(ci + co)
@@ -74,7 +75,8 @@ def test_conv_fwd_dgrad_wgrad(N, n, h, w, ci, co):
     assert rel(f64(out), ref) < 1e-5
     got16 = f64(o16)
     ref16 = U.bf16(U.silu(ref))
-    assert np.all(np.abs(got16 - ref16) <= 2.0 ** -7 * np.abs(ref16) + 1e-30)
+    # one BF16 ulp, plus the FP32 accumulation error where a pre-activation cancels to ~0
+    assert np.all(np.abs(got16 - ref16) <= 2.0 ** -7 * np.abs(ref16) + 1e-5 * np.sqrt(np.mean(ref ** 2)))
     # aux (SiLU' of a pre-activation) and residual on channel 0
     auxg = torch.tensor(aux, dtype=torch.float32, device="cuda")
     resg = torch.tensor(res, dtype=torch.float32, device="cuda")
