@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graphs", type=int, default=1, help="replay each gradient as a captured HIP graph")
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
+    ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
     ap.add_argument("--workload", default="2d", choices=["2d", "3d"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations")
@@ -155,7 +156,11 @@ def main():
         time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, free / 1e9, total / 1e9))
 
     tuned = None
-    if args.tune:
+    if args.tile:
+        fwi.fwi_set_tile(cfg.ndim, args.tile)
+        tuned = (args.tile, float("nan"))
+        log("tile height forced to %d" % args.tile)
+    elif args.tune:
         tuned = fwi.fwi_tune(batch0, time_ax, v, ws, os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
         log("tuner: tile height %d, %.3f ms per gradient time step" % tuned)
     stream = torch.cuda.Stream()  # graphs need a non-default stream
@@ -219,20 +224,28 @@ def main():
         1e3 * fwd_ms / max(fwd_n, 1), fwd_n, 1e3 * adj_ms / max(adj_n, 1), adj_n))
 
     # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
-    # adjoint + imaging step: lt^{k+1}, lt^{k+2} read, lt^k write, W^{k-1} read, FP64
-    # accumulator read+write = 32 B per simulation cell, plus c once per sample cell.
+    # adjoint + imaging step: lt^{k+1}, lt^{k+2} read, lt^k write, W^{k-1} read = 16 B per
+    # simulation cell; c read and the FP64 imaging accumulator read+written: 2D sums a
+    # sample's supergathers in one workgroup (4 + 16 B per sample cell), 3D keeps one
+    # accumulator per simulation (16 B per simulation cell, 4 B per sample cell).
     # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
     # 16 B per simulation cell (12 B when recomputing from checkpoints without a store),
     # plus c once per sample cell.
     # with checkpoints the forward sweeps (first pass: 12 B; recomputation: 16 B) average
     # to 14 B per simulation cell
     fwd_bytes = pad_cells * (16 if ckpt == 0 else 14) + samp_cells * 4
-    adj_bytes = pad_cells * 32 + samp_cells * 4
-    kname = "k_step2d" if cfg.ndim == 2 else "k_step3d"
-    if adj_ms >= fwd_ms:
-        name, nbytes, ms, n = "adjoint+imaging step (%s<bz,true>)" % kname, adj_bytes, adj_ms, adj_n
+    if cfg.ndim == 2:
+        adj_bytes = pad_cells * 16 + samp_cells * 20
+        adj_name = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)"
+        fwd_name = "forward step (k_step2d<bz>)"
     else:
-        name, nbytes, ms, n = "forward step (%s<bz,false>)" % kname, fwd_bytes, fwd_ms, fwd_n
+        adj_bytes = pad_cells * 32 + samp_cells * 4
+        adj_name = "adjoint+imaging step (k_step3d<bz,true>)"
+        fwd_name = "forward step (k_step3d<bz,false>)"
+    if adj_ms >= fwd_ms:
+        name, nbytes, ms, n = adj_name, adj_bytes, adj_ms, adj_n
+    else:
+        name, nbytes, ms, n = fwd_name, fwd_bytes, fwd_ms, fwd_n
     avg_s = ms / max(n, 1) / 1e3
     achieved = nbytes / avg_s / 1e9
     traffic = None

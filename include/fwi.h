@@ -205,12 +205,15 @@ fwi_status fwi_langevin(int32_t nsample, const int64_t *model_off, float *v, con
 fwi_status fwi_poll_status(void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Kernel timing for roofline measurement.  While enabled (process-wide), every time-step
- * kernel launch of fwi_forward / fwi_adjoint / fwi_gradient is bracketed by two HIP
- * events recorded on the launch's stream (launches captured into a replay graph are not
- * timed).  fwi_timing_read synchronizes the events and returns the accumulated kernel time
- * and launch count of one kind: 0 = forward or recomputation step, 1 = adjoint + imaging
- * step; reset != 0 zeroes that kind afterwards.
+ * Kernel timing for roofline measurement.  While enabled (process-wide), each run of
+ * consecutive time-step launches of one kind inside fwi_forward / fwi_adjoint /
+ * fwi_gradient (a forward sweep, or one checkpoint segment's recomputation or adjoint
+ * sweep) is bracketed by two HIP events recorded on the launch's stream, with no event
+ * between its launches; launches captured into a replay graph are not timed.
+ * fwi_timing_read synchronizes the events and returns the accumulated time and launch
+ * count of one kind: 0 = forward or recomputation step, 1 = adjoint + imaging step (time /
+ * count = average launch duration including the dispatch gaps of back-to-back launches);
+ * reset != 0 zeroes that kind afterwards.
  */
 fwi_status fwi_timing_enable(int32_t on);
 fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, int32_t reset);

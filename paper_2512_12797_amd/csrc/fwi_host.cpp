@@ -156,6 +156,7 @@ struct Plan {
     std::vector<SimDesc> sims;
     std::vector<SampleDesc> samples;
     std::vector<Tile> tiles;
+    std::vector<GTile> gtiles;  // 2D adjoint strips (per-sample imaging)
     std::vector<EvRow> evrows;
     std::vector<int32_t> evvec;
     std::vector<SrcPos> src;
@@ -165,12 +166,15 @@ struct Plan {
     int64_t max_cell = 0;    // largest padded sample grid
     int nt_rec = 0;
     int per_xcd = 0;
+    bool grouped = false;    // 2D: adjoint images per sample (accumulator slots = samples)
+    int bzg = 16, nw = 1, per_xcd_g = 0;
+    int64_t gcells = 0;      // imaging accumulator cells
     // layout
     int nlev = 2, K = 0, nseg = 1;
     bool fwd_only = false;  // ckpt_every == -1: no adjoint state is kept
     int64_t wst_levels = 0, ck_slots = 0;
     int nchunk_res = 1, nchunk_fin = 1;
-    size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_evrows = 0, t_evvec = 0, t_src = 0, t_bytes = 0;
+    size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_gtiles = 0, t_evrows = 0, t_evvec = 0, t_src = 0, t_bytes = 0;
     size_t t_alloc = 0;  // table region reserved in the workspace (largest over tile heights)
     size_t o_status = 0, o_tables = 0, o_cf = 0, o_fields = 0, o_wst = 0, o_ck = 0, o_gacc = 0, o_rho = 0,
            o_part = 0, o_npart = 0, o_mis = 0, total = 0;
@@ -277,6 +281,26 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
 
 size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz);
 
+// Wavefronts per workgroup of the per-sample 2D adjoint for samples of up to g sims and
+// ngt strips: the sims split as evenly as possible over the waves (busy fraction) while
+// the launch still gives about 24 waves per CU (fill); ties go to fewer waves.
+int grouped_waves(int g, int64_t ngt)
+{
+    if (g <= 1) return 1;
+    int best = 1;
+    double best_score = -1.0;
+    for (int w = std::min(4, g); w <= 16; ++w) {
+        const double busy = (double)g / (double)(((g + w - 1) / w) * w);
+        const double fill = std::min(1.0, (double)(ngt * w) / (256.0 * 24.0));
+        const double score = busy * fill;
+        if (score > best_score + 1e-12) {
+            best_score = score;
+            best = w;
+        }
+    }
+    return best;
+}
+
 fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p, int bz_override = 0,
                       bool size_for_all_tiles = true)
 {
@@ -342,6 +366,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         S.sample = k;
         stencil_weights(g, S.w, S.gmax, S.inv_vol);
         S.dt = t->dt;
+        S.tile0 = (int32_t)p.tiles.size();
         p.cells += Sm.ncell;
         p.data += (int64_t)p.nt_rec * S.nrec;
         // tiles: z block, then y block, then x strip
@@ -401,6 +426,37 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         i = j;
     }
     if (p.tiles.size() >= (size_t)1 << 30) return fail(FWI_E_UNSUPPORTED, "too many tiles");
+    // imaging accumulators: 2D adjoints sum a sample's sims in one workgroup (one slot per
+    // sample, laid out like the coefficients); 3D keeps one slot per sim
+    p.grouped = p.ndim == 2;
+    int gmax = 0;
+    for (auto &Sm : p.samples) {
+        if (Sm.sim_beg < 0) Sm.sim_beg = 0;
+        gmax = std::max(gmax, Sm.sim_cnt);
+        if (p.grouped) {
+            Sm.g_off = Sm.c_off;
+            Sm.g_cnt = 1;
+        } else {
+            Sm.g_off = Sm.sim_cnt > 0 ? p.sims[Sm.sim_beg].u_off : 0;
+            Sm.g_cnt = Sm.sim_cnt;
+        }
+    }
+    p.gcells = p.grouped ? p.coefs : p.cells;
+    if (p.grouped) {
+        p.bzg = p.bz == 8 ? 8 : 16;
+        for (int k = 0; k < b->nsample; ++k) {
+            const SampleDesc &Sm = p.samples[k];
+            const int ntx = (Sm.N[2] + kTileX - 1) / kTileX;
+            const int ntz = (Sm.N[0] + p.bzg - 1) / p.bzg;
+            for (int iz = 0; iz < ntz; ++iz)
+                for (int ix = 0; ix < ntx; ++ix) {
+                    const int z0 = iz * p.bzg;
+                    p.gtiles.push_back(GTile{k, ix * kTileX, z0, (z0 / p.bz) * ntx + ix});
+                }
+        }
+        p.nw = grouped_waves(gmax, (int64_t)p.gtiles.size());
+        p.per_xcd_g = (int)((p.gtiles.size() + 7) / 8);
+    }
     // 2D: a workgroup runs 4 tiles (one per wavefront); 3D: one tile per workgroup
     const size_t nwg = p.ndim == 2 ? (p.tiles.size() + 3) / 4 : p.tiles.size();
     p.per_xcd = (int)((nwg + 7) / 8);
@@ -412,6 +468,8 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     o = align_up(o + p.samples.size() * sizeof(SampleDesc));
     p.t_tiles = o;
     o = align_up(o + p.tiles.size() * sizeof(Tile));
+    p.t_gtiles = o;
+    o = align_up(o + std::max<size_t>(1, p.gtiles.size()) * sizeof(GTile));
     p.t_evrows = o;
     o = align_up(o + std::max<size_t>(1, p.evrows.size()) * sizeof(EvRow));
     p.t_evvec = o;
@@ -454,7 +512,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.o_ck = w;
     w = align_up(w + (size_t)p.ck_slots * p.cells * 4);
     p.o_gacc = w;
-    w = align_up(w + (p.fwd_only ? 0 : (size_t)p.cells * 8));
+    w = align_up(w + (p.fwd_only ? 0 : (size_t)p.gcells * 8));
     p.o_rho = w;
     w = align_up(w + (size_t)std::max<int64_t>(1, p.data) * 4);
     p.o_part = w;
@@ -502,6 +560,7 @@ fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
     memcpy(h + p.t_sims, p.sims.data(), p.sims.size() * sizeof(SimDesc));
     memcpy(h + p.t_samples, p.samples.data(), p.samples.size() * sizeof(SampleDesc));
     memcpy(h + p.t_tiles, p.tiles.data(), p.tiles.size() * sizeof(Tile));
+    if (!p.gtiles.empty()) memcpy(h + p.t_gtiles, p.gtiles.data(), p.gtiles.size() * sizeof(GTile));
     if (!p.evrows.empty()) memcpy(h + p.t_evrows, p.evrows.data(), p.evrows.size() * sizeof(EvRow));
     if (!p.evvec.empty()) memcpy(h + p.t_evvec, p.evvec.data(), p.evvec.size() * sizeof(int32_t));
     if (!p.src.empty()) memcpy(h + p.t_src, p.src.data(), p.src.size() * sizeof(SrcPos));
@@ -514,54 +573,79 @@ fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
 
 // ------------------------------------------------------------ kernel timing
 
-// When enabled, every time-step launch is bracketed by a pair of HIP events recorded on
-// the launch's stream; fwi_timing_read turns the pairs into per-kind totals.
+// When enabled, each run of consecutive time-step launches of one kind (a forward sweep, a
+// recomputation segment, an adjoint segment) is bracketed by one pair of HIP events recorded
+// on the launch's stream, so the per-launch average is the run's span over its launch count
+// (kernel time plus the dispatch gaps between back-to-back launches, with no event between
+// them); fwi_timing_read turns the pairs into per-kind totals.
 struct Timing {
     std::mutex m;
     bool on = false;
     std::vector<hipEvent_t> pool;
-    struct Pair {
+    struct Run {
         hipEvent_t a, b;
         int kind;
+        int64_t launches;
     };
-    std::vector<Pair> pending;
+    std::vector<Run> pending;
     double total_ms[2] = {0, 0};
     int64_t count[2] = {0, 0};
 };
 Timing g_timing;
 
-// event pairs recorded while this thread captures a graph (owned by that graph)
-thread_local std::vector<Timing::Pair> t_capture_pairs;
-
-hipError_t timed_step(const StepArgs &a, const Plan &p, bool adjoint, hipStream_t st)
+hipError_t pooled_event(hipEvent_t *ev)
 {
-    {
-        std::lock_guard<std::mutex> lk(g_timing.m);
-        if (!g_timing.on) return launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
-    }
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(st, &cs);
-    if (e != hipSuccess) return e;
-    // captured launches are not timed (the runtime gives no elapsed time for events
-    // recorded by graph replays)
-    if (cs == hipStreamCaptureStatusActive) return launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
-    std::lock_guard<std::mutex> lk(g_timing.m);
-    hipEvent_t ev[2];
-    for (int i = 0; i < 2; ++i) {
-        if (g_timing.pool.empty()) {
-            e = hipEventCreate(&ev[i]);
-            if (e != hipSuccess) return e;
-        } else {
-            ev[i] = g_timing.pool.back();
-            g_timing.pool.pop_back();
-        }
-    }
-    e = hipEventRecord(ev[0], st);
-    if (e == hipSuccess) e = launch_step(a, p.ndim, adjoint, p.bz, p.ty, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-    g_timing.pending.push_back({ev[0], ev[1], adjoint ? 1 : 0});
-    return e;
+    if (g_timing.pool.empty()) return hipEventCreate(ev);
+    *ev = g_timing.pool.back();
+    g_timing.pool.pop_back();
+    return hipSuccess;
 }
+
+// One timed run of launches; inactive when timing is off or the stream is being captured
+// (the runtime gives no elapsed time for events recorded by graph replays).
+struct RunTimer {
+    hipEvent_t a = nullptr;
+    int kind = 0;
+    hipStream_t st = nullptr;
+
+    hipError_t begin(int k, hipStream_t s)
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_timing.m);
+            if (!g_timing.on) return hipSuccess;
+        }
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess || cs == hipStreamCaptureStatusActive) return e;
+        std::lock_guard<std::mutex> lk(g_timing.m);
+        e = pooled_event(&a);
+        if (e != hipSuccess) return e;
+        kind = k;
+        st = s;
+        e = hipEventRecord(a, st);
+        if (e != hipSuccess) {
+            g_timing.pool.push_back(a);
+            a = nullptr;
+        }
+        return e;
+    }
+    hipError_t end(int64_t launches)
+    {
+        if (!a) return hipSuccess;
+        std::lock_guard<std::mutex> lk(g_timing.m);
+        hipEvent_t b;
+        hipError_t e = pooled_event(&b);
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        if (e != hipSuccess) {
+            g_timing.pool.push_back(a);
+            a = nullptr;
+            return e;
+        }
+        g_timing.pending.push_back({a, b, kind, launches});
+        a = nullptr;
+        return hipSuccess;
+    }
+};
 
 // ------------------------------------------------------------------ graphs
 
@@ -578,8 +662,6 @@ struct GraphCache {
         uint64_t key;
         hipGraphExec_t exec;
         uint64_t used;
-        std::vector<Timing::Pair> pairs;  // timing events inside the graph
-        bool timed_pending;               // replayed since the last fwi_timing_read
     };
     std::vector<Entry> entries;
     uint64_t tick = 0;
@@ -610,9 +692,12 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
     k.add(p.ndim); k.add(p.bz); k.add(p.ty); k.add(p.per_xcd); k.add(p.cells); k.add(p.coefs); k.add(p.data);
     k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
     k.add(p.nchunk_res); k.add(p.nchunk_fin);
+    k.add(p.grouped); k.add(p.bzg); k.add(p.nw); k.add(p.per_xcd_g); k.add(p.gcells);
+    const size_t ngt = p.gtiles.size();
+    k.add(ngt);
     const size_t nt = p.tiles.size();
     k.add(nt);
-    const size_t offs[] = {p.t_sims, p.t_samples, p.t_tiles, p.t_evrows, p.t_evvec, p.t_src, p.t_bytes,
+    const size_t offs[] = {p.t_sims, p.t_samples, p.t_tiles, p.t_gtiles, p.t_evrows, p.t_evvec, p.t_src, p.t_bytes,
                            p.o_status, p.o_tables, p.o_cf, p.o_fields, p.o_wst, p.o_ck, p.o_gacc, p.o_rho,
                            p.o_part, p.o_npart, p.o_mis, p.total};
     k.bytes(offs, sizeof offs);
@@ -621,15 +706,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
     k.bytes(b->wavelet, sizeof(float) * t->nt);
 }
 
-void destroy_entry(GraphCache::Entry &e)
-{
-    (void)hipGraphExecDestroy(e.exec);
-    for (auto &pr : e.pairs) {
-        (void)hipEventDestroy(pr.a);
-        (void)hipEventDestroy(pr.b);
-    }
-    e.pairs.clear();
-}
+void destroy_entry(GraphCache::Entry &e) { (void)hipGraphExecDestroy(e.exec); }
 
 template <class Body>
 fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
@@ -646,29 +723,21 @@ fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
             e.used = ++g_graphs.tick;
             g_graphs.replays++;
             HIP_TRY(hipGraphLaunch(e.exec, st));
-            e.timed_pending = !e.pairs.empty();
             return FWI_OK;
         }
-    t_capture_pairs.clear();
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     fwi_status s = body(st);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(st, &graph);
-    GraphCache::Entry ent{key, nullptr, 0, std::move(t_capture_pairs), false};
-    t_capture_pairs.clear();
+    GraphCache::Entry ent{key, nullptr, 0};
     if (s || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
-        destroy_entry(ent);
         return s ? s : fail(FWI_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     }
     e = hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
         ent.exec = nullptr;
-        for (auto &pr : ent.pairs) {
-            (void)hipEventDestroy(pr.a);
-            (void)hipEventDestroy(pr.b);
-        }
         return fail(FWI_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     if (g_graphs.entries.size() >= kMaxGraphs) {
@@ -678,7 +747,6 @@ fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
         g_graphs.entries.erase(old);
     }
     ent.used = ++g_graphs.tick;
-    ent.timed_pending = !ent.pairs.empty();
     g_graphs.entries.push_back(std::move(ent));
     g_graphs.captures++;
     HIP_TRY(hipGraphLaunch(g_graphs.entries.back().exec, st));
@@ -693,6 +761,7 @@ struct Dev {
     const SimDesc *sims;
     const SampleDesc *samples;
     const Tile *tiles;
+    const GTile *gtiles;
     const EvRow *evrows;
     const int32_t *evvec;
     const SrcPos *src;
@@ -716,6 +785,7 @@ Dev carve(const Plan &p, void *ws)
     d.sims = (const SimDesc *)(tb + p.t_sims);
     d.samples = (const SampleDesc *)(tb + p.t_samples);
     d.tiles = (const Tile *)(tb + p.t_tiles);
+    d.gtiles = (const GTile *)(tb + p.t_gtiles);
     d.evrows = (const EvRow *)(tb + p.t_evrows);
     d.evvec = (const int32_t *)(tb + p.t_evvec);
     d.src = (const SrcPos *)(tb + p.t_src);
@@ -744,6 +814,12 @@ StepArgs base_args(const Plan &p, const Dev &d)
     a.ntiles = (int32_t)p.tiles.size();
     a.per_xcd = p.per_xcd;
     a.rec_j = -1;
+    a.samples = d.samples;
+    a.gtiles = d.gtiles;
+    a.ngtiles = (int32_t)p.gtiles.size();
+    a.per_xcd_g = p.per_xcd_g;
+    a.nw = p.nw;
+    a.bzg = p.bzg;
     return a;
 }
 
@@ -772,6 +848,8 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
     StepArgs a = base_args(p, d);
     a.dat = dat;
     float *cur = d.lev[0], *prev = d.lev[1];
+    RunTimer tm;
+    HIP_TRY(tm.begin(0, st));
     for (int n = 0; n < t->nt; ++n) {
         a.cur = cur;
         a.prev = prev;
@@ -785,9 +863,10 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
             a.cka = d.ck + (size_t)(2 * (slot - 1)) * p.cells;
             a.ckb = d.ck + (size_t)(2 * (slot - 1) + 1) * p.cells;
         }
-        HIP_TRY(timed_step(a, p, false, st));
+        HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.ty, st));
         std::swap(cur, prev);
     }
+    HIP_TRY(tm.end(t->nt));
     return FWI_OK;
 }
 
@@ -795,7 +874,7 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
 fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fwi_time *t, const float *v,
                        const float *rho, float *grad, float *grad_norm, hipStream_t st)
 {
-    HIP_TRY(launch_fill_f64(d.gacc, p.cells, 0.0, st));
+    HIP_TRY(launch_fill_f64(d.gacc, p.gcells, 0.0, st));
     float *L0 = p.K == 0 ? d.lev[0] : d.lev[2];
     float *L1 = p.K == 0 ? d.lev[1] : d.lev[3];
     HIP_TRY(launch_fill_f32(L0, p.cells, 0.0f, st));
@@ -810,15 +889,18 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         a.next = lprev;
         a.wimg = wimg;
         a.rec_j = k % t->rec_every == 0 ? k / t->rec_every - 1 : -1;
-        HIP_TRY(timed_step(a, p, true, st));
+        HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.ty, st));
         std::swap(lcur, lprev);
         return FWI_OK;
     };
+    RunTimer tm;
     if (p.K == 0) {
+        HIP_TRY(tm.begin(1, st));
         for (int k = t->nt; k >= 1; --k) {
             fwi_status s = adj_step(k, d.wst + (size_t)(k - 1) * p.cells);
             if (s) return s;
         }
+        HIP_TRY(tm.end(t->nt));
     } else {
         float *P0 = d.lev[0], *P1 = d.lev[1];
         StepArgs f = base_args(p, d);
@@ -833,6 +915,7 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
                 cur = d.ck + (size_t)(2 * (sg - 1)) * p.cells;
                 prev = d.ck + (size_t)(2 * (sg - 1) + 1) * p.cells;
             }
+            HIP_TRY(tm.begin(0, st));
             for (int n = ns; n < ne; ++n) {
                 float *next;
                 if (prev == P0 || prev == P1)
@@ -844,14 +927,17 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
                 f.next = next;
                 f.fn = b->wavelet[n];
                 f.wst = d.wst + (size_t)(n - ns) * p.cells;
-                HIP_TRY(timed_step(f, p, false, st));
+                HIP_TRY(launch_step(f, p.ndim, false, p.bz, p.ty, st));
                 prev = cur;
                 cur = next;
             }
+            HIP_TRY(tm.end(ne - ns));
+            HIP_TRY(tm.begin(1, st));
             for (int k = ne; k >= ns + 1; --k) {
                 fwi_status s = adj_step(k, d.wst + (size_t)(k - 1 - ns) * p.cells);
                 if (s) return s;
             }
+            HIP_TRY(tm.end(ne - ns));
         }
     }
     HIP_TRY(launch_finalize(d.samples, d.sims, b->nsample, d.gacc, v, grad, d.npart, p.nchunk_fin, d.status, st));
@@ -1063,32 +1149,15 @@ fwi_status fwi_timing_enable(int32_t on)
 fwi_status fwi_timing_read(int32_t kind, double *total_ms, int64_t *launches, int32_t reset)
 {
     if (kind < 0 || kind > 1 || !total_ms || !launches) return fail(FWI_E_ARG, "bad kind or null output");
-    // graphs replayed since the last read: durations of their latest replay
-    std::vector<Timing::Pair> from_graphs;
-    {
-        std::lock_guard<std::mutex> lk(g_graphs.m);
-        for (auto &e : g_graphs.entries)
-            if (e.timed_pending) {
-                from_graphs.insert(from_graphs.end(), e.pairs.begin(), e.pairs.end());
-                e.timed_pending = false;
-            }
-    }
     std::lock_guard<std::mutex> lk(g_timing.m);
-    for (auto &pr : from_graphs) {
+    for (auto &r : g_timing.pending) {
         float ms = 0.0f;
-        HIP_TRY(hipEventSynchronize(pr.b));
-        HIP_TRY(hipEventElapsedTime(&ms, pr.a, pr.b));
-        g_timing.total_ms[pr.kind] += ms;
-        g_timing.count[pr.kind] += 1;
-    }
-    for (auto &pr : g_timing.pending) {
-        float ms = 0.0f;
-        HIP_TRY(hipEventSynchronize(pr.b));
-        HIP_TRY(hipEventElapsedTime(&ms, pr.a, pr.b));
-        g_timing.total_ms[pr.kind] += ms;
-        g_timing.count[pr.kind] += 1;
-        g_timing.pool.push_back(pr.a);
-        g_timing.pool.push_back(pr.b);
+        HIP_TRY(hipEventSynchronize(r.b));
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        g_timing.total_ms[r.kind] += ms;
+        g_timing.count[r.kind] += r.launches;
+        g_timing.pool.push_back(r.a);
+        g_timing.pool.push_back(r.b);
     }
     g_timing.pending.clear();
     *total_ms = g_timing.total_ms[kind];
@@ -1195,7 +1264,7 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
         if (s) return s;
         HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, st));
         HIP_TRY(launch_fill_f32(d.lev[0], 2 * p.cells, 0.0f, st));
-        if (!p.fwd_only) HIP_TRY(launch_fill_f64(d.gacc, p.cells, 0.0, st));
+        if (!p.fwd_only) HIP_TRY(launch_fill_f64(d.gacc, p.gcells, 0.0, st));
         StepArgs a = base_args(p, d);
         a.fn = 0.0f;
         a.wst = p.fwd_only ? nullptr : d.wst;

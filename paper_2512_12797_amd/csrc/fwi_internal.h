@@ -28,7 +28,7 @@ struct SimDesc {
     int32_t ndim;
     float w[3][5];      // stencil weights C_k / h_a^2, axes (z, y, x); zero for an unused axis
     float inv_vol;      // 1 / prod h
-    float pad0;
+    int32_t tile0;      // index of this sim's first tile
     double gmax[3];     // sponge gmax per axis (z, y, x); zero for an unused axis
     double dt;
 };
@@ -48,6 +48,9 @@ struct SampleDesc {
     double kappa;
     int64_t nphys;      // physical cells
     int64_t ncell;      // padded cells
+    int64_t g_off;      // element offset of its first imaging accumulator slot
+    int32_t g_cnt;      // accumulator slots (padded grids of ncell cells, consecutive)
+    int32_t pad0;
 };
 
 struct Tile {
@@ -56,6 +59,15 @@ struct Tile {
     int32_t ev_beg;     // first receiver event row of this tile
     int32_t ev_cnt;     // number of event rows
     int32_t pad0, pad1;
+};
+
+// Tile of the 2D adjoint with per-sample imaging: one 64 x bzg strip of a sample's grid,
+// swept for every sim of the sample.  tix is the index, within each sim's tile list, of
+// the sim tile that contains the strip (for its receiver event rows).
+struct GTile {
+    int32_t sample;
+    int32_t x0, z0;
+    int32_t tix;
 };
 
 // One row (2D: a grid row; 3D: an xy plane) of a tile that holds receivers.  vec_off
@@ -86,11 +98,18 @@ struct StepArgs {
     float *cka, *ckb;       // checkpoint slots for u^{n+1}, u^n (nullable)
     float *dat;             // forward: recorded data (nullable)
     const float *rho;       // adjoint: residual
-    double *gacc;           // adjoint: per-sim imaging accumulator
+    double *gacc;           // adjoint: imaging accumulator (per sample in 2D, per sim in 3D)
     int32_t ntiles;
     int32_t per_xcd;        // tiles per XCD chunk (grid = 8 * per_xcd)
     int32_t rec_j;          // recording slot j, or -1
     float fn;               // wavelet sample f[n] (forward)
+    // 2D adjoint with per-sample imaging
+    const SampleDesc *samples;
+    const GTile *gtiles;
+    int32_t ngtiles;
+    int32_t per_xcd_g;      // grouped tiles per XCD chunk
+    int32_t nw;             // wavefronts per grouped workgroup (1..16)
+    int32_t bzg;            // rows per grouped tile (8 or 16)
 };
 
 }  // namespace fwi

@@ -12,7 +12,7 @@
 // FP64 and rounded once, and c precomputed per sample in FP64 and rounded once.
 // The scaled adjoint lt = c lambda obeys the same recursion backward in time with
 // c-weighted receiver injection; the imaging term lt^k (L u^{k-1} + q^{k-1}) is summed
-// in FP64 per sim.
+// in FP64, per sample in 2D (all of a sample's sims in one workgroup) and per sim in 3D.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -32,6 +32,7 @@ __device__ __forceinline__ double sponge_axis(int p, int n, int nb, double gmax)
 #pragma clang fp contract(off)
     if (nb == 0) return 0.0;
     int d = p < nb ? nb - p : (p > nb + n - 1 ? p - (nb + n - 1) : 0);
+    if (d == 0) return 0.0;  // interior (same value as the formula, without the division)
     double r = (double)d / (double)nb;
     return gmax * r * r;
 }
@@ -372,6 +373,207 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
             wq[PF - 1] = wn;
             gq[PF - 1] = gn;
         }
+    }
+}
+
+// ------------------------------------------------------ 2D adjoint, per-sample imaging
+
+// 2D adjoint + imaging step with the imaging sum taken per sample.  A workgroup of nw
+// wavefronts owns one 64 x BZ strip of one sample's grid; wave w sweeps the strip for the
+// sample's sims w, w + nw, ... with the same register queues as the per-sim step and adds
+// the exact FP64 products lt^k W^{k-1} of each row into registers.  The waves' partial
+// sums are then added in wave order through LDS and wave 0 applies one read-modify-write
+// to the sample's FP64 accumulator, so the accumulator costs 16 B per sample cell and step
+// instead of 16 B per sim cell.  The summation order depends only on nw, which makes the
+// result independent of the tile heights.
+//
+// The row loop is fully unrolled: the queues then shift by register renaming, so loads
+// stay in flight across rows instead of being waited for by the shift.  Rows of a strip
+// that fall below the grid are swept too: their loads read 0, their stores fall outside
+// the buffer and are dropped, and their partial sums are never written.
+template <int BZ>
+__global__ __launch_bounds__(1024) void k_adj2d(const StepArgs A)
+{
+    constexpr int PF = 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+    const int lane = threadIdx.x & 63;
+    const int gt = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd_g));
+    if (gt >= A.ngtiles) return;  // uniform per block: nobody reaches the barriers below
+    // descriptors are read before the first store so that they stay in scalar registers
+    const int nw = A.nw;
+    const GTile G = A.gtiles[gt];
+    const SampleDesc &Sm = A.samples[G.sample];
+    const int Nx = Sm.N[2], Nz = Sm.N[0];
+    const int nz_phys = Sm.n[0], nx_phys = Sm.n[2], nb = Sm.nb;
+    const double gmz = Sm.gmax[0], gmx = Sm.gmax[2];
+    const double dt = Sm.dt;
+    const int sim_beg = Sm.sim_beg, sim_cnt = Sm.sim_cnt;
+    const int64_t ncell = Sm.ncell, g_off = Sm.g_off;
+    const SimDesc &S0 = A.sims[sim_beg];
+    const int64_t u_off0 = S0.u_off;  // sims of a sample are consecutive, ncell apart
+    float wz[5], wx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        wz[k] = S0.w[0][k];
+        wx[k] = S0.w[2][k];
+    }
+    const uint32_t fbytes = (uint32_t)Nz * (uint32_t)Nx * 4u;
+    const int x = G.x0 + lane;
+    const bool xin = x < Nx;
+    const int z0 = G.z0;
+    const int nrow = min(BZ, Nz - z0);
+    const rsrc_t rC = make_rsrc(A.cf + Sm.c_off, fbytes);
+    const int rec_j = A.rec_j;
+    const EvRow *__restrict__ evrows = A.evrows;
+    const int32_t *__restrict__ evvec = A.evvec;
+    const double gx = sponge_axis(x, nx_phys, nb, gmx);
+
+    const uint32_t xo = 4u * (uint32_t)min(x, Nx - 1);
+    const int hx = lane < 4 ? G.x0 - kHalo + lane : G.x0 + kTileX - 4 + lane;
+    const bool hl = lane < 8 && hx >= 0 && hx < Nx;
+    const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
+    const uint32_t rowb = 4u * (uint32_t)Nx;
+    auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
+
+    __shared__ float rows[16][2][kTileX + 2 * kHalo];
+    __shared__ double red[BZ][kTileX];
+    __shared__ float2 abt[BZ][kTileX];  // leapfrog a, b of the strip's cells (shared by all sims)
+
+    // a and b depend on the cell only: computed once per strip, not once per sim
+    for (int r = wave; r < BZ; r += nw) {
+        double gam = 0.0;
+        gam = gam + sponge_axis(z0 + r, nz_phys, nb, gmz);
+        gam = gam + gx;
+        float a, b;
+        sponge_ab(gam, dt, a, b);
+        abt[r][lane] = make_float2(a, b);
+    }
+    __syncthreads();
+
+    double acc[BZ];
+#pragma unroll
+    for (int r = 0; r < BZ; ++r) acc[r] = 0.0;
+
+    for (int j = wave; j < sim_cnt; j += nw) {
+        const int sim = sim_beg + j;
+        const int64_t u_off = u_off0 + (int64_t)j * ncell;
+        const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
+        const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
+        const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
+        const rsrc_t rW = make_rsrc(A.wimg + u_off, fbytes);
+        // lane offsets pass through an empty asm so that the row offsets built from them
+        // are recomputed per sim next to their loads, not hoisted out of the sim loop
+        // (which would keep every row's offsets live in registers)
+        uint32_t xs = xo, hs = ho;  // clamped into the row
+        int zs = z0;                // and the strip origin (uniform): same for the row offsets
+        asm volatile("" : "+v"(xs), "+v"(hs), "+s"(zs));
+        // wavefield reads and the store: lanes past the x edge (or not halo lanes) take
+        // the out-of-range offset as a whole; point operands read the clamped column
+        auto coff = [&](int zz) -> uint32_t { return xin ? roff(zz) + xs : kOOB; };
+        auto hoff = [&](int zz) -> uint32_t { return hl ? roff(zz) + hs : kOOB; };
+        // per-sim fields read after stores: vector loads, made uniform explicitly
+        const int tile0 = __builtin_amdgcn_readfirstlane(A.sims[sim].tile0);
+        const int nrec = __builtin_amdgcn_readfirstlane(A.sims[sim].nrec);
+        const int64_t d_off = A.sims[sim].d_off;
+        const int d_lo = __builtin_amdgcn_readfirstlane((int)(d_off & 0xFFFFFFFF));
+        const int d_hi = __builtin_amdgcn_readfirstlane((int)(d_off >> 32));
+        const int64_t d_off_u = (int64_t)(((uint64_t)(uint32_t)d_hi << 32) | (uint32_t)d_lo);
+
+        // centre queue rows z-4 .. z+8, halo and point operands 4 rows ahead
+        float q[BZ + 12], hq[BZ + PF], cq[BZ + PF], pq[BZ + PF], wq[BZ + PF];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = bload(rU, coff(zs - kHalo + k));
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const uint32_t o = roff(zs + k);
+            hq[k] = bload(rU, hoff(zs + k));
+            cq[k] = bload(rC, o + xs);
+            pq[k] = bload(rP, o + xs);
+            wq[k] = bload(rW, o + xs);
+        }
+        const float *Rho = rec_j >= 0 ? A.rho + d_off_u + (int64_t)rec_j * nrec : nullptr;
+        // receiver event rows of the sim tile that holds this strip, from row z0 on
+        int ev = 0, ev_end = 0, ev_z = -1, ev_off = 0;
+        if (rec_j >= 0) {
+            const Tile &T = A.tiles[tile0 + G.tix];
+            ev = __builtin_amdgcn_readfirstlane(T.ev_beg);
+            ev_end = ev + __builtin_amdgcn_readfirstlane(T.ev_cnt);
+            while (ev < ev_end) {
+                ev_z = __builtin_amdgcn_readfirstlane(evrows[ev].z);
+                if (ev_z >= z0) break;
+                ++ev;
+            }
+            if (ev < ev_end)
+                ev_off = __builtin_amdgcn_readfirstlane(evrows[ev].vec_off);
+            else
+                ev_z = -1;
+        }
+
+#pragma unroll
+        for (int r = 0; r < BZ; ++r) {
+            const int z = zs + r;
+            q[r + 12] = bload(rU, coff(z + 8));
+            const uint32_t of = roff(z + PF);
+            hq[r + PF] = bload(rU, hoff(z + PF));
+            cq[r + PF] = bload(rC, of + xs);
+            pq[r + PF] = bload(rP, of + xs);
+            wq[r + PF] = bload(rW, of + xs);
+
+            float *row = rows[wave][r & 1];
+            row[lane + kHalo] = q[r + 4];
+            if (lane < 4)
+                row[lane] = hq[r];
+            else if (lane < 8)
+                row[kTileX + lane] = hq[r];
+            wave_lds_sync();
+            float lx = wx[0] * q[r + 4];
+            lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+            lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+            lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+            lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+            float lz = wz[0] * q[r + 4];
+            lz += wz[1] * (q[r + 3] + q[r + 5]);
+            lz += wz[2] * (q[r + 2] + q[r + 6]);
+            lz += wz[3] * (q[r + 1] + q[r + 7]);
+            lz += wz[4] * (q[r + 0] + q[r + 8]);
+            float wv = lz + lx;
+
+            const float2 ab = abt[r][lane];
+            if (z == ev_z) {  // uniform
+                const int rid = evvec[ev_off + lane];
+                if (rid >= 0) wv += Rho[rid];
+                ++ev;
+                ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+                ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
+            }
+            const float un = ab.x * q[r + 4] - ab.y * pq[r] + cq[r] * wv;
+            bstore(rN, coff(z), un);
+            acc[r] += (double)un * (double)wq[r];  // the product of two floats is exact in FP64
+            // keep each row's loads in its own row: the prefetch distance stays PF rows
+            // instead of the scheduler hoisting every load of the strip to the top
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    // partial sums of waves 1 .. nw-1 are added to wave 0's, in wave order
+    for (int w = 1; w < nw; ++w) {
+        __syncthreads();
+        if (wave == w)
+#pragma unroll
+            for (int r = 0; r < BZ; ++r) red[r][lane] = acc[r];
+        __syncthreads();
+        if (wave == 0)
+#pragma unroll
+            for (int r = 0; r < BZ; ++r) acc[r] += red[r][lane];
+    }
+    if (wave == 0) {
+        const rsrc_t rG = make_rsrc(A.gacc + g_off, 2 * fbytes);
+        double g[BZ];
+#pragma unroll
+        for (int r = 0; r < BZ; ++r) g[r] = bload64(rG, (xin && r < nrow) ? 2 * (roff(z0 + r) + xo) : kOOB);
+#pragma unroll
+        for (int r = 0; r < BZ; ++r)
+            bstore64(rG, (xin && r < nrow) ? 2 * (roff(z0 + r) + xo) : kOOB, g[r] + acc[r]);
     }
 }
 
@@ -722,8 +924,8 @@ __global__ __launch_bounds__(256) void k_finalize(const SampleDesc *__restrict__
         const int yl = iy == 0 ? 0 : iy + nby, yh = iy == ny - 1 ? Ny - 1 : iy + nby;
         const int zl = iz == 0 ? 0 : iz + S.nb, zh = iz == nz - 1 ? S.N[0] - 1 : iz + S.nb;
         double sum = 0.0;
-        for (int s = 0; s < S.sim_cnt; ++s) {
-            const double *g = gacc + sims[S.sim_beg + s].u_off;
+        for (int s = 0; s < S.g_cnt; ++s) {
+            const double *g = gacc + S.g_off + (int64_t)s * S.ncell;
             for (int pz = zl; pz <= zh; ++pz)
                 for (int py = yl; py <= yh; ++py) {
                     const int64_t base = ((int64_t)pz * Ny + py) * Nx;
@@ -917,10 +1119,22 @@ static hipError_t step3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t
     return hipGetLastError();
 }
 
+static hipError_t adj2d_dispatch(const StepArgs &a, hipStream_t st)
+{
+    if (a.nw < 1 || a.nw > 16) return hipErrorInvalidValue;
+    dim3 grid(8 * a.per_xcd_g);
+    switch (a.bzg) {
+    case 8: k_adj2d<8><<<grid, 64 * a.nw, 0, st>>>(a); break;
+    case 16: k_adj2d<16><<<grid, 64 * a.nw, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty, hipStream_t st)
 {
     if (a.ntiles <= 0) return hipSuccess;
-    if (ndim == 2) return adjoint ? step2d_dispatch<true>(a, bz, st) : step2d_dispatch<false>(a, bz, st);
+    if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : step2d_dispatch<false>(a, bz, st);
     return adjoint ? step3d_dispatch<true>(a, bz, ty, st) : step3d_dispatch<false>(a, bz, ty, st);
 }
 
