@@ -193,7 +193,7 @@ void stencil_weights(const fwi_grid &g, float w[3][5], double gmax[3], float &in
 }
 
 // Tile heights the kernels are instantiated for (rows per 2D tile, planes per 3D tile).
-const int kBz2[] = {8, 16, 32, 64};
+const int kBz2[] = {8, 16, 32};
 const int kBz3[] = {16, 32, 64};
 
 // Process-wide tile choices: forced per dimensionality (fwi_set_tile) or tuned per batch
@@ -228,7 +228,7 @@ std::string shape_signature(const fwi_batch *b)
 
 bool valid_bz(int ndim, int bz)
 {
-    if (ndim == 2) return bz == 8 || bz == 16 || bz == 32 || bz == 64;
+    if (ndim == 2) return bz == 8 || bz == 16 || bz == 32;
     return bz == 16 || bz == 32 || bz == 64;
 }
 
@@ -264,7 +264,7 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
     };
     if (p.ndim == 2) {
         p.bz = 8;
-        for (int c : {64, 32, 16, 8})
+        for (int c : {32, 16, 8})
             if (count(c) >= 1024) {
                 p.bz = c;
                 break;

@@ -126,24 +126,6 @@ __device__ __forceinline__ LaneSrc scan_sources_2d(const SrcPos *__restrict__ sr
     return r;
 }
 
-// Laplacian of the centre row held in `row` (x neighbours, offset 4) and queue q (z).
-template <int NQ>
-__device__ __forceinline__ float lap2d(const float *row, int lane, const float (&q)[NQ], const float (&wz)[5],
-                                       const float (&wx)[5])
-{
-    float lx = wx[0] * q[4];
-    lx += wx[1] * (row[lane + 3] + row[lane + 5]);
-    lx += wx[2] * (row[lane + 2] + row[lane + 6]);
-    lx += wx[3] * (row[lane + 1] + row[lane + 7]);
-    lx += wx[4] * (row[lane + 0] + row[lane + 8]);
-    float lz = wz[0] * q[4];
-    lz += wz[1] * (q[3] + q[5]);
-    lz += wz[2] * (q[2] + q[6]);
-    lz += wz[3] * (q[1] + q[7]);
-    lz += wz[4] * (q[0] + q[8]);
-    return lz + lx;
-}
-
 // Wave-scope ordering of LDS traffic: a wavefront executes in order, so making the
 // compiler keep program order is all that is needed between a wave's own LDS write and
 // its reads of neighbouring lanes.
@@ -184,19 +166,22 @@ __device__ __forceinline__ void bstore64(rsrc_t r, uint32_t off, double v)
                                           (int)off, 0, 0);
 }
 
-// 2D step.  A workgroup holds 4 independent wavefronts; each owns one 64 x BZ tile and
-// streams it along z.  Every global load for row z+4 is issued while row z is computed
-// (centre queue q, halo queue hq, and 4-deep queues of the point operands), so the
-// memory latency of a row overlaps four rows of work.  Loads are unconditional buffer
-// loads (rows outside the grid read 0); lanes beyond the grid's x extent keep 0.
-template <int BZ, bool ADJ>
-__global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
+// 2D forward step.  A workgroup holds 4 independent wavefronts; each owns one 64 x BZ tile
+// of one sim and streams it along z.  Every global load for row z+4 is issued while row z
+// is computed (centre queue q 8 rows ahead, halo queue hq and the point operands 4 rows
+// ahead), so the memory latency of a row overlaps four rows of work.  The row loop is
+// fully unrolled: the queues shift by register renaming, so loads stay in flight across
+// rows instead of being waited for by a shift.  Loads are unconditional buffer loads (rows
+// outside the grid read 0, stores there are dropped, so a tile that overhangs the bottom
+// of the grid needs no row guard); lanes beyond the grid's x extent keep 0.
+template <int BZ>
+__global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
 {
     constexpr int PF = 4;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    // the tile index is uniform per wavefront: say so, so that tile and simulation
-    // descriptors are fetched with scalar loads once, outside the row loop
+    // the tile index is uniform per wavefront: tile and simulation descriptors are
+    // fetched with scalar loads once, before the first store
     const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd) * 4 + wave);
     if (t >= A.ntiles) return;  // waves are independent: no workgroup barrier below
     const Tile T = A.tiles[t];
@@ -215,16 +200,13 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
     const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
     const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
     const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
-    const rsrc_t rW = make_rsrc(ADJ ? A.wimg + u_off : (A.wst ? A.wst + u_off : A.next), ADJ || A.wst ? fbytes : 0);
-    const rsrc_t rG = make_rsrc(ADJ ? (const void *)(A.gacc + u_off) : (const void *)A.next, ADJ ? 2 * fbytes : 0);
+    const rsrc_t rW = make_rsrc(A.wst ? A.wst + u_off : A.next, A.wst ? fbytes : 0);
     const rsrc_t rKa = make_rsrc(A.cka ? A.cka + u_off : A.next, A.cka ? fbytes : 0);
     const rsrc_t rKb = make_rsrc(A.ckb ? A.ckb + u_off : A.next, A.ckb ? fbytes : 0);
     const int rec_j = A.rec_j;
-    float *Dat = (!ADJ && A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
-    const float *Rho = (ADJ && rec_j >= 0) ? A.rho + d_off + (int64_t)rec_j * nrec : nullptr;
+    float *Dat = (A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
     const EvRow *__restrict__ evrows = A.evrows;
     const int32_t *__restrict__ evvec = A.evvec;
-
     float wz[5], wx[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -235,15 +217,9 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
 
     const double gx = sponge_axis(x, nx_phys, nb, gmx);
     const double dt = S.dt;
-
-    LaneSrc src{-1, 0.0f, false};
-    bool multi = false;
-    float famp = 0.0f;
-    if (!ADJ) {
-        src = scan_sources_2d(A.src, src_beg, src_cnt, x, z0, z1);
-        multi = __any(src.multi);
-        famp = A.fn * S.inv_vol;
-    }
+    const LaneSrc src = scan_sources_2d(A.src, src_beg, src_cnt, x, z0, z1);
+    const bool multi = __any(src.multi);
+    const float famp = A.fn * S.inv_vol;
 
     // byte offsets: lane column (clamped into the row for lanes past the edge, whose
     // values are then forced to 0), halo column for lanes 0..7
@@ -253,14 +229,13 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
     const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
     const uint32_t rowb = 4u * (uint32_t)Nx;
     auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
-    // wavefield reads: lanes past the x edge (or not halo lanes) use an out-of-range offset
-    // so that the hardware returns 0 and no select on the loaded value is needed
+    // wavefield reads and stores: lanes past the x edge (or not halo lanes) take the
+    // out-of-range offset as a whole, so no select on the loaded value is needed and the
+    // row term cannot wrap a store back into range
     auto coff = [&](int zz) -> uint32_t { return xin ? roff(zz) + xo : kOOB; };
     auto hoff = [&](int zz) -> uint32_t { return hl ? roff(zz) + ho : kOOB; };
 
-    // centre queue: rows z-4 .. z+8 (q[4] is row z; row z+8 arrives while row z is done)
-    float q[13], hq[PF + 1], cq[PF], pq[PF], wq[PF];
-    double gq[PF];
+    float q[BZ + 12], hq[BZ + PF], cq[BZ + PF], pq[BZ + PF];
 #pragma unroll
     for (int k = 0; k < 12; ++k) q[k] = bload(rU, coff(z0 - kHalo + k));
 #pragma unroll
@@ -269,10 +244,6 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
         hq[k] = bload(rU, hoff(z0 + k));
         cq[k] = bload(rC, o + xo);
         pq[k] = bload(rP, o + xo);
-        if (ADJ) {
-            wq[k] = bload(rW, o + xo);
-            gq[k] = bload64(rG, 2 * (o + xo));
-        }
     }
     // receiver event rows of this tile, kept in scalar registers (one row per z)
     const bool rec = rec_j >= 0 && T.ev_cnt > 0;
@@ -281,31 +252,33 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
     int ev_z = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
     int ev_off = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
 
-    int par = 0;
-    for (int z = z0; z < z1; ++z) {
-        // ---- prefetch: centre row z+8, halo and point operands of row z+4 (reads
-        // beyond the tile are harmless and unused)
-        q[12] = bload(rU, coff(z + 8));
+#pragma unroll
+    for (int r = 0; r < BZ; ++r) {
+        const int z = z0 + r;
+        q[r + 12] = bload(rU, coff(z + 8));
         const uint32_t of = roff(z + PF);
-        const float hn = bload(rU, hoff(z + PF));
-        const float cn = bload(rC, of + xo);
-        const float pn = bload(rP, of + xo);
-        float wn = 0.0f;
-        double gn = 0.0;
-        if (ADJ) {
-            wn = bload(rW, of + xo);
-            gn = bload64(rG, 2 * (of + xo));
-        }
-        // ---- row z
-        float *row = rows[wave][par];
-        row[lane + kHalo] = q[4];
+        hq[r + PF] = bload(rU, hoff(z + PF));
+        cq[r + PF] = bload(rC, of + xo);
+        pq[r + PF] = bload(rP, of + xo);
+
+        float *row = rows[wave][r & 1];
+        row[lane + kHalo] = q[r + 4];
         if (lane < 4)
-            row[lane] = hq[0];
+            row[lane] = hq[r];
         else if (lane < 8)
-            row[kTileX + lane] = hq[0];
+            row[kTileX + lane] = hq[r];
         wave_lds_sync();
-        float wv = lap2d(row, lane, q, wz, wx);
-        par ^= 1;
+        float lx = wx[0] * q[r + 4];
+        lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+        lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+        lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+        lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+        float lz = wz[0] * q[r + 4];
+        lz += wz[1] * (q[r + 3] + q[r + 5]);
+        lz += wz[2] * (q[r + 2] + q[r + 6]);
+        lz += wz[3] * (q[r + 1] + q[r + 7]);
+        lz += wz[4] * (q[r + 0] + q[r + 8]);
+        float wv = lz + lx;
 
         float a, b;
         {
@@ -314,65 +287,33 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs A)
             gam = gam + gx;
             sponge_ab(gam, dt, a, b);
         }
-        const bool evrow = z == ev_z;  // uniform
-        if (!ADJ) {
-            if (z == src.z) wv += src.w * famp;
-            if (multi) {
-                float extra = 0.0f;
-                if (src.multi)
-                    for (int s = 0; s < src_cnt; ++s) {
-                        const SrcPos p = A.src[src_beg + s];
-                        if (p.x == x && p.z == z && z != src.z) extra += p.w;
-                    }
-                wv += extra * famp;
-            }
-        } else if (evrow) {
-            // c-weighted injection of the residual at this row's receivers
-            const int rid = evvec[ev_off + lane];
-            if (rid >= 0) wv += Rho[rid];
+        if (z == src.z) wv += src.w * famp;
+        if (multi) {
+            float extra = 0.0f;
+            if (src.multi)
+                for (int s2 = 0; s2 < src_cnt; ++s2) {
+                    const SrcPos p = A.src[src_beg + s2];
+                    if (p.x == x && p.z == z && z != src.z) extra += p.w;
+                }
+            wv += extra * famp;
         }
-        // lanes past the x edge store to an out-of-range offset (dropped); the select is
-        // on the whole offset so that the row term cannot wrap it back into range
-        const uint32_t o = xin ? roff(z) + xo : kOOB;
-        const float un = a * q[4] - b * pq[0] + cq[0] * wv;
+        const uint32_t o = coff(z);
+        const float un = a * q[r + 4] - b * pq[r] + cq[r] * wv;
         bstore(rN, o, un);
-        if (!ADJ) {
-            bstore(rW, o, wv);
-            bstore(rKa, o, un);
-            bstore(rKb, o, q[4]);
-            if (evrow && Dat) {
+        bstore(rW, o, wv);
+        bstore(rKa, o, un);
+        bstore(rKb, o, q[r + 4]);
+        if (z == ev_z) {  // uniform
+            if (Dat) {
                 const int rid = evvec[ev_off + lane];
                 if (rid >= 0) Dat[rid] = un;
             }
-        } else {
-            bstore64(rG, xin ? 2 * o : kOOB, gq[0] + (double)un * (double)wq[0]);
-        }
-        if (evrow) {
             ++ev;
             ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
             ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
         }
-        // ---- shift the queues
-#pragma unroll
-        for (int k = 0; k < 12; ++k) q[k] = q[k + 1];
-#pragma unroll
-        for (int k = 0; k < PF - 1; ++k) hq[k] = hq[k + 1];
-        hq[PF - 1] = hn;
-#pragma unroll
-        for (int k = 0; k < PF - 1; ++k) {
-            cq[k] = cq[k + 1];
-            pq[k] = pq[k + 1];
-            if (ADJ) {
-                wq[k] = wq[k + 1];
-                gq[k] = gq[k + 1];
-            }
-        }
-        cq[PF - 1] = cn;
-        pq[PF - 1] = pn;
-        if (ADJ) {
-            wq[PF - 1] = wn;
-            gq[PF - 1] = gn;
-        }
+        // keep each row's loads in its own row (prefetch distance PF rows)
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -1090,16 +1031,14 @@ hipError_t launch_prep(const SampleDesc *smp, int nsample, int64_t max_cell, con
     return hipGetLastError();
 }
 
-template <bool ADJ>
-static hipError_t step2d_dispatch(const StepArgs &a, int bz, hipStream_t st)
+static hipError_t fwd2d_dispatch(const StepArgs &a, int bz, hipStream_t st)
 {
     // per_xcd counts workgroups of 4 tiles here
     dim3 grid(8 * a.per_xcd);
     switch (bz) {
-    case 8: k_step2d<8, ADJ><<<grid, 256, 0, st>>>(a); break;
-    case 16: k_step2d<16, ADJ><<<grid, 256, 0, st>>>(a); break;
-    case 32: k_step2d<32, ADJ><<<grid, 256, 0, st>>>(a); break;
-    case 64: k_step2d<64, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 8: k_fwd2d<8><<<grid, 256, 0, st>>>(a); break;
+    case 16: k_fwd2d<16><<<grid, 256, 0, st>>>(a); break;
+    case 32: k_fwd2d<32><<<grid, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1134,7 +1073,7 @@ static hipError_t adj2d_dispatch(const StepArgs &a, hipStream_t st)
 hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty, hipStream_t st)
 {
     if (a.ntiles <= 0) return hipSuccess;
-    if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : step2d_dispatch<false>(a, bz, st);
+    if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : fwd2d_dispatch(a, bz, st);
     return adjoint ? step3d_dispatch<true>(a, bz, ty, st) : step3d_dispatch<false>(a, bz, ty, st);
 }
 

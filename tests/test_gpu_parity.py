@@ -289,3 +289,60 @@ def test_device_flags_model_above_vmax(F):
         F.fwi_poll_status(ws)
     assert e.value.status == F.FWI_E_NONFINITE
     F.fwi_poll_status(ws)  # cleared
+
+
+# ------------------------------------------- per-sample imaging (2D adjoint)
+
+def grouped_problem(F, counts, seed):
+    """One sample per entry of counts (each on its own grid size), with that many
+    supergathers of 1-3 random +-1 sources each; receivers every third column of row 1."""
+    r = np.random.default_rng(seed)
+    grids, models, sample_of, srcs, recs = [], [], [], [], []
+    for k, G in enumerate(counts):
+        nz, nx = 30 + 7 * k, 61 + 13 * k
+        g = F.Grid(nz=nz, nx=nx, dz=10.0, dx=10.0, nb=6, v_ref=3000.0, v_max=3300.0)
+        grids.append(g)
+        models.append(f32(r.uniform(1800, 3200, g.nphys)))
+        rec = (np.arange(0, nx, 3) + nx).astype(np.int32)
+        for _ in range(G):
+            n = int(r.integers(1, 4))
+            srcs.append((r.integers(0, g.nphys, n).astype(np.int32), r.choice([-1.0, 1.0], n)))
+            recs.append(rec)
+            sample_of.append(k)
+    return grids, models, sample_of, srcs, recs
+
+
+@pytest.mark.parametrize("counts", [(1, 3, 7, 17), (32,)])
+def test_per_sample_imaging_any_group_size(F, counts):
+    # the 2D adjoint sums a sample's supergathers inside one workgroup; samples of 1, 3,
+    # 7 and 17 supergathers share one launch (one wave count for all, idle waves in the
+    # small samples), and 32 supergathers of one sample fill 16-wave workgroups.
+    # Adjoint + imaging alone against a shared FP32 residual, kappa != 1.
+    say("case per-sample imaging, supergathers per sample %s" % (counts,))
+    grids, models, sample_of, srcs, recs = grouped_problem(F, counts, seed=sum(counts))
+    nt, R = 120, 2
+    batch = F.Batch(grids, sample_of, srcs, recs, W.ricker(15.0, 1e-3, nt))
+    time = F.time_axis(1e-3, nt, R, 0)
+    r = np.random.default_rng(7)
+    rho = [f32(r.standard_normal((nt // R, batch.nrec[s])) * 1e-3) for s in range(batch.nsim)]
+    kappa = [0.5 + k for k in range(len(counts))]
+    v = dev(np.concatenate([m.ravel() for m in models]))
+    ws = F.alloc_workspace(batch, time)
+    F.fwi_forward(batch, time, v, None, ws)
+    grad = torch.zeros(batch.model_size, device="cuda")
+    F.fwi_adjoint(batch, time, v, dev(np.concatenate([x.ravel() for x in rho])), kappa, grad, None, ws)
+    F.fwi_poll_status(ws)
+    gg = split_model(grad.cpu().numpy().astype(np.float64), batch)
+    for k in range(len(counts)):
+        ref = np.zeros(grids[k].nphys)
+        for s in range(batch.nsim):
+            if sample_of[s] != k:
+                continue
+            a, b = batch.src_ptr[s], batch.src_ptr[s + 1]
+            gs, _ = oracle.adjoint(ogrid(grids[k]), models[k], 1e-3, nt, R, batch.src_cell[a:b], f32(batch.src_w[a:b]),
+                                   f32(batch.wavelet), batch.rec_cell[batch.rec_ptr[s]:batch.rec_ptr[s + 1]], rho[s],
+                                   coef_fp32=True)
+            ref += gs
+        e = rel(gg[k], kappa[k] * ref)
+        say("  sample %d (%d supergathers) gradient rel %.2e" % (k, counts[k], e))
+        assert e < TOL
