@@ -239,7 +239,7 @@ fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays);
 
 /*
  * Tile height of the step kernels: rows per 2D tile (8, 16, 32) or planes per 3D tile
- * (16, 32, 64); the 2D adjoint sweeps strips of 8 rows when the tile height is 8 and of
+ * (16, 32); the 2D adjoint sweeps strips of 8 rows when the tile height is 8 and of
  * 16 rows otherwise.  fwi_set_tile forces one for every batch of that dimensionality (0 returns
  * to automatic choice).  fwi_tune times one forward and one adjoint step of every candidate
  * on the caller's batch, model v (device) and workspace (>= fwi_workspace_size, whose

@@ -72,6 +72,11 @@ fwi_status check_grid(const fwi_grid &g, int i)
     const int64_t N = (int64_t)(g.nz + 2 * g.nb) * (g.ndim == 3 ? g.ny + 2 * g.nb : 1) * (g.nx + 2 * g.nb);
     // fields are addressed through 32-bit byte offsets (FP64 accumulators: 8 bytes/cell)
     if (N >= (int64_t)1 << 28) return fail(FWI_E_UNSUPPORTED, "grid %d: more than 2^28 padded cells", i);
+    // the sweeps address up to 80 rows (2D) / planes (3D) past the grid with offsets that
+    // must stay below bit 31 even when doubled (out-of-grid lanes carry bit 31)
+    const int64_t slice = (int64_t)4 * (g.ndim == 3 ? (int64_t)(g.ny + 2 * g.nb) * (g.nx + 2 * g.nb) : g.nx + 2 * g.nb);
+    if ((int64_t)(g.nz + 2 * g.nb + 80) * slice > (int64_t)1 << 30)
+        return fail(FWI_E_UNSUPPORTED, "grid %d: (padded nz + 80) x row or plane bytes exceeds 2^30", i);
     return FWI_OK;
 }
 
@@ -194,7 +199,7 @@ void stencil_weights(const fwi_grid &g, float w[3][5], double gmax[3], float &in
 
 // Tile heights the kernels are instantiated for (rows per 2D tile, planes per 3D tile).
 const int kBz2[] = {8, 16, 32};
-const int kBz3[] = {16, 32, 64};
+const int kBz3[] = {16, 32};
 
 // Process-wide tile choices: forced per dimensionality (fwi_set_tile) or tuned per batch
 // shape (fwi_tune).
@@ -229,7 +234,7 @@ std::string shape_signature(const fwi_batch *b)
 bool valid_bz(int ndim, int bz)
 {
     if (ndim == 2) return bz == 8 || bz == 16 || bz == 32;
-    return bz == 16 || bz == 32 || bz == 64;
+    return bz == 16 || bz == 32;
 }
 
 void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
@@ -271,7 +276,7 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
             }
     } else {
         p.bz = 16;
-        for (int c : {64, 32, 16})
+        for (int c : {32, 16})
             if (count(c) >= 1024) {
                 p.bz = c;
                 break;
@@ -282,23 +287,16 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
 size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz);
 
 // Wavefronts per workgroup of the per-sample 2D adjoint for samples of up to g sims and
-// ngt strips: the sims split as evenly as possible over the waves (busy fraction) while
-// the launch still gives about 24 waves per CU (fill); ties go to fewer waves.
+// ngt strips.  Four waves (fewer for smaller samples) pack the kernel's occupancy (six
+// waves per SIMD) into whole workgroups and keep workgroups short; more waves per
+// workgroup only when the launch would otherwise hold fewer than about 24 waves per CU.
+// (On the 16-sample x 10-supergather 2D workload, 4 waves measured faster than 2, 5 or 10.)
 int grouped_waves(int g, int64_t ngt)
 {
     if (g <= 1) return 1;
-    int best = 1;
-    double best_score = -1.0;
-    for (int w = std::min(4, g); w <= 16; ++w) {
-        const double busy = (double)g / (double)(((g + w - 1) / w) * w);
-        const double fill = std::min(1.0, (double)(ngt * w) / (256.0 * 24.0));
-        const double score = busy * fill;
-        if (score > best_score + 1e-12) {
-            best_score = score;
-            best = w;
-        }
-    }
-    return best;
+    int w = std::min(g, 4);
+    while (w < std::min(g, 16) && ngt * w < 256 * 24) ++w;
+    return w;
 }
 
 fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p, int bz_override = 0,
@@ -426,8 +424,8 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         i = j;
     }
     if (p.tiles.size() >= (size_t)1 << 30) return fail(FWI_E_UNSUPPORTED, "too many tiles");
-    // imaging accumulators: 2D adjoints sum a sample's sims in one workgroup (one slot per
-    // sample, laid out like the coefficients); 3D keeps one slot per sim
+    // imaging accumulators: 2D, one per sample (laid out like the coefficients; an adjoint
+    // workgroup sweeps its strip for every sim of the sample); 3D, one per sim
     p.grouped = p.ndim == 2;
     int gmax = 0;
     for (auto &Sm : p.samples) {
@@ -442,21 +440,28 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         }
     }
     p.gcells = p.grouped ? p.coefs : p.cells;
-    if (p.grouped) {
-        p.bzg = p.bz == 8 ? 8 : 16;
-        for (int k = 0; k < b->nsample; ++k) {
-            const SampleDesc &Sm = p.samples[k];
-            const int ntx = (Sm.N[2] + kTileX - 1) / kTileX;
-            const int ntz = (Sm.N[0] + p.bzg - 1) / p.bzg;
-            for (int iz = 0; iz < ntz; ++iz)
+    p.bzg = p.ndim == 2 ? (p.bz == 8 ? 8 : 16) : p.bz;
+    for (int k = 0; k < (p.grouped ? b->nsample : 0); ++k) {
+        const SampleDesc &Sm = p.samples[k];
+        const int ntx = (Sm.N[2] + kTileX - 1) / kTileX;
+        const int nty = (Sm.N[1] + TYt - 1) / TYt;
+        const int ntz = (Sm.N[0] + p.bzg - 1) / p.bzg;
+        for (int iz = 0; iz < ntz; ++iz)
+            for (int iy = 0; iy < nty; ++iy)
                 for (int ix = 0; ix < ntx; ++ix) {
                     const int z0 = iz * p.bzg;
-                    p.gtiles.push_back(GTile{k, ix * kTileX, z0, (z0 / p.bz) * ntx + ix});
+                    GTile G;
+                    memset(&G, 0, sizeof G);
+                    G.sample = k;
+                    G.x0 = ix * kTileX;
+                    G.y0 = iy * TYt;
+                    G.z0 = z0;
+                    G.tix = ((z0 / p.bz) * nty + iy) * ntx + ix;
+                    p.gtiles.push_back(G);
                 }
-        }
-        p.nw = grouped_waves(gmax, (int64_t)p.gtiles.size());
-        p.per_xcd_g = (int)((p.gtiles.size() + 7) / 8);
     }
+    p.nw = p.grouped ? grouped_waves(gmax, (int64_t)p.gtiles.size()) : 1;
+    p.per_xcd_g = (int)((p.gtiles.size() + 7) / 8);
     // 2D: a workgroup runs 4 tiles (one per wavefront); 3D: one tile per workgroup
     const size_t nwg = p.ndim == 2 ? (p.tiles.size() + 3) / 4 : p.tiles.size();
     p.per_xcd = (int)((nwg + 7) / 8);

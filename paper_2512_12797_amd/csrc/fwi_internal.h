@@ -61,13 +61,14 @@ struct Tile {
     int32_t pad0, pad1;
 };
 
-// Tile of the 2D adjoint with per-sample imaging: one 64 x bzg strip of a sample's grid,
+// Tile of the 2D adjoint with per-sample imaging: a 64 x bzg strip of a sample's grid,
 // swept for every sim of the sample.  tix is the index, within each sim's tile list, of
-// the sim tile that contains the strip (for its receiver event rows).
+// the sim tile that contains it (for its receiver event rows).
 struct GTile {
     int32_t sample;
-    int32_t x0, z0;
+    int32_t x0, y0, z0;
     int32_t tix;
+    int32_t pad0, pad1, pad2;
 };
 
 // One row (2D: a grid row; 3D: an xy plane) of a tile that holds receivers.  vec_off
@@ -98,7 +99,7 @@ struct StepArgs {
     float *cka, *ckb;       // checkpoint slots for u^{n+1}, u^n (nullable)
     float *dat;             // forward: recorded data (nullable)
     const float *rho;       // adjoint: residual
-    double *gacc;           // adjoint: imaging accumulator (per sample in 2D, per sim in 3D)
+    double *gacc;           // adjoint: imaging accumulators (2D: per sample; 3D: per sim)
     int32_t ntiles;
     int32_t per_xcd;        // tiles per XCD chunk (grid = 8 * per_xcd)
     int32_t rec_j;          // recording slot j, or -1

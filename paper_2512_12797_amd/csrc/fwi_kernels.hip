@@ -12,7 +12,7 @@
 // FP64 and rounded once, and c precomputed per sample in FP64 and rounded once.
 // The scaled adjoint lt = c lambda obeys the same recursion backward in time with
 // c-weighted receiver injection; the imaging term lt^k (L u^{k-1} + q^{k-1}) is summed
-// in FP64, per sample in 2D (all of a sample's sims in one workgroup) and per sim in 3D.
+// in FP64 into one accumulator per sample (a workgroup covers all of a sample's sims).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -300,9 +300,10 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
         const uint32_t o = coff(z);
         const float un = a * q[r + 4] - b * pq[r] + cq[r] * wv;
         bstore(rN, o, un);
-        bstore(rW, o, wv);
-        bstore(rKa, o, un);
-        bstore(rKb, o, q[r + 4]);
+        // optional outputs: uniform branches skip the instructions when a buffer is absent
+        if (A.wst) bstore(rW, o, wv);
+        if (A.cka) bstore(rKa, o, un);
+        if (A.ckb) bstore(rKb, o, q[r + 4]);
         if (z == ev_z) {  // uniform
             if (Dat) {
                 const int rid = evvec[ev_off + lane];
@@ -520,43 +521,56 @@ __global__ __launch_bounds__(1024) void k_adj2d(const StepArgs A)
 
 // ------------------------------------------------------------ 3D stepping
 
-// 3D step.  Block: 64 x 4 threads; tile 64 x 8 cells in (x, y); each thread owns the two
-// rows y = y0 + ty and y0 + ty + 4 and streams the tile along z.  The xy plane (tile plus
-// a 4-cell halo in x and y) goes through a double-buffered LDS plane with one barrier
-// per plane; the z-derivative comes from a register queue that runs 8 planes ahead, and
-// the halo and point operands are fetched 4 planes ahead with unconditional buffer loads.
+// 3D step.  Block: 64 x kTileY3 threads, one wavefront per row of a 64 x kTileY3 (x, y)
+// tile, streamed along z.  The xy plane (tile plus a 4-cell halo in x and y) goes through
+// a double-buffered LDS plane with one barrier per plane: each wave writes its own row,
+// waves 0..7 also one y-halo row each and lanes 0..7 of every wave the row's x-halo
+// cells.  The z-derivative comes from a register queue that runs 8 planes ahead, and the
+// halo and point operands are fetched 4 planes ahead with unconditional buffer loads.
+//
+// The step is VALU-bound rather than HBM-bound (25-point stencil, one cell per lane), so
+// the sweep keeps instructions per cell low: the plane loop is fully unrolled (queues
+// shift by register renaming, no moves), every lane offset carries a poison bit instead
+// of a per-access select, and the sponge coefficients a, b of planes outside the z-sponge
+// are computed once per column.
 
 struct Plane3 {
     float v[2][kTileY3 + 2 * kHalo][kTileX + 2 * kHalo];
 };
 
+// Lane base offsets for the unrolled sweeps: a lane that must read 0 / drop its store
+// gets bit 31 set, so plane offset + base stays outside every buffer for all planes the
+// sweep touches.  The host guarantees (padded planes + 80) * plane bytes <= 2^30, so
+// plane offsets (and their doubles, for the FP64 accumulator) never reach bit 31.
+constexpr uint32_t kPoison = 0x80000000u;
+
+// One sim's sweep of one 3D tile (origin x0, y0, z0).  S supplies the grid, weights and
+// (forward) the sources; u_off / d_off / nrec locate the sim's fields and data; the
+// receiver event planes are ev_beg .. ev_beg + ev_cnt; the adjoint adds its imaging
+// products into the FP64 accumulator at gacc.
 template <int BZ, bool ADJ>
-__global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
+__device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int64_t u_off, int64_t d_off, int nrec,
+                                        int tx0, int ty0, int z0, int ev_beg, int ev_cnt, double *gacc, Plane3 &P)
 {
-    constexpr int RPT = kTileY3 / 4;
+    static_assert(kTileY3 >= 8, "one y-halo row per wave needs at least 8 waves");
     constexpr int PF = 4;
-    const int t = xcd_tile(blockIdx.x, A.per_xcd);
-    if (t >= A.ntiles) return;  // uniform per block
-    const Tile T = A.tiles[t];
-    const SimDesc &S = A.sims[T.sim];
     const int Nx = S.N[2], Ny = S.N[1], Nz = S.N[0];
     const int nz_phys = S.n[0], ny_phys = S.n[1], nx_phys = S.n[2], nb = S.nb;
     const double gmz = S.gmax[0], gmy = S.gmax[1], gmx = S.gmax[2];
-    const int64_t u_off = S.u_off, d_off = S.d_off;
-    const int nrec = S.nrec, src_beg = S.src_beg, src_cnt = S.src_cnt;
+    const int src_beg = S.src_beg, src_cnt = S.src_cnt;
     const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
     const uint32_t fbytes = pbytes * (uint32_t)Nz;
     const int lane = threadIdx.x & 63;
-    const int ty = threadIdx.x >> 6;
-    const int x = T.x0 + lane;
-    const int z0 = T.z0;
+    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's row (uniform)
+    const int x = tx0 + lane;
+    const int y = ty0 + ty;
     const int z1 = min(z0 + BZ, Nz);
     const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
     const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
     const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
     const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
     const rsrc_t rW = make_rsrc(ADJ ? A.wimg + u_off : (A.wst ? A.wst + u_off : A.next), ADJ || A.wst ? fbytes : 0);
-    const rsrc_t rG = make_rsrc(ADJ ? (const void *)(A.gacc + u_off) : (const void *)A.next, ADJ ? 2 * fbytes : 0);
+    const rsrc_t rG = make_rsrc(ADJ ? (const void *)gacc : (const void *)A.next, ADJ ? 2 * fbytes : 0);
     const rsrc_t rKa = make_rsrc(A.cka ? A.cka + u_off : A.next, A.cka ? fbytes : 0);
     const rsrc_t rKb = make_rsrc(A.ckb ? A.ckb + u_off : A.next, A.ckb ? fbytes : 0);
     const int rec_j = A.rec_j;
@@ -564,7 +578,6 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
     const float *Rho = (ADJ && rec_j >= 0) ? A.rho + d_off + (int64_t)rec_j * nrec : nullptr;
     const EvRow *__restrict__ evrows = A.evrows;
     const int32_t *__restrict__ evvec = A.evvec;
-    __shared__ Plane3 P;
 
     float wz[5], wy[5], wx[5];
 #pragma unroll
@@ -575,224 +588,193 @@ __global__ __launch_bounds__(256) void k_step3d(const StepArgs A)
     }
     const double dt = S.dt;
     const double gx = sponge_axis(x, nx_phys, nb, gmx);
+    const double gy = sponge_axis(y, ny_phys, nb, gmy);  // uniform per wave
+    float a_col, b_col;  // a, b of this column outside the z-sponge
+    {
+        double gam = 0.0;
+        gam = gam + gy;
+        gam = gam + gx;
+        sponge_ab(gam, dt, a_col, b_col);
+    }
 
     auto poff = [&](int zz) -> uint32_t { return (uint32_t)zz * pbytes; };  // zz < 0 wraps out of range
-    int yr[RPT];
-    bool in[RPT];
-    double gy[RPT];
-    uint32_t col[RPT];  // byte offset of (y, x) within a plane (clamped for lanes outside)
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        yr[r] = T.y0 + ty + 4 * r;
-        in[r] = x < Nx && yr[r] < Ny;
-        gy[r] = sponge_axis(yr[r], ny_phys, nb, gmy);
-        col[r] = 4u * ((uint32_t)min(yr[r], Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
-    }
-    auto coff = [&](int r, int zz) -> uint32_t { return in[r] ? poff(zz) + col[r] : kOOB; };
+    const bool in = x < Nx && y < Ny;
+    const uint32_t col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
+    const uint32_t cb = in ? col : kPoison;          // own cell
+    const uint32_t cb2 = in ? 2u * col : kPoison;    // own cell, FP64 accumulator
+    // y-halo row of waves 0..7: rows y0-4 .. y0-1, then y0+TY .. y0+TY+3
+    const int hy = ty < 4 ? ty0 - kHalo + ty : ty0 + kTileY3 + ty - 4;
+    const int hrow = ty < 4 ? ty : kTileY3 + ty;  // its LDS row
+    const bool hyl = ty < 8 && x < Nx && hy >= 0 && hy < Ny;
+    const uint32_t hyb =
+        hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1)) : kPoison;
+    // x-halo of this row: lanes 0..3 left of the tile, 4..7 right of it
+    const int hxx = lane < 4 ? tx0 - kHalo + lane : tx0 + kTileX - 4 + lane;
+    const int hcol = lane < 4 ? lane : kTileX + lane;  // its LDS column
+    const bool hxl = lane < 8 && y < Ny && hxx >= 0 && hxx < Nx;
+    const uint32_t hxb =
+        hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
 
-    // y-halo rows: LDS rows ty (y0-4+ty) and TY+4+ty (y0+TY+ty); x-halo: 8 columns x TY
-    // rows by the first TY*8 threads
-    const int hy0 = T.y0 - kHalo + ty, hy1 = T.y0 + kTileY3 + ty;
-    const bool hyl0 = x < Nx && hy0 >= 0, hyl1 = x < Nx && hy1 < Ny;
-    const uint32_t hyo0 = 4u * ((uint32_t)max(hy0, 0) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
-    const uint32_t hyo1 = 4u * ((uint32_t)min(hy1, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
-    const int xh_t = threadIdx.x;
-    const bool xh_on = xh_t < kTileY3 * 8;
-    const int xh_row = (xh_t >> 3) & (kTileY3 - 1), xh_c = xh_t & 7;
-    const int xh_col = xh_c < 4 ? xh_c : kTileX + xh_c;  // LDS column
-    const int xh_x = T.x0 - kHalo + xh_col;
-    const int xh_y = T.y0 + xh_row;
-    const bool xhl = xh_on && xh_x >= 0 && xh_x < Nx && xh_y < Ny;
-    const uint32_t xho = 4u * ((uint32_t)min(xh_y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(xh_x, 0), Nx - 1));
-    auto h0off = [&](int zz) -> uint32_t { return hyl0 ? poff(zz) + hyo0 : kOOB; };
-    auto h1off = [&](int zz) -> uint32_t { return hyl1 ? poff(zz) + hyo1 : kOOB; };
-    auto hxoff = [&](int zz) -> uint32_t { return xhl ? poff(zz) + xho : kOOB; };
-
-    // sources in this thread's columns
-    int sz[RPT];
-    float sw[RPT];
+    // sources in this thread's column
+    int sz = -1;
+    float sw = 0.0f;
     bool smulti = false;
     float famp = 0.0f;
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        sz[r] = -1;
-        sw[r] = 0.0f;
-    }
     if (!ADJ) {
         famp = A.fn * S.inv_vol;
         for (int s = 0; s < src_cnt; ++s) {
             const SrcPos p = A.src[src_beg + s];
-            if (p.x != x || p.z < z0 || p.z >= z1) continue;
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (p.y == yr[r]) {
-                    if (sz[r] < 0 || sz[r] == p.z) {
-                        sz[r] = p.z;
-                        sw[r] += p.w;
-                    } else {
-                        smulti = true;
-                    }
-                }
-        }
-    }
-    const bool multi = __syncthreads_or(smulti);
-
-    float q[RPT][13], cq[RPT][PF], pq[RPT][PF], wq[RPT][PF];
-    double gq[RPT][PF];
-    float h0q[PF], h1q[PF], hxq[PF];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r)
-#pragma unroll
-        for (int k = 0; k < 12; ++k) q[r][k] = bload(rU, coff(r, z0 - kHalo + k));
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-        const int zz = z0 + k;
-        h0q[k] = bload(rU, h0off(zz));
-        h1q[k] = bload(rU, h1off(zz));
-        hxq[k] = bload(rU, hxoff(zz));
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const uint32_t o = poff(zz) + col[r];
-            cq[r][k] = bload(rC, o);
-            pq[r][k] = bload(rP, o);
-            if (ADJ) {
-                wq[r][k] = bload(rW, o);
-                gq[r][k] = bload64(rG, 2 * o);
+            if (p.x != x || p.y != y || p.z < z0 || p.z >= z1) continue;
+            if (sz < 0 || sz == p.z) {
+                sz = p.z;
+                sw += p.w;
+            } else {
+                smulti = true;
             }
         }
     }
-    const bool rec = rec_j >= 0 && T.ev_cnt > 0;
-    int ev = T.ev_beg;
-    const int ev_end = T.ev_beg + T.ev_cnt;
-    int ev_z = rec ? evrows[ev].z : -1;
-    int ev_off = rec ? evrows[ev].vec_off : 0;
+    const bool multi = ADJ ? false : __syncthreads_or(smulti);
 
-    int par = 0;
-    for (int z = z0; z < z1; ++z) {
+    // queues indexed by plane (the plane loop is fully unrolled)
+    float q[BZ + 12], cq[BZ + PF], pq[BZ + PF], wq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
+    double gq[BZ + PF];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q[k] = bload(rU, poff(z0 - kHalo + k) + cb);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const uint32_t pz = poff(z0 + k);
+        hyq[k] = bload(rU, pz + hyb);
+        hxq[k] = bload(rU, pz + hxb);
+        cq[k] = bload(rC, pz + cb);
+        pq[k] = bload(rP, pz + cb);
+        if (ADJ) {
+            wq[k] = bload(rW, pz + cb);
+            gq[k] = bload64(rG, 2u * pz + cb2);
+        }
+    }
+    const bool rec = rec_j >= 0 && ev_cnt > 0;
+    int ev = ev_beg;
+    const int ev_end = ev_beg + ev_cnt;
+    int ev_z = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+    int ev_off = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
+
+    // planes below the grid are swept too: their loads read 0 and their stores fall
+    // outside the buffers, so the tile needs no plane guard
+#pragma unroll
+    for (int r = 0; r < BZ; ++r) {
+        const int z = z0 + r;
         // ---- prefetch: centre plane z+8, halos and point operands of plane z+4
-        float cn[RPT], pn[RPT], wn[RPT];
-        double gn[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) q[r][12] = bload(rU, coff(r, z + 8));
-        const float h0n = bload(rU, h0off(z + PF));
-        const float h1n = bload(rU, h1off(z + PF));
-        const float hxn = bload(rU, hxoff(z + PF));
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const uint32_t o = poff(z + PF) + col[r];
-            cn[r] = bload(rC, o);
-            pn[r] = bload(rP, o);
+        q[r + 12] = bload(rU, poff(z + 8) + cb);
+        {
+            const uint32_t pz = poff(z + PF);
+            hyq[r + PF] = bload(rU, pz + hyb);
+            hxq[r + PF] = bload(rU, pz + hxb);
+            cq[r + PF] = bload(rC, pz + cb);
+            pq[r + PF] = bload(rP, pz + cb);
             if (ADJ) {
-                wn[r] = bload(rW, o);
-                gn[r] = bload64(rG, 2 * o);
+                wq[r + PF] = bload(rW, pz + cb);
+                gq[r + PF] = bload64(rG, 2u * pz + cb2);
             }
         }
         // ---- plane z into LDS
-        float(*V)[kTileX + 2 * kHalo] = P.v[par];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) V[ty + 4 * r + kHalo][lane + kHalo] = q[r][4];
-        V[ty][lane + kHalo] = h0q[0];
-        V[kTileY3 + kHalo + ty][lane + kHalo] = h1q[0];
-        if (xh_on) V[xh_row + kHalo][xh_col] = hxq[0];
+        float(*V)[kTileX + 2 * kHalo] = P.v[r & 1];
+        V[ty + kHalo][lane + kHalo] = q[r + 4];
+        if (ty < 8) V[hrow][lane + kHalo] = hyq[r];
+        if (lane < 8) V[ty + kHalo][hcol] = hxq[r];
         __syncthreads();
-        par ^= 1;
 
-        const double gz = sponge_axis(z, nz_phys, nb, gmz);
+        const int ly = ty + kHalo, lx = lane + kHalo;
+        const float *qq = &q[r];  // qq[4] is plane z
+        float sx = wx[0] * qq[4];
+        sx += wx[1] * (V[ly][lx - 1] + V[ly][lx + 1]);
+        sx += wx[2] * (V[ly][lx - 2] + V[ly][lx + 2]);
+        sx += wx[3] * (V[ly][lx - 3] + V[ly][lx + 3]);
+        sx += wx[4] * (V[ly][lx - 4] + V[ly][lx + 4]);
+        float sy = wy[0] * qq[4];
+        sy += wy[1] * (V[ly - 1][lx] + V[ly + 1][lx]);
+        sy += wy[2] * (V[ly - 2][lx] + V[ly + 2][lx]);
+        sy += wy[3] * (V[ly - 3][lx] + V[ly + 3][lx]);
+        sy += wy[4] * (V[ly - 4][lx] + V[ly + 4][lx]);
+        float szz = wz[0] * qq[4];
+        szz += wz[1] * (qq[3] + qq[5]);
+        szz += wz[2] * (qq[2] + qq[6]);
+        szz += wz[3] * (qq[1] + qq[7]);
+        szz += wz[4] * (qq[0] + qq[8]);
+        float wv = szz + sy + sx;
+        float a = a_col, b = b_col;
+        const double gz = sponge_axis(z, nz_phys, nb, gmz);  // uniform
+        if (gz != 0.0) {
+            double gam = 0.0;
+            gam = gam + gz;
+            gam = gam + gy;
+            gam = gam + gx;
+            sponge_ab(gam, dt, a, b);
+        }
         const bool evrow = z == ev_z;  // uniform
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int ly = ty + 4 * r + kHalo;
-            const int lx = lane + kHalo;
-            float sx = wx[0] * q[r][4];
-            sx += wx[1] * (V[ly][lx - 1] + V[ly][lx + 1]);
-            sx += wx[2] * (V[ly][lx - 2] + V[ly][lx + 2]);
-            sx += wx[3] * (V[ly][lx - 3] + V[ly][lx + 3]);
-            sx += wx[4] * (V[ly][lx - 4] + V[ly][lx + 4]);
-            float sy = wy[0] * q[r][4];
-            sy += wy[1] * (V[ly - 1][lx] + V[ly + 1][lx]);
-            sy += wy[2] * (V[ly - 2][lx] + V[ly + 2][lx]);
-            sy += wy[3] * (V[ly - 3][lx] + V[ly + 3][lx]);
-            sy += wy[4] * (V[ly - 4][lx] + V[ly + 4][lx]);
-            float szz = wz[0] * q[r][4];
-            szz += wz[1] * (q[r][3] + q[r][5]);
-            szz += wz[2] * (q[r][2] + q[r][6]);
-            szz += wz[3] * (q[r][1] + q[r][7]);
-            szz += wz[4] * (q[r][0] + q[r][8]);
-            float wv = szz + sy + sx;
-            float a, b;
-            {
-                double gam = 0.0;
-                gam = gam + gz;
-                gam = gam + gy[r];
-                gam = gam + gx;
-                sponge_ab(gam, dt, a, b);
+        if (!ADJ) {
+            if (z == sz) wv += sw * famp;
+            if (multi) {
+                float extra = 0.0f;
+                if (in)
+                    for (int s = 0; s < src_cnt; ++s) {
+                        const SrcPos p = A.src[src_beg + s];
+                        if (p.x == x && p.y == y && p.z == z && z != sz) extra += p.w;
+                    }
+                wv += extra * famp;
             }
-            if (!ADJ) {
-                if (z == sz[r]) wv += sw[r] * famp;
-                if (multi) {
-                    float extra = 0.0f;
-                    if (in[r])
-                        for (int s = 0; s < src_cnt; ++s) {
-                            const SrcPos p = A.src[src_beg + s];
-                            if (p.x == x && p.y == yr[r] && p.z == z && z != sz[r]) extra += p.w;
-                        }
-                    wv += extra * famp;
-                }
-            } else if (evrow) {
-                const int rid = evvec[ev_off + (ty + 4 * r) * kTileX + lane];
-                if (rid >= 0) wv += Rho[rid];
+        } else if (evrow) {
+            const int rid = evvec[ev_off + ty * kTileX + lane];
+            if (rid >= 0) wv += Rho[rid];
+        }
+        const uint32_t o = poff(z) + cb;
+        const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
+        bstore(rN, o, un);
+        if (!ADJ) {
+            // optional outputs: uniform branches skip the instructions when absent
+            if (A.wst) bstore(rW, o, wv);
+            if (A.cka) bstore(rKa, o, un);
+            if (A.ckb) bstore(rKb, o, qq[4]);
+            if (evrow && Dat) {
+                const int rid = evvec[ev_off + ty * kTileX + lane];
+                if (rid >= 0) Dat[rid] = un;
             }
-            const uint32_t o = in[r] ? poff(z) + col[r] : kOOB;
-            const float un = a * q[r][4] - b * pq[r][0] + cq[r][0] * wv;
-            bstore(rN, o, un);
-            if (!ADJ) {
-                bstore(rW, o, wv);
-                bstore(rKa, o, un);
-                bstore(rKb, o, q[r][4]);
-                if (evrow && Dat) {
-                    const int rid = evvec[ev_off + (ty + 4 * r) * kTileX + lane];
-                    if (rid >= 0) Dat[rid] = un;
-                }
-            } else {
-                bstore64(rG, in[r] ? 2 * o : kOOB, gq[r][0] + (double)un * (double)wq[r][0]);
-            }
+        } else {
+            bstore64(rG, 2u * poff(z) + cb2, gq[r] + (double)un * (double)wq[r]);
         }
         if (evrow) {
             ++ev;
-            ev_z = ev < ev_end ? evrows[ev].z : -1;
-            ev_off = ev < ev_end ? evrows[ev].vec_off : 0;
+            ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+            ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
         }
-        // ---- shift the queues
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) q[r][k] = q[r][k + 1];
-#pragma unroll
-            for (int k = 0; k < PF - 1; ++k) {
-                cq[r][k] = cq[r][k + 1];
-                pq[r][k] = pq[r][k + 1];
-                if (ADJ) {
-                    wq[r][k] = wq[r][k + 1];
-                    gq[r][k] = gq[r][k + 1];
-                }
-            }
-            cq[r][PF - 1] = cn[r];
-            pq[r][PF - 1] = pn[r];
-            if (ADJ) {
-                wq[r][PF - 1] = wn[r];
-                gq[r][PF - 1] = gn[r];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < PF - 1; ++k) {
-            h0q[k] = h0q[k + 1];
-            h1q[k] = h1q[k + 1];
-            hxq[k] = hxq[k + 1];
-        }
-        h0q[PF - 1] = h0n;
-        h1q[PF - 1] = h1n;
-        hxq[PF - 1] = hxn;
+        // keep each plane's loads in its own plane (prefetch distance PF planes)
+        __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// 3D forward step: one tile of one sim per workgroup.
+template <int BZ>
+__global__ __launch_bounds__(64 * kTileY3) void k_fwd3d(const StepArgs A)
+{
+    const int t = xcd_tile(blockIdx.x, A.per_xcd);
+    if (t >= A.ntiles) return;  // uniform per block
+    const Tile T = A.tiles[t];
+    const SimDesc &S = A.sims[T.sim];
+    __shared__ Plane3 P;
+    sweep3d<BZ, false>(A, S, S.u_off, S.d_off, S.nrec, T.x0, T.y0, T.z0, T.ev_beg, T.ev_cnt, nullptr, P);
+}
+
+// 3D adjoint + imaging step, one tile of one sim per workgroup, imaging into the sim's
+// own FP64 accumulator.  (Sweeping a tile for all of a sample's sims in one workgroup,
+// as the 2D adjoint does, serialises the sims and measured slower in 3D.)
+template <int BZ>
+__global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
+{
+    const int t = xcd_tile(blockIdx.x, A.per_xcd);
+    if (t >= A.ntiles) return;  // uniform per block
+    const Tile T = A.tiles[t];
+    const SimDesc &S = A.sims[T.sim];
+    __shared__ Plane3 P;
+    sweep3d<BZ, true>(A, S, S.u_off, S.d_off, S.nrec, T.x0, T.y0, T.z0, T.ev_beg, T.ev_cnt, A.gacc + S.u_off, P);
 }
 
 // ---------------------------------------------------------- misfit/residual
@@ -1044,15 +1026,25 @@ static hipError_t fwd2d_dispatch(const StepArgs &a, int bz, hipStream_t st)
     return hipGetLastError();
 }
 
-template <bool ADJ>
-static hipError_t step3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
+static hipError_t fwd3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
 {
     dim3 grid(8 * a.per_xcd);
     if (ty != kTileY3) return hipErrorInvalidValue;
     switch (bz) {
-    case 16: k_step3d<16, ADJ><<<grid, 256, 0, st>>>(a); break;
-    case 32: k_step3d<32, ADJ><<<grid, 256, 0, st>>>(a); break;
-    case 64: k_step3d<64, ADJ><<<grid, 256, 0, st>>>(a); break;
+    case 16: k_fwd3d<16><<<grid, 64 * kTileY3, 0, st>>>(a); break;
+    case 32: k_fwd3d<32><<<grid, 64 * kTileY3, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t adj3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
+{
+    dim3 grid(8 * a.per_xcd);
+    if (ty != kTileY3) return hipErrorInvalidValue;
+    switch (bz) {
+    case 16: k_adj3d<16><<<grid, 64 * kTileY3, 0, st>>>(a); break;
+    case 32: k_adj3d<32><<<grid, 64 * kTileY3, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1074,7 +1066,7 @@ hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty
 {
     if (a.ntiles <= 0) return hipSuccess;
     if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : fwd2d_dispatch(a, bz, st);
-    return adjoint ? step3d_dispatch<true>(a, bz, ty, st) : step3d_dispatch<false>(a, bz, ty, st);
+    return adjoint ? adj3d_dispatch(a, bz, ty, st) : fwd3d_dispatch(a, bz, ty, st);
 }
 
 hipError_t launch_residual(const SimDesc *sims, int nsim, int nt_rec, const float *d, const float *dobs, float *rho,
