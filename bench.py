@@ -253,7 +253,9 @@ def main():
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
-            if tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name:
+            # counters are valid for the measured kernel sources, kernel and tile height only
+            if (tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name
+                    and tuned is not None and tj.get("tile_rows") == tuned[0]):
                 traffic = tj.get("bytes_per_launch")
         except (ValueError, OSError):
             traffic = None

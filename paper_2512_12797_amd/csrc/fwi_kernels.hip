@@ -143,6 +143,12 @@ __device__ __forceinline__ void wave_lds_sync()
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit data format
 constexpr uint32_t kOOB = 0xFFFFFFF0u;  // an offset beyond every resource
+// Lane base offsets of the sweeps: a lane that must read 0 / drop its store gets bit 31
+// set, so row (plane) offset + base stays outside every buffer for all rows the sweep
+// touches, with one add per access instead of an add and a select.  The host guarantees
+// (padded rows or planes + 80) * row or plane bytes <= 2^30, so row offsets (and their
+// doubles, for FP64 accumulators) never reach bit 31.
+constexpr uint32_t kPoison = 0x80000000u;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
 {
@@ -217,6 +223,12 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
 
     const double gx = sponge_axis(x, nx_phys, nb, gmx);
     const double dt = S.dt;
+    float a_col, b_col;  // a, b of this column outside the z-sponge
+    {
+        double gam = 0.0;
+        gam = gam + gx;
+        sponge_ab(gam, dt, a_col, b_col);
+    }
     const LaneSrc src = scan_sources_2d(A.src, src_beg, src_cnt, x, z0, z1);
     const bool multi = __any(src.multi);
     const float famp = A.fn * S.inv_vol;
@@ -229,11 +241,12 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
     const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
     const uint32_t rowb = 4u * (uint32_t)Nx;
     auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
-    // wavefield reads and stores: lanes past the x edge (or not halo lanes) take the
-    // out-of-range offset as a whole, so no select on the loaded value is needed and the
-    // row term cannot wrap a store back into range
-    auto coff = [&](int zz) -> uint32_t { return xin ? roff(zz) + xo : kOOB; };
-    auto hoff = [&](int zz) -> uint32_t { return hl ? roff(zz) + ho : kOOB; };
+    // wavefield reads and stores: lanes past the x edge (or not halo lanes) carry the
+    // poison bit, so they read 0 and drop their stores; point operands read the clamped
+    // column
+    const uint32_t xb = xin ? xo : kPoison, hb = hl ? ho : kPoison;
+    auto coff = [&](int zz) -> uint32_t { return roff(zz) + xb; };
+    auto hoff = [&](int zz) -> uint32_t { return roff(zz) + hb; };
 
     float q[BZ + 12], hq[BZ + PF], cq[BZ + PF], pq[BZ + PF];
 #pragma unroll
@@ -280,10 +293,11 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
         lz += wz[4] * (q[r + 0] + q[r + 8]);
         float wv = lz + lx;
 
-        float a, b;
-        {
+        float a = a_col, b = b_col;
+        const double gz = sponge_axis(z, nz_phys, nb, gmz);  // uniform
+        if (gz != 0.0) {
             double gam = 0.0;
-            gam = gam + sponge_axis(z, nz_phys, nb, gmz);
+            gam = gam + gz;
             gam = gam + gx;
             sponge_ab(gam, dt, a, b);
         }
@@ -409,10 +423,11 @@ __global__ __launch_bounds__(1024) void k_adj2d(const StepArgs A)
         uint32_t xs = xo, hs = ho;  // clamped into the row
         int zs = z0;                // and the strip origin (uniform): same for the row offsets
         asm volatile("" : "+v"(xs), "+v"(hs), "+s"(zs));
-        // wavefield reads and the store: lanes past the x edge (or not halo lanes) take
-        // the out-of-range offset as a whole; point operands read the clamped column
-        auto coff = [&](int zz) -> uint32_t { return xin ? roff(zz) + xs : kOOB; };
-        auto hoff = [&](int zz) -> uint32_t { return hl ? roff(zz) + hs : kOOB; };
+        // wavefield reads and the store: lanes past the x edge (or not halo lanes) carry
+        // the poison bit; point operands read the clamped column
+        const uint32_t xb = xin ? xs : kPoison, hb = hl ? hs : kPoison;
+        auto coff = [&](int zz) -> uint32_t { return roff(zz) + xb; };
+        auto hoff = [&](int zz) -> uint32_t { return roff(zz) + hb; };
         // per-sim fields read after stores: vector loads, made uniform explicitly
         const int tile0 = __builtin_amdgcn_readfirstlane(A.sims[sim].tile0);
         const int nrec = __builtin_amdgcn_readfirstlane(A.sims[sim].nrec);
@@ -537,12 +552,6 @@ __global__ __launch_bounds__(1024) void k_adj2d(const StepArgs A)
 struct Plane3 {
     float v[2][kTileY3 + 2 * kHalo][kTileX + 2 * kHalo];
 };
-
-// Lane base offsets for the unrolled sweeps: a lane that must read 0 / drop its store
-// gets bit 31 set, so plane offset + base stays outside every buffer for all planes the
-// sweep touches.  The host guarantees (padded planes + 80) * plane bytes <= 2^30, so
-// plane offsets (and their doubles, for the FP64 accumulator) never reach bit 31.
-constexpr uint32_t kPoison = 0x80000000u;
 
 // One sim's sweep of one 3D tile (origin x0, y0, z0).  S supplies the grid, weights and
 // (forward) the sources; u_off / d_off / nrec locate the sim's fields and data; the
