@@ -21,6 +21,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -93,7 +94,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
-              "(see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "between GPUs, so one GPU's share is the whole measurement; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -161,7 +162,8 @@ def main():
         tuned = (args.tile, float("nan"))
         log("tile height forced to %d" % args.tile)
     elif args.tune:
-        tuned = fwi.fwi_tune(batch0, time_ax, v, ws, os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+        cache = os.environ.get("FWI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "fwi_tune_cache.json"))
+        tuned = fwi.fwi_tune(batch0, time_ax, v, ws, cache)
         log("tuner: tile height %d, %.3f ms per gradient time step" % tuned)
     stream = torch.cuda.Stream()  # graphs need a non-default stream
     torch.cuda.set_stream(stream)

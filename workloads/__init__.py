@@ -198,20 +198,20 @@ class Config:
         return self.nt // self.rec_every
 
 
-# configs[0]: 128x128 at 10 m, dt 1 ms, 1000 steps, 20-cell sponge, 8 shots of a 15 Hz
+# 2D single-shot parity workload: 128x128 at 10 m, dt 1 ms, 1000 steps, 20-cell sponge, 8 shots of a 15 Hz
 # Ricker, 128 receivers, single-source misfit.
 C1 = Config("2d-128x128-8shot-single", 2, 128, 128, 10.0, 20, 1e-3, 1000, 1, 15.0, 8, 1500.0, 4000.0,
             shots_per_group=1, groups=8, nsample=1)
-# configs[1]: 400x150 at 20 m, 2 ms x 2000 recorded samples (two 1 ms internal steps per
+# 2D encoded workload (the benchmark): 400x150 at 20 m, 2 ms x 2000 recorded samples (two 1 ms internal steps per
 # sample to respect the stability limit at 6000 m/s), 80 shots encoded into supergathers of
 # 8, 16 posterior samples x 10 supergathers.
 C2 = Config("2d-400x150-80shot-s8-16x10", 2, 150, 400, 20.0, 20, 1e-3, 4000, 2, 6.0, 80, 2000.0, 6000.0,
             shots_per_group=8, groups=10, nsample=16)
-# configs[2]: uneven 2D grids 256x128, 512x200, 800x200 at 10 m, 2000 steps, salt models.
+# 2D uneven workload: grids 256x128, 512x200, 800x200 at 10 m, 2000 steps, salt models.
 C3_SIZES = ((128, 256), (200, 512), (200, 800))  # (nz, nx)
 C3 = Config("2d-uneven-salt-32", 2, 128, 256, 10.0, 20, 1e-3, 2000, 1, 10.0, 16, 1500.0, 4500.0,
             shots_per_group=8, groups=1, nsample=32, extra={"sizes": C3_SIZES, "ckpt_every": 10})
-# configs[4]: 3D 200x200x100 at 25 m, dt 2 ms, 1500 steps, 10-cell sponge, 64 shots in 4
+# 3D workload: 200x200x100 at 25 m, dt 2 ms, 1500 steps, 10-cell sponge, 64 shots in 4
 # supergathers of 16, 8 posterior samples.
 C5 = Config("3d-200x200x100-64shot-s16-8x4", 3, 100, 200, 25.0, 10, 2e-3, 1500, 1, 4.0, 64, 1500.0, 4500.0,
             ny=200, shots_per_group=16, groups=4, nsample=8)
