@@ -89,8 +89,12 @@ def main():
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d"],
-                    help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations")
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error"],
+                    help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
+                         "equal-error: posterior samples/hour of plain, encoded and preconditioned chains at equal "
+                         "posterior-mean RMSE (several minutes)")
+    ap.add_argument("--plain-steps", type=int, default=20, help="equal-error: plain-chain steps that set the target")
+    ap.add_argument("--max-steps", type=int, default=60, help="equal-error: steps of the encoded chains")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
@@ -101,6 +105,12 @@ def main():
     from paper_2512_12797_amd import fwi, problems
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "equal-error":
+        from paper_2512_12797_amd import chains
+        res = chains.equal_error(seed=args.seed, plain_steps=args.plain_steps, max_steps=args.max_steps, log=log)
+        res.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32"})
+        print(json.dumps(res), flush=True)
+        return
     dev = torch.device("cuda:0")
     cfg = W.C2 if args.workload == "2d" else W.C5
     nt = args.nt or cfg.nt

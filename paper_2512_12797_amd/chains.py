@@ -1,0 +1,271 @@
+"""Posterior samples per hour at equal posterior-model error.
+
+Three gradient estimators drive the same clean-space Langevin refinement (Eqs. 8-9) of
+16 posterior samples on the 2D encoded workload (400 x 150 at 20 m, 80 shots):
+
+* plain: the full-shot gradient of Eq. 1 (every shot its own simulation);
+* encoded: the Eq. 6 estimate from G = 10 supergathers of s = 8 +-1-encoded shots,
+  redrawn every step (what the benchmark times);
+* preconditioned: the encoded estimate mapped by the learned U-Net towards the
+  full-shot gradient, with the plain-gradient guard.
+
+The target posterior-mean RMSE (m/s against the true model, physical grid) is the one the
+plain chain reaches after a fixed number of steps; each form's wall time to reach it is
+its number of steps times its measured time per step, and samples per hour follow.  The
+plain form is timed two ways: as a naive solver (one simulation per launch, samples one
+after the other; extrapolated from a few timed calls) and batched like the encoded form.
+Each chain's trajectory is computed with the batched library (the estimator, not the
+launch pattern, decides the trajectory).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+import workloads as W
+
+from . import fwi, precond, problems
+from .unet import UNet
+
+
+class Survey:
+    """The 2D encoded workload: grid, acquisition, true and starting models, noisy data."""
+
+    def __init__(self, seed=1000, start_sigma=6.0, device="cuda", log=print):
+        self.cfg = cfg = W.C2
+        self.dev = device
+        self.log = log
+        self.grid = problems.grid_of(cfg)
+        self.wav = W.ricker(cfg.freq, cfg.dt, cfg.nt)
+        self.shots = problems.shot_cells(cfg, self.grid)
+        self.rec = problems.receiver_cells(cfg, self.grid)
+        self.nrec = len(self.rec)
+        self.nt_rec = cfg.nt_rec
+        self.vtrue = W.thrust_2d(cfg.nz, cfg.nx, seed=seed)
+        # starting model: the truth Gaussian-smoothed by start_sigma cells (120 m by default:
+        # from the 320 m smoothing of the throughput benchmark the 6 Hz descent is
+        # cycle-skipped and lowers the misfit while moving away from the truth)
+        self.start_sigma = start_sigma
+        self.vstart = np.clip(W.smooth(self.vtrue, start_sigma), cfg.vmin, cfg.vmax)
+        self.t_fwd = fwi.time_axis(cfg.dt, cfg.nt, cfg.rec_every, -1)
+        self.t_grad = fwi.time_axis(cfg.dt, cfg.nt, cfg.rec_every, 0)
+        self.ws = None
+        self.d_shots, self.sigma = self.observed(self.vtrue, seed)
+
+    def workspace(self, batch, t):
+        n = fwi.fwi_workspace_size(batch, t)
+        if self.ws is None or self.ws.numel() < n:
+            self.ws = None
+            torch.cuda.empty_cache()
+            self.ws = torch.empty(n, dtype=torch.uint8, device=self.dev)
+        return self.ws
+
+    def observed(self, vtrue, seed, noise=0.01):
+        """Single-shot data of a true model with Gaussian noise at `noise` x clean RMS."""
+        b = problems.single_shot_batch(self.cfg, self.grid, self.shots, self.wav)
+        d = torch.empty(len(self.shots), self.nt_rec, self.nrec, device=self.dev)
+        fwi.fwi_forward(b, self.t_fwd, torch.tensor(vtrue.ravel(), dtype=torch.float32, device=self.dev), d,
+                        self.workspace(b, self.t_fwd))
+        g = torch.Generator(device=self.dev)
+        g.manual_seed(seed)
+        sigma = noise * float(d.pow(2).mean().sqrt())
+        d += sigma * torch.randn(d.shape, generator=g, device=self.dev)
+        return d, sigma
+
+    # ---------------------------------------------------------------- gradients
+    def full_gradient(self, v, nsample, d_shots=None, per_launch=2):
+        """Full-shot gradient of each sample (device [nsample, nphys]); `per_launch`
+        samples (x 80 single-shot simulations) per batched launch sequence."""
+        d_shots = self.d_shots if d_shots is None else d_shots
+        nphys = self.grid.nphys
+        out = torch.empty(nsample, nphys, device=self.dev)
+        for k0 in range(0, nsample, per_launch):
+            m = min(per_launch, nsample - k0)
+            b = problems.single_shot_batch(self.cfg, self.grid, self.shots, self.wav, nsample=m)
+            dobs = d_shots.reshape(1, -1).expand(m, -1).reshape(-1).contiguous()
+            fwi.fwi_gradient(b, self.t_grad, v[k0:k0 + m].reshape(-1).contiguous(), dobs, 1.0 / self.sigma ** 2,
+                             None, None, None, out[k0:k0 + m].reshape(-1), None, self.workspace(b, self.t_grad))
+        return out
+
+    def encoded_gradient(self, v, nsample, seed, step, d_shots=None):
+        """Eq. 6 estimate from G = 10 supergathers of 8 encoded shots per sample."""
+        d_shots = self.d_shots if d_shots is None else d_shots
+        cfg = self.cfg
+        b, groups = problems.encoded_batch(cfg, [self.grid] * nsample, self.wav, seed, step)
+        ptr, shot, w = problems.encode_tables(groups, cfg.shots_per_group)
+        d_enc = torch.empty(b.nsim, self.nt_rec, self.nrec, device=self.dev)
+        fwi.fwi_encode(d_shots, torch.from_numpy(ptr).to(self.dev), torch.from_numpy(shot).to(self.dev),
+                       torch.from_numpy(w).to(self.dev), d_enc)
+        out = torch.empty(nsample, self.grid.nphys, device=self.dev)
+        fwi.fwi_gradient(b, self.t_grad, v.reshape(-1).contiguous(), d_enc, 1.0 / self.sigma ** 2,
+                         [g[2] for g in groups], None, None, out.reshape(-1), None, self.workspace(b, self.t_grad))
+        return out
+
+
+# ------------------------------------------------------------------ network
+
+PAD_ROWS = 2  # 150 rows -> 152, divisible by 2^3 for a 4-level U-Net
+
+
+def net_input(g_enc, v):
+    """[S, nz, nx] encoded gradients and models -> (x [S, nz+2, nx, 2], res, scale)."""
+    scale = g_enc.flatten(1).pow(2).mean(1).sqrt() + 1e-30
+    gn = g_enc / scale[:, None, None]
+    vn = (v - 3000.0) / 1500.0
+    x = torch.stack([gn, vn], dim=-1)
+    x = torch.nn.functional.pad(x, (0, 0, 0, 0, 0, PAD_ROWS))
+    return x.contiguous(), x[..., 0].contiguous(), scale
+
+
+def make_pairs(sv: Survey, ntruth=32, fractions=(0.0, 0.35, 0.7), nenc=2, seed0=50000):
+    """Training pairs at the workload's geometry: for seeded thrust models (not the test
+    model), models between a smoothed start and the truth, their encoded gradients
+    (input) and full-shot gradients (target), both scaled by the encoded gradient's RMS."""
+    cfg = sv.cfg
+    xs, tgs = [], []
+    t0 = time.perf_counter()
+    for i in range(ntruth):
+        truth = W.thrust_2d(cfg.nz, cfg.nx, seed=seed0 + i)
+        start = np.clip(W.smooth(truth, sv.start_sigma), cfg.vmin, cfg.vmax)
+        d_i, _ = sv.observed(truth, seed0 + i)
+        ms = np.stack([start + f * (truth - start) for f in fractions])
+        v = torch.tensor(ms.reshape(len(fractions), -1), dtype=torch.float32, device=sv.dev)
+        gfull = sv.full_gradient(v, len(fractions), d_shots=d_i).view(len(fractions), cfg.nz, cfg.nx)
+        for e in range(nenc):
+            genc = sv.encoded_gradient(v, len(fractions), seed0 + i, 1000 + e, d_shots=d_i)
+            genc = genc.view(len(fractions), cfg.nz, cfg.nx)
+            x, _, scale = net_input(genc, v.view(len(fractions), cfg.nz, cfg.nx))
+            xs.append(x)
+            tgs.append(torch.nn.functional.pad(gfull / scale[:, None, None], (0, 0, 0, PAD_ROWS)))
+        sv.log("pairs: %d/%d truths, %.1f s" % (i + 1, ntruth, time.perf_counter() - t0))
+    x = torch.cat(xs)
+    return {"x": x, "res": x[..., 0].contiguous(), "target": torch.cat(tgs).contiguous()}
+
+
+def precondition(net, g_enc, v):
+    """Network estimate of the full-shot gradient, guarded by the plain encoded one."""
+    S, nz, nx = g_enc.shape
+    x, res, scale = net_input(g_enc, v)
+    pred = precond.predict(net, x, res)[:, :nz, :] * scale[:, None, None]
+    out, keep = precond.guard(pred, g_enc)
+    return out, keep
+
+
+# -------------------------------------------------------------------- chains
+
+def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16):
+    """Langevin refinement of `nsample` samples from the smoothed start; returns the
+    posterior-mean RMSE after each step, the mean wall time per step (direct launches,
+    steps after the first: the first carries one-time host costs) and, for the
+    preconditioned form, how many samples kept the network's gradient at each step."""
+    cfg = sv.cfg
+    nz, nx = cfg.nz, cfg.nx
+    v = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
+    off = np.arange(nsample + 1, dtype=np.int64) * sv.grid.nphys
+    vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
+    lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+    rmse, kept = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        if t == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        if form == "plain":
+            g = sv.full_gradient(v, nsample)
+        else:
+            g = sv.encoded_gradient(v, nsample, seed, t)
+            if form == "preconditioned":
+                g, keep = precondition(net, g.view(nsample, nz, nx), v.view(nsample, nz, nx))
+                g = g.reshape(nsample, -1).contiguous()
+                kept.append(int(keep.sum()))
+        fwi.fwi_langevin(off, v.reshape(-1), g.reshape(-1).contiguous(), None, seed, t, eta, math.sqrt(2 * eta), lo,
+                         hi)
+        rmse.append(float((v.double().mean(0) - vt).pow(2).mean().sqrt()))
+    torch.cuda.synchronize()
+    return rmse, (time.perf_counter() - t0) / max(1, steps - 1), kept
+
+
+def time_naive_plain(sv: Survey, v, ncall=8):
+    """Seconds per Langevin step of a naive plain solver: every shot of every sample its
+    own gradient call (one simulation per launch), one after the other; extrapolated from
+    `ncall` timed calls."""
+    cfg = sv.cfg
+    calls = []
+    for s in range(ncall):
+        b = fwi.Batch([sv.grid], [0], [([int(sv.shots[s])], [1.0])], [sv.rec], sv.wav)
+        calls.append((b, sv.d_shots[s].reshape(-1).contiguous()))
+    ws = torch.empty(fwi.fwi_workspace_size(calls[0][0], sv.t_grad), dtype=torch.uint8, device=sv.dev)
+    grad = torch.empty(sv.grid.nphys, device=sv.dev)
+    vv = v[0].contiguous()
+    fwi.fwi_gradient(calls[0][0], sv.t_grad, vv, calls[0][1], 1.0, None, None, None, grad, None, ws)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, d in calls:
+        fwi.fwi_gradient(b, sv.t_grad, vv, d, 1.0, None, None, None, grad, None, ws)
+    torch.cuda.synchronize()
+    per_call = (time.perf_counter() - t0) / ncall
+    return per_call * len(sv.shots) * 16
+
+
+def first_reaching(rmse, target):
+    for i, r in enumerate(rmse):
+        if r <= target:
+            return i + 1
+    return None
+
+
+def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=1500, max_update=30.0,
+                start_sigma=6.0, log=print):
+    """The whole comparison; returns a dict (one JSON object)."""
+    sv = Survey(seed=seed, start_sigma=start_sigma, log=log)
+    nsample = 16
+    v0 = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
+    g0 = sv.full_gradient(v0[:1], 1)
+    eta = max_update / float(g0.abs().max())  # the largest first update, m/s; all forms alike
+    log("eta %.3e" % eta)
+
+    naive_s = time_naive_plain(sv, v0)
+    log("plain, naive solver: %.1f s per step (extrapolated)" % naive_s)
+    r_plain, s_plain, _ = run_chain(sv, "plain", plain_steps, eta, seed)
+    target = r_plain[-1]
+    log("plain: %d steps, %.2f s per step, RMSE %.1f -> %.1f m/s" % (plain_steps, s_plain, r_plain[0], target))
+    r_enc, s_enc, _ = run_chain(sv, "encoded", max_steps, eta, seed)
+    log("encoded: %.3f s per step, RMSE after %d steps %.1f" % (s_enc, max_steps, r_enc[-1]))
+
+    t0 = time.perf_counter()
+    pairs = make_pairs(sv, ntruth=ntruth)
+    P = pairs["x"].shape[0]
+    net = UNet(chans=(32, 64, 128, 256), seed=0)
+    hist = precond.train(net, pairs, np.arange(P), steps=train_steps, batch=8, lr=2e-3, lr_final=2e-4, log=log)
+    t_train = time.perf_counter() - t0
+    del pairs
+    r_pre, s_pre, kept = run_chain(sv, "preconditioned", max_steps, eta, seed, net=net)
+    log("preconditioned: %.3f s per step, RMSE after %d steps %.1f" % (s_pre, max_steps, r_pre[-1]))
+
+    def entry(rmse, s_step, label):
+        n = first_reaching(rmse, target)
+        wall = None if n is None else n * s_step
+        return {"steps_to_target": n, "s_per_step": round(s_step, 4), "wall_s": None if wall is None else round(wall, 2),
+                "samples_per_hour": None if wall is None else round(nsample / wall * 3600, 1), "timing": label,
+                "rmse": [round(r, 2) for r in rmse]}
+
+    return {
+        "metric": "posterior samples/hour at equal posterior-mean RMSE", "unit": "samples/hour",
+        "workload": "2d-400x150-thrust-80shot: 16 samples from a start smoothed by %g cells, Langevin eta=%.3e "
+                    "(largest first update %g m/s), nu=sqrt(2 eta)" % (start_sigma, eta, max_update),
+        "target_rmse_mps": round(target, 2), "start_rmse_mps": round(float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2))), 2),
+        "plain_steps": plain_steps,
+        "forms": {
+            "plain_naive": {**entry(r_plain, naive_s, "one simulation per launch, samples in turn; extrapolated "
+                                                      "from 8 timed single-shot gradients"), "rmse": None},
+            "plain_batched": entry(r_plain, s_plain, "measured: 2 samples x 80 single-shot simulations per launch"),
+            "encoded": entry(r_enc, s_enc, "measured: 16 samples x 10 supergathers of 8 in one launch per step"),
+            "preconditioned": {**entry(r_pre, s_pre, "measured: encoded + U-Net inference + guard"),
+                               "network_kept_fraction": round(float(np.mean(kept)) / nsample, 3) if kept else None,
+                               "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]]},
+        },
+    }
