@@ -108,6 +108,35 @@ fwi_status fwi_nn_pack_weights(const float *wf, int32_t cout, int32_t cin, uint1
 /* Round f32 to bf16 (n elements). */
 fwi_status fwi_nn_to_bf16(const float *x, int64_t n, uint16_t *out, void *stream);
 
+/*
+ * Network input of the gradient preconditioner (form: learned map from the encoded
+ * gradient to the full-shot gradient).  For nimg images g (device f32 [nimg][h][w]) with
+ * models v (device f32, same layout):
+ *   scale_i = sqrt(mean over the image of g^2) (FP64, fixed order; 1 for an all-zero
+ *             image), or scale_in[i] when scale_in (device f32 [nimg]) is given;
+ *   x_bf16  (device bf16 [nimg][hp][w][16], 16-byte aligned, nullable): channel 0 = g/scale_i, channel 1 =
+ *             (v - v_shift)/v_scale, channels 2..15 and rows h..hp-1 zero;
+ *   res     (device f32 [nimg][hp][w], nullable): g/scale_i (the residual the network's
+ *             output adds to), rows h..hp-1 zero.
+ * scale_out (device f32 [nimg], nullable if scale_in is given) receives the scales.  With
+ * scale_in and res only (v nullable), this scales training targets by the inputs' scales.
+ * Rows are padded so that hp fits the network's pooling depth.
+ */
+fwi_status fwi_nn_prep(const float *g, const float *v, int32_t nimg, int32_t h, int32_t w, int32_t hp,
+                       float v_shift, float v_scale, const float *scale_in, float *scale_out, uint16_t *x_bf16,
+                       float *res, void *stream);
+
+/*
+ * Guarded use of the network's gradient: p_i = scale_i * channel 0 of pred (device f32
+ * [nimg][hp][w][c]) over the first h rows is kept when its cosine with the plain gradient
+ * g_i (device f32 [nimg][h][w]) is >= cos_min and |p_i|/|g_i| lies in [ratio_lo,
+ * ratio_hi] (FP64 statistics, fixed order); otherwise g_i is used.  out: device f32
+ * [nimg][h][w]; keep: device int32 [nimg] (1 = network output kept).
+ */
+fwi_status fwi_nn_guard(const float *pred, int32_t c, const float *scale, const float *g, int32_t nimg, int32_t h,
+                        int32_t w, int32_t hp, float cos_min, float ratio_lo, float ratio_hi, float *out,
+                        int32_t *keep, void *stream);
+
 /* Thread-local detail of the last non-OK status returned by an fwi_nn_* call. */
 const char *fwi_nn_last_error(void);
 

@@ -182,3 +182,38 @@ class UNetOracle:
             if i > 0:
                 d_skip[i - 1] = d_skip[i - 1] + 0.25 * up2(dx)
         return grads
+
+
+def prep_input(g, v, hp, v_shift, v_scale, scale=None):
+    """Network input of the gradient preconditioner, FP64: per image scale = RMS of g (1 for
+    an all-zero image) unless given; channel 0 = g/scale, channel 1 = (v - v_shift)/v_scale
+    (both rounded to BF16 as network inputs), rows padded with zeros to hp.  Returns
+    (x [N, hp, W, 2] BF16-rounded, res [N, hp, W] = g/scale unrounded, scale [N])."""
+    g = np.asarray(g, dtype=np.float64)
+    n, h, w = g.shape
+    if scale is None:
+        rms = np.sqrt((g.reshape(n, -1) ** 2).mean(1))
+        scale = np.where(rms > 0, rms, 1.0)
+    scale = np.asarray(scale, dtype=np.float64)
+    res = np.zeros((n, hp, w))
+    res[:, :h] = g / scale[:, None, None]
+    x = np.zeros((n, hp, w, 2))
+    x[:, :h, :, 0] = res[:, :h]
+    if v is not None:
+        x[:, :h, :, 1] = (np.asarray(v, dtype=np.float64) - v_shift) / v_scale
+    return bf16(x), res, scale
+
+
+def guard(pred0, scale, g, cos_min, ratio_lo, ratio_hi):
+    """Guarded gradient: p = scale * pred0 (first h rows of [N, hp, W]) is kept when
+    cos(p, g) >= cos_min and |p|/|g| is in [ratio_lo, ratio_hi], else g is used."""
+    g = np.asarray(g, dtype=np.float64)
+    n, h, w = g.shape
+    p = np.asarray(pred0, dtype=np.float64)[:, :h] * np.asarray(scale, dtype=np.float64)[:, None, None]
+    pf, gf = p.reshape(n, -1), g.reshape(n, -1)
+    pn, gn = np.linalg.norm(pf, axis=1), np.linalg.norm(gf, axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cos = (pf * gf).sum(1) / (pn * gn)
+        ratio = pn / gn
+    keep = (pn > 0) & (gn > 0) & (cos >= cos_min) & (ratio >= ratio_lo) & (ratio <= ratio_hi)
+    return np.where(keep[:, None, None], p, g), keep

@@ -110,48 +110,36 @@ class Survey:
 PAD_ROWS = 2  # 150 rows -> 152, divisible by 2^3 for a 4-level U-Net
 
 
-def net_input(g_enc, v):
-    """[S, nz, nx] encoded gradients and models -> (x [S, nz+2, nx, 2], res, scale)."""
-    scale = g_enc.flatten(1).pow(2).mean(1).sqrt() + 1e-30
-    gn = g_enc / scale[:, None, None]
-    vn = (v - 3000.0) / 1500.0
-    x = torch.stack([gn, vn], dim=-1)
-    x = torch.nn.functional.pad(x, (0, 0, 0, 0, 0, PAD_ROWS))
-    return x.contiguous(), x[..., 0].contiguous(), scale
-
-
 def make_pairs(sv: Survey, ntruth=32, fractions=(0.0, 0.35, 0.7), nenc=2, seed0=50000):
     """Training pairs at the workload's geometry: for seeded thrust models (not the test
     model), models between a smoothed start and the truth, their encoded gradients
     (input) and full-shot gradients (target), both scaled by the encoded gradient's RMS."""
     cfg = sv.cfg
-    xs, tgs = [], []
+    nf, hp = len(fractions), cfg.nz + PAD_ROWS
+    xs, rs, tgs = [], [], []
     t0 = time.perf_counter()
     for i in range(ntruth):
         truth = W.thrust_2d(cfg.nz, cfg.nx, seed=seed0 + i)
         start = np.clip(W.smooth(truth, sv.start_sigma), cfg.vmin, cfg.vmax)
         d_i, _ = sv.observed(truth, seed0 + i)
         ms = np.stack([start + f * (truth - start) for f in fractions])
-        v = torch.tensor(ms.reshape(len(fractions), -1), dtype=torch.float32, device=sv.dev)
-        gfull = sv.full_gradient(v, len(fractions), d_shots=d_i).view(len(fractions), cfg.nz, cfg.nx)
+        v = torch.tensor(ms.reshape(nf, -1), dtype=torch.float32, device=sv.dev)
+        gfull = sv.full_gradient(v, nf, d_shots=d_i).view(nf, cfg.nz, cfg.nx)
         for e in range(nenc):
-            genc = sv.encoded_gradient(v, len(fractions), seed0 + i, 1000 + e, d_shots=d_i)
-            genc = genc.view(len(fractions), cfg.nz, cfg.nx)
-            x, _, scale = net_input(genc, v.view(len(fractions), cfg.nz, cfg.nx))
-            xs.append(x)
-            tgs.append(torch.nn.functional.pad(gfull / scale[:, None, None], (0, 0, 0, PAD_ROWS)))
+            genc = sv.encoded_gradient(v, nf, seed0 + i, 1000 + e, d_shots=d_i).view(nf, cfg.nz, cfg.nx)
+            x16, res, scale = precond.prepare(genc, v.view(nf, cfg.nz, cfg.nx), hp)
+            xs.append(x16)
+            rs.append(res)
+            tgs.append(precond.scaled(gfull, scale, hp))
         sv.log("pairs: %d/%d truths, %.1f s" % (i + 1, ntruth, time.perf_counter() - t0))
-    x = torch.cat(xs)
-    return {"x": x, "res": x[..., 0].contiguous(), "target": torch.cat(tgs).contiguous()}
+    return {"x16": torch.cat(xs), "res": torch.cat(rs), "target": torch.cat(tgs)}
 
 
 def precondition(net, g_enc, v):
     """Network estimate of the full-shot gradient, guarded by the plain encoded one."""
     S, nz, nx = g_enc.shape
-    x, res, scale = net_input(g_enc, v)
-    pred = precond.predict(net, x, res)[:, :nz, :] * scale[:, None, None]
-    out, keep = precond.guard(pred, g_enc)
-    return out, keep
+    x16, res, scale = precond.prepare(g_enc, v, nz + PAD_ROWS)
+    return precond.guard(precond.predict(net, x16, res), scale, g_enc)
 
 
 # -------------------------------------------------------------------- chains
@@ -238,7 +226,7 @@ def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=
 
     t0 = time.perf_counter()
     pairs = make_pairs(sv, ntruth=ntruth)
-    P = pairs["x"].shape[0]
+    P = pairs["x16"].shape[0]
     net = UNet(chans=(32, 64, 128, 256), seed=0)
     hist = precond.train(net, pairs, np.arange(P), steps=train_steps, batch=8, lr=2e-3, lr_final=2e-4, log=log)
     t_train = time.perf_counter() - t0

@@ -452,6 +452,110 @@ __global__ void k_to_bf16(const float *__restrict__ x, int64_t n, uint16_t *__re
 
 // ------------------------------------------------------------------- host
 
+// --------------------------------------------------- network input and guard
+
+// Per-image RMS of g over its h x w cells, in FP64 with a fixed reduction order (one block
+// per image): scale = sqrt(mean g^2), or 1 for an all-zero image.
+__global__ __launch_bounds__(256) void k_prep_scale(const float *__restrict__ g, int64_t hw, float *__restrict__ scale)
+{
+    const float *gi = g + (int64_t)blockIdx.x * hw;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < hw; k += 256) {
+        const double x = gi[k];
+        s += x * x;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rms = sqrt(red[0] / (double)hw);
+        scale[blockIdx.x] = rms > 0.0 ? (float)rms : 1.0f;
+    }
+}
+
+// Network input of image i, rows padded from h to hp with zeros:
+//   x[i][y][x][0] = bf16(g / scale_i), x[i][y][x][1] = bf16((v - v_shift) / v_scale),
+//   channels 2..15 zero;  res[i][y][x] = g / scale_i (the residual added to the output).
+__global__ void k_prep_write(const float *__restrict__ g, const float *__restrict__ v, int nimg, int h, int w, int hp,
+                             float v_shift, float v_scale, const float *__restrict__ scale, uint16_t *__restrict__ x,
+                             float *__restrict__ res)
+{
+    const int64_t per = (int64_t)hp * w, total = (int64_t)nimg * per;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t img = i / per, r = i % per;
+        const int y = (int)(r / w), xx = (int)(r % w);
+        float gn = 0.0f, vn = 0.0f;
+        if (y < h) {
+            const int64_t src = (img * h + y) * w + xx;
+            gn = g[src] / scale[img];
+            if (v) vn = (v[src] - v_shift) / v_scale;
+        }
+        if (res) res[i] = gn;
+        if (x) {
+            uint4 lo = make_uint4((uint32_t)f2bf(gn) | ((uint32_t)f2bf(vn) << 16), 0u, 0u, 0u);
+            uint4 *o = reinterpret_cast<uint4 *>(x + i * 16);
+            o[0] = lo;
+            o[1] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
+// Guard statistics of image i: p = pred[i][y][x][0] * scale_i over the h physical rows
+// against the plain gradient g_i, in FP64 with a fixed reduction order; keeps the network
+// output when cos(p, g) >= cos_min and |p| / |g| lies in [ratio_lo, ratio_hi].
+__global__ __launch_bounds__(256) void k_guard_stats(const float *__restrict__ pred, int C,
+                                                     const float *__restrict__ scale, const float *__restrict__ g,
+                                                     int h, int w, int hp, float cos_min, float ratio_lo,
+                                                     float ratio_hi, int32_t *__restrict__ keep)
+{
+    const int img = blockIdx.x;
+    const int64_t hw = (int64_t)h * w;
+    const double sc = scale[img];
+    double spg = 0.0, spp = 0.0, sgg = 0.0;
+    for (int64_t k = threadIdx.x; k < hw; k += 256) {
+        const double p = sc * (double)pred[((int64_t)img * hp * w + k) * C];
+        const double q = g[(int64_t)img * hw + k];
+        spg += p * q;
+        spp += p * p;
+        sgg += q * q;
+    }
+    __shared__ double r0[256], r1[256], r2[256];
+    r0[threadIdx.x] = spg;
+    r1[threadIdx.x] = spp;
+    r2[threadIdx.x] = sgg;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            r0[threadIdx.x] += r0[threadIdx.x + o];
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+            r2[threadIdx.x] += r2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double pn = sqrt(r1[0]), gn = sqrt(r2[0]);
+        const bool ok = pn > 0.0 && gn > 0.0 && r0[0] / (pn * gn) >= (double)cos_min && pn / gn >= (double)ratio_lo &&
+                        pn / gn <= (double)ratio_hi;
+        keep[img] = ok ? 1 : 0;
+    }
+}
+
+// out[i][y][x] = keep_i ? pred[i][y][x][0] * scale_i : g[i][y][x]  (physical rows only).
+__global__ void k_guard_write(const float *__restrict__ pred, int C, const float *__restrict__ scale,
+                              const float *__restrict__ g, int nimg, int h, int w, int hp,
+                              const int32_t *__restrict__ keep, float *__restrict__ out)
+{
+    const int64_t hw = (int64_t)h * w, total = (int64_t)nimg * hw;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t img = i / hw, k = i % hw;
+        out[i] = keep[img] ? pred[((int64_t)img * hp * w + k) * C] * scale[img] : g[i];
+    }
+}
+
 thread_local std::string g_nn_err;
 
 fwi_status nn_fail(fwi_status s, const char *fmt, ...)
@@ -651,6 +755,45 @@ fwi_status fwi_nn_to_bf16(const float *x, int64_t n, uint16_t *out, void *stream
 {
     if (!x || !out || n <= 0) return nn_fail(FWI_E_ARG, "to_bf16: bad arguments");
     k_to_bf16<<<grid_for(n), 256, 0, (hipStream_t)stream>>>(x, n, out);
+    NN_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+fwi_status fwi_nn_prep(const float *g, const float *v, int32_t nimg, int32_t h, int32_t w, int32_t hp,
+                       float v_shift, float v_scale, const float *scale_in, float *scale_out, uint16_t *x_bf16,
+                       float *res, void *stream)
+{
+    if (!g || nimg < 1 || h < 1 || w < 1 || hp < h) return nn_fail(FWI_E_ARG, "prep: bad shape");
+    if (!scale_in && !scale_out) return nn_fail(FWI_E_ARG, "prep: need scale_in or scale_out");
+    if (!x_bf16 && !res) return nn_fail(FWI_E_ARG, "prep: no output");
+    if (x_bf16 && (!v || !(v_scale != 0.0f))) return nn_fail(FWI_E_ARG, "prep: the network input needs v and v_scale != 0");
+    if ((uintptr_t)x_bf16 % 16) return nn_fail(FWI_E_ARG, "prep: x_bf16 must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const float *scale = scale_in;
+    if (!scale_in) {
+        k_prep_scale<<<nimg, 256, 0, st>>>(g, (int64_t)h * w, scale_out);
+        NN_TRY(hipGetLastError());
+        scale = scale_out;
+    } else if (scale_out) {
+        NN_TRY(hipMemcpyAsync(scale_out, scale_in, sizeof(float) * nimg, hipMemcpyDeviceToDevice, st));
+    }
+    const int64_t n = (int64_t)nimg * hp * w;
+    k_prep_write<<<grid_for(n), 256, 0, st>>>(g, v, nimg, h, w, hp, v_shift, v_scale, scale, x_bf16, res);
+    NN_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+fwi_status fwi_nn_guard(const float *pred, int32_t c, const float *scale, const float *g, int32_t nimg, int32_t h,
+                        int32_t w, int32_t hp, float cos_min, float ratio_lo, float ratio_hi, float *out,
+                        int32_t *keep, void *stream)
+{
+    if (!pred || !scale || !g || !out || !keep || c < 1 || nimg < 1 || h < 1 || w < 1 || hp < h)
+        return nn_fail(FWI_E_ARG, "guard: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    k_guard_stats<<<nimg, 256, 0, st>>>(pred, c, scale, g, h, w, hp, cos_min, ratio_lo, ratio_hi, keep);
+    NN_TRY(hipGetLastError());
+    const int64_t n = (int64_t)nimg * h * w;
+    k_guard_write<<<grid_for(n), 256, 0, st>>>(pred, c, scale, g, nimg, h, w, hp, keep, out);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }

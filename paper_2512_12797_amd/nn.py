@@ -38,6 +38,9 @@ def lib():
             "fwi_nn_adam": [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, P],
             "fwi_nn_pack_weights": [P, C.c_int32, C.c_int32, P, P, P],
             "fwi_nn_to_bf16": [P, C.c_int64, P, P],
+            "fwi_nn_prep": [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, P, P, P, P, P],
+            "fwi_nn_guard": [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float,
+                             C.c_float, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -130,3 +133,13 @@ def pack_weights(wf, cout, cin, w_bf16, wt_bf16):
 
 def to_bf16(x, out):
     _ok(lib().fwi_nn_to_bf16(_p(x), x.numel(), _p(out), _s()))
+
+
+def prep(g, v, nimg, h, w, hp, v_shift, v_scale, scale_in=None, scale_out=None, x_bf16=None, res=None):
+    _ok(lib().fwi_nn_prep(_p(g), _p(v), nimg, h, w, hp, v_shift, v_scale, _p(scale_in), _p(scale_out), _p(x_bf16),
+                          _p(res), _s()))
+
+
+def guard(pred, c, scale, g, nimg, h, w, hp, cos_min, ratio_lo, ratio_hi, out, keep):
+    _ok(lib().fwi_nn_guard(_p(pred), c, _p(scale), _p(g), nimg, h, w, hp, cos_min, ratio_lo, ratio_hi, _p(out),
+                           _p(keep), _s()))

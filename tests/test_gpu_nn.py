@@ -220,3 +220,56 @@ def test_network_forward_backward_vs_oracle(N, chans, hw):
         assert ew < 1e-2 and eb < 1e-2, (k, ew, eb)
     say("  parameter-gradient rel: median %.2e, worst %.2e over %d layers" % (np.median(errs), max(errs), len(order)))
     assert np.median(errs) < 3e-3
+
+
+# ------------------------------------------------ preconditioner input and guard
+
+def test_prep_matches_oracle():
+    from paper_2512_12797_amd import nn
+    r = np.random.default_rng(11)
+    n, h, w, hp = 5, 37, 70, 40
+    g = (r.standard_normal((n, h, w)) * 10.0 ** r.uniform(-6, 3, (n, 1, 1))).astype(np.float32)
+    g[3] = 0.0  # an all-zero image keeps scale 1
+    v = r.uniform(1500, 4500, (n, h, w)).astype(np.float32)
+    tg, tv = torch.tensor(g, device="cuda"), torch.tensor(v, device="cuda")
+    x16 = torch.empty(n, hp, w, 16, dtype=torch.int16, device="cuda")
+    res = torch.empty(n, hp, w, device="cuda")
+    scale = torch.empty(n, device="cuda")
+    nn.prep(tg, tv, n, h, w, hp, 3000.0, 1500.0, None, scale, x16, res)
+    ox, ores, oscale = U.prep_input(g, v, hp, 3000.0, 1500.0)
+    assert rel(scale.cpu().numpy(), oscale) < 1e-6 and scale[3].item() == 1.0
+    assert rel(res.cpu().numpy(), ores) < 1e-6
+    xg = nn.as_float(x16).cpu().numpy().astype(np.float64)
+    assert np.all(xg[..., 2:] == 0)
+    # BF16 inputs: within one BF16 ulp of the oracle's rounding of its FP64 value
+    for c in range(2):
+        d = np.abs(xg[..., c] - ox[..., c])
+        assert np.all(d <= 2.0 ** -7 * np.abs(ox[..., c]) + 1e-30)
+    # targets scaled by given scales, v absent
+    t2 = torch.empty(n, hp, w, device="cuda")
+    nn.prep(tg, None, n, h, w, hp, 3000.0, 1500.0, scale, None, None, t2)
+    assert torch.equal(t2, res)
+
+
+def test_guard_matches_oracle():
+    from paper_2512_12797_amd import nn
+    r = np.random.default_rng(12)
+    n, h, w, hp, C = 6, 30, 50, 32, 32
+    g = r.standard_normal((n, h, w)).astype(np.float32)
+    scale = r.uniform(0.5, 2.0, n).astype(np.float32)
+    pred = np.zeros((n, hp, w, C), dtype=np.float32)
+    base = g / scale[:, None, None]
+    pred[0, :h, :, 0] = base[0] + 0.3 * r.standard_normal((h, w))   # agrees: kept
+    pred[1, :h, :, 0] = -base[1]                                      # opposite: cosine < 0
+    pred[2, :h, :, 0] = 10.0 * base[2]                                # too large: ratio > 5
+    pred[3, :h, :, 0] = 0.1 * base[3]                                 # too small: ratio < 0.2
+    pred[4] = 0.0                                                     # zero: rejected
+    pred[5, :h, :, 0] = 2.0 * base[5] + r.standard_normal((h, w))     # kept
+    pred[:, h:, :, 0] = 1e6                                           # padding rows are ignored
+    out = torch.empty(n, h, w, device="cuda")
+    keep = torch.empty(n, dtype=torch.int32, device="cuda")
+    nn.guard(torch.tensor(pred, device="cuda"), C, torch.tensor(scale, device="cuda"), torch.tensor(g, device="cuda"),
+             n, h, w, hp, 0.3, 0.2, 5.0, out, keep)
+    oo, okeep = U.guard(pred[..., 0], scale, g, 0.3, 0.2, 5.0)
+    assert list(keep.cpu().numpy().astype(bool)) == list(okeep) == [True, False, False, False, False, True]
+    assert rel(out.cpu().numpy(), oo) < 1e-6
