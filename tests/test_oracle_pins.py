@@ -4,8 +4,10 @@ Each test checks the oracle against mathematics the paper and the discretization
 exactness of the stencil on polynomials, the closed-form stability limit, analytic
 Green's functions of the acoustic wave equation, the adjoint identity, reciprocity,
 finite differences of the misfit, linearity of encoding and exact unbiasedness of the
-+-1 estimator (Eq. 6), an independent Philox implementation (NumPy's) and the stationary
-law of the Langevin chain (Eqs. 8-9) on a linear-Gaussian problem.
++-1 estimator (Eq. 6) over sign patterns and (with kappa) over random shot subsets, the
+sponge against a domain too large to reflect, an independent Philox implementation
+(NumPy's) and the stationary law of the Langevin chain (Eqs. 8-9) on a linear-Gaussian
+problem.
 """
 import math
 
@@ -392,3 +394,66 @@ def test_langevin_linear_gaussian_stationary_law():
     # the clamp is applied after the update
     out = oracle.langevin(np.array([1.0, 2.0]), np.array([0.0, 0.0]), np.array([10.0, -10.0]), 0.1, 1.0, 0.0, 5.0)
     assert np.array_equal(out, [5.0, 0.0])
+
+
+# ------------------------------------------------------------------ sponge
+
+def _box_field(nb, n=80, N=None, v0=2000.0, h=10.0, dt=1e-3, nt=600, R=10):
+    """u over an n x n box (every cell recorded every R steps) from a centred 15 Hz source,
+    computed on an n x n grid with nb sponge cells, or, with N, inside an N x N grid
+    (whose boundaries are too far to be heard within nt steps)."""
+    wav = W.ricker(15.0, dt, nt)
+    M = N or n
+    g = oracle.Grid(nz=M, nx=M, dz=h, dx=h, nb=nb, v_ref=v0)
+    o = (M - n) // 2
+    rec = np.array([(o + i) * M + o + j for i in range(n) for j in range(n)], dtype=np.int32)
+    src = [(o + n // 2) * M + o + n // 2]
+    return oracle.forward(g, np.full(M * M, v0), dt, nt, R, src, [1.0], wav, rec, coef_fp32=False)
+
+
+def test_sponge_absorbs_outgoing_waves():
+    # A point source in a homogeneous 800 m box with a 20-cell sponge against the same
+    # box inside a 4 km domain (no reflection back within 0.6 s): after the wave has left
+    # the box its energy is <= 1 % of the peak, and the reflected field (box
+    # minus reference) stays below 10 % of the direct wave's peak norm.  Rigid walls
+    # (no sponge) fail both bounds.
+    ref = _box_field(20, N=400)
+    peak_e = (ref ** 2).sum(1).max()
+    peak_n = np.linalg.norm(ref, axis=1).max()
+    late = slice(45, None)  # t >= 0.45 s (the 2D wave leaves a slowly decaying tail behind its front)
+    assert (ref[late] ** 2).sum(1).max() < 1e-3 * peak_e  # the reference box is empty by then
+    box = _box_field(20)
+    assert (box[late] ** 2).sum(1).max() < 1e-2 * peak_e
+    assert np.linalg.norm(box - ref, axis=1).max() < 0.10 * peak_n
+    walls = _box_field(0)
+    assert (walls[late] ** 2).sum(1).max() > 0.1 * peak_e
+    assert np.linalg.norm(walls - ref, axis=1).max() > 0.5 * peak_n
+
+
+# ------------------------------------------------------- kappa, random subsets
+
+def test_kappa_makes_random_subsets_exactly_unbiased():
+    # Eq. 6 with B a uniformly random subset of s of the N_s shots and kappa = N_s/s: the
+    # mean over every subset and every +-1 pattern of kappa x (encoded gradient) is the
+    # full-shot gradient, exactly (sign averaging removes cross terms, subset averaging
+    # gives each shot weight s/N_s).
+    g, v, dt, nt, R, _, _, rec, wav, _ = _fd_setup(seed=21)
+    shots = np.array([g.nx + 3, g.nx + 11, g.nx + 19, g.nx + 28], dtype=np.int32)
+    vtrue = v * (1 + 0.04 * np.cos(np.arange(g.nphys) / 29.0))
+    d_i = [oracle.forward(g, vtrue, dt, nt, R, [s], [1.0], wav, rec, coef_fp32=False) for s in shots]
+    full = sum(oracle.gradient(g, v, dt, nt, R, [s], [1.0], wav, rec, d_i[k], 1.0, coef_fp32=False)[2]
+               for k, s in enumerate(shots))
+    ns, s = len(shots), 2
+    kappa = ns / s
+    acc, count = np.zeros(g.nphys), 0
+    for a in range(ns):
+        for b in range(a + 1, ns):
+            for bits in range(4):
+                w = np.array([1.0 if bits & 1 else -1.0, 1.0 if bits & 2 else -1.0])
+                d_enc = oracle.encode(d_i, [0, 2], [a, b], w)[0]
+                acc += kappa * oracle.gradient(g, v, dt, nt, R, shots[[a, b]], w, wav, rec, d_enc, 1.0,
+                                               coef_fp32=False)[2]
+                count += 1
+    assert rel(acc / count, full) < 1e-12
+    # a wrong scale (kappa = 1) is off by N_s/s
+    assert rel(acc / count / kappa, full) > 0.4
