@@ -138,14 +138,15 @@ class Batch:
         self.model_off[1:] = np.cumsum([g.nphys for g in self.grids])
         self.src_ptr = np.zeros(self.nsim + 1, dtype=np.int32)
         self.src_ptr[1:] = np.cumsum([len(s[0]) for s in sources])
-        self.src_cell = np.ascontiguousarray(np.concatenate([np.asarray(s[0], dtype=np.int32) for s in sources])
-                                             if self.nsim else np.zeros(0), dtype=np.int32)
-        self.src_w = np.ascontiguousarray(np.concatenate([np.asarray(s[1], dtype=np.float32) for s in sources]),
-                                          dtype=np.float32)
+        def cat(parts, dtype):
+            return np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=dtype) for x in parts])
+                                        if len(parts) else np.zeros(0), dtype=dtype)
+
+        self.src_cell = cat([s[0] for s in sources], np.int32)
+        self.src_w = cat([s[1] for s in sources], np.float32)
         self.rec_ptr = np.zeros(self.nsim + 1, dtype=np.int32)
         self.rec_ptr[1:] = np.cumsum([len(r) for r in receivers])
-        self.rec_cell = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.int32) for r in receivers]),
-                                             dtype=np.int32)
+        self.rec_cell = cat(receivers, np.int32)
         self.wavelet = np.ascontiguousarray(wavelet, dtype=np.float32)
         self.nrec = np.diff(self.rec_ptr)
         self._grid_arr = (FwiGrid * self.nsample)(*[g.c() for g in self.grids])

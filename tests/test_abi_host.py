@@ -71,6 +71,16 @@ def test_validation_errors(F):
     expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g, g], [1, 0], [([31], [1.0])] * 2, [rec] * 2, wav), t)
     expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g, g], [0, 0], [([31], [1.0])] * 2, [rec] * 2, wav), t)
     expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g], [0], [([31], [np.nan])], [rec], wav), t)
+    # empty batch
+    expect(F, F.FWI_E_ARG, F.fwi_check, F.Batch([g], [], [], [], wav), t)
+    # size limits: more than 2^28 padded cells; fewer, but offsets 80 rows past the grid
+    # beyond 2^30 bytes (a very wide, shallow grid)
+    big = F.Grid(nz=16400, nx=16400, dz=10.0, dx=10.0, nb=20, v_ref=3000.0, v_max=3000.0)
+    expect(F, F.FWI_E_UNSUPPORTED, F.fwi_check, F.Batch([big], [0], [([5], [1.0])], [rec[:1]], wav), t)
+    wide = F.Grid(nz=23, nx=(1 << 22) - 40, dz=10.0, dx=10.0, nb=20, v_ref=3000.0, v_max=3000.0)
+    expect(F, F.FWI_E_UNSUPPORTED, F.fwi_check, F.Batch([wide], [0], [([5], [1.0])], [rec[:1]], wav), t)
+    ok = F.Grid(nz=16000, nx=16000, dz=10.0, dx=10.0, nb=20, v_ref=3000.0, v_max=3000.0)
+    F.fwi_check(F.Batch([ok], [0], [([5], [1.0])], [rec[:1]], wav), t)
     g3 = F.Grid(nz=4, ny=4, nx=4, dz=10, dy=10, dx=10, nb=1, v_ref=2000, v_max=2000, ndim=3)
     expect(F, F.FWI_E_UNSUPPORTED, F.fwi_check, F.Batch([g, g3], [0, 1], [([31], [1.0]), ([1], [1.0])],
                                                         [rec, np.array([2], dtype=np.int32)], wav), t)
