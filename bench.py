@@ -95,6 +95,7 @@ def main():
                          "posterior-mean RMSE (several minutes)")
     ap.add_argument("--plain-steps", type=int, default=20, help="equal-error: plain-chain steps that set the target")
     ap.add_argument("--max-steps", type=int, default=60, help="equal-error: steps of the encoded chains")
+    ap.add_argument("--net-seeds", type=int, default=3, help="equal-error: networks trained (seeds 0..n-1)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
@@ -107,7 +108,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains
-        res = chains.equal_error(seed=args.seed, plain_steps=args.plain_steps, max_steps=args.max_steps, log=log)
+        res = chains.equal_error(seed=args.seed, plain_steps=args.plain_steps, max_steps=args.max_steps,
+                                 net_seeds=tuple(range(args.net_seeds)), log=log)
         res.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32"})
         print(json.dumps(res), flush=True)
         return

@@ -207,7 +207,7 @@ def first_reaching(rmse, target):
 
 
 def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=1500, max_update=30.0,
-                start_sigma=6.0, log=print):
+                start_sigma=6.0, net_seeds=(0,), log=print):
     """The whole comparison; returns a dict (one JSON object)."""
     sv = Survey(seed=seed, start_sigma=start_sigma, log=log)
     nsample = 16
@@ -227,12 +227,19 @@ def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=
     t0 = time.perf_counter()
     pairs = make_pairs(sv, ntruth=ntruth)
     P = pairs["x16"].shape[0]
-    net = UNet(chans=(32, 64, 128, 256), seed=0)
-    hist = precond.train(net, pairs, np.arange(P), steps=train_steps, batch=8, lr=2e-3, lr_final=2e-4, log=log)
-    t_train = time.perf_counter() - t0
+    log("pairs: %d in %.1f s" % (P, time.perf_counter() - t0))
+    runs = []
+    for ns in net_seeds:
+        t1 = time.perf_counter()
+        net = UNet(chans=(32, 64, 128, 256), seed=ns)
+        hist = precond.train(net, pairs, np.arange(P), steps=train_steps, batch=8, lr=2e-3, lr_final=2e-4,
+                             seed=ns, log=log)
+        t_train = time.perf_counter() - t1
+        r_pre, s_pre, kept = run_chain(sv, "preconditioned", max_steps, eta, seed, net=net)
+        log("preconditioned (network seed %d): %.3f s per step, reaches the target after %s steps" %
+            (ns, s_pre, first_reaching(r_pre, target)))
+        runs.append((ns, r_pre, s_pre, kept, t_train, hist))
     del pairs
-    r_pre, s_pre, kept = run_chain(sv, "preconditioned", max_steps, eta, seed, net=net)
-    log("preconditioned: %.3f s per step, RMSE after %d steps %.1f" % (s_pre, max_steps, r_pre[-1]))
 
     def entry(rmse, s_step, label):
         n = first_reaching(rmse, target)
@@ -252,8 +259,10 @@ def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=
                                                       "from 8 timed single-shot gradients"), "rmse": None},
             "plain_batched": entry(r_plain, s_plain, "measured: 2 samples x 80 single-shot simulations per launch"),
             "encoded": entry(r_enc, s_enc, "measured: 16 samples x 10 supergathers of 8 in one launch per step"),
-            "preconditioned": {**entry(r_pre, s_pre, "measured: encoded + U-Net inference + guard"),
-                               "network_kept_fraction": round(float(np.mean(kept)) / nsample, 3) if kept else None,
-                               "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]]},
+            "preconditioned": [
+                {**entry(r_pre, s_pre, "measured: encoded + U-Net inference + guard"), "network_seed": ns,
+                 "network_kept_fraction": round(float(np.mean(kept)) / nsample, 3) if kept else None,
+                 "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]]}
+                for ns, r_pre, s_pre, kept, t_train, hist in runs],
         },
     }
