@@ -76,6 +76,96 @@ def cpu_baseline(batch, grid, wav, nt_sample, R, vstart, cfg):
                       "%.1f s wall" % (len(sims), nt_sample, cfg.nt, dt)}
 
 
+PEAK_BF16_TFLOPS = 2500.0  # dense MFMA, BF16
+
+
+def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
+    """The preconditioner's 4-level U-Net on a batch of 256 x 256 inputs: inference and
+    training-step time, and every convolution of one forward pass timed with HIP events
+    against its roofline min(BF16 MFMA peak, arithmetic intensity x HBM peak)."""
+    from paper_2512_12797_amd import nn, precond
+    from paper_2512_12797_amd.unet import UNet
+    net = UNet(chans=chans, seed=0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(args.seed)
+    g = torch.randn(b, n, n, device="cuda", generator=gen)
+    v = 1500.0 + 3000.0 * torch.rand(b, n, n, device="cuda", generator=gen)
+    x16, res, scale = precond.prepare(g, v)
+    tg = torch.randn(b, n, n, device="cuda", generator=gen)
+    loss = torch.empty(1, device="cuda")
+    work = torch.empty(2 * b * 256, device="cuda")
+    rflat = res.reshape(-1)
+
+    def train_step():
+        out = net.forward(x16, rflat, b, n, n, keep=True)
+        dp = torch.empty_like(out)
+        dp16 = nn.bf16_empty(*out.shape)
+        nn.rel_mse(out, 32, tg, b, n * n, loss, dp, dp16, work)
+        net.backward(dp, dp16)
+        net.adam_step(1e-4)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_inf = timed(lambda: net.forward(x16, rflat, b, n, n), max(args.steps, 5))
+    t_train = timed(train_step, max(args.steps, 5))
+    # per-layer convolutions of one forward pass (FLOPs with the channels the kernels
+    # compute; algorithmic bytes: input BF16 once, outputs as written, weights)
+    layers = []
+    orig = nn.conv3x3
+
+    def conv_timed(x, shape, w, cout, bias=None, aux=None, act=False, out_f32=None, out_bf16=None, res=None):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        orig(x, shape, w, cout, bias, aux, act, out_f32, out_bf16, res)
+        e1.record()
+        layers.append((shape, cout, out_f32 is not None, out_bf16 is not None, aux is not None, res is not None,
+                       e0, e1))
+
+    nn.conv3x3 = conv_timed
+    try:
+        net.forward(x16, rflat, b, n, n)
+        torch.cuda.synchronize()
+    finally:
+        nn.conv3x3 = orig
+    rows, tot_fl, tot_ms = [], 0.0, 0.0
+    for (nb_, h, w, cin), cout, f32o, bfo, auxo, reso, e0, e1 in layers:
+        ms = e0.elapsed_time(e1)
+        fl = 2.0 * 9 * cin * cout * nb_ * h * w
+        by = nb_ * h * w * (2 * cin + cout * (4 * f32o + 2 * bfo + 4 * auxo) + 4 * reso) + 2 * 9 * cin * cout
+        ai = fl / by
+        roof = min(PEAK_BF16_TFLOPS, ai * PEAK_HBM_GBS / 1e3)
+        ach = fl / (ms / 1e3) / 1e12
+        rows.append({"hw": [h, w], "cin": cin, "cout": cout, "us": round(ms * 1e3, 1), "tflops": round(ach, 1),
+                     "flop_per_byte": round(ai, 1), "bound": "mfma" if roof >= PEAK_BF16_TFLOPS else "hbm",
+                     "roof_tflops": round(roof, 1), "frac": round(ach / roof, 3)})
+        tot_fl += fl
+        tot_ms += ms
+    # levels of net.layers(): encoder levels 0..L-1, decoder levels 0..L-2 (two convolutions
+    # each), then the output convolution at level 0
+    lv = [i for i in range(net.L) for _ in (0, 1)] + [i for i in range(net.L - 1) for _ in (0, 1)] + [0]
+    real = sum(2.0 * 9 * (2 if l is net.enc[0][0] else l.cin) * l.cout_real * b * (n >> k) ** 2
+               for k, l in zip(lv, net.layers()))
+    return {"metric": "U-Net preconditioner inference throughput", "value": round(real / t_inf / 1e12, 2),
+            "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 (fp32 accumulate)",
+            "data": "synthetic", "config": {"workload": "unet-4level-32/64/128/256-256x256-batch%d" % b,
+                                            "params": net.nparams(), "real_gflop_per_image": round(real / b / 1e9, 2)},
+            "inference_ms": round(t_inf * 1e3, 3), "train_step_ms": round(t_train * 1e3, 3),
+            "train_tflops": round(3.0 * real / t_train / 1e12, 2),
+            "roofline": {"bound": "mixed", "achieved": round(tot_fl / (tot_ms / 1e3) / 1e12, 1),
+                         "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tot_fl / (tot_ms / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+                         "note": "all forward convolutions, executed FLOPs / summed kernel time; per-layer bounds below"},
+            "layers": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,10 +179,11 @@ def main():
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error"],
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
                          "equal-error: posterior samples/hour of plain, encoded and preconditioned chains at equal "
-                         "posterior-mean RMSE (several minutes)")
+                         "posterior-mean RMSE (several minutes); unet: the gradient preconditioner's network "
+                         "(inference, training step, per-layer convolution rooflines)")
     ap.add_argument("--plain-steps", type=int, default=20, help="equal-error: plain-chain steps that set the target")
     ap.add_argument("--max-steps", type=int, default=60, help="equal-error: steps of the encoded chains")
     ap.add_argument("--net-seeds", type=int, default=3, help="equal-error: networks trained (seeds 0..n-1)")
@@ -106,6 +197,9 @@ def main():
     from paper_2512_12797_amd import fwi, problems
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "unet":
+        print(json.dumps(unet_bench(torch, args)), flush=True)
+        return
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains
         res = chains.equal_error(seed=args.seed, plain_steps=args.plain_steps, max_steps=args.max_steps,
