@@ -80,9 +80,14 @@ PEAK_BF16_TFLOPS = 2500.0  # dense MFMA, BF16
 
 
 def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
-    """The preconditioner's 4-level U-Net on a batch of 256 x 256 inputs: inference and
-    training-step time, and every convolution of one forward pass timed with HIP events
-    against its roofline min(BF16 MFMA peak, arithmetic intensity x HBM peak)."""
+    """The preconditioner's 4-level U-Net on a batch of 256 x 256 inputs: inference (one HIP
+    graph replay of the forward pass) and training-step time, and every convolution of the
+    forward pass and weight gradient of the backward pass timed on its own against its
+    roofline min(BF16 MFMA peak, arithmetic intensity x HBM peak).
+
+    Per-kernel and training-step times are averages over back-to-back launches queued behind
+    a GPU-side spin that outlasts the host's enqueueing, so that host launch overhead does
+    not enter the device-side events."""
     from paper_2512_12797_amd import nn, precond
     from paper_2512_12797_amd.unet import UNet
     net = UNet(chans=chans, seed=0)
@@ -96,6 +101,39 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
     work = torch.empty(2 * b * 256, device="cuda")
     rflat = res.reshape(-1)
 
+    # spin length per millisecond (the spin counts the device clock)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    torch.cuda._sleep(1 << 22)
+    e1.record()
+    torch.cuda.synchronize()
+    assert e0.elapsed_time(e1) > 0.05, "the spin kernel did not spin"
+    spin_per_ms = (1 << 22) / e0.elapsed_time(e1)
+
+    def gpu_time(fn, reps):
+        """Seconds per call of fn, device-side, over reps calls queued behind a spin."""
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        spin_ms = 2.0 * (time.perf_counter() - t0) * 1e3 + 1.0
+        for _ in range(4):
+            torch.cuda._sleep(int(spin_per_ms * spin_ms))
+            e0.record()
+            h0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            host_ms = (time.perf_counter() - h0) * 1e3
+            e1.record()
+            torch.cuda.synchronize()
+            if host_ms < spin_ms:
+                return e0.elapsed_time(e1) / 1e3 / reps
+            spin_ms = 2.0 * host_ms + 1.0  # the host was slower than planned (e.g. under a profiler)
+        raise RuntimeError("host enqueueing kept outlasting the spin")
+
     def train_step():
         out = net.forward(x16, rflat, b, n, n, keep=True)
         dp = torch.empty_like(out)
@@ -104,50 +142,88 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
         net.backward(dp, dp16)
         net.adam_step(1e-4)
 
-    def timed(fn, reps):
-        for _ in range(2):
-            fn()
+    # inference: the forward pass captured once as a HIP graph; every replay must reproduce
+    # the eager result bit for bit
+    ref = net.forward(x16, rflat, b, n, n).clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        net.forward(x16, rflat, b, n, n)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out_g = net.forward(x16, rflat, b, n, n)
+    for _ in range(3):
+        graph.replay()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+        assert torch.equal(out_g, ref), "graph replay differs from the eager forward pass"
+        net.forward(x16, rflat, b, n, n)
+    reps = max(args.steps, 20)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / 1e3 / reps
+    t_inf_eager = gpu_time(lambda: net.forward(x16, rflat, b, n, n), 5)
+    del graph
 
-    t_inf = timed(lambda: net.forward(x16, rflat, b, n, n), max(args.steps, 5))
-    t_train = timed(train_step, max(args.steps, 5))
-    # per-layer convolutions of one forward pass (FLOPs with the channels the kernels
-    # compute; algorithmic bytes: input BF16 once, outputs as written, weights)
-    layers = []
-    orig = nn.conv3x3
+    # per-kernel: record the calls of one forward pass and one training step, then time each
+    convs, wgrads = [], []
+    orig_conv, orig_wgrad = nn.conv3x3, nn.wgrad
 
-    def conv_timed(x, shape, w, cout, bias=None, aux=None, act=False, out_f32=None, out_bf16=None, res=None):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        orig(x, shape, w, cout, bias, aux, act, out_f32, out_bf16, res)
-        e1.record()
-        layers.append((shape, cout, out_f32 is not None, out_bf16 is not None, aux is not None, res is not None,
-                       e0, e1))
+    def rec_conv(*a, **k):
+        convs.append((a, k))
+        orig_conv(*a, **k)
 
-    nn.conv3x3 = conv_timed
+    def rec_wgrad(*a):
+        wgrads.append(a)
+        orig_wgrad(*a)
+
+    nn.conv3x3 = rec_conv
     try:
         net.forward(x16, rflat, b, n, n)
-        torch.cuda.synchronize()
     finally:
-        nn.conv3x3 = orig
-    rows, tot_fl, tot_ms = [], 0.0, 0.0
-    for (nb_, h, w, cin), cout, f32o, bfo, auxo, reso, e0, e1 in layers:
-        ms = e0.elapsed_time(e1)
-        fl = 2.0 * 9 * cin * cout * nb_ * h * w
-        by = nb_ * h * w * (2 * cin + cout * (4 * f32o + 2 * bfo + 4 * auxo) + 4 * reso) + 2 * 9 * cin * cout
+        nn.conv3x3 = orig_conv
+    nn.wgrad = rec_wgrad
+    try:
+        train_step()
+    finally:
+        nn.wgrad = orig_wgrad
+    torch.cuda.synchronize()
+    t_train = gpu_time(train_step, max(args.steps, 5))
+
+    def row(kind, h, w, cin, cout, fl, by, sec):
         ai = fl / by
         roof = min(PEAK_BF16_TFLOPS, ai * PEAK_HBM_GBS / 1e3)
-        ach = fl / (ms / 1e3) / 1e12
-        rows.append({"hw": [h, w], "cin": cin, "cout": cout, "us": round(ms * 1e3, 1), "tflops": round(ach, 1),
-                     "flop_per_byte": round(ai, 1), "bound": "mfma" if roof >= PEAK_BF16_TFLOPS else "hbm",
-                     "roof_tflops": round(roof, 1), "frac": round(ach / roof, 3)})
+        ach = fl / sec / 1e12
+        return {"kernel": kind, "hw": [h, w], "cin": cin, "cout": cout, "us": round(sec * 1e6, 1),
+                "tflops": round(ach, 1), "flop_per_byte": round(ai, 1),
+                "bound": "mfma" if roof >= PEAK_BF16_TFLOPS else "hbm", "roof_tflops": round(roof, 1),
+                "frac": round(ach / roof, 3)}
+
+    rows, tot_fl, tot_s = [], 0.0, 0.0
+    for a, k in convs:
+        x, shape, w_, cout = a[:4]
+        nb_, h, w, cin = shape
+        sec = gpu_time(lambda: orig_conv(*a, **k), 10)
+        fl = 2.0 * 9 * cin * cout * nb_ * h * w
+        by = nb_ * h * w * (2 * cin + cout * (4 * (k.get("out_f32") is not None) + 2 * (k.get("out_bf16") is not None)
+                                              + 4 * (k.get("aux") is not None))
+                            + 4 * (k.get("res") is not None)) + 2 * 9 * cin * cout
+        rows.append(row("conv3x3 forward", h, w, cin, cout, fl, by, sec))
         tot_fl += fl
-        tot_ms += ms
+        tot_s += sec
+    wrows = []
+    for a in wgrads:
+        dz, dz32, x, shape, cout, dw, db, wk = a
+        nb_, h, w, cin = shape
+        sec = gpu_time(lambda: orig_wgrad(*a), 10)
+        fl = 2.0 * 9 * cin * cout * nb_ * h * w
+        by = nb_ * h * w * (2 * cin + 2 * cout + 4 * cout * (db is not None)) + 4 * 9 * cin * cout
+        wrows.append(row("weight gradient", h, w, cin, cout, fl, by, sec))
     # levels of net.layers(): encoder levels 0..L-1, decoder levels 0..L-2 (two convolutions
     # each), then the output convolution at level 0
     lv = [i for i in range(net.L) for _ in (0, 1)] + [i for i in range(net.L - 1) for _ in (0, 1)] + [0]
@@ -157,13 +233,13 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
             "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 (fp32 accumulate)",
             "data": "synthetic", "config": {"workload": "unet-4level-32/64/128/256-256x256-batch%d" % b,
                                             "params": net.nparams(), "real_gflop_per_image": round(real / b / 1e9, 2)},
-            "inference_ms": round(t_inf * 1e3, 3), "train_step_ms": round(t_train * 1e3, 3),
-            "train_tflops": round(3.0 * real / t_train / 1e12, 2),
-            "roofline": {"bound": "mixed", "achieved": round(tot_fl / (tot_ms / 1e3) / 1e12, 1),
+            "inference_ms": round(t_inf * 1e3, 3), "inference_eager_ms": round(t_inf_eager * 1e3, 3),
+            "train_step_ms": round(t_train * 1e3, 3), "train_tflops": round(3.0 * real / t_train / 1e12, 2),
+            "roofline": {"bound": "mixed", "achieved": round(tot_fl / tot_s / 1e12, 1),
                          "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(tot_fl / (tot_ms / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+                         "frac": round(tot_fl / tot_s / 1e12 / PEAK_BF16_TFLOPS, 4),
                          "note": "all forward convolutions, executed FLOPs / summed kernel time; per-layer bounds below"},
-            "layers": rows}
+            "layers": rows, "weight_gradients": wrows}
 
 
 def main():

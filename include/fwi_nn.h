@@ -48,6 +48,17 @@ fwi_status fwi_nn_conv3x3(const uint16_t *x, fwi_nn_shape in, const uint16_t *w,
                           void *stream);
 
 /*
+ * The same convolution over the channel concatenation [up2(a), b] of a decoder level, without materialising it:
+ * input channel ci < ca is a[n][y/2][x/2][ci] (a: bf16 [in.n][in.h/2][in.w/2][ca], nearest 2x upsampling), channel
+ * ci >= ca is b[n][y][x][ci - ca] (b: bf16 [in.n][in.h][in.w][in.c - ca]).  in.c is the concatenated channel count;
+ * ca and in.c - ca must be positive multiples of 16, in.h and in.w even.  Results equal fwi_nn_conv3x3 on the
+ * materialised concatenation bit for bit.  (U-Net decoders: the skip connection of Ronneberger et al. 2015.)
+ */
+fwi_status fwi_nn_conv3x3_upcat(const uint16_t *a, int32_t ca, const uint16_t *b, fwi_nn_shape in, const uint16_t *w,
+                                int32_t cout, const float *bias, const float *aux, const float *res, int32_t act,
+                                float *out_f32, uint16_t *out_bf16, void *stream);
+
+/*
  * Weight and bias gradients of that convolution:
  *   dw[co][tap][ci] = sum_p dz[p][co] * x[p + offset(tap)][ci]     (FP32, deterministic)
  *   db[co] = sum_p dz_f32[p][co]                                   (db nullable)
@@ -57,6 +68,10 @@ fwi_status fwi_nn_conv3x3(const uint16_t *x, fwi_nn_shape in, const uint16_t *w,
 int64_t fwi_nn_wgrad_work(fwi_nn_shape in, int32_t cout);
 fwi_status fwi_nn_wgrad(const uint16_t *dz, const float *dz_f32, const uint16_t *x, fwi_nn_shape in, int32_t cout,
                         float *dw, float *db, float *work, void *stream);
+/* The same with the input [up2(a), b] as in fwi_nn_conv3x3_upcat (work: fwi_nn_wgrad_work(in, cout) floats). */
+fwi_status fwi_nn_wgrad_upcat(const uint16_t *dz, const float *dz_f32, const uint16_t *a, int32_t ca,
+                              const uint16_t *b, fwi_nn_shape in, int32_t cout, float *dw, float *db, float *work,
+                              void *stream);
 
 /* 2x2 average pooling (h, w even): out[n][y][x][c] = bf16(mean of the 4 inputs).
  * Backward: dx[n][2y+i][2x+j][c] (+)= dout[n][y][x][c] / 4 (accumulate != 0 adds). */

@@ -37,218 +37,358 @@ __device__ __forceinline__ float dsilu(float z)
     const float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
+// The same with the hardware exponential and reciprocal (about 2 ulp), for the convolution epilogue where they run
+// on every output element; exp(-z) overflowing to infinity gives sigmoid 0 as it should.
+__device__ __forceinline__ float sigmoid_hw(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_hw(float z) { return z * sigmoid_hw(z); }
+__device__ __forceinline__ float dsilu_hw(float z)
+{
+    const float s = sigmoid_hw(z);
+    return s * (1.0f + z * (1.0f - s));
+}
 
 // ------------------------------------------------------------------ conv3x3
 
-// Block = 4 wavefronts in a 2 x 2 arrangement; each wavefront accumulates MT x NT tiles of
-// 32 pixels x 32 output channels (each loaded fragment feeds NT or MT matrix operations)
-// and fetches the fragments of the next K step while the current ones are multiplied.
-template <int MT, int NT>
+// Hardware dispatches workgroup b to XCD b % 8 (each XCD has its own L2): give every XCD a contiguous range of tiles so
+// that neighbouring tiles, which share halo rows, are fetched into the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) { return nb % 8 ? b : (b % 8) * (nb / 8) + b / 8; }
+
+// Workgroup output tile: TY image rows x 32 columns of one image x CO_T output channels; 4 wavefronts, WM along the
+// rows x 4/WM along the channels, each MT rows x NT groups of 32 channels.  The K loop runs over the input channels
+// in chunks of 16.  Per chunk, LDS holds the (TY+2) x 34 input patch (halo included, zeros outside the image) as two
+// planes of 8 channels and the chunk's weights of all 9 taps; each tap is one MFMA k-step whose pixel operand is read
+// from the patch shifted by the tap.  A = weights (rows = output channels), B = pixels (columns): accumulator
+// register r of a lane then holds output channel 8(r/4) + 4(lane/32) + r%4 of pixel lane%32, so the epilogue reads
+// and writes 4 consecutive channels per lane.  The next chunk's global loads are in flight during the current
+// chunk's matrix operations.
+// With cu > 0 the input is the channel concatenation [up(xu), x] without materialising it: channels [0, cu) come from
+// xu at half resolution (nearest 2x upsampling: pixel (y, x) reads xu(y/2, x/2)), channels [cu, Cin) from x, which
+// then has Cin - cu channels per pixel.
+template <int TY, int CO_T, int WM>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x, int N, int H, int W, int Cin,
                                                  const uint16_t *__restrict__ w, int Cout,
                                                  const float *__restrict__ bias, const float *__restrict__ aux,
                                                  const float *__restrict__ res, int act, float *__restrict__ of32,
-                                                 uint16_t *__restrict__ obf)
+                                                 uint16_t *__restrict__ obf, const uint16_t *__restrict__ xu, int cu)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t P = (int64_t)N * H * W;
-    const int64_t p0 = (int64_t)blockIdx.x * (64 * MT) + (wave & 1) * (32 * MT);
-    const int co0 = blockIdx.y * (64 * NT) + (wave >> 1) * (32 * NT);
-    if (co0 >= Cout || p0 >= P) return;  // uniform per wavefront; no barriers below
-    const int kh = (lane >> 5) * 8;
-    int py[MT], px[MT], pn[MT];
-    bool pin[MT];
+    constexpr int WN = 4 / WM, MT = TY / WM, NT = CO_T / 32 / WN;
+    static_assert(WM * WN == 4 && MT * WM == TY && NT * WN * 32 == CO_T, "tile shape");
+    constexpr int PC = 34, PPL = (TY + 2) * PC;  // patch columns, pixels per plane
+    constexpr int NP = 2 * PPL, NWT = 18 * CO_T;  // 16-byte pieces of a chunk: patch, weights
+    constexpr int RP = (NP + 255) / 256, RW = (NWT + 255) / 256;
+    __shared__ uint4 sp[NP];
+    __shared__ uint4 sw[NWT];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, hl = lane >> 5;
+    const int wm = wave % WM, wn = wave / WM;
+    const int nseg = (W + 31) >> 5, nrt = (H + TY - 1) / TY;
+    const int bt = xcd_tile(blockIdx.x, gridDim.x);
+    const int seg = bt % nseg, rt = (bt / nseg) % nrt, n = bt / (nseg * nrt);
+    const int y0 = rt * TY, x0 = seg * 32, cb = blockIdx.y * CO_T;
+
+    // loader roles: patch piece q = tid + 256 i is channel half q & 1 of patch pixel q >> 1 (both halves of a pixel
+    // are adjacent in memory); weight piece q is half q & 1 of tap (q >> 1) % 9 of output channel (q >> 1) / 9
+    const int cx = Cin - cu;  // channels per pixel of x
+    int64_t poff[RP], uoff[RP];
+    int pdst[RP];
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
-        const int64_t p = p0 + 32 * i + (lane & 31);
-        pin[i] = p < P;
-        px[i] = pin[i] ? (int)(p % W) : 0;
-        const int64_t t = pin[i] ? p / W : 0;
-        py[i] = (int)(t % H);
-        pn[i] = (int)(t / H);
+    for (int i = 0; i < RP; ++i) {
+        const int q = tid + 256 * i, pix = q >> 1, h = q & 1;
+        const int pr = pix / PC, pc = pix - pr * PC;
+        const int yy = y0 - 1 + pr, xx = x0 - 1 + pc;
+        const bool v = q < NP && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        poff[i] = v ? (((int64_t)n * H + yy) * W + xx) * cx + 8 * h : -1;
+        uoff[i] = v && cu > 0 ? (((int64_t)n * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) * cu + 8 * h : -1;
+        pdst[i] = q < NP ? h * PPL + pix : -1;
     }
-    const uint16_t *wrow[NT];
-    bool cin_[NT];
+    uint4 rp[RP], rw[RW];
+    auto gload = [&](int c0) {
+        const bool up = c0 < cu;  // uniform: cu is a multiple of the chunk width
+        const uint16_t *src = up ? xu + c0 : x + (c0 - cu);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = co0 + 32 * j + (lane & 31);
-        cin_[j] = co < Cout;
-        wrow[j] = w + (int64_t)(cin_[j] ? co : 0) * 9 * Cin + kh;
-    }
-    const int csteps = Cin / 16;
-    const int ksteps = 9 * csteps;
-    auto load_a = [&](int ks, uint4 (&a)[MT]) {
-        const int tap = ks / csteps, c0 = (ks - tap * csteps) * 16;
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        for (int i = 0; i < RP; ++i) {
+            const int64_t o = up ? uoff[i] : poff[i];
+            rp[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (o >= 0) rp[i] = *(const uint4 *)(src + o);
+        }
 #pragma unroll
-        for (int i = 0; i < MT; ++i) {
-            const int yy = py[i] + dy, xs = px[i] + dx;
-            const bool v = pin[i] && yy >= 0 && yy < H && xs >= 0 && xs < W;
-            a[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (v) a[i] = *(const uint4 *)(x + (((int64_t)pn[i] * H + yy) * W + xs) * Cin + kh + c0);
+        for (int i = 0; i < RW; ++i) {
+            const int q = tid + 256 * i, t = q >> 1;
+            rw[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (q < NWT) rw[i] = *(const uint4 *)(w + ((int64_t)(cb + t / 9) * 9 + t % 9) * Cin + c0 + 8 * (q & 1));
         }
     };
-    auto load_b = [&](int ks, uint4 (&b)[NT]) {
-        const int tap = ks / csteps, c0 = (ks - tap * csteps) * 16;
+    auto lstore = [&]() {
 #pragma unroll
-        for (int j = 0; j < NT; ++j) b[j] = *(const uint4 *)(wrow[j] + tap * Cin + c0);
+        for (int i = 0; i < RP; ++i)
+            if (pdst[i] >= 0) sp[pdst[i]] = rp[i];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int q = tid + 256 * i, t = q >> 1;
+            if (q < NWT) sw[((t % 9) * 2 + (q & 1)) * CO_T + t / 9] = rw[i];
+        }
     };
     f32x16 acc[MT][NT];
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = f32x16{};
-    uint4 a[MT], b[NT], an[MT], bn[NT];
-    load_a(0, a);
-    load_b(0, b);
-    for (int ks = 0; ks < ksteps; ++ks) {
-        if (ks + 1 < ksteps) {
-            load_a(ks + 1, an);
-            load_b(ks + 1, bn);
-        }
+    gload(0);
+    const int nck = Cin >> 4;
+    for (int ck = 0; ck < nck; ++ck) {
+        __syncthreads();
+        lstore();
+        __syncthreads();
+        if (ck + 1 < nck) gload(16 * (ck + 1));
 #pragma unroll
-        for (int i = 0; i < MT; ++i)
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8 a[NT], b[MT];
 #pragma unroll
             for (int j = 0; j < NT; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[i]),
-                                                                    __builtin_bit_cast(bf16x8, b[j]), acc[i][j], 0, 0,
-                                                                    0);
+                a[j] = __builtin_bit_cast(bf16x8, sw[(tap * 2 + hl) * CO_T + (wn * NT + j) * 32 + l32]);
 #pragma unroll
-        for (int i = 0; i < MT; ++i) a[i] = an[i];
+            for (int i = 0; i < MT; ++i)
+                b[i] = __builtin_bit_cast(bf16x8, sp[hl * PPL + (wm * MT + i + dy) * PC + l32 + dx]);
 #pragma unroll
-        for (int j = 0; j < NT; ++j) b[j] = bn[j];
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[i], acc[i][j], 0, 0, 0);
+        }
     }
+    const int xx = x0 + l32;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int c = co0 + 32 * j + (lane & 31);
-        if (!cin_[j]) continue;
-        const float bb = bias ? bias[c] : 0.0f;
+    for (int i = 0; i < MT; ++i) {
+        const int y = y0 + wm * MT + i;
+        if (y >= H || xx >= W) continue;
+        const int64_t p = ((int64_t)n * H + y) * W + xx;
 #pragma unroll
-        for (int i = 0; i < MT; ++i)
+        for (int j = 0; j < NT; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t pr = p0 + 32 * i + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
-                if (pr >= P) continue;
-                float val = acc[i][j][r] + bb;
-                const int64_t o = pr * Cout + c;
-                if (aux) val *= dsilu(aux[o]);
-                if (res && c == 0) val += res[pr];
-                if (of32) of32[o] = val;
-                if (obf) obf[o] = f2bf(act ? silu(val) : val);
+            for (int g = 0; g < 4; ++g) {
+                const int c = cb + (wn * NT + j) * 32 + 8 * g + 4 * hl;
+                const int64_t o = p * Cout + c;
+                float v[4] = {acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]};
+                if (bias) {
+                    const float4 bb = *(const float4 *)(bias + c);
+                    v[0] += bb.x, v[1] += bb.y, v[2] += bb.z, v[3] += bb.w;
+                }
+                if (aux) {
+                    const float4 z = *(const float4 *)(aux + o);
+                    v[0] *= dsilu_hw(z.x), v[1] *= dsilu_hw(z.y), v[2] *= dsilu_hw(z.z), v[3] *= dsilu_hw(z.w);
+                }
+                if (res && c == 0) v[0] += res[p];
+                if (of32) *(float4 *)(of32 + o) = make_float4(v[0], v[1], v[2], v[3]);
+                if (obf) {
+                    uint16_t h4[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h4[e] = f2bf(act ? silu_hw(v[e]) : v[e]);
+                    *(uint2 *)(obf + o) = make_uint2((uint32_t)h4[0] | ((uint32_t)h4[1] << 16),
+                                                     (uint32_t)h4[2] | ((uint32_t)h4[3] << 16));
+                }
             }
     }
 }
 
 // ------------------------------------------------------------------- wgrad
 
-// One wavefront per (32 output channels, 32 input channels, pixel chunk), all 9 taps:
-// M = co, N = ci, K = pixels in steps of 16.  Each step loads the 16-pixel x 32-channel
-// tiles of dz (once) and of x at the 9 shifted positions with one coalesced 16-byte load
-// per lane, stages them in LDS and reads them back in the matrix-operand layout.
-__global__ __launch_bounds__(64) void k_wgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
-                                              int N, int H, int W, int Cin, int Cout, int64_t per_chunk,
-                                              float *__restrict__ work)
+// Weight-gradient partials over a chunk of pixel tiles (TY rows x 32 columns of one image), one workgroup per
+// (32 output channels, 32 input channels, chunk):  M = input channels, N = output channels, K = pixels, one
+// accumulator per tap.  Per tile, LDS holds dz transposed to [co][row][32 columns] and the input patch (TY+2 rows,
+// halo included) transposed to [ci][row][40 columns], so that 8 consecutive pixels of one channel are one 16-byte
+// read; the transposition is done while storing (pairs of pixels packed into 32-bit words).  The column shift of a
+// tap comes from one aligned 16-byte + 4-byte read per patch row: shift 0 is the 16 bytes, shift 2 drops the first
+// word and appends the extra one, shift 1 is the funnel shift by 16 bits of consecutive words.  Channel pitches are
+// odd multiples of 16 bytes so that the 32 rows of an operand read fall in distinct banks.  The 4 wavefronts split
+// the tile's 2*TY k-steps; their accumulators are added in wavefront order at the end (deterministic).
+// The input may be the concatenation [up(xu), x] as in k_conv3x3 (cu > 0).
+template <int TY>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
+                                               int N, int H, int W, int Cin, int Cout, int ntiles, int per_chunk,
+                                               float *__restrict__ work, const uint16_t *__restrict__ xu, int cu)
 {
-    __shared__ uint16_t ta[16][32];
-    __shared__ uint16_t tb[16][32];
-    const int lane = threadIdx.x;
-    const int nci = (Cin + 31) / 32;
+    constexpr int PR = TY + 2;
+    constexpr int DZP = TY * 32 + 8;                                  // elements per output channel
+    constexpr int XRP = 40;                                           // elements per patch row
+    constexpr int XP = PR * XRP + (((PR * XRP / 8) % 2) == 0 ? 8 : 0);  // elements per input channel
+    constexpr int LDS_ELEMS = 32 * DZP + 32 * XP;
+    static_assert(LDS_ELEMS * 2 >= 4 * 64 * 16 * 4, "reduction buffer");
+    constexpr int NDZ = TY * 64;                 // dz items: (row, pixel pair, 8-channel group)
+    constexpr int NX = PR * 17 * 4;              // patch items: (row, column pair, 8-channel group)
+    constexpr int RD = (NDZ + 255) / 256, RX = (NX + 255) / 256;
+    __shared__ __align__(16) uint16_t smem[LDS_ELEMS];
+    uint16_t *sdz = smem, *sx = smem + 32 * DZP;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, hl = lane >> 5;
+    const int nci = (Cin + 31) >> 5;
     const int cit = blockIdx.x % nci, cot = blockIdx.x / nci;
-    const int chunk = blockIdx.y;
-    const int64_t P = (int64_t)N * H * W;
-    const int64_t pb = (int64_t)chunk * per_chunk;
-    const int64_t pe = std::min<int64_t>(pb + per_chunk, P);
-    const int lr = lane >> 2, lc = (lane & 3) * 8;  // loader role: tile row (pixel) lr, 8 channels from lc
-    const int co_ld = cot * 32 + lc, ci_ld = cit * 32 + lc;
-    const int kr = 8 * (lane >> 5), mc = lane & 31;  // operand role: rows kr..kr+7, column mc
+    const int ci0 = cit * 32, cb = cot * 32;
+    const int nseg = (W + 31) >> 5, nrt = (H + TY - 1) / TY;
+    const int t_beg = blockIdx.y * per_chunk, t_end = std::min(t_beg + per_chunk, ntiles);
+
+    uint4 rd[RD][2], rx[RX][2];
+    auto gload = [&](int t) {
+        const int seg = t % nseg, rt = (t / nseg) % nrt, n = t / (nseg * nrt);
+        const int y0 = rt * TY, x0 = seg * 32;
+#pragma unroll
+        for (int i = 0; i < RD; ++i) {
+            const int q = tid + 256 * i, g8 = q & 3, pp = (q >> 2) & 15, r = q >> 6;
+            const int y = y0 + r, xa = x0 + 2 * pp;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                rd[i][e] = make_uint4(0u, 0u, 0u, 0u);
+                if (q < NDZ && y < H && xa + e < W)
+                    rd[i][e] = *(const uint4 *)(dz + (((int64_t)n * H + y) * W + xa + e) * Cout + cb + 8 * g8);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {
+            const int q = tid + 256 * i, g8 = q & 3, rest = q >> 2;
+            const int cp = rest % 17, pr = rest / 17;
+            const int y = y0 - 1 + pr, xa = x0 - 1 + 2 * cp;
+            const int ci = ci0 + 8 * g8;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int xe = xa + e;
+                rx[i][e] = make_uint4(0u, 0u, 0u, 0u);
+                if (q < NX && y >= 0 && y < H && xe >= 0 && xe < W && ci < Cin)
+                    rx[i][e] = ci < cu ? *(const uint4 *)(xu + (((int64_t)n * (H >> 1) + (y >> 1)) * (W >> 1) + (xe >> 1)) * cu + ci)
+                                       : *(const uint4 *)(x + (((int64_t)n * H + y) * W + xe) * (Cin - cu) + ci - cu);
+            }
+        }
+    };
+    // 8 channels of two adjacent pixels -> 8 words (pixel pair) at the channels' rows
+    auto put8 = [](uint16_t *dst, int pitch, const uint4 &a, const uint4 &b) {
+        const uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            *(uint32_t *)(dst + (2 * k) * pitch) = (av[k] & 0xffffu) | (bv[k] << 16);
+            *(uint32_t *)(dst + (2 * k + 1) * pitch) = (av[k] >> 16) | (bv[k] & 0xffff0000u);
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < RD; ++i) {
+            const int q = tid + 256 * i, g8 = q & 3, pp = (q >> 2) & 15, r = q >> 6;
+            if (q < NDZ) put8(sdz + (8 * g8) * DZP + r * 32 + 2 * pp, DZP, rd[i][0], rd[i][1]);
+        }
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {
+            const int q = tid + 256 * i, g8 = q & 3, rest = q >> 2;
+            const int cp = rest % 17, pr = rest / 17;
+            if (q < NX) put8(sx + (8 * g8) * XP + pr * XRP + 2 * cp, XP, rx[i][0], rx[i][1]);
+        }
+    };
     f32x16 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
-    for (int64_t pk = pb; pk < pe; pk += 16) {
-        const int64_t pp = pk + lr;
-        const bool pv = pp < pe;
-        uint4 av = make_uint4(0u, 0u, 0u, 0u);
-        if (pv) av = *(const uint4 *)(dz + pp * Cout + co_ld);
-        int y = 0, xx = 0, n = 0;
-        if (pv) {
-            xx = (int)(pp % W);
-            const int64_t tt = pp / W;
-            y = (int)(tt % H);
-            n = (int)(tt / H);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        *(uint4 *)&ta[lr][lc] = av;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        bf16x8 a;
+    if (t_beg < t_end) gload(t_beg);
+    for (int t = t_beg; t < t_end; ++t) {
+        __syncthreads();
+        lstore();
+        __syncthreads();
+        if (t + 1 < t_end) gload(t + 1);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = __builtin_bit_cast(__bf16, ta[kr + j][mc]);
+        for (int kk = 0; kk < TY / 2; ++kk) {
+            const int ks = wave + 4 * kk;  // k-step: row ks / 2, 16-column half ks % 2
+            const int r = ks >> 1, g = 2 * (ks & 1) + hl;
+            const bf16x8 b = __builtin_bit_cast(bf16x8, *(const uint4 *)(sdz + l32 * DZP + r * 32 + 8 * g));
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
-            uint4 bv = make_uint4(0u, 0u, 0u, 0u);
-            if (pv && ci_ld < Cin && yy >= 0 && yy < H && xs >= 0 && xs < W)
-                bv = *(const uint4 *)(x + (((int64_t)n * H + yy) * W + xs) * Cin + ci_ld);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            *(uint4 *)&tb[lr][lc] = bv;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            bf16x8 b;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) b[j] = __builtin_bit_cast(__bf16, tb[kr + j][mc]);
-            acc[tap] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[tap], 0, 0, 0);
+            for (int dy = 0; dy < 3; ++dy) {
+                const uint16_t *src = sx + l32 * XP + (r + dy) * XRP + 8 * g;
+                const uint4 d = *(const uint4 *)src;
+                const uint32_t e4 = *(const uint32_t *)(src + 8);
+                const uint4 s1 = make_uint4(__builtin_amdgcn_alignbit(d.y, d.x, 16), __builtin_amdgcn_alignbit(d.z, d.y, 16),
+                                            __builtin_amdgcn_alignbit(d.w, d.z, 16), __builtin_amdgcn_alignbit(e4, d.w, 16));
+                const uint4 s2 = make_uint4(d.y, d.z, d.w, e4);
+                acc[3 * dy] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, d), b, acc[3 * dy], 0, 0, 0);
+                acc[3 * dy + 1] =
+                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, s1), b, acc[3 * dy + 1], 0, 0, 0);
+                acc[3 * dy + 2] =
+                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, s2), b, acc[3 * dy + 2], 0, 0, 0);
+            }
         }
     }
-    // acc[tap][r]: row (co) 8*(r/4) + 4*(lane/32) + r%4, column (ci) lane%32
-    float *wk = work + (int64_t)chunk * Cout * 9 * Cin;
-    const int cic = cit * 32 + (lane & 31);
-    if (cic < Cin)
+    // acc[tap][r]: row (input channel) ci0 + 8(r/4) + 4(lane/32) + r%4, column (output channel) cb + lane%32.
+    // Sum the 4 wavefronts in order, one tap per round; wavefront tap%4 adds and stores.
+    float *red = reinterpret_cast<float *>(smem);
+    float *wk = work + (int64_t)blockIdx.y * Cout * 9 * Cin;
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
+    for (int tap = 0; tap < 9; ++tap) {
+        __syncthreads();
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int cor = cot * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
-                wk[((int64_t)cor * 9 + tap) * Cin + cic] = acc[tap][r];
+        for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc[tap][r];
+        __syncthreads();
+        if (wave == (tap & 3)) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int ci = ci0 + 8 * g + 4 * hl;
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 4 * g + e;
+                    v[e] = ((red[r * 64 + lane] + red[(16 + r) * 64 + lane]) + red[(32 + r) * 64 + lane]) +
+                           red[(48 + r) * 64 + lane];
+                }
+                if (ci < Cin)
+                    *(float4 *)(wk + ((int64_t)(cb + l32) * 9 + tap) * Cin + ci) = make_float4(v[0], v[1], v[2], v[3]);
             }
+        }
+    }
 }
 
-__global__ void k_sum_chunks(const float *__restrict__ work, int nchunk, int64_t n, float *__restrict__ out)
+// Column sums over groups of 32 rows of a [rows][n] matrix: out[g][i] = sum of m[r][i], r in [32 g, 32 g + 32)
+// (rows in increasing order; deterministic).
+__global__ void k_sum_rows32(const float *__restrict__ m, int rows, int64_t n, float *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int r0 = 32 * blockIdx.y, r1 = std::min(r0 + 32, rows);
     float s = 0.0f;
-    for (int c = 0; c < nchunk; ++c) s += work[(int64_t)c * n + i];
-    out[i] = s;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += m[(int64_t)r * n + i];
+    out[(int64_t)blockIdx.y * n + i] = s;
 }
 
-// db partials: block = pixel chunk; the 256 threads form (256/C) pixel lanes x C channels
-// (C <= 256, a power of two up to the padding) so that every load row is coalesced; the
-// pixel lanes are then summed in a fixed-order LDS tree.
+// db partials: workgroup = chunk of `per_chunk` pixels and channels [256 y, 256 y + cw), cw = min(256, C - 256 y);
+// thread t sums channel t % cw over the pixels pb + t / cw, stepping by 256 / cw (coalesced rows).  Partials of the
+// pixel lanes are added in a fixed order.
 __global__ __launch_bounds__(256) void k_bias_partial(const float *__restrict__ dz, int64_t P, int C, int64_t per_chunk,
                                                       float *__restrict__ work)
 {
     __shared__ float red[256];
+    const int c0 = 256 * blockIdx.y, cw = std::min(256, C - c0), lanes = 256 / cw;
+    const int c = threadIdx.x % cw, pl = threadIdx.x / cw;
     const int64_t pb = (int64_t)blockIdx.x * per_chunk, pe = std::min<int64_t>(pb + per_chunk, P);
-    for (int c0 = 0; c0 < C; c0 += 256) {
-        const int cw = std::min(256, C - c0);           // channels in this pass
-        const int lanes = 256 / cw;                     // pixel lanes
-        const int c = threadIdx.x % cw, pl = threadIdx.x / cw;
-        float s = 0.0f;
-        if (pl < lanes)
-            for (int64_t p = pb + pl; p < pe; p += lanes) s += dz[p * C + c0 + c];
-        red[threadIdx.x] = pl < lanes ? s : 0.0f;
-        __syncthreads();
-        if (threadIdx.x < cw) {
-            float t = 0.0f;
-            for (int l = 0; l < lanes; ++l) t += red[l * cw + threadIdx.x];
-            work[(int64_t)blockIdx.x * C + c0 + threadIdx.x] = t;
-        }
+    float s = 0.0f;
+    if (pl < lanes) {
+#pragma unroll 4
+        for (int64_t p = pb + pl; p < pe; p += lanes) s += dz[p * C + c0 + c];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < cw) {
+        float t = 0.0f;
+        for (int l = 0; l < lanes; ++l) t += red[l * cw + threadIdx.x];
+        work[(int64_t)blockIdx.x * C + c0 + threadIdx.x] = t;
+    }
+}
+
+// db[c] = sum over the nchunk partials of channel c: one workgroup per channel, strided partial sums per thread,
+// then a fixed LDS tree.
+__global__ __launch_bounds__(256) void k_bias_final(const float *__restrict__ work, int nchunk, int C,
+                                                    float *__restrict__ db)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int k = threadIdx.x; k < nchunk; k += 256) s += work[(int64_t)k * C + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
+    if (threadIdx.x == 0) db[c] = red[0];
 }
 
 // ------------------------------------------------------------- elementwise
@@ -579,14 +719,123 @@ int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n 
 
 bool shape_ok(const fwi_nn_shape &s) { return s.n > 0 && s.h > 0 && s.w > 0 && s.c > 0; }
 
-int wgrad_chunks(const fwi_nn_shape &in, int cout)
+// Convolution tiles (rows, output channels, wavefronts along the rows), in order of preference: larger tiles reuse
+// each operand read for more matrix operations; the first whose grid has at least kConvMinBlocks workgroups (two per
+// compute unit) is used, else the smallest tile.
+struct ConvCfg {
+    int ty, cot, wm;
+};
+constexpr ConvCfg kConvCfgs[] = {{8, 128, 4}, {8, 64, 4}, {4, 128, 2}, {8, 32, 4}, {4, 64, 2}, {4, 32, 4}};
+constexpr int64_t kConvMinBlocks = 512;
+
+int64_t conv_tiles(const fwi_nn_shape &in, int ty) { return (int64_t)in.n * ((in.h + ty - 1) / ty) * ((in.w + 31) / 32); }
+
+ConvCfg pick_conv(const fwi_nn_shape &in, int cout)
 {
+    ConvCfg last = kConvCfgs[0];
+    for (const ConvCfg &c : kConvCfgs) {
+        if (cout % c.cot) continue;
+        last = c;
+        if (conv_tiles(in, c.ty) * (cout / c.cot) >= kConvMinBlocks) return c;
+    }
+    return last;
+}
+
+// Weight-gradient partition: pixel tiles of ty rows x 32 columns, chunks of per_chunk tiles, one workgroup per
+// (32 x 32 channel block, chunk); about 1024 workgroups, with the partial sums capped at 6 M floats.  Bias partials:
+// chunks of bias_per pixels.
+struct WgradPlan {
+    int ty, ntiles, per_chunk, nch;
+    int64_t nw, bias_per, bias_chunks;
+};
+
+WgradPlan wgrad_plan(const fwi_nn_shape &in, int cout)
+{
+    WgradPlan p;
+    p.ty = 4;  // k_wgrad<8> needs 260 registers: one wavefront per SIMD
+    p.ntiles = (int)conv_tiles(in, p.ty);
+    const int64_t cc = (int64_t)(cout / 32) * ((in.c + 31) / 32);
+    p.nw = (int64_t)cout * 9 * in.c;
+    int64_t nch = std::max<int64_t>(1, (1024 + cc - 1) / cc);
+    nch = std::min<int64_t>(nch, std::max<int64_t>(1, ((int64_t)6 << 20) / p.nw));
+    nch = std::min<int64_t>(nch, p.ntiles);
+    p.per_chunk = (int)((p.ntiles + nch - 1) / nch);
+    p.nch = (p.ntiles + p.per_chunk - 1) / p.per_chunk;
     const int64_t P = (int64_t)in.n * in.h * in.w;
-    const int64_t per_tile = (int64_t)cout * 9 * in.c;
-    int64_t ch = std::max<int64_t>(1, P / 4096);
-    ch = std::min<int64_t>(ch, 128);
-    ch = std::min<int64_t>(ch, std::max<int64_t>(1, ((int64_t)64 << 20) / per_tile));
-    return (int)ch;
+    p.bias_per = 16 * (256 / std::min(cout, 256));
+    p.bias_chunks = (P + p.bias_per - 1) / p.bias_per;
+    return p;
+}
+
+fwi_status conv_launch(const uint16_t *x, const uint16_t *xu, int cu, fwi_nn_shape in, const uint16_t *w, int cout,
+                       const float *bias, const float *aux, const float *res, int act, float *out_f32,
+                       uint16_t *out_bf16, hipStream_t st)
+{
+    if (!w || !shape_ok(in) || in.c % 16 || cout <= 0 || cout % 32)
+        return nn_fail(FWI_E_ARG, "conv3x3: need input channels %% 16 == 0 and output channels %% 32 == 0");
+    if (!out_f32 && !out_bf16) return nn_fail(FWI_E_ARG, "conv3x3: no output");
+    if (((uintptr_t)x | (uintptr_t)xu | (uintptr_t)w | (uintptr_t)bias | (uintptr_t)aux | (uintptr_t)out_f32) % 16 ||
+        (uintptr_t)out_bf16 % 8)
+        return nn_fail(FWI_E_ARG, "conv3x3: inputs, w, bias, aux and out_f32 must be 16-byte aligned, out_bf16 8-byte");
+    const ConvCfg c = pick_conv(in, cout);
+    const int64_t nt = conv_tiles(in, c.ty);
+    if (nt >= ((int64_t)1 << 31)) return nn_fail(FWI_E_ARG, "conv3x3: too many tiles");
+    const dim3 grid((unsigned)nt, (unsigned)(cout / c.cot));
+#define NN_CONV(TY, COT, WM)                                                                                          \
+    if (c.ty == TY && c.cot == COT && c.wm == WM)                                                                     \
+        k_conv3x3<TY, COT, WM><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, \
+                                                     out_bf16, xu, cu);
+    NN_CONV(8, 128, 4)
+    NN_CONV(8, 64, 4)
+    NN_CONV(4, 128, 2)
+    NN_CONV(8, 32, 4)
+    NN_CONV(4, 64, 2)
+    NN_CONV(4, 32, 4)
+#undef NN_CONV
+    NN_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+// Row groups of the two-pass chunk sum
+int64_t sum_groups(int nch) { return (nch + 31) / 32; }
+
+fwi_status wgrad_launch(const uint16_t *dz, const float *dz_f32, const uint16_t *x, const uint16_t *xu, int cu,
+                        fwi_nn_shape in, int cout, float *dw, float *db, float *work, hipStream_t st)
+{
+    if (!dz || !dw || !work || !shape_ok(in) || in.c % 16 || cout <= 0 || cout % 32 || (db && !dz_f32))
+        return nn_fail(FWI_E_ARG, "wgrad: bad arguments");
+    if (((uintptr_t)dz | (uintptr_t)x | (uintptr_t)xu | (uintptr_t)dw | (uintptr_t)work) % 16)
+        return nn_fail(FWI_E_ARG, "wgrad: dz, the inputs, dw and work must be 16-byte aligned");
+    const WgradPlan p = wgrad_plan(in, cout);
+    const dim3 grid((unsigned)((cout / 32) * ((in.c + 31) / 32)), (unsigned)p.nch);
+    k_wgrad<4><<<grid, 256, 0, st>>>(dz, x, in.n, in.h, in.w, in.c, cout, p.ntiles, p.per_chunk, work, xu, cu);
+    NN_TRY(hipGetLastError());
+    // chunk partials -> groups of 32 -> dw (one pass when there is a single group)
+    const int64_t G = sum_groups(p.nch);
+    const unsigned gx = (unsigned)((p.nw + 255) / 256);
+    float *tmp = work + (int64_t)p.nch * p.nw;
+    k_sum_rows32<<<dim3(gx, (unsigned)G), 256, 0, st>>>(work, p.nch, p.nw, G == 1 ? dw : tmp);
+    NN_TRY(hipGetLastError());
+    if (G > 1) {
+        k_sum_rows32<<<dim3(gx, 1), 256, 0, st>>>(tmp, (int)G, p.nw, dw);
+        NN_TRY(hipGetLastError());
+    }
+    if (db) {
+        const int64_t P = (int64_t)in.n * in.h * in.w;
+        float *bw = tmp + G * p.nw;
+        k_bias_partial<<<dim3((unsigned)p.bias_chunks, (unsigned)((cout + 255) / 256)), 256, 0, st>>>(dz_f32, P, cout,
+                                                                                                      p.bias_per, bw);
+        NN_TRY(hipGetLastError());
+        k_bias_final<<<cout, 256, 0, st>>>(bw, (int)p.bias_chunks, cout, db);
+        NN_TRY(hipGetLastError());
+    }
+    return FWI_OK;
+}
+
+bool upcat_ok(const fwi_nn_shape &in, int ca)
+{
+    return shape_ok(in) && ca > 0 && ca % 16 == 0 && in.c > ca && (in.c - ca) % 16 == 0 && in.h % 2 == 0 &&
+           in.w % 2 == 0;
 }
 
 }  // namespace
@@ -597,57 +846,40 @@ fwi_status fwi_nn_conv3x3(const uint16_t *x, fwi_nn_shape in, const uint16_t *w,
                           const float *aux, const float *res, int32_t act, float *out_f32, uint16_t *out_bf16,
                           void *stream)
 {
-    if (!x || !w || !shape_ok(in) || in.c % 16 || cout <= 0 || cout % 32)
-        return nn_fail(FWI_E_ARG, "conv3x3: need input channels %% 16 == 0 and output channels %% 32 == 0");
-    if (!out_f32 && !out_bf16) return nn_fail(FWI_E_ARG, "conv3x3: no output");
-    const int64_t P = (int64_t)in.n * in.h * in.w;
-    hipStream_t st = (hipStream_t)stream;
-    // 64 x 64 wavefront tiles where the output channels allow it and the grid stays large
-    if (cout % 64 == 0 && P >= 64 * 1024) {
-        dim3 grid((unsigned)((P + 127) / 128), (unsigned)((cout + 127) / 128));
-        k_conv3x3<2, 2><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, out_bf16);
-    } else if (P >= 64 * 1024) {
-        dim3 grid((unsigned)((P + 127) / 128), (unsigned)((cout + 63) / 64));
-        k_conv3x3<2, 1><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, out_bf16);
-    } else {
-        dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
-        k_conv3x3<1, 1><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, out_bf16);
-    }
-    NN_TRY(hipGetLastError());
-    return FWI_OK;
+    if (!x) return nn_fail(FWI_E_ARG, "conv3x3: no input");
+    return conv_launch(x, nullptr, 0, in, w, cout, bias, aux, res, act, out_f32, out_bf16, (hipStream_t)stream);
+}
+
+fwi_status fwi_nn_conv3x3_upcat(const uint16_t *a, int32_t ca, const uint16_t *b, fwi_nn_shape in, const uint16_t *w,
+                                int32_t cout, const float *bias, const float *aux, const float *res, int32_t act,
+                                float *out_f32, uint16_t *out_bf16, void *stream)
+{
+    if (!a || !b || !upcat_ok(in, ca))
+        return nn_fail(FWI_E_ARG, "conv3x3_upcat: need ca %% 16 == 0, (c - ca) %% 16 == 0, c > ca > 0, even h and w");
+    return conv_launch(b, a, ca, in, w, cout, bias, aux, res, act, out_f32, out_bf16, (hipStream_t)stream);
 }
 
 int64_t fwi_nn_wgrad_work(fwi_nn_shape in, int32_t cout)
 {
-    if (!shape_ok(in) || cout <= 0) return 0;
-    return (int64_t)wgrad_chunks(in, cout) * cout * 9 * in.c + (int64_t)std::max<int64_t>(1, ((int64_t)in.n * in.h * in.w + 4095) / 4096) * cout;
+    if (!shape_ok(in) || cout <= 0 || cout % 32 || in.c % 16) return 0;
+    const WgradPlan p = wgrad_plan(in, cout);
+    return ((int64_t)p.nch + sum_groups(p.nch)) * p.nw + p.bias_chunks * cout;
 }
 
 fwi_status fwi_nn_wgrad(const uint16_t *dz, const float *dz_f32, const uint16_t *x, fwi_nn_shape in, int32_t cout,
                         float *dw, float *db, float *work, void *stream)
 {
-    if (!dz || !x || !dw || !work || !shape_ok(in) || in.c % 16 || cout % 32 || (db && !dz_f32))
-        return nn_fail(FWI_E_ARG, "wgrad: bad arguments");
-    hipStream_t st = (hipStream_t)stream;
-    const int64_t P = (int64_t)in.n * in.h * in.w;
-    const int nch = wgrad_chunks(in, cout);
-    const int64_t per = (P + nch - 1) / nch;
-    const int nci = (in.c + 31) / 32;
-    dim3 grid((unsigned)((cout / 32) * nci), (unsigned)nch);
-    k_wgrad<<<grid, 64, 0, st>>>(dz, x, in.n, in.h, in.w, in.c, cout, per, work);
-    NN_TRY(hipGetLastError());
-    const int64_t nw = (int64_t)cout * 9 * in.c;
-    k_sum_chunks<<<grid_for(nw), 256, 0, st>>>(work, nch, nw, dw);
-    NN_TRY(hipGetLastError());
-    if (db) {
-        const int bch = (int)std::max<int64_t>(1, (P + 4095) / 4096);
-        float *bw = work + (int64_t)nch * nw;
-        k_bias_partial<<<bch, 256, 0, st>>>(dz_f32, P, cout, (P + bch - 1) / bch, bw);
-        NN_TRY(hipGetLastError());
-        k_sum_chunks<<<grid_for(cout), 256, 0, st>>>(bw, bch, cout, db);
-        NN_TRY(hipGetLastError());
-    }
-    return FWI_OK;
+    if (!x) return nn_fail(FWI_E_ARG, "wgrad: no input");
+    return wgrad_launch(dz, dz_f32, x, nullptr, 0, in, cout, dw, db, work, (hipStream_t)stream);
+}
+
+fwi_status fwi_nn_wgrad_upcat(const uint16_t *dz, const float *dz_f32, const uint16_t *a, int32_t ca,
+                              const uint16_t *b, fwi_nn_shape in, int32_t cout, float *dw, float *db, float *work,
+                              void *stream)
+{
+    if (!a || !b || !upcat_ok(in, ca))
+        return nn_fail(FWI_E_ARG, "wgrad_upcat: need ca %% 16 == 0, (c - ca) %% 16 == 0, c > ca > 0, even h and w");
+    return wgrad_launch(dz, dz_f32, b, a, ca, in, cout, dw, db, work, (hipStream_t)stream);
 }
 
 fwi_status fwi_nn_pool2(const uint16_t *x, fwi_nn_shape in, uint16_t *out, void *stream)

@@ -26,7 +26,9 @@ def lib():
         P = C.c_void_p
         sig = {
             "fwi_nn_conv3x3": [P, Shape, P, C.c_int32, P, P, P, C.c_int32, P, P, P],
+            "fwi_nn_conv3x3_upcat": [P, C.c_int32, P, Shape, P, C.c_int32, P, P, P, C.c_int32, P, P, P],
             "fwi_nn_wgrad": [P, P, P, Shape, C.c_int32, P, P, P, P],
+            "fwi_nn_wgrad_upcat": [P, P, P, C.c_int32, P, Shape, C.c_int32, P, P, P, P],
             "fwi_nn_pool2": [P, Shape, P, P],
             "fwi_nn_pool2_bwd": [P, Shape, P, C.c_int32, P],
             "fwi_nn_up2": [P, Shape, P, P],
@@ -81,6 +83,17 @@ def as_float(t16):
 def conv3x3(x, shape, w, cout, bias=None, aux=None, act=False, out_f32=None, out_bf16=None, res=None):
     _ok(lib().fwi_nn_conv3x3(_p(x), Shape(*shape), _p(w), cout, _p(bias), _p(aux), _p(res), int(act), _p(out_f32),
                              _p(out_bf16), _s()))
+
+
+def conv3x3_upcat(a, ca, b, shape, w, cout, bias=None, aux=None, act=False, out_f32=None, out_bf16=None, res=None):
+    """conv3x3 over the concatenation [up2(a), b] (shape: the concatenated input)."""
+    _ok(lib().fwi_nn_conv3x3_upcat(_p(a), ca, _p(b), Shape(*shape), _p(w), cout, _p(bias), _p(aux), _p(res),
+                                   int(act), _p(out_f32), _p(out_bf16), _s()))
+
+
+def wgrad_upcat(dz, dz_f32, a, ca, b, shape, cout, dw, db, work):
+    _ok(lib().fwi_nn_wgrad_upcat(_p(dz), _p(dz_f32), _p(a), ca, _p(b), Shape(*shape), cout, _p(dw), _p(db),
+                                 _p(work), _s()))
 
 
 def wgrad_work(shape, cout):

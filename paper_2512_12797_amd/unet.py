@@ -85,7 +85,9 @@ class UNet:
     # ------------------------------------------------------------ forward
     def forward(self, x16, res, n, h, w, keep=False):
         """x16: bf16 [n, h, w, 16]; res: f32 [n*h*w] added to output channel 0.
-        Returns f32 [n, h, w, 32] (channel 0 = prediction)."""
+        Returns f32 [n, h, w, 32] (channel 0 = prediction).  keep: store what the backward
+        pass needs, including the FP32 pre-activations (inference writes only the BF16
+        activations)."""
         assert h % (1 << (self.L - 1)) == 0 and w % (1 << (self.L - 1)) == 0
         dev = self.device
         st = {"x": x16, "n": n, "h": h, "w": w, "res": res}
@@ -97,10 +99,10 @@ class UNet:
                 nn.pool2(cur, (n, 2 * hi, 2 * wi, cur_c), pooled)
                 cur = pooled
                 st["pool%d" % i] = pooled
-            za = torch.empty(n, hi, wi, ca.cout, device=dev)
+            za = torch.empty(n, hi, wi, ca.cout, device=dev) if keep else None
             aa = nn.bf16_empty(n, hi, wi, ca.cout, device=dev)
             nn.conv3x3(cur, (n, hi, wi, cur_c), ca.w16, ca.cout, ca.b, act=True, out_f32=za, out_bf16=aa)
-            zb = torch.empty(n, hi, wi, cb.cout, device=dev)
+            zb = torch.empty(n, hi, wi, cb.cout, device=dev) if keep else None
             ab = nn.bf16_empty(n, hi, wi, cb.cout, device=dev)
             nn.conv3x3(aa, (n, hi, wi, ca.cout), cb.w16, cb.cout, cb.b, act=True, out_f32=zb, out_bf16=ab)
             st["enc%d" % i] = (cur, za, aa, zb, ab)
@@ -108,19 +110,16 @@ class UNet:
         for i in range(self.L - 2, -1, -1):
             hi, wi = h >> i, w >> i
             da, db = self.dec[i]
-            up = nn.bf16_empty(n, hi, wi, cur_c, device=dev)
-            nn.up2(cur, (n, hi // 2, wi // 2, cur_c), up)
+            # first convolution over [up2(cur), skip], read in place by the kernel
             skip = st["enc%d" % i][4]
-            cat = nn.bf16_empty(n, hi, wi, cur_c + self.chans[i], device=dev)
-            nn.concat(up, cur_c, skip, self.chans[i], n * hi * wi, cat)
-            za = torch.empty(n, hi, wi, da.cout, device=dev)
+            za = torch.empty(n, hi, wi, da.cout, device=dev) if keep else None
             aa = nn.bf16_empty(n, hi, wi, da.cout, device=dev)
-            nn.conv3x3(cat, (n, hi, wi, cur_c + self.chans[i]), da.w16, da.cout, da.b, act=True, out_f32=za,
-                       out_bf16=aa)
-            zb = torch.empty(n, hi, wi, db.cout, device=dev)
+            nn.conv3x3_upcat(cur, cur_c, skip, (n, hi, wi, cur_c + self.chans[i]), da.w16, da.cout, da.b, act=True,
+                             out_f32=za, out_bf16=aa)
+            zb = torch.empty(n, hi, wi, db.cout, device=dev) if keep else None
             ab = nn.bf16_empty(n, hi, wi, db.cout, device=dev)
             nn.conv3x3(aa, (n, hi, wi, da.cout), db.w16, db.cout, db.b, act=True, out_f32=zb, out_bf16=ab)
-            st["dec%d" % i] = (cat, za, aa, zb, ab, cur_c)
+            st["dec%d" % i] = ((cur, skip), za, aa, zb, ab, cur_c)
             cur, cur_c = ab, db.cout
         out = torch.empty(n, h, w, 32, device=dev)
         nn.conv3x3(cur, (n, h, w, cur_c), self.out.w16, 32, self.out.b, res=res, out_f32=out)
@@ -133,10 +132,15 @@ class UNet:
     def _conv_bwd(self, conv, x16, shape_in, dz32, dz16, aux=None, want_dx=True):
         """Weight/bias gradients of `conv` and the gradient w.r.t. its input: with aux
         (the input's pre-activation) the result is dL/dz of the previous layer (f32, bf16);
-        without, dL/dx in f32."""
+        without, dL/dx in f32.  x16 is the input, or (a, b) for the concatenation
+        [up2(a), b] of a decoder's first convolution."""
         n, h, w, cin = shape_in
         work = torch.empty(nn.wgrad_work(shape_in, conv.cout), device=self.device)
-        nn.wgrad(dz16, dz32, x16, shape_in, conv.cout, conv.dw, conv.db, work)
+        if isinstance(x16, tuple):
+            a, b = x16
+            nn.wgrad_upcat(dz16, dz32, a, cin - b.shape[-1], b, shape_in, conv.cout, conv.dw, conv.db, work)
+        else:
+            nn.wgrad(dz16, dz32, x16, shape_in, conv.cout, conv.dw, conv.db, work)
         if not want_dx:
             return None
         o32 = torch.empty(n, h, w, cin, device=self.device)
@@ -156,11 +160,11 @@ class UNet:
         for i in range(self.L - 1):
             hi, wi = h >> i, w >> i
             da_conv, db_conv = self.dec[i]
-            cat, za, aa, zb, ab, cdeep = st["dec%d" % i]
+            cat_src, za, aa, zb, ab, cdeep = st["dec%d" % i]
             # second conv of the level: input aa (pre-activation za)
             dz, dz16 = self._conv_bwd(db_conv, aa, (n, hi, wi, da_conv.cout), dz, dz16, aux=za)
             # first conv: input = concat(up(deeper), skip)
-            dcat = self._conv_bwd(da_conv, cat, (n, hi, wi, cdeep + self.chans[i]), dz, dz16)
+            dcat = self._conv_bwd(da_conv, cat_src, (n, hi, wi, cdeep + self.chans[i]), dz, dz16)
             dup = torch.empty(n, hi, wi, cdeep, device=dev)
             d_skip[i] = torch.empty(n, hi, wi, self.chans[i], device=dev)
             nn.split_bwd(dcat, cdeep, self.chans[i], n * hi * wi, dup, False, d_skip[i], False)

@@ -106,6 +106,44 @@ def test_conv_fwd_dgrad_wgrad(N, n, h, w, ci, co):
     assert rel(f64(db), dz.reshape(-1, co).sum(0)) < 1e-5
 
 
+@pytest.mark.parametrize("n,h,w,ca,cb,co", [(2, 16, 20, 32, 16, 32), (1, 64, 66, 64, 32, 64), (3, 10, 8, 16, 48, 96)])
+def test_upcat_conv_and_wgrad(N, n, h, w, ca, cb, co):
+    """Convolution and weight gradient over [up2(a), b] read in place: against the oracle on
+    the concatenated input, and bit for bit against the same kernels on the materialised
+    concatenation (upsampling and concatenation only copy BF16 values)."""
+    say("case upcat %s" % ((n, h, w, ca, cb, co),))
+    r = np.random.default_rng(ca + 3 * cb + co)
+    a = U.bf16(r.standard_normal((n, h // 2, w // 2, ca)))
+    b = U.bf16(r.standard_normal((n, h, w, cb)))
+    cat = np.concatenate([U.up2(a), b], axis=-1)
+    ci = ca + cb
+    wt = U.bf16(r.standard_normal((co, 9, ci)) / np.sqrt(9 * ci))
+    bias = r.standard_normal(co).astype(np.float32).astype(np.float64)
+    ag, bg, wg = to_bf16_bits(a), to_bf16_bits(b), to_bf16_bits(wt)
+    biasg = torch.tensor(bias, dtype=torch.float32, device="cuda")
+    out = torch.empty(n, h, w, co, device="cuda")
+    o16 = N.bf16_empty(n, h, w, co)
+    N.conv3x3_upcat(ag, ca, bg, (n, h, w, ci), wg, co, bias=biasg, act=True, out_f32=out, out_bf16=o16)
+    assert rel(f64(out), U.conv3x3(cat, wt, bias)) < 1e-5
+    catg = to_bf16_bits(cat)
+    out2 = torch.empty_like(out)
+    o216 = N.bf16_empty(n, h, w, co)
+    N.conv3x3(catg, (n, h, w, ci), wg, co, bias=biasg, act=True, out_f32=out2, out_bf16=o216)
+    assert torch.equal(out, out2) and torch.equal(o16, o216)
+    dz = U.bf16(r.standard_normal((n, h, w, co)))
+    dzg = to_bf16_bits(dz)
+    dz32 = torch.tensor(dz, dtype=torch.float32, device="cuda")
+    dw = torch.empty(co, 9, ci, device="cuda")
+    db = torch.empty(co, device="cuda")
+    work = torch.empty(N.wgrad_work((n, h, w, ci), co), device="cuda")
+    N.wgrad_upcat(dzg, dz32, ag, ca, bg, (n, h, w, ci), co, dw, db, work)
+    assert rel(f64(dw), U.conv3x3_wgrad(dz, cat)) < 1e-5
+    assert rel(f64(db), dz.reshape(-1, co).sum(0)) < 1e-5
+    dw2 = torch.empty_like(dw)
+    N.wgrad(dzg, dz32, catg, (n, h, w, ci), co, dw2, None, work)
+    assert torch.equal(dw, dw2)
+
+
 def test_elementwise_kernels(N):
     say("case elementwise")
     r = np.random.default_rng(5)
