@@ -172,26 +172,29 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
 
     # per-kernel: record the calls of one forward pass and one training step, then time each
     convs, wgrads = [], []
-    orig_conv, orig_wgrad = nn.conv3x3, nn.wgrad
+    orig = {k: getattr(nn, k) for k in ("conv3x3", "conv3x3_upcat", "wgrad", "wgrad_upcat")}
 
-    def rec_conv(*a, **k):
-        convs.append((a, k))
-        orig_conv(*a, **k)
+    def recorder(name, into):
+        def rec(*a, **k):
+            into.append((orig[name], a, k))
+            orig[name](*a, **k)
+        return rec
 
-    def rec_wgrad(*a):
-        wgrads.append(a)
-        orig_wgrad(*a)
-
-    nn.conv3x3 = rec_conv
+    # (call, shape, cout, keyword arguments) of every convolution and weight gradient
+    for k in ("conv3x3", "conv3x3_upcat"):
+        setattr(nn, k, recorder(k, convs))
     try:
         net.forward(x16, rflat, b, n, n)
     finally:
-        nn.conv3x3 = orig_conv
-    nn.wgrad = rec_wgrad
+        for k in ("conv3x3", "conv3x3_upcat"):
+            setattr(nn, k, orig[k])
+    for k in ("wgrad", "wgrad_upcat"):
+        setattr(nn, k, recorder(k, wgrads))
     try:
         train_step()
     finally:
-        nn.wgrad = orig_wgrad
+        for k in ("wgrad", "wgrad_upcat"):
+            setattr(nn, k, orig[k])
     torch.cuda.synchronize()
     t_train = gpu_time(train_step, max(args.steps, 5))
 
@@ -205,25 +208,30 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
                 "frac": round(ach / roof, 3)}
 
     rows, tot_fl, tot_s = [], 0.0, 0.0
-    for a, k in convs:
-        x, shape, w_, cout = a[:4]
+    for fn, a, k in convs:
+        shape, cout = (a[1], a[3]) if fn is orig["conv3x3"] else (a[3], a[5])
         nb_, h, w, cin = shape
-        sec = gpu_time(lambda: orig_conv(*a, **k), 10)
+        sec = gpu_time(lambda: fn(*a, **k), 10)
         fl = 2.0 * 9 * cin * cout * nb_ * h * w
-        by = nb_ * h * w * (2 * cin + cout * (4 * (k.get("out_f32") is not None) + 2 * (k.get("out_bf16") is not None)
-                                              + 4 * (k.get("aux") is not None))
+        ca = 0 if fn is orig["conv3x3"] else a[1]  # channels read at half resolution
+        by = nb_ * h * w * (2 * (cin - ca) + 2 * ca / 4.0
+                            + cout * (4 * (k.get("out_f32") is not None) + 2 * (k.get("out_bf16") is not None)
+                                      + 4 * (k.get("aux") is not None))
                             + 4 * (k.get("res") is not None)) + 2 * 9 * cin * cout
-        rows.append(row("conv3x3 forward", h, w, cin, cout, fl, by, sec))
+        rows.append(row("conv3x3 forward" + ("" if fn is orig["conv3x3"] else " [up2(a), b]"), h, w, cin, cout, fl,
+                        by, sec))
         tot_fl += fl
         tot_s += sec
     wrows = []
-    for a in wgrads:
-        dz, dz32, x, shape, cout, dw, db, wk = a
+    for fn, a, k in wgrads:
+        shape, cout, db = (a[3], a[4], a[6]) if fn is orig["wgrad"] else (a[5], a[6], a[8])
         nb_, h, w, cin = shape
-        sec = gpu_time(lambda: orig_wgrad(*a), 10)
+        sec = gpu_time(lambda: fn(*a), 10)
         fl = 2.0 * 9 * cin * cout * nb_ * h * w
-        by = nb_ * h * w * (2 * cin + 2 * cout + 4 * cout * (db is not None)) + 4 * 9 * cin * cout
-        wrows.append(row("weight gradient", h, w, cin, cout, fl, by, sec))
+        ca = 0 if fn is orig["wgrad"] else a[3]
+        by = nb_ * h * w * (2 * (cin - ca) + 2 * ca / 4.0 + 2 * cout + 4 * cout * (db is not None)) + 4 * 9 * cin * cout
+        wrows.append(row("weight gradient" + ("" if fn is orig["wgrad"] else " [up2(a), b]"), h, w, cin, cout, fl, by,
+                         sec))
     # levels of net.layers(): encoder levels 0..L-1, decoder levels 0..L-2 (two convolutions
     # each), then the output convolution at level 0
     lv = [i for i in range(net.L) for _ in (0, 1)] + [i for i in range(net.L - 1) for _ in (0, 1)] + [0]

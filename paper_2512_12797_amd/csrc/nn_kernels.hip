@@ -199,26 +199,25 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x,
 // read; the transposition is done while storing (pairs of pixels packed into 32-bit words).  The column shift of a
 // tap comes from one aligned 16-byte + 4-byte read per patch row: shift 0 is the 16 bytes, shift 2 drops the first
 // word and appends the extra one, shift 1 is the funnel shift by 16 bits of consecutive words.  Channel pitches are
-// odd multiples of 16 bytes so that the 32 rows of an operand read fall in distinct banks.  The 4 wavefronts split
-// the tile's 2*TY k-steps; their accumulators are added in wavefront order at the end (deterministic).
+// odd multiples of 16 bytes so that the 32 rows of an operand read fall in distinct banks.  Three wavefronts, one
+// per tap row dy, each with the accumulators of its 3 taps: no reduction between wavefronts, and few enough
+// registers for several workgroups per compute unit to hide the tile loads.
 // The input may be the concatenation [up(xu), x] as in k_conv3x3 (cu > 0).
 template <int TY>
-__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
+__global__ __launch_bounds__(192) void k_wgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
                                                int N, int H, int W, int Cin, int Cout, int ntiles, int per_chunk,
                                                float *__restrict__ work, const uint16_t *__restrict__ xu, int cu)
 {
-    constexpr int PR = TY + 2;
-    constexpr int DZP = TY * 32 + 8;                                  // elements per output channel
-    constexpr int XRP = 40;                                           // elements per patch row
+    constexpr int NTH = 192, PR = TY + 2;
+    constexpr int DZP = TY * 32 + 8;                                    // elements per output channel
+    constexpr int XRP = 40;                                             // elements per patch row
     constexpr int XP = PR * XRP + (((PR * XRP / 8) % 2) == 0 ? 8 : 0);  // elements per input channel
-    constexpr int LDS_ELEMS = 32 * DZP + 32 * XP;
-    static_assert(LDS_ELEMS * 2 >= 4 * 64 * 16 * 4, "reduction buffer");
-    constexpr int NDZ = TY * 64;                 // dz items: (row, pixel pair, 8-channel group)
-    constexpr int NX = PR * 17 * 4;              // patch items: (row, column pair, 8-channel group)
-    constexpr int RD = (NDZ + 255) / 256, RX = (NX + 255) / 256;
-    __shared__ __align__(16) uint16_t smem[LDS_ELEMS];
-    uint16_t *sdz = smem, *sx = smem + 32 * DZP;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, hl = lane >> 5;
+    constexpr int NDZ = TY * 64;                                        // dz items: (row, pixel pair, 8 channels)
+    constexpr int NX = PR * 17 * 4;                                     // patch items: (row, column pair, 8 channels)
+    constexpr int RD = (NDZ + NTH - 1) / NTH, RX = (NX + NTH - 1) / NTH;
+    __shared__ __align__(16) uint16_t sdz[32 * DZP];
+    __shared__ __align__(16) uint16_t sx[32 * XP];
+    const int tid = threadIdx.x, dy = tid >> 6, lane = tid & 63, l32 = lane & 31, hl = lane >> 5;
     const int nci = (Cin + 31) >> 5;
     const int cit = blockIdx.x % nci, cot = blockIdx.x / nci;
     const int ci0 = cit * 32, cb = cot * 32;
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dz, 
         const int y0 = rt * TY, x0 = seg * 32;
 #pragma unroll
         for (int i = 0; i < RD; ++i) {
-            const int q = tid + 256 * i, g8 = q & 3, pp = (q >> 2) & 15, r = q >> 6;
+            const int q = tid + NTH * i, g8 = q & 3, pp = (q >> 2) & 15, r = q >> 6;
             const int y = y0 + r, xa = x0 + 2 * pp;
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
@@ -242,7 +241,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dz, 
         }
 #pragma unroll
         for (int i = 0; i < RX; ++i) {
-            const int q = tid + 256 * i, g8 = q & 3, rest = q >> 2;
+            const int q = tid + NTH * i, g8 = q & 3, rest = q >> 2;
             const int cp = rest % 17, pr = rest / 17;
             const int y = y0 - 1 + pr, xa = x0 - 1 + 2 * cp;
             const int ci = ci0 + 8 * g8;
@@ -268,19 +267,19 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dz, 
     auto lstore = [&]() {
 #pragma unroll
         for (int i = 0; i < RD; ++i) {
-            const int q = tid + 256 * i, g8 = q & 3, pp = (q >> 2) & 15, r = q >> 6;
+            const int q = tid + NTH * i, g8 = q & 3, pp = (q >> 2) & 15, r = q >> 6;
             if (q < NDZ) put8(sdz + (8 * g8) * DZP + r * 32 + 2 * pp, DZP, rd[i][0], rd[i][1]);
         }
 #pragma unroll
         for (int i = 0; i < RX; ++i) {
-            const int q = tid + 256 * i, g8 = q & 3, rest = q >> 2;
+            const int q = tid + NTH * i, g8 = q & 3, rest = q >> 2;
             const int cp = rest % 17, pr = rest / 17;
             if (q < NX) put8(sx + (8 * g8) * XP + pr * XRP + 2 * cp, XP, rx[i][0], rx[i][1]);
         }
     };
-    f32x16 acc[9];
+    f32x16 acc[3];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
+    for (int t = 0; t < 3; ++t) acc[t] = f32x16{};
     if (t_beg < t_end) gload(t_beg);
     for (int t = t_beg; t < t_end; ++t) {
         __syncthreads();
@@ -288,52 +287,31 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dz, 
         __syncthreads();
         if (t + 1 < t_end) gload(t + 1);
 #pragma unroll
-        for (int kk = 0; kk < TY / 2; ++kk) {
-            const int ks = wave + 4 * kk;  // k-step: row ks / 2, 16-column half ks % 2
+        for (int ks = 0; ks < 2 * TY; ++ks) {  // k-step: row ks / 2, 16-column half ks % 2
             const int r = ks >> 1, g = 2 * (ks & 1) + hl;
             const bf16x8 b = __builtin_bit_cast(bf16x8, *(const uint4 *)(sdz + l32 * DZP + r * 32 + 8 * g));
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-                const uint16_t *src = sx + l32 * XP + (r + dy) * XRP + 8 * g;
-                const uint4 d = *(const uint4 *)src;
-                const uint32_t e4 = *(const uint32_t *)(src + 8);
-                const uint4 s1 = make_uint4(__builtin_amdgcn_alignbit(d.y, d.x, 16), __builtin_amdgcn_alignbit(d.z, d.y, 16),
-                                            __builtin_amdgcn_alignbit(d.w, d.z, 16), __builtin_amdgcn_alignbit(e4, d.w, 16));
-                const uint4 s2 = make_uint4(d.y, d.z, d.w, e4);
-                acc[3 * dy] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, d), b, acc[3 * dy], 0, 0, 0);
-                acc[3 * dy + 1] =
-                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, s1), b, acc[3 * dy + 1], 0, 0, 0);
-                acc[3 * dy + 2] =
-                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, s2), b, acc[3 * dy + 2], 0, 0, 0);
-            }
+            const uint16_t *src = sx + l32 * XP + (r + dy) * XRP + 8 * g;
+            const uint4 d = *(const uint4 *)src;
+            const uint32_t e4 = *(const uint32_t *)(src + 8);
+            const uint4 s1 = make_uint4(__builtin_amdgcn_alignbit(d.y, d.x, 16), __builtin_amdgcn_alignbit(d.z, d.y, 16),
+                                        __builtin_amdgcn_alignbit(d.w, d.z, 16), __builtin_amdgcn_alignbit(e4, d.w, 16));
+            const uint4 s2 = make_uint4(d.y, d.z, d.w, e4);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, d), b, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, s1), b, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, s2), b, acc[2], 0, 0, 0);
         }
     }
-    // acc[tap][r]: row (input channel) ci0 + 8(r/4) + 4(lane/32) + r%4, column (output channel) cb + lane%32.
-    // Sum the 4 wavefronts in order, one tap per round; wavefront tap%4 adds and stores.
-    float *red = reinterpret_cast<float *>(smem);
+    // acc[dx][r]: row (input channel) ci0 + 8(r/4) + 4(lane/32) + r%4, column (output channel) cb + lane%32
     float *wk = work + (int64_t)blockIdx.y * Cout * 9 * Cin;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        __syncthreads();
+    for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc[tap][r];
-        __syncthreads();
-        if (wave == (tap & 3)) {
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int ci = ci0 + 8 * g + 4 * hl;
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int r = 4 * g + e;
-                    v[e] = ((red[r * 64 + lane] + red[(16 + r) * 64 + lane]) + red[(32 + r) * 64 + lane]) +
-                           red[(48 + r) * 64 + lane];
-                }
-                if (ci < Cin)
-                    *(float4 *)(wk + ((int64_t)(cb + l32) * 9 + tap) * Cin + ci) = make_float4(v[0], v[1], v[2], v[3]);
-            }
+        for (int g = 0; g < 4; ++g) {
+            const int ci = ci0 + 8 * g + 4 * hl;
+            if (ci < Cin)
+                *(float4 *)(wk + ((int64_t)(cb + l32) * 9 + 3 * dy + dx) * Cin + ci) =
+                    make_float4(acc[dx][4 * g], acc[dx][4 * g + 1], acc[dx][4 * g + 2], acc[dx][4 * g + 3]);
         }
-    }
 }
 
 // Column sums over groups of 32 rows of a [rows][n] matrix: out[g][i] = sum of m[r][i], r in [32 g, 32 g + 32)
@@ -494,6 +472,109 @@ __global__ void k_silu_bwd(const float *__restrict__ da, const float *__restrict
     }
 }
 
+// Vector forms of the elementwise kernels above for channel counts that are multiples of 4 (8 for BF16 pooling) and
+// 16-byte aligned tensors: one thread per 4 channels (16-byte loads and stores), the same arithmetic per element.
+__global__ void k_pool2_v8(const uint16_t *__restrict__ x, int N, int H, int W, int C, uint16_t *__restrict__ out)
+{
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    const int64_t n_out = (int64_t)N * Ho * Wo * C8;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C8) * 8;
+        int64_t t = i / C8;
+        const int xo = (int)(t % Wo);
+        t /= Wo;
+        const int yo = (int)(t % Ho);
+        const int n = (int)(t / Ho);
+        const int64_t b = (((int64_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
+        const uint4 q[4] = {*(const uint4 *)(x + b), *(const uint4 *)(x + b + C), *(const uint4 *)(x + b + (int64_t)W * C),
+                            *(const uint4 *)(x + b + (int64_t)W * C + C)};
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t w0 = (&q[0].x)[k], w1 = (&q[1].x)[k], w2 = (&q[2].x)[k], w3 = (&q[3].x)[k];
+            const float lo = bf2f(w0 & 0xffffu) + bf2f(w1 & 0xffffu) + bf2f(w2 & 0xffffu) + bf2f(w3 & 0xffffu);
+            const float hi = bf2f(w0 >> 16) + bf2f(w1 >> 16) + bf2f(w2 >> 16) + bf2f(w3 >> 16);
+            o[k] = (uint32_t)f2bf(0.25f * lo) | ((uint32_t)f2bf(0.25f * hi) << 16);
+        }
+        *(uint4 *)(out + i * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
+__global__ void k_pool2_bwd_v4(const float *__restrict__ dout, int N, int H, int W, int C, float *__restrict__ dx,
+                               int accum)
+{
+    const int C4 = C / 4;
+    const int64_t n_in = (int64_t)N * H * W * C4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C4) * 4;
+        int64_t t = i / C4;
+        const int xx = (int)(t % W);
+        t /= W;
+        const int y = (int)(t % H);
+        const int n = (int)(t / H);
+        float4 g = *(const float4 *)(dout + (((int64_t)n * (H / 2) + y / 2) * (W / 2) + xx / 2) * C + c);
+        g.x *= 0.25f, g.y *= 0.25f, g.z *= 0.25f, g.w *= 0.25f;
+        float4 *d = (float4 *)(dx + i * 4);
+        if (accum) {
+            const float4 o = *d;
+            g.x = o.x + g.x, g.y = o.y + g.y, g.z = o.z + g.z, g.w = o.w + g.w;
+        }
+        *d = g;
+    }
+}
+
+__global__ void k_up2_bwd_v4(const float *__restrict__ dout, int N, int H, int W, int C, float *__restrict__ dx)
+{
+    const int C4 = C / 4, Wo = 2 * W;
+    const int64_t n_in = (int64_t)N * H * W * C4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C4) * 4;
+        int64_t t = i / C4;
+        const int xx = (int)(t % W);
+        t /= W;
+        const int y = (int)(t % H);
+        const int n = (int)(t / H);
+        const int64_t b = (((int64_t)n * 2 * H + 2 * y) * Wo + 2 * xx) * C + c;
+        const float4 p0 = *(const float4 *)(dout + b), p1 = *(const float4 *)(dout + b + C);
+        const float4 p2 = *(const float4 *)(dout + b + (int64_t)Wo * C), p3 = *(const float4 *)(dout + b + (int64_t)Wo * C + C);
+        *(float4 *)(dx + i * 4) = make_float4(p0.x + p1.x + p2.x + p3.x, p0.y + p1.y + p2.y + p3.y,
+                                              p0.z + p1.z + p2.z + p3.z, p0.w + p1.w + p2.w + p3.w);
+    }
+}
+
+__global__ void k_split_bwd_v4(const float *__restrict__ d, int ca, int cb, int64_t npix, float *__restrict__ da,
+                               int acc_a, float *__restrict__ db, int acc_b)
+{
+    const int C4 = (ca + cb) / 4;
+    const int64_t n = npix * C4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C4) * 4;
+        const int64_t p = i / C4;
+        const float4 v = *(const float4 *)(d + i * 4);
+        float *dst = c < ca ? (da ? da + p * ca + c : nullptr) : (db ? db + p * cb + c - ca : nullptr);
+        if (!dst) continue;
+        float4 r = v;
+        if (c < ca ? acc_a : acc_b) {
+            const float4 o = *(const float4 *)dst;
+            r = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+        }
+        *(float4 *)dst = r;
+    }
+}
+
+__global__ void k_silu_bwd_v4(const float *__restrict__ da, const float *__restrict__ z, int64_t n4,
+                              float *__restrict__ df, uint16_t *__restrict__ db)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 a = *(const float4 *)(da + i * 4), zz = *(const float4 *)(z + i * 4);
+        const float4 g = make_float4(a.x * dsilu(zz.x), a.y * dsilu(zz.y), a.z * dsilu(zz.z), a.w * dsilu(zz.w));
+        if (df) *(float4 *)(df + i * 4) = g;
+        if (db)
+            *(uint2 *)(db + i * 4) = make_uint2((uint32_t)f2bf(g.x) | ((uint32_t)f2bf(g.y) << 16),
+                                                (uint32_t)f2bf(g.z) | ((uint32_t)f2bf(g.w) << 16));
+    }
+}
+
 // relative MSE: partial sums per (chunk, image) of (pred - t)^2 and t^2
 __global__ __launch_bounds__(256) void k_relmse_partial(const float *__restrict__ pred, int C, const float *__restrict__ tg,
                                                         int64_t hw, float *__restrict__ work)
@@ -525,22 +606,43 @@ __global__ __launch_bounds__(256) void k_relmse_partial(const float *__restrict_
     }
 }
 
-// one thread: per-image sums in fixed order, loss, and per-image scale 2 / (nimg |t_i|^2)
-__global__ void k_relmse_final(float *__restrict__ work, int nimg, int nch, float *__restrict__ loss)
+// One workgroup: per-image sums in fixed order (a thread per image), the per-image scale 2 / (nimg |t_i|^2) and
+// relative error into work, then the loss summed in image order by thread 0.
+__global__ __launch_bounds__(256) void k_relmse_final(float *__restrict__ work, int nimg, int nch, float *__restrict__ loss)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float L = 0.0f;
-    for (int i = 0; i < nimg; ++i) {
+    float *scale = work + (int64_t)nimg * nch * 2, *li = scale + nimg;
+    for (int i = threadIdx.x; i < nimg; i += blockDim.x) {
         float sn = 0.0f, sd = 0.0f;
         for (int c = 0; c < nch; ++c) {
             sn += work[((int64_t)i * nch + c) * 2];
             sd += work[((int64_t)i * nch + c) * 2 + 1];
         }
         const float den = sd > 0.0f ? sd : 1.0f;
-        L += sn / den;
-        work[(int64_t)nimg * nch * 2 + i] = 2.0f / ((float)nimg * den);
+        li[i] = sn / den;
+        scale[i] = 2.0f / ((float)nimg * den);
     }
-    if (loss) loss[0] = L / (float)nimg;
+    __syncthreads();
+    if (threadIdx.x == 0 && loss) {
+        float L = 0.0f;
+        for (int i = 0; i < nimg; ++i) L += li[i];
+        loss[0] = L / (float)nimg;
+    }
+}
+
+// dL/dpred with 4 channels per thread (c % 4 == 0): only channel 0 is nonzero.
+__global__ void k_relmse_grad_v4(const float *__restrict__ pred, int C, const float *__restrict__ tg, int nimg,
+                                 int64_t hw, const float *__restrict__ scale, float *__restrict__ dpred,
+                                 uint16_t *__restrict__ dpb)
+{
+    const int C4 = C / 4;
+    const int64_t n = (int64_t)nimg * hw * C4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pk = i / C4;
+        const int img = (int)(pk / hw);
+        const float g = i % C4 == 0 ? scale[img] * (pred[pk * C] - tg[pk]) : 0.0f;
+        *(float4 *)(dpred + i * 4) = make_float4(g, 0.0f, 0.0f, 0.0f);
+        if (dpb) *(uint2 *)(dpb + i * 4) = make_uint2((uint32_t)f2bf(g), 0u);
+    }
 }
 
 __global__ void k_relmse_grad(const float *__restrict__ pred, int C, const float *__restrict__ tg, int nimg, int64_t hw,
@@ -719,6 +821,9 @@ int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n 
 
 bool shape_ok(const fwi_nn_shape &s) { return s.n > 0 && s.h > 0 && s.w > 0 && s.c > 0; }
 
+// null pointers count as aligned
+template <typename... T> bool aligned16(const T *...p) { return (((uintptr_t)p | ...) % 16) == 0; }
+
 // Convolution tiles (rows, output channels, wavefronts along the rows), in order of preference: larger tiles reuse
 // each operand read for more matrix operations; the first whose grid has at least kConvMinBlocks workgroups (two per
 // compute unit) is used, else the smallest tile.
@@ -742,8 +847,8 @@ ConvCfg pick_conv(const fwi_nn_shape &in, int cout)
 }
 
 // Weight-gradient partition: pixel tiles of ty rows x 32 columns, chunks of per_chunk tiles, one workgroup per
-// (32 x 32 channel block, chunk); about 1024 workgroups, with the partial sums capped at 6 M floats.  Bias partials:
-// chunks of bias_per pixels.
+// (32 x 32 channel block, chunk); about 1024 workgroups (four per compute unit), with the partial sums capped at
+// 8 M floats.  Bias partials: chunks of bias_per pixels.
 struct WgradPlan {
     int ty, ntiles, per_chunk, nch;
     int64_t nw, bias_per, bias_chunks;
@@ -752,12 +857,12 @@ struct WgradPlan {
 WgradPlan wgrad_plan(const fwi_nn_shape &in, int cout)
 {
     WgradPlan p;
-    p.ty = 4;  // k_wgrad<8> needs 260 registers: one wavefront per SIMD
+    p.ty = 4;
     p.ntiles = (int)conv_tiles(in, p.ty);
     const int64_t cc = (int64_t)(cout / 32) * ((in.c + 31) / 32);
     p.nw = (int64_t)cout * 9 * in.c;
     int64_t nch = std::max<int64_t>(1, (1024 + cc - 1) / cc);
-    nch = std::min<int64_t>(nch, std::max<int64_t>(1, ((int64_t)6 << 20) / p.nw));
+    nch = std::min<int64_t>(nch, std::max<int64_t>(1, ((int64_t)8 << 20) / p.nw));
     nch = std::min<int64_t>(nch, p.ntiles);
     p.per_chunk = (int)((p.ntiles + nch - 1) / nch);
     p.nch = (p.ntiles + p.per_chunk - 1) / p.per_chunk;
@@ -808,7 +913,7 @@ fwi_status wgrad_launch(const uint16_t *dz, const float *dz_f32, const uint16_t 
         return nn_fail(FWI_E_ARG, "wgrad: dz, the inputs, dw and work must be 16-byte aligned");
     const WgradPlan p = wgrad_plan(in, cout);
     const dim3 grid((unsigned)((cout / 32) * ((in.c + 31) / 32)), (unsigned)p.nch);
-    k_wgrad<4><<<grid, 256, 0, st>>>(dz, x, in.n, in.h, in.w, in.c, cout, p.ntiles, p.per_chunk, work, xu, cu);
+    k_wgrad<4><<<grid, 192, 0, st>>>(dz, x, in.n, in.h, in.w, in.c, cout, p.ntiles, p.per_chunk, work, xu, cu);
     NN_TRY(hipGetLastError());
     // chunk partials -> groups of 32 -> dw (one pass when there is a single group)
     const int64_t G = sum_groups(p.nch);
@@ -885,8 +990,11 @@ fwi_status fwi_nn_wgrad_upcat(const uint16_t *dz, const float *dz_f32, const uin
 fwi_status fwi_nn_pool2(const uint16_t *x, fwi_nn_shape in, uint16_t *out, void *stream)
 {
     if (!x || !out || !shape_ok(in) || in.h % 2 || in.w % 2) return nn_fail(FWI_E_ARG, "pool2: bad shape");
-    k_pool2<<<grid_for((int64_t)in.n * in.h * in.w * in.c / 4), 256, 0, (hipStream_t)stream>>>(x, in.n, in.h, in.w,
-                                                                                                in.c, out);
+    const int64_t n_out = (int64_t)in.n * (in.h / 2) * (in.w / 2) * in.c;
+    if (in.c % 8 == 0 && aligned16(x, out))
+        k_pool2_v8<<<grid_for(n_out / 8), 256, 0, (hipStream_t)stream>>>(x, in.n, in.h, in.w, in.c, out);
+    else
+        k_pool2<<<grid_for(n_out), 256, 0, (hipStream_t)stream>>>(x, in.n, in.h, in.w, in.c, out);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -894,8 +1002,12 @@ fwi_status fwi_nn_pool2(const uint16_t *x, fwi_nn_shape in, uint16_t *out, void 
 fwi_status fwi_nn_pool2_bwd(const float *dout, fwi_nn_shape in, float *dx, int32_t accumulate, void *stream)
 {
     if (!dout || !dx || !shape_ok(in) || in.h % 2 || in.w % 2) return nn_fail(FWI_E_ARG, "pool2_bwd: bad shape");
-    k_pool2_bwd<<<grid_for((int64_t)in.n * in.h * in.w * in.c), 256, 0, (hipStream_t)stream>>>(dout, in.n, in.h, in.w,
-                                                                                                in.c, dx, accumulate);
+    const int64_t n_in = (int64_t)in.n * in.h * in.w * in.c;
+    if (in.c % 4 == 0 && aligned16(dout, dx))
+        k_pool2_bwd_v4<<<grid_for(n_in / 4), 256, 0, (hipStream_t)stream>>>(dout, in.n, in.h, in.w, in.c, dx,
+                                                                            accumulate);
+    else
+        k_pool2_bwd<<<grid_for(n_in), 256, 0, (hipStream_t)stream>>>(dout, in.n, in.h, in.w, in.c, dx, accumulate);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -912,8 +1024,11 @@ fwi_status fwi_nn_up2(const uint16_t *x, fwi_nn_shape in, uint16_t *out, void *s
 fwi_status fwi_nn_up2_bwd(const float *dout, fwi_nn_shape in, float *dx, void *stream)
 {
     if (!dout || !dx || !shape_ok(in)) return nn_fail(FWI_E_ARG, "up2_bwd: bad shape");
-    k_up2_bwd<<<grid_for((int64_t)in.n * in.h * in.w * in.c), 256, 0, (hipStream_t)stream>>>(dout, in.n, in.h, in.w,
-                                                                                              in.c, dx);
+    const int64_t n_in = (int64_t)in.n * in.h * in.w * in.c;
+    if (in.c % 4 == 0 && aligned16(dout, dx))
+        k_up2_bwd_v4<<<grid_for(n_in / 4), 256, 0, (hipStream_t)stream>>>(dout, in.n, in.h, in.w, in.c, dx);
+    else
+        k_up2_bwd<<<grid_for(n_in), 256, 0, (hipStream_t)stream>>>(dout, in.n, in.h, in.w, in.c, dx);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -931,7 +1046,11 @@ fwi_status fwi_nn_split_bwd(const float *d, int32_t ca, int32_t cb, int64_t npix
                             int32_t acc_b, void *stream)
 {
     if (!d || ca <= 0 || cb <= 0 || npix <= 0) return nn_fail(FWI_E_ARG, "split_bwd: bad arguments");
-    k_split_bwd<<<grid_for(npix * (ca + cb)), 256, 0, (hipStream_t)stream>>>(d, ca, cb, npix, da, acc_a, db, acc_b);
+    if (ca % 4 == 0 && cb % 4 == 0 && aligned16(d, da, db))
+        k_split_bwd_v4<<<grid_for(npix * (ca + cb) / 4), 256, 0, (hipStream_t)stream>>>(d, ca, cb, npix, da, acc_a, db,
+                                                                                         acc_b);
+    else
+        k_split_bwd<<<grid_for(npix * (ca + cb)), 256, 0, (hipStream_t)stream>>>(d, ca, cb, npix, da, acc_a, db, acc_b);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -939,7 +1058,10 @@ fwi_status fwi_nn_split_bwd(const float *d, int32_t ca, int32_t cb, int64_t npix
 fwi_status fwi_nn_silu_bwd(const float *da, const float *z, int64_t n, float *dz_f32, uint16_t *dz_bf16, void *stream)
 {
     if (!da || !z || n <= 0) return nn_fail(FWI_E_ARG, "silu_bwd: bad arguments");
-    k_silu_bwd<<<grid_for(n), 256, 0, (hipStream_t)stream>>>(da, z, n, dz_f32, dz_bf16);
+    if (n % 4 == 0 && aligned16(da, z, dz_f32) && (uintptr_t)dz_bf16 % 8 == 0)
+        k_silu_bwd_v4<<<grid_for(n / 4), 256, 0, (hipStream_t)stream>>>(da, z, n / 4, dz_f32, dz_bf16);
+    else
+        k_silu_bwd<<<grid_for(n), 256, 0, (hipStream_t)stream>>>(da, z, n, dz_f32, dz_bf16);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -953,12 +1075,16 @@ fwi_status fwi_nn_rel_mse(const float *pred, int32_t c, const float *target, int
     const int nch = 64;
     k_relmse_partial<<<dim3(nch, nimg), 256, 0, st>>>(pred, c, target, hw, work);
     NN_TRY(hipGetLastError());
-    k_relmse_final<<<1, 64, 0, st>>>(work, nimg, nch, loss);
+    k_relmse_final<<<1, 256, 0, st>>>(work, nimg, nch, loss);
     NN_TRY(hipGetLastError());
     if (dpred) {
-        k_relmse_grad<<<grid_for((int64_t)nimg * hw * c), 256, 0, st>>>(pred, c, target, nimg, hw,
-                                                                         work + (int64_t)nimg * nch * 2, dpred,
-                                                                         dpred_bf16);
+        if (c % 4 == 0 && aligned16(dpred) && (uintptr_t)dpred_bf16 % 8 == 0)
+            k_relmse_grad_v4<<<grid_for((int64_t)nimg * hw * c / 4), 256, 0, st>>>(
+                pred, c, target, nimg, hw, work + (int64_t)nimg * nch * 2, dpred, dpred_bf16);
+        else
+            k_relmse_grad<<<grid_for((int64_t)nimg * hw * c), 256, 0, st>>>(pred, c, target, nimg, hw,
+                                                                             work + (int64_t)nimg * nch * 2, dpred,
+                                                                             dpred_bf16);
         NN_TRY(hipGetLastError());
     }
     return FWI_OK;

@@ -180,6 +180,27 @@ def test_elementwise_kernels(N):
     N.silu_bwd(torch.tensor(da, device="cuda"), torch.tensor(z, device="cuda"), o, o16)
     ref = da.astype(np.float64) * U.dsilu(z.astype(np.float64))
     assert rel(f64(o), ref) < 1e-6
+    # the scalar forms (channel counts and lengths that are not multiples of 4)
+    a6 = U.bf16(r.standard_normal((1, 4, 6, 6)))
+    p6 = N.bf16_empty(1, 2, 3, 6)
+    N.pool2(to_bf16_bits(a6), (1, 4, 6, 6), p6)
+    assert np.array_equal(f64(p6), U.bf16(U.pool2(a6)))
+    d6 = r.standard_normal((1, 2, 3, 6)).astype(np.float32)
+    dx6 = torch.zeros(1, 4, 6, 6, device="cuda")
+    N.pool2_bwd(torch.tensor(d6, device="cuda"), (1, 4, 6, 6), dx6, False)
+    assert np.allclose(f64(dx6), 0.25 * U.up2(d6.astype(np.float64)), rtol=1e-7)
+    du6 = torch.empty(1, 2, 3, 6, device="cuda")
+    N.up2_bwd(torch.tensor(np.repeat(np.repeat(d6, 2, 1), 2, 2).copy(), device="cuda"), (1, 2, 3, 6), du6)
+    assert rel(f64(du6), 4.0 * d6.astype(np.float64)) < 1e-6
+    g9 = r.standard_normal((5, 8)).astype(np.float32)
+    ga3, gb5 = torch.empty(5, 3, device="cuda"), torch.empty(5, 5, device="cuda")
+    N.split_bwd(torch.tensor(g9, device="cuda"), 3, 5, 5, ga3, False, gb5, False)
+    assert np.array_equal(f64(ga3), g9[:, :3].astype(np.float64)) and np.array_equal(f64(gb5), g9[:, 3:])
+    z7 = r.standard_normal(1001).astype(np.float32)
+    da7 = r.standard_normal(1001).astype(np.float32)
+    o7 = torch.empty(1001, device="cuda")
+    N.silu_bwd(torch.tensor(da7, device="cuda"), torch.tensor(z7, device="cuda"), o7, None)
+    assert rel(f64(o7), da7.astype(np.float64) * U.dsilu(z7.astype(np.float64))) < 1e-6
     # loss: relative squared error of channel 0
     pred = r.standard_normal((3, 40, 32)).astype(np.float32)
     tg = r.standard_normal((3, 40)).astype(np.float32)
