@@ -429,11 +429,11 @@ def main():
     if cfg.ndim == 2:
         adj_bytes = pad_cells * 16 + samp_cells * 20
         adj_name = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)"
-        fwd_name = "forward step (k_step2d<bz>)"
+        fwd_name = "forward step (k_fwd2d<bz>)"
     else:
         adj_bytes = pad_cells * 32 + samp_cells * 4
-        adj_name = "adjoint+imaging step (k_step3d<bz,true>)"
-        fwd_name = "forward step (k_step3d<bz,false>)"
+        adj_name = "adjoint+imaging step (k_adj3d<bz>)"
+        fwd_name = "forward step (k_fwd3d<bz>)"
     if adj_ms >= fwd_ms:
         name, nbytes, ms, n = adj_name, adj_bytes, adj_ms, adj_n
     else:
