@@ -1,11 +1,12 @@
 // nn_kernels.hip -- gfx950 kernels of the learned gradient preconditioner (include/fwi_nn.h).
 //
-// 3x3 convolutions are implicit GEMMs on the BF16 matrix cores: M = pixels, N = output
-// channels, K = 9 taps x input channels, one v_mfma_f32_32x32x16_bf16 per 16-wide K step.
-// Operand lane layout of that instruction (checked on the hardware): A lane l holds row
-// l%32, k = 8*(l/32) .. +7; B lane l holds column l%32, the same k; accumulator register r
-// holds row 8*(r/4) + 4*(l/32) + r%4, column l%32.  With NHWC activations and [Cout][9][Cin]
-// weights both operands are single 16-byte loads per lane.
+// 3x3 convolutions are implicit GEMMs on the BF16 matrix cores (output channels x pixels,
+// K = 9 taps x input channels), their weight gradients GEMMs over pixels (input x output
+// channels per tap), one v_mfma_f32_32x32x16_bf16 per 16-wide K step.  Operand lane layout
+// of that instruction (checked on the hardware): A lane l holds row l%32, k = 8*(l/32) ..
+// +7; B lane l holds column l%32, the same k; accumulator register r holds row
+// 8*(r/4) + 4*(l/32) + r%4, column l%32.  Activations are NHWC, weights [Cout][9][Cin]; the
+// operand tiles are staged in LDS (see each kernel) and read as one 16-byte load per lane.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,16 +56,16 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) { return nb % 8 ? b : (b 
 
 // Workgroup output tile: TY image rows x 32 columns of one image x CO_T output channels; 4 wavefronts, WM along the
 // rows x 4/WM along the channels, each MT rows x NT groups of 32 channels.  The K loop runs over the input channels
-// in chunks of 16.  Per chunk, LDS holds the (TY+2) x 34 input patch (halo included, zeros outside the image) as two
-// planes of 8 channels and the chunk's weights of all 9 taps; each tap is one MFMA k-step whose pixel operand is read
-// from the patch shifted by the tap.  A = weights (rows = output channels), B = pixels (columns): accumulator
+// in chunks of CK (16 or 32).  Per chunk, LDS holds the (TY+2) x 34 input patch (halo included, zeros outside the
+// image) as CK/8 planes of 8 channels and the chunk's weights of all 9 taps; each tap is CK/16 MFMA k-steps whose
+// pixel operand is read from the patch shifted by the tap.  A = weights (rows = output channels), B = pixels (columns): accumulator
 // register r of a lane then holds output channel 8(r/4) + 4(lane/32) + r%4 of pixel lane%32, so the epilogue reads
 // and writes 4 consecutive channels per lane.  The next chunk's global loads are in flight during the current
 // chunk's matrix operations.
 // With cu > 0 the input is the channel concatenation [up(xu), x] without materialising it: channels [0, cu) come from
 // xu at half resolution (nearest 2x upsampling: pixel (y, x) reads xu(y/2, x/2)), channels [cu, Cin) from x, which
 // then has Cin - cu channels per pixel.
-template <int TY, int CO_T, int WM>
+template <int TY, int CO_T, int WM, int CK>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x, int N, int H, int W, int Cin,
                                                  const uint16_t *__restrict__ w, int Cout,
                                                  const float *__restrict__ bias, const float *__restrict__ aux,
@@ -73,8 +74,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x,
 {
     constexpr int WN = 4 / WM, MT = TY / WM, NT = CO_T / 32 / WN;
     static_assert(WM * WN == 4 && MT * WM == TY && NT * WN * 32 == CO_T, "tile shape");
-    constexpr int PC = 34, PPL = (TY + 2) * PC;  // patch columns, pixels per plane
-    constexpr int NP = 2 * PPL, NWT = 18 * CO_T;  // 16-byte pieces of a chunk: patch, weights
+    constexpr int PC = 34, PPL = (TY + 2) * PC;            // patch columns, pixels per plane
+    constexpr int NH = CK / 8, NP = NH * PPL, NWT = 9 * NH * CO_T;  // planes; 16-byte pieces: patch, weights
     constexpr int RP = (NP + 255) / 256, RW = (NWT + 255) / 256;
     __shared__ uint4 sp[NP];
     __shared__ uint4 sw[NWT];
@@ -85,46 +86,49 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x,
     const int seg = bt % nseg, rt = (bt / nseg) % nrt, n = bt / (nseg * nrt);
     const int y0 = rt * TY, x0 = seg * 32, cb = blockIdx.y * CO_T;
 
-    // loader roles: patch piece q = tid + 256 i is channel half q & 1 of patch pixel q >> 1 (both halves of a pixel
-    // are adjacent in memory); weight piece q is half q & 1 of tap (q >> 1) % 9 of output channel (q >> 1) / 9
+    // loader roles: patch piece q = tid + 256 i is 8-channel group q % NH of patch pixel q / NH (a pixel's groups
+    // are adjacent in memory); weight piece q is group q % NH of tap (q / NH) % 9 of output channel (q / NH) / 9
+    // piece offsets within this image (the host keeps an image of either input below 2^31 elements)
     const int cx = Cin - cu;  // channels per pixel of x
-    int64_t poff[RP], uoff[RP];
-    int pdst[RP];
+    const uint16_t *ximg = x + (int64_t)n * H * W * cx;
+    const uint16_t *uimg = cu > 0 ? xu + (int64_t)n * (H >> 1) * (W >> 1) * cu : xu;
+    int poff[RP], uoff[RP];
 #pragma unroll
     for (int i = 0; i < RP; ++i) {
-        const int q = tid + 256 * i, pix = q >> 1, h = q & 1;
+        const int q = tid + 256 * i, pix = q / NH, h = q % NH;
         const int pr = pix / PC, pc = pix - pr * PC;
         const int yy = y0 - 1 + pr, xx = x0 - 1 + pc;
         const bool v = q < NP && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        poff[i] = v ? (((int64_t)n * H + yy) * W + xx) * cx + 8 * h : -1;
-        uoff[i] = v && cu > 0 ? (((int64_t)n * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1)) * cu + 8 * h : -1;
-        pdst[i] = q < NP ? h * PPL + pix : -1;
+        poff[i] = v ? (yy * W + xx) * cx + 8 * h : -1;
+        uoff[i] = v && cu > 0 ? ((yy >> 1) * (W >> 1) + (xx >> 1)) * cu + 8 * h : -1;
     }
     uint4 rp[RP], rw[RW];
     auto gload = [&](int c0) {
-        const bool up = c0 < cu;  // uniform: cu is a multiple of the chunk width
-        const uint16_t *src = up ? xu + c0 : x + (c0 - cu);
+        const bool up = c0 < cu;  // uniform: cu is a multiple of the chunk width CK
+        const uint16_t *src = up ? uimg + c0 : ximg + (c0 - cu);
 #pragma unroll
         for (int i = 0; i < RP; ++i) {
-            const int64_t o = up ? uoff[i] : poff[i];
+            const int o = up ? uoff[i] : poff[i];
             rp[i] = make_uint4(0u, 0u, 0u, 0u);
             if (o >= 0) rp[i] = *(const uint4 *)(src + o);
         }
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int q = tid + 256 * i, t = q >> 1;
+            const int q = tid + 256 * i, t = q / NH;
             rw[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (q < NWT) rw[i] = *(const uint4 *)(w + ((int64_t)(cb + t / 9) * 9 + t % 9) * Cin + c0 + 8 * (q & 1));
+            if (q < NWT) rw[i] = *(const uint4 *)(w + ((int64_t)(cb + t / 9) * 9 + t % 9) * Cin + c0 + 8 * (q % NH));
         }
     };
     auto lstore = [&]() {
 #pragma unroll
-        for (int i = 0; i < RP; ++i)
-            if (pdst[i] >= 0) sp[pdst[i]] = rp[i];
+        for (int i = 0; i < RP; ++i) {
+            const int q = tid + 256 * i;
+            if (q < NP) sp[(q % NH) * PPL + q / NH] = rp[i];
+        }
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int q = tid + 256 * i, t = q >> 1;
-            if (q < NWT) sw[((t % 9) * 2 + (q & 1)) * CO_T + t / 9] = rw[i];
+            const int q = tid + 256 * i, t = q / NH;
+            if (q < NWT) sw[((t % 9) * NH + q % NH) * CO_T + t / 9] = rw[i];
         }
     };
     f32x16 acc[MT][NT];
@@ -133,27 +137,33 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x,
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = f32x16{};
     gload(0);
-    const int nck = Cin >> 4;
+    const int nck = Cin / CK;
     for (int ck = 0; ck < nck; ++ck) {
         __syncthreads();
         lstore();
         __syncthreads();
-        if (ck + 1 < nck) gload(16 * (ck + 1));
+        if (ck + 1 < nck) gload(CK * (ck + 1));
+        // k-steps in the order of 16-channel chunks (all taps of channels 0-15, then of 16-31): the accumulation
+        // order, and so every result bit, does not depend on CK
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;
-            bf16x8 a[NT], b[MT];
+        for (int kk = 0; kk < CK / 16; ++kk) {  // k-step: planes 2 kk (lanes 0-31) and 2 kk + 1 (lanes 32-63)
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                a[j] = __builtin_bit_cast(bf16x8, sw[(tap * 2 + hl) * CO_T + (wn * NT + j) * 32 + l32]);
-#pragma unroll
-            for (int i = 0; i < MT; ++i)
-                b[i] = __builtin_bit_cast(bf16x8, sp[hl * PPL + (wm * MT + i + dy) * PC + l32 + dx]);
-#pragma unroll
-            for (int i = 0; i < MT; ++i)
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+                const int h = 2 * kk + hl;
+                bf16x8 a[NT], b[MT];
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[i], acc[i][j], 0, 0, 0);
+                    a[j] = __builtin_bit_cast(bf16x8, sw[(tap * NH + h) * CO_T + (wn * NT + j) * 32 + l32]);
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+                    b[i] = __builtin_bit_cast(bf16x8, sp[h * PPL + (wm * MT + i + dy) * PC + l32 + dx]);
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[i], acc[i][j], 0, 0, 0);
+            }
         }
     }
     const int xx = x0 + l32;
@@ -826,7 +836,8 @@ template <typename... T> bool aligned16(const T *...p) { return (((uintptr_t)p |
 
 // Convolution tiles (rows, output channels, wavefronts along the rows), in order of preference: larger tiles reuse
 // each operand read for more matrix operations; the first whose grid has at least kConvMinBlocks workgroups (two per
-// compute unit) is used, else the smallest tile.
+// compute unit) is used, else the smallest tile.  Input channels are staged 32 at a time when the channel counts
+// allow and the grid is small (half the load phases and barriers), else 16.
 struct ConvCfg {
     int ty, cot, wm;
 };
@@ -882,14 +893,24 @@ fwi_status conv_launch(const uint16_t *x, const uint16_t *xu, int cu, fwi_nn_sha
     if (((uintptr_t)x | (uintptr_t)xu | (uintptr_t)w | (uintptr_t)bias | (uintptr_t)aux | (uintptr_t)out_f32) % 16 ||
         (uintptr_t)out_bf16 % 8)
         return nn_fail(FWI_E_ARG, "conv3x3: inputs, w, bias, aux and out_f32 must be 16-byte aligned, out_bf16 8-byte");
+    if ((int64_t)in.h * in.w * in.c >= ((int64_t)1 << 31))
+        return nn_fail(FWI_E_ARG, "conv3x3: one image must hold fewer than 2^31 elements");
     const ConvCfg c = pick_conv(in, cout);
     const int64_t nt = conv_tiles(in, c.ty);
     if (nt >= ((int64_t)1 << 31)) return nn_fail(FWI_E_ARG, "conv3x3: too many tiles");
     const dim3 grid((unsigned)nt, (unsigned)(cout / c.cot));
+    // 32-channel chunks need more registers (half the occupancy at the smallest tile): worth it when the grid is at
+    // most about two workgroups per compute unit, so occupancy does not limit it
+    const bool ck32 = in.c % 32 == 0 && cu % 32 == 0 && nt * (cout / c.cot) <= 1024;
 #define NN_CONV(TY, COT, WM)                                                                                          \
-    if (c.ty == TY && c.cot == COT && c.wm == WM)                                                                     \
-        k_conv3x3<TY, COT, WM><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act, out_f32, \
-                                                     out_bf16, xu, cu);
+    if (c.ty == TY && c.cot == COT && c.wm == WM) {                                                                   \
+        if (ck32)                                                                                                     \
+            k_conv3x3<TY, COT, WM, 32><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act,  \
+                                                             out_f32, out_bf16, xu, cu);                              \
+        else                                                                                                          \
+            k_conv3x3<TY, COT, WM, 16><<<grid, 256, 0, st>>>(x, in.n, in.h, in.w, in.c, w, cout, bias, aux, res, act,  \
+                                                             out_f32, out_bf16, xu, cu);                              \
+    }
     NN_CONV(8, 128, 4)
     NN_CONV(8, 64, 4)
     NN_CONV(4, 128, 2)
