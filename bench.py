@@ -253,8 +253,8 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nt", type=int, default=0, help="override internal steps (profiling runs only)")
     ap.add_argument("--ckpt", default="auto", help="auto | 0 (keep all imaging operands) | K (checkpoint)")
     ap.add_argument("--seed", type=int, default=1000)
