@@ -426,13 +426,14 @@ def main():
     # with checkpoints the forward sweeps (first pass: 12 B; recomputation: 16 B) average
     # to 14 B per simulation cell
     fwd_bytes = pad_cells * (16 if ckpt == 0 else 14) + samp_cells * 4
+    # adjoint + imaging: lt^{k+1}, lt^{k+2}, W^{k-1} read and lt^k written per simulation
+    # cell; c read and the FP64 per-sample accumulator read + written per sample cell
+    adj_bytes = pad_cells * 16 + samp_cells * 20
     if cfg.ndim == 2:
-        adj_bytes = pad_cells * 16 + samp_cells * 20
         adj_name = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)"
         fwd_name = "forward step (k_fwd2d<bz>)"
     else:
-        adj_bytes = pad_cells * 32 + samp_cells * 4
-        adj_name = "adjoint+imaging step (k_adj3d<bz>)"
+        adj_name = "adjoint+imaging step (k_adj3d<16>, per-sample imaging)"
         fwd_name = "forward step (k_fwd3d<bz>)"
     if adj_ms >= fwd_ms:
         name, nbytes, ms, n = adj_name, adj_bytes, adj_ms, adj_n

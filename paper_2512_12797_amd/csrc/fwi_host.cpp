@@ -161,7 +161,7 @@ struct Plan {
     std::vector<SimDesc> sims;
     std::vector<SampleDesc> samples;
     std::vector<Tile> tiles;
-    std::vector<GTile> gtiles;  // 2D adjoint strips (per-sample imaging)
+    std::vector<GTile> gtiles;  // adjoint strips (2D) or tiles (3D) of the samples' grids
     std::vector<EvRow> evrows;
     std::vector<int32_t> evvec;
     std::vector<SrcPos> src;
@@ -171,7 +171,7 @@ struct Plan {
     int64_t max_cell = 0;    // largest padded sample grid
     int nt_rec = 0;
     int per_xcd = 0;
-    bool grouped = false;    // 2D: adjoint images per sample (accumulator slots = samples)
+    bool grouped = false;    // adjoint images per sample (accumulator slots = samples)
     int bzg = 16, nw = 1, per_xcd_g = 0;
     int64_t gcells = 0;      // imaging accumulator cells
     // layout
@@ -424,9 +424,9 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         i = j;
     }
     if (p.tiles.size() >= (size_t)1 << 30) return fail(FWI_E_UNSUPPORTED, "too many tiles");
-    // imaging accumulators: 2D, one per sample (laid out like the coefficients; an adjoint
-    // workgroup sweeps its strip for every sim of the sample); 3D, one per sim
-    p.grouped = p.ndim == 2;
+    // imaging accumulators: one per sample, laid out like the coefficients (an adjoint
+    // workgroup sweeps its strip or tile for every sim of the sample)
+    p.grouped = true;
     int gmax = 0;
     for (auto &Sm : p.samples) {
         if (Sm.sim_beg < 0) Sm.sim_beg = 0;
@@ -440,7 +440,9 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         }
     }
     p.gcells = p.grouped ? p.coefs : p.cells;
-    p.bzg = p.ndim == 2 ? (p.bz == 8 ? 8 : 16) : p.bz;
+    // grouped strip / tile height: 2D 8 or 16 rows; 3D 16 planes (the LDS of the per-sample
+    // sums of taller tiles would leave one workgroup per compute unit)
+    p.bzg = p.ndim == 2 ? (p.bz == 8 ? 8 : 16) : 16;
     for (int k = 0; k < (p.grouped ? b->nsample : 0); ++k) {
         const SampleDesc &Sm = p.samples[k];
         const int ntx = (Sm.N[2] + kTileX - 1) / kTileX;
@@ -460,7 +462,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
                     p.gtiles.push_back(G);
                 }
     }
-    p.nw = p.grouped ? grouped_waves(gmax, (int64_t)p.gtiles.size()) : 1;
+    p.nw = p.ndim == 2 ? grouped_waves(gmax, (int64_t)p.gtiles.size()) : kTileY3;
     p.per_xcd_g = (int)((p.gtiles.size() + 7) / 8);
     // 2D: a workgroup runs 4 tiles (one per wavefront); 3D: one tile per workgroup
     const size_t nwg = p.ndim == 2 ? (p.tiles.size() + 3) / 4 : p.tiles.size();

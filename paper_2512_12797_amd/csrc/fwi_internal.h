@@ -99,7 +99,7 @@ struct StepArgs {
     float *cka, *ckb;       // checkpoint slots for u^{n+1}, u^n (nullable)
     float *dat;             // forward: recorded data (nullable)
     const float *rho;       // adjoint: residual
-    double *gacc;           // adjoint: imaging accumulators (2D: per sample; 3D: per sim)
+    double *gacc;           // adjoint: imaging accumulators, one per sample
     int32_t ntiles;
     int32_t per_xcd;        // tiles per XCD chunk (grid = 8 * per_xcd)
     int32_t rec_j;          // recording slot j, or -1

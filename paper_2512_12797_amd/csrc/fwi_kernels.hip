@@ -553,13 +553,12 @@ struct Plane3 {
     float v[2][kTileY3 + 2 * kHalo][kTileX + 2 * kHalo];
 };
 
-// One sim's sweep of one 3D tile (origin x0, y0, z0).  S supplies the grid, weights and
-// (forward) the sources; u_off / d_off / nrec locate the sim's fields and data; the
-// receiver event planes are ev_beg .. ev_beg + ev_cnt; the adjoint adds its imaging
-// products into the FP64 accumulator at gacc.
-template <int BZ, bool ADJ>
+// One sim's forward sweep of one 3D tile (origin x0, y0, z0).  S supplies the grid,
+// weights and sources; u_off / d_off / nrec locate the sim's fields and data; the receiver
+// event planes are ev_beg .. ev_beg + ev_cnt.
+template <int BZ>
 __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int64_t u_off, int64_t d_off, int nrec,
-                                        int tx0, int ty0, int z0, int ev_beg, int ev_cnt, double *gacc, Plane3 &P)
+                                        int tx0, int ty0, int z0, int ev_beg, int ev_cnt, Plane3 &P)
 {
     static_assert(kTileY3 >= 8, "one y-halo row per wave needs at least 8 waves");
     constexpr int PF = 4;
@@ -578,13 +577,11 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
     const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
     const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
     const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
-    const rsrc_t rW = make_rsrc(ADJ ? A.wimg + u_off : (A.wst ? A.wst + u_off : A.next), ADJ || A.wst ? fbytes : 0);
-    const rsrc_t rG = make_rsrc(ADJ ? (const void *)gacc : (const void *)A.next, ADJ ? 2 * fbytes : 0);
+    const rsrc_t rW = make_rsrc(A.wst ? A.wst + u_off : A.next, A.wst ? fbytes : 0);
     const rsrc_t rKa = make_rsrc(A.cka ? A.cka + u_off : A.next, A.cka ? fbytes : 0);
     const rsrc_t rKb = make_rsrc(A.ckb ? A.ckb + u_off : A.next, A.ckb ? fbytes : 0);
     const int rec_j = A.rec_j;
-    float *Dat = (!ADJ && A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
-    const float *Rho = (ADJ && rec_j >= 0) ? A.rho + d_off + (int64_t)rec_j * nrec : nullptr;
+    float *Dat = (A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
     const EvRow *__restrict__ evrows = A.evrows;
     const int32_t *__restrict__ evvec = A.evvec;
 
@@ -610,7 +607,6 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
     const bool in = x < Nx && y < Ny;
     const uint32_t col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
     const uint32_t cb = in ? col : kPoison;          // own cell
-    const uint32_t cb2 = in ? 2u * col : kPoison;    // own cell, FP64 accumulator
     // y-halo row of waves 0..7: rows y0-4 .. y0-1, then y0+TY .. y0+TY+3
     const int hy = ty < 4 ? ty0 - kHalo + ty : ty0 + kTileY3 + ty - 4;
     const int hrow = ty < 4 ? ty : kTileY3 + ty;  // its LDS row
@@ -628,25 +624,21 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
     int sz = -1;
     float sw = 0.0f;
     bool smulti = false;
-    float famp = 0.0f;
-    if (!ADJ) {
-        famp = A.fn * S.inv_vol;
-        for (int s = 0; s < src_cnt; ++s) {
-            const SrcPos p = A.src[src_beg + s];
-            if (p.x != x || p.y != y || p.z < z0 || p.z >= z1) continue;
-            if (sz < 0 || sz == p.z) {
-                sz = p.z;
-                sw += p.w;
-            } else {
-                smulti = true;
-            }
+    const float famp = A.fn * S.inv_vol;
+    for (int s = 0; s < src_cnt; ++s) {
+        const SrcPos p = A.src[src_beg + s];
+        if (p.x != x || p.y != y || p.z < z0 || p.z >= z1) continue;
+        if (sz < 0 || sz == p.z) {
+            sz = p.z;
+            sw += p.w;
+        } else {
+            smulti = true;
         }
     }
-    const bool multi = ADJ ? false : __syncthreads_or(smulti);
+    const bool multi = __syncthreads_or(smulti);
 
     // queues indexed by plane (the plane loop is fully unrolled)
-    float q[BZ + 12], cq[BZ + PF], pq[BZ + PF], wq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
-    double gq[BZ + PF];
+    float q[BZ + 12], cq[BZ + PF], pq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
 #pragma unroll
     for (int k = 0; k < 12; ++k) q[k] = bload(rU, poff(z0 - kHalo + k) + cb);
 #pragma unroll
@@ -656,10 +648,6 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
         hxq[k] = bload(rU, pz + hxb);
         cq[k] = bload(rC, pz + cb);
         pq[k] = bload(rP, pz + cb);
-        if (ADJ) {
-            wq[k] = bload(rW, pz + cb);
-            gq[k] = bload64(rG, 2u * pz + cb2);
-        }
     }
     const bool rec = rec_j >= 0 && ev_cnt > 0;
     int ev = ev_beg;
@@ -680,10 +668,6 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
             hxq[r + PF] = bload(rU, pz + hxb);
             cq[r + PF] = bload(rC, pz + cb);
             pq[r + PF] = bload(rP, pz + cb);
-            if (ADJ) {
-                wq[r + PF] = bload(rW, pz + cb);
-                gq[r + PF] = bload64(rG, 2u * pz + cb2);
-            }
         }
         // ---- plane z into LDS
         float(*V)[kTileX + 2 * kHalo] = P.v[r & 1];
@@ -720,35 +704,26 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
             sponge_ab(gam, dt, a, b);
         }
         const bool evrow = z == ev_z;  // uniform
-        if (!ADJ) {
-            if (z == sz) wv += sw * famp;
-            if (multi) {
-                float extra = 0.0f;
-                if (in)
-                    for (int s = 0; s < src_cnt; ++s) {
-                        const SrcPos p = A.src[src_beg + s];
-                        if (p.x == x && p.y == y && p.z == z && z != sz) extra += p.w;
-                    }
-                wv += extra * famp;
-            }
-        } else if (evrow) {
-            const int rid = evvec[ev_off + ty * kTileX + lane];
-            if (rid >= 0) wv += Rho[rid];
+        if (z == sz) wv += sw * famp;
+        if (multi) {
+            float extra = 0.0f;
+            if (in)
+                for (int s = 0; s < src_cnt; ++s) {
+                    const SrcPos p = A.src[src_beg + s];
+                    if (p.x == x && p.y == y && p.z == z && z != sz) extra += p.w;
+                }
+            wv += extra * famp;
         }
         const uint32_t o = poff(z) + cb;
         const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
         bstore(rN, o, un);
-        if (!ADJ) {
-            // optional outputs: uniform branches skip the instructions when absent
-            if (A.wst) bstore(rW, o, wv);
-            if (A.cka) bstore(rKa, o, un);
-            if (A.ckb) bstore(rKb, o, qq[4]);
-            if (evrow && Dat) {
-                const int rid = evvec[ev_off + ty * kTileX + lane];
-                if (rid >= 0) Dat[rid] = un;
-            }
-        } else {
-            bstore64(rG, 2u * poff(z) + cb2, gq[r] + (double)un * (double)wq[r]);
+        // optional outputs: uniform branches skip the instructions when absent
+        if (A.wst) bstore(rW, o, wv);
+        if (A.cka) bstore(rKa, o, un);
+        if (A.ckb) bstore(rKb, o, qq[4]);
+        if (evrow && Dat) {
+            const int rid = evvec[ev_off + ty * kTileX + lane];
+            if (rid >= 0) Dat[rid] = un;
         }
         if (evrow) {
             ++ev;
@@ -769,21 +744,204 @@ __global__ __launch_bounds__(64 * kTileY3) void k_fwd3d(const StepArgs A)
     const Tile T = A.tiles[t];
     const SimDesc &S = A.sims[T.sim];
     __shared__ Plane3 P;
-    sweep3d<BZ, false>(A, S, S.u_off, S.d_off, S.nrec, T.x0, T.y0, T.z0, T.ev_beg, T.ev_cnt, nullptr, P);
+    sweep3d<BZ>(A, S, S.u_off, S.d_off, S.nrec, T.x0, T.y0, T.z0, T.ev_beg, T.ev_cnt, P);
 }
 
-// 3D adjoint + imaging step, one tile of one sim per workgroup, imaging into the sim's
-// own FP64 accumulator.  (Sweeping a tile for all of a sample's sims in one workgroup,
-// as the 2D adjoint does, serialises the sims and measured slower in 3D.)
+// 3D adjoint + imaging step with the imaging sum taken per sample.  A workgroup (one
+// wavefront per tile row, as in the forward) owns one 64 x kTileY3 x BZ tile of a sample's
+// grid and sweeps it for each of the sample's sims in turn; every thread keeps the FP64
+// sum over sims of its cells' exact products lt^k W^{k-1} in LDS and applies one
+// read-modify-write to the sample's accumulator at the end, so the accumulator costs 16 B
+// per sample cell and step instead of 16 B per sim cell.  Per cell the sum runs over the
+// sims in order and then into the accumulator step by step: the result does not depend on
+// tile heights or the schedule.  Consecutive sims reuse the double-buffered plane without
+// an extra barrier: a slot is rewritten only after every wave has passed the barrier of
+// the plane that follows its last read.
 template <int BZ>
 __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
 {
-    const int t = xcd_tile(blockIdx.x, A.per_xcd);
-    if (t >= A.ntiles) return;  // uniform per block
-    const Tile T = A.tiles[t];
-    const SimDesc &S = A.sims[T.sim];
+    static_assert(kTileY3 >= 8, "one y-halo row per wave needs at least 8 waves");
+    constexpr int PF = 4;
+    const int gt = xcd_tile(blockIdx.x, A.per_xcd_g);
+    if (gt >= A.ngtiles) return;  // uniform per block
+    // sample-level descriptors are read before the first store (scalar loads)
+    const GTile G = A.gtiles[gt];
+    const SampleDesc &Sm = A.samples[G.sample];
+    const int Nx = Sm.N[2], Ny = Sm.N[1], Nz = Sm.N[0];
+    const int nz_phys = Sm.n[0], ny_phys = Sm.n[1], nx_phys = Sm.n[2], nb = Sm.nb;
+    const double gmz = Sm.gmax[0], gmy = Sm.gmax[1], gmx = Sm.gmax[2];
+    const double dt = Sm.dt;
+    const int sim_beg = Sm.sim_beg, sim_cnt = Sm.sim_cnt;
+    if (sim_cnt == 0) return;  // uniform per block: a sample without sims adds nothing
+    const int64_t ncell = Sm.ncell, g_off = Sm.g_off;
+    const SimDesc &S0 = A.sims[sim_beg];
+    const int64_t u_off0 = S0.u_off;  // sims of a sample are consecutive, ncell apart
+    float wz[5], wy[5], wx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        wz[k] = S0.w[0][k];
+        wy[k] = S0.w[1][k];
+        wx[k] = S0.w[2][k];
+    }
+    const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
+    const uint32_t fbytes = pbytes * (uint32_t)Nz;
+    const int lane = threadIdx.x & 63;
+    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's row (uniform)
+    const int tx0 = G.x0, ty0 = G.y0, z0 = G.z0;
+    const int x = tx0 + lane;
+    const int y = ty0 + ty;
+    const rsrc_t rC = make_rsrc(A.cf + Sm.c_off, fbytes);
+    const int rec_j = A.rec_j;
+    const EvRow *__restrict__ evrows = A.evrows;
+    const int32_t *__restrict__ evvec = A.evvec;
+
+    const double gx = sponge_axis(x, nx_phys, nb, gmx);
+    const double gy = sponge_axis(y, ny_phys, nb, gmy);  // uniform per wave
+    float a_col, b_col;  // a, b of this column outside the z-sponge
+    {
+        double gam = 0.0;
+        gam = gam + gy;
+        gam = gam + gx;
+        sponge_ab(gam, dt, a_col, b_col);
+    }
+    auto poff = [&](int zz) -> uint32_t { return (uint32_t)zz * pbytes; };  // zz < 0 wraps out of range
+    const bool in = x < Nx && y < Ny;
+    const uint32_t col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
+    const uint32_t cb = in ? col : kPoison;
+    const int hy = ty < 4 ? ty0 - kHalo + ty : ty0 + kTileY3 + ty - 4;
+    const int hrow = ty < 4 ? ty : kTileY3 + ty;
+    const bool hyl = ty < 8 && x < Nx && hy >= 0 && hy < Ny;
+    const uint32_t hyb =
+        hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1)) : kPoison;
+    const int hxx = lane < 4 ? tx0 - kHalo + lane : tx0 + kTileX - 4 + lane;
+    const int hcol = lane < 4 ? lane : kTileX + lane;
+    const bool hxl = lane < 8 && y < Ny && hxx >= 0 && hxx < Nx;
+    const uint32_t hxb =
+        hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
+
     __shared__ Plane3 P;
-    sweep3d<BZ, true>(A, S, S.u_off, S.d_off, S.nrec, T.x0, T.y0, T.z0, T.ev_beg, T.ev_cnt, A.gacc + S.u_off, P);
+    __shared__ double red[BZ][kTileY3][kTileX];
+
+    for (int j = 0; j < sim_cnt; ++j) {
+        const int sim = sim_beg + j;
+        const int64_t u_off = u_off0 + (int64_t)j * ncell;
+        const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
+        const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
+        const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
+        const rsrc_t rW = make_rsrc(A.wimg + u_off, fbytes);
+        // lane offsets pass through an empty asm so that the plane offsets built from them
+        // are recomputed per sim next to their loads, not hoisted out of the sim loop
+        uint32_t cbs = cb, hybs = hyb, hxbs = hxb;
+        asm volatile("" : "+v"(cbs), "+v"(hybs), "+v"(hxbs));
+        // per-sim fields read after stores: vector loads, made uniform explicitly
+        const int tile0 = __builtin_amdgcn_readfirstlane(A.sims[sim].tile0);
+        const int nrec = __builtin_amdgcn_readfirstlane(A.sims[sim].nrec);
+        const int64_t d_off = A.sims[sim].d_off;
+        const int d_lo = __builtin_amdgcn_readfirstlane((int)(d_off & 0xFFFFFFFF));
+        const int d_hi = __builtin_amdgcn_readfirstlane((int)(d_off >> 32));
+        const int64_t d_off_u = (int64_t)(((uint64_t)(uint32_t)d_hi << 32) | (uint32_t)d_lo);
+        const float *Rho = rec_j >= 0 ? A.rho + d_off_u + (int64_t)rec_j * nrec : nullptr;
+        // receiver event planes of the sim tile that holds this tile, from plane z0 on (a
+        // sim tile may be taller than BZ)
+        int ev = 0, ev_end = 0, ev_z = -1, ev_off = 0;
+        if (rec_j >= 0) {
+            const Tile &T = A.tiles[tile0 + G.tix];
+            ev = __builtin_amdgcn_readfirstlane(T.ev_beg);
+            ev_end = ev + __builtin_amdgcn_readfirstlane(T.ev_cnt);
+            while (ev < ev_end) {
+                ev_z = __builtin_amdgcn_readfirstlane(evrows[ev].z);
+                if (ev_z >= z0) break;
+                ++ev;
+            }
+            if (ev < ev_end)
+                ev_off = __builtin_amdgcn_readfirstlane(evrows[ev].vec_off);
+            else
+                ev_z = -1;
+        }
+
+        float q[BZ + 12], cq[BZ + PF], pq[BZ + PF], wq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = bload(rU, poff(z0 - kHalo + k) + cbs);
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const uint32_t pz = poff(z0 + k);
+            hyq[k] = bload(rU, pz + hybs);
+            hxq[k] = bload(rU, pz + hxbs);
+            cq[k] = bload(rC, pz + cbs);
+            pq[k] = bload(rP, pz + cbs);
+            wq[k] = bload(rW, pz + cbs);
+        }
+        // planes below the grid are swept too: their loads read 0 and their stores fall
+        // outside the buffers
+#pragma unroll
+        for (int r = 0; r < BZ; ++r) {
+            const int z = z0 + r;
+            q[r + 12] = bload(rU, poff(z + 8) + cbs);
+            {
+                const uint32_t pz = poff(z + PF);
+                hyq[r + PF] = bload(rU, pz + hybs);
+                hxq[r + PF] = bload(rU, pz + hxbs);
+                cq[r + PF] = bload(rC, pz + cbs);
+                pq[r + PF] = bload(rP, pz + cbs);
+                wq[r + PF] = bload(rW, pz + cbs);
+            }
+            float(*V)[kTileX + 2 * kHalo] = P.v[r & 1];
+            V[ty + kHalo][lane + kHalo] = q[r + 4];
+            if (ty < 8) V[hrow][lane + kHalo] = hyq[r];
+            if (lane < 8) V[ty + kHalo][hcol] = hxq[r];
+            __syncthreads();
+
+            const int ly = ty + kHalo, lx = lane + kHalo;
+            const float *qq = &q[r];  // qq[4] is plane z
+            float sx = wx[0] * qq[4];
+            sx += wx[1] * (V[ly][lx - 1] + V[ly][lx + 1]);
+            sx += wx[2] * (V[ly][lx - 2] + V[ly][lx + 2]);
+            sx += wx[3] * (V[ly][lx - 3] + V[ly][lx + 3]);
+            sx += wx[4] * (V[ly][lx - 4] + V[ly][lx + 4]);
+            float sy = wy[0] * qq[4];
+            sy += wy[1] * (V[ly - 1][lx] + V[ly + 1][lx]);
+            sy += wy[2] * (V[ly - 2][lx] + V[ly + 2][lx]);
+            sy += wy[3] * (V[ly - 3][lx] + V[ly + 3][lx]);
+            sy += wy[4] * (V[ly - 4][lx] + V[ly + 4][lx]);
+            float szz = wz[0] * qq[4];
+            szz += wz[1] * (qq[3] + qq[5]);
+            szz += wz[2] * (qq[2] + qq[6]);
+            szz += wz[3] * (qq[1] + qq[7]);
+            szz += wz[4] * (qq[0] + qq[8]);
+            float wv = szz + sy + sx;
+            float a = a_col, b = b_col;
+            const double gz = sponge_axis(z, nz_phys, nb, gmz);  // uniform
+            if (gz != 0.0) {
+                double gam = 0.0;
+                gam = gam + gz;
+                gam = gam + gy;
+                gam = gam + gx;
+                sponge_ab(gam, dt, a, b);
+            }
+            if (z == ev_z) {  // uniform
+                const int rid = evvec[ev_off + ty * kTileX + lane];
+                if (rid >= 0) wv += Rho[rid];
+                ++ev;
+                ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+                ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
+            }
+            const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
+            bstore(rN, poff(z) + cbs, un);
+            const double pr = (double)un * (double)wq[r];  // the product of two floats is exact in FP64
+            red[r][ty][lane] = j == 0 ? pr : red[r][ty][lane] + pr;
+            // keep each plane's loads in its own plane (prefetch distance PF planes)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // one read-modify-write of the sample's accumulator per cell (cells outside the grid:
+    // poisoned or out-of-range offsets, so the load reads 0 and the store is dropped)
+    const rsrc_t rG = make_rsrc(A.gacc + g_off, 2 * fbytes);
+    const uint32_t cb2 = in ? 2u * col : kPoison;
+#pragma unroll
+    for (int r = 0; r < BZ; ++r) {
+        const uint32_t o = 2u * poff(z0 + r) + cb2;
+        bstore64(rG, o, bload64(rG, o) + red[r][ty][lane]);
+    }
 }
 
 // ---------------------------------------------------------- misfit/residual
@@ -1047,15 +1205,11 @@ static hipError_t fwd3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t 
     return hipGetLastError();
 }
 
-static hipError_t adj3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
+static hipError_t adj3d_dispatch(const StepArgs &a, int ty, hipStream_t st)
 {
-    dim3 grid(8 * a.per_xcd);
-    if (ty != kTileY3) return hipErrorInvalidValue;
-    switch (bz) {
-    case 16: k_adj3d<16><<<grid, 64 * kTileY3, 0, st>>>(a); break;
-    case 32: k_adj3d<32><<<grid, 64 * kTileY3, 0, st>>>(a); break;
-    default: return hipErrorInvalidValue;
-    }
+    dim3 grid(8 * a.per_xcd_g);  // one workgroup per tile of a sample's grid
+    if (ty != kTileY3 || a.bzg != 16) return hipErrorInvalidValue;
+    k_adj3d<16><<<grid, 64 * kTileY3, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -1075,7 +1229,7 @@ hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty
 {
     if (a.ntiles <= 0) return hipSuccess;
     if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : fwd2d_dispatch(a, bz, st);
-    return adjoint ? adj3d_dispatch(a, bz, ty, st) : fwd3d_dispatch(a, bz, ty, st);
+    return adjoint ? adj3d_dispatch(a, ty, st) : fwd3d_dispatch(a, bz, ty, st);
 }
 
 hipError_t launch_residual(const SimDesc *sims, int nsim, int nt_rec, const float *d, const float *dobs, float *rho,
