@@ -1,0 +1,117 @@
+"""Stored fixtures (tests/golden/), no GPU.
+
+* oracle_tiny_2d.json, written by tests/golden/make_oracle_golden.py from the oracle alone:
+  the oracle must keep reproducing it (a later change to the oracle's arithmetic shows up
+  here); the GPU parity suite compares the HIP path against the same stored values.
+* paper_geometry.json, the acquisition values the paper prints (2D synthetic examples and
+  the table of the three 3D OBN areas): the seeded geometry generators and the library's
+  CFL check are held against them.
+"""
+import importlib.util
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+LIMIT = math.sqrt(315.0 / 512.0)  # bound on v dt sqrt(sum h^-2) of the 8th-order leapfrog scheme
+
+
+def _maker():
+    spec = importlib.util.spec_from_file_location("make_oracle_golden", os.path.join(GOLDEN, "make_oracle_golden.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_oracle_reproduces_stored_golden():
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_tiny_2d.json")))
+    mk = _maker()
+    assert ref["problem"] == json.loads(json.dumps(mk.PROBLEM))
+    got = mk.compute()
+    assert np.allclose(got["misfit"], ref["misfit"], rtol=1e-12, atol=0)
+    assert np.allclose(got["d_pred_norm"], ref["d_pred_norm"], rtol=1e-12, atol=0)
+    for a, b in zip(got["d_pred_samples"], ref["d_pred_samples"]):
+        assert [x[:2] for x in a] == [x[:2] for x in b]
+        assert np.allclose([x[2] for x in a], [x[2] for x in b], rtol=1e-12, atol=0)
+    g, r = np.array(got["gradient"]), np.array(ref["gradient"])
+    assert np.linalg.norm(g - r) <= 1e-12 * np.linalg.norm(r)
+
+
+def _paper():
+    return json.load(open(os.path.join(GOLDEN, "paper_geometry.json")))
+
+
+def test_2d_source_spacing_of_the_paper_examples():
+    """Sources spread evenly over the node line (x_i = floor((i + 1/2) nx / N_s)) give the
+    spacings the paper states for the Arid and Salt examples.  The Overthrust statement
+    (about 78 m for 256 sources over 801 nodes at 20 m) does not fit its own numbers
+    (16.0 km / 256 = 62.6 m): recorded here as an inconsistency of the text."""
+    for e in _paper()["two_d"]:
+        xs = W.surface_shots_2d(e["nx"], e["sources"]) % e["nx"]
+        mean = (xs[-1] - xs[0]) / (e["sources"] - 1) * e["dx"]
+        line = e["nodes"] * e["node_spacing"] / e["sources"]
+        assert abs(mean - line) < 0.01 * line
+        if e["model"] == "SEG/EAGE Overthrust":
+            assert abs(line - e["source_spacing_approx"]) > 10.0
+        else:
+            assert abs(line - e["source_spacing_approx"]) < 1.0
+
+
+def test_3d_receiver_and_source_lattices_of_the_paper_areas():
+    """Receivers every receiver_spacing / dx cells on the surface give the stated receiver
+    counts of all three areas; 24 x 24 evenly spread sources give 576 sources at the stated
+    spacing for areas A (128 x 80 m / 24 = 427 m, stated 0.42 km) and C (1.28 km).  Area
+    B's stated 0.42 km does not fit 576 sources over its 20 km footprint (853 m)."""
+    for e in _paper()["three_d"]:
+        nx, ny, _ = e["n"]
+        every = int(round(e["receiver_spacing"] / e["h"][0]))
+        assert len(W.receiver_lattice_3d(ny, nx, every)) == e["receivers"]
+        side = int(round(math.sqrt(e["sources"])))
+        assert side * side == e["sources"]
+        src = W.surface_lattice_3d(ny, nx, side, side)
+        assert len(src) == e["sources"]
+        spacing = nx / side * e["h"][0]
+        if e["area"] == "B":
+            assert abs(spacing - e["source_spacing"]) > 100.0
+        else:
+            assert abs(spacing - e["source_spacing"]) < 0.02 * e["source_spacing"]
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2512_12797_amd import fwi
+    if not os.path.exists(fwi.LIB_PATH):
+        pytest.skip("library not built")
+    fwi.lib()
+    return fwi
+
+
+def test_3d_paper_time_steps_against_the_cfl_limit(F):
+    """The 3D areas' sampling intervals against the 8th-order leapfrog CFL limit
+    v dt sqrt(sum h^-2) <= sqrt(315/512) (the Laplacian's Nyquist eigenvalue is
+    -(2048/315) sum h^-2): at a salt velocity of 4500 m/s all three areas can be modelled
+    at their sampling interval (0.413 for A and B, 0.551 for C, whose 40 m vertical spacing
+    is half the lateral one); the library's host check accepts just below the closed-form
+    velocity limit and rejects just above it."""
+    for e in _paper()["three_d"]:
+        nx, ny, nz = e["n"]
+        hx, hy, hz = e["h"]
+        s = math.sqrt(hx ** -2 + hy ** -2 + hz ** -2)
+        v_lim = LIMIT / (e["dt"] * s)
+        assert v_lim > 4500.0
+        wav = W.ricker(e["reference_frequency"], e["dt"], 20)
+        t = F.time_axis(e["dt"], 20, 1, 0)
+        for v_max, ok in ((4500.0, True), (0.999 * v_lim, True), (1.001 * v_lim, False)):
+            g = F.Grid(nz=nz, ny=ny, nx=nx, dz=hz, dy=hy, dx=hx, nb=10, v_ref=v_max, v_max=v_max, ndim=3)
+            b = F.Batch([g], [0], [([0], [1.0])], [np.array([0], dtype=np.int32)], wav)
+            if ok:
+                assert abs(F.fwi_check(b, t) / (v_max * e["dt"] * s) - 1) < 1e-12
+            else:
+                with pytest.raises(F.FwiError) as err:
+                    F.fwi_check(b, t)
+                assert err.value.status == F.FWI_E_CFL

@@ -235,6 +235,42 @@ def test_3d_parity(F, ckpt):
     assert e < TOL
 
 
+# ------------------------------------------------------ stored oracle golden
+
+def test_stored_oracle_golden(F):
+    """The HIP path against the oracle's stored values for the tiny encoded 2D problem of
+    tests/golden/oracle_tiny_2d.json (written by tests/golden/make_oracle_golden.py from the
+    oracle alone): per-supergather misfits, data norms and sampled data, and the sample's
+    gradient, all within 1e-5 relative."""
+    import importlib.util
+    import json
+    import os
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_oracle_golden", os.path.join(gdir, "make_oracle_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    ref = json.load(open(os.path.join(gdir, "oracle_tiny_2d.json")))
+    p = mk.PROBLEM
+    say("case stored oracle golden")
+    og, v, truth, wav, sims, rec = mk.build_problem(p)
+    g = F.Grid(nz=og.nz, nx=og.nx, dz=og.dz, dx=og.dx, nb=og.nb, v_ref=og.v_ref, v_max=3000.0)
+    batch = F.Batch([g], [0] * len(sims), [(c, w) for c, w in sims], [rec] * len(sims), wav)
+    time = F.time_axis(p["dt"], p["nt"], p["rec_every"], 0)
+    dobs = mk.observed(p)
+    dp, mis, gr, _ = run_gradient(F, batch, time, [v], np.concatenate([d.ravel() for d in dobs]),
+                                  p["inv_sigma2"], [1.0])
+    nt_rec = p["nt"] // p["rec_every"]
+    gd = split_data(dp, batch, nt_rec)
+    for s in range(len(sims)):
+        assert abs(mis[s] / ref["misfit"][s] - 1) < TOL
+        assert abs(np.linalg.norm(gd[s]) / ref["d_pred_norm"][s] - 1) < TOL
+        pts = ref["d_pred_samples"][s]
+        assert rel(np.array([gd[s][t, r] for t, r, _ in pts]), np.array([x for _, _, x in pts])) < TOL
+    e = rel(gr, np.array(ref["gradient"]))
+    say("  gradient rel %.2e" % e)
+    assert e < TOL
+
+
 # ------------------------------------------------------- encode, Langevin
 
 def test_encode_matches_oracle(F):
