@@ -66,9 +66,14 @@ def test_3d_receiver_and_source_lattices_of_the_paper_areas():
     """Receivers every receiver_spacing / dx cells on the surface give the stated receiver
     counts of all three areas; 24 x 24 evenly spread sources give 576 sources at the stated
     spacing for areas A (128 x 80 m / 24 = 427 m, stated 0.42 km) and C (1.28 km).  Area
-    B's stated 0.42 km does not fit 576 sources over its 20 km footprint (853 m)."""
+    B's stated 0.42 km does not fit 576 sources over its 20 km footprint (853 m), nor its
+    stated 5.12 km depth extent its 256 x 40 m grid (10.24 km); the record lengths are
+    n_t dt throughout."""
     for e in _paper()["three_d"]:
-        nx, ny, _ = e["n"]
+        nx, ny, nz = e["n"]
+        assert abs(e["nt"] * e["dt"] - e["record_length"]) < 1e-9
+        depth = nz * e["h"][2]
+        assert (abs(depth - e["depth_extent"]) < 1e-9) == (e["area"] != "B")
         every = int(round(e["receiver_spacing"] / e["h"][0]))
         assert len(W.receiver_lattice_3d(ny, nx, every)) == e["receivers"]
         side = int(round(math.sqrt(e["sources"])))
