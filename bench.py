@@ -250,6 +250,57 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
             "layers": rows, "weight_gradients": wrows}
 
 
+def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e-3, G=1):
+    """The learned preconditioner at the pair configuration's full scale: about 10k pairs
+    (2500 seeded thrust / salt models on 256 x 256 patches at 10 m, 32 surface shots of a
+    10 Hz Ricker over 1500 steps, 4 encoded supergathers of 8 shots per model) generated by
+    the library, split 90 / 10 by model, the network trained on the first part and judged
+    on the held-out part: relative L2 error to the full-shot gradient of the plain encoded
+    gradient, of the network's estimate and of the guarded result."""
+    from paper_2512_12797_amd import precond
+    from paper_2512_12797_amd.unet import UNet
+    cfg = precond.PairConfig(G=G)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs = precond.make_pairs(cfg, nmodels, enc_per_model, seed=args.seed, models_per_batch=6,
+                               log=lambda m: log(m) if ("%d models" % nmodels in m or m.count("00 models")) else None)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    npairs = int(pairs["scale"].shape[0])
+    npad = cfg.n + 2 * cfg.nb
+    cell_steps = float(pairs["solves"]) * npad * npad * cfg.nt
+    mid = pairs["model_id"].numpy()
+    held = mid >= int(round(0.9 * nmodels))
+    train_idx = np.nonzero(~held)[0]
+    test_idx = torch.from_numpy(np.nonzero(held)[0]).to("cuda")
+    net = UNet(seed=args.seed)
+    t1 = time.perf_counter()
+    hist = precond.train(net, pairs, train_idx, steps=steps, batch=8, lr=lr, lr_final=lr / 10, seed=args.seed,
+                         log=lambda m: log(m) if m.startswith("train step") and int(m.split()[2]) % 2000 == 0 else None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    x, res, tg = pairs["x16"][test_idx], pairs["res"][test_idx], pairs["target"][test_idx]
+    plain = precond.rel_err(res, tg)
+    out = precond.predict(net, x, res)
+    netw = precond.rel_err(precond.channel0(out), tg)
+    guarded, keep = precond.guard(out, torch.ones(x.shape[0], device="cuda"), res)
+    guard_err = precond.rel_err(guarded, tg)
+    return {"metric": "held-out relative L2 error to the full-shot gradient (plain encoded -> preconditioned)",
+            "value": round(float(netw.mean()), 4), "unit": "relative L2", "higher_is_better": False, "n_gpus": 1,
+            "dtype": "f32 solver, bf16 network (fp32 accumulate)", "data": "synthetic",
+            "config": {"workload": "precond-256x256-10m-32shot-s8-1500steps", "models": nmodels,
+                       "pairs": npairs, "train_pairs": int(len(train_idx)), "heldout_pairs": int(test_idx.numel()),
+                       "supergathers": G, "shots_per_supergather": cfg.s, "kappa": cfg.kappa,
+                       "train_steps": steps, "batch": 8, "lr": lr},
+            "plain_encoded_error": round(float(plain.mean()), 4), "network_error": round(float(netw.mean()), 4),
+            "guarded_error": round(float(guard_err.mean()), 4), "guard_kept": round(float(keep.float().mean()), 3),
+            "final_train_loss": round(hist[-1][1], 5),
+            "pair_generation_s": round(t_pairs, 1), "pairs_per_s": round(npairs / t_pairs, 1),
+            "pair_generation_padded_gcell_steps_per_s": round(cell_steps / t_pairs / 1e9, 1),
+            "training_s": round(t_train, 1), "training_samples_per_s": round(steps * 8 / t_train, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,14 +314,20 @@ def main():
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet"],
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
                          "equal-error: posterior samples/hour of plain, encoded and preconditioned chains at equal "
                          "posterior-mean RMSE (several minutes); unet: the gradient preconditioner's network "
-                         "(inference, training step, per-layer convolution rooflines)")
+                         "(inference, training step, per-layer convolution rooflines); precond: ~10k solver-made "
+                         "training pairs at 256^2, training, held-out error against the plain encoded gradient "
+                         "(about 10 minutes)")
     ap.add_argument("--plain-steps", type=int, default=20, help="equal-error: plain-chain steps that set the target")
     ap.add_argument("--max-steps", type=int, default=60, help="equal-error: steps of the encoded chains")
     ap.add_argument("--net-seeds", type=int, default=3, help="equal-error: networks trained (seeds 0..n-1)")
+    ap.add_argument("--pc-models", type=int, default=2500, help="precond: seeded models (4 pairs each)")
+    ap.add_argument("--pc-steps", type=int, default=20000, help="precond: training steps (batch 8)")
+    ap.add_argument("--pc-lr", type=float, default=1e-3, help="precond: initial Adam learning rate (cosine to 1/10)")
+    ap.add_argument("--pc-G", type=int, default=1, help="precond: supergathers of 8 shots summed per encoded gradient")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
@@ -283,6 +340,10 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.workload == "unet":
         print(json.dumps(unet_bench(torch, args)), flush=True)
+        return
+    if args.workload == "precond":
+        print(json.dumps(precond_bench(torch, args, nmodels=args.pc_models, steps=args.pc_steps, lr=args.pc_lr,
+                                       G=args.pc_G)), flush=True)
         return
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains
