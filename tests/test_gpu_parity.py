@@ -235,6 +235,62 @@ def test_3d_parity(F, ckpt):
     assert e < TOL
 
 
+def test_3d_uneven_batch_per_sample_imaging(F):
+    """Two 3D samples of different grid sizes with 3 and 1 supergathers, receivers on planes
+    through the whole depth, against the oracle, with 16- and 32-plane forward tiles (the
+    adjoint sweeps 16-plane tiles of each sample's grid for all of its supergathers; under
+    32-plane forward tiles it skips the receiver events above its first plane) -- and the
+    two tile heights bit-identical."""
+    say("case 3d uneven batch")
+    grids = [F.Grid(nz=30, ny=9, nx=40, dz=20.0, dy=22.0, dx=25.0, nb=4, v_ref=3500.0, v_max=3600.0, ndim=3),
+             F.Grid(nz=20, ny=12, nx=70, dz=20.0, dy=22.0, dx=25.0, nb=3, v_ref=3500.0, v_max=3600.0, ndim=3)]
+    r = np.random.default_rng(11)
+
+    def cell(g, z, y, x):
+        return (z * g.ny + y) * g.nx + x
+
+    g0, g1 = grids
+    srcs = [([cell(g0, 1, 4, 20), cell(g0, 1, 1, 5)], [1.0, -1.0]),
+            ([cell(g0, 15, 8, 39), cell(g0, 2, 0, 0), cell(g0, 29, 4, 10)], [-1.0, 1.0, 1.0]),
+            ([cell(g0, 1, 6, 33)], [1.0]),
+            ([cell(g1, 1, 6, 35), cell(g1, 10, 2, 3)], [1.0, -1.0])]
+    rec0 = np.array([cell(g0, z, y, x) for z in (1, 10, 20, 29) for y in range(0, 9, 4) for x in range(0, 40, 7)],
+                    dtype=np.int32)
+    rec1 = np.array([cell(g1, z, y, x) for z in (1, 12, 19) for y in range(0, 12, 5) for x in range(0, 70, 9)],
+                    dtype=np.int32)
+    nt, R = 120, 2
+    wav = W.ricker(7.0, 2e-3, nt)
+    batch = F.Batch(grids, [0, 0, 0, 1], srcs, [rec0, rec0, rec0, rec1], wav)
+    time = F.time_axis(2e-3, nt, R, 0)
+    models = [f32(r.uniform(1800, 3400, g.nphys)) for g in grids]
+    truths = [f32(m * 0.9) for m in models]
+    dobs = [f32(0.5 * d) for d in oracle_forward_sims(batch, 2e-3, nt, R, truths, coef_fp32=False)]
+    flat = np.concatenate([d.ravel() for d in dobs])
+    kappa = [1.5, 1.0]
+    outs = []
+    try:
+        for bz in (16, 32):
+            F.fwi_set_tile(3, bz)
+            outs.append(run_gradient(F, batch, time, models, flat, 1.0, kappa))
+    finally:
+        F.fwi_set_tile(3, 0)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    dp, mis, gr, _ = outs[0]
+    odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, models, dobs, 1.0, kappa)
+    gdp = split_data(dp, batch, nt // R)
+    for s in range(batch.nsim):
+        e = rel(gdp[s], odp[s])
+        ratio = np.linalg.norm(odp[s] - dobs[s]) / np.linalg.norm(dobs[s])
+        say("  sim %d data rel %.2e (residual ratio %.2f)" % (s, e, ratio))
+        assert e < TOL and abs(mis[s] / omis[s] - 1) < TOL and ratio >= 0.3
+    gs = split_model(gr, batch)
+    for k in range(2):
+        e = rel(gs[k], ogr[k])
+        say("  sample %d gradient rel %.2e" % (k, e))
+        assert e < TOL
+
+
 # ------------------------------------------------------ stored oracle golden
 
 def test_stored_oracle_golden(F):
