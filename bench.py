@@ -295,6 +295,8 @@ def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e
                        "train_steps": steps, "batch": 8, "lr": lr},
             "plain_encoded_error": round(float(plain.mean()), 4), "network_error": round(float(netw.mean()), 4),
             "guarded_error": round(float(guard_err.mean()), 4), "guard_kept": round(float(keep.float().mean()), 3),
+            "median_plain_network_guarded": [round(float(np.median(x)), 4) for x in (plain, netw, guard_err)],
+            "heldout_improved_fraction": round(float(np.mean(netw < plain)), 3),
             "final_train_loss": round(hist[-1][1], 5),
             "pair_generation_s": round(t_pairs, 1), "pairs_per_s": round(npairs / t_pairs, 1),
             "pair_generation_padded_gcell_steps_per_s": round(cell_steps / t_pairs / 1e9, 1),
