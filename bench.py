@@ -315,6 +315,10 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay each gradient as a captured HIP graph")
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
+    ap.add_argument("--fwd-steps", type=int, default=1, choices=[1, 2],
+                    help="2D keep-all schedule: time steps per forward launch")
+    ap.add_argument("--adj-steps", type=int, default=2, choices=[1, 2],
+                    help="2D keep-all schedule: time steps per adjoint launch")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
     ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
@@ -418,6 +422,7 @@ def main():
         cache = os.environ.get("FWI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "fwi_tune_cache.json"))
         tuned = fwi.fwi_tune(batch0, time_ax, v, ws, cache)
         log("tuner: tile height %d, %.3f ms per gradient time step" % tuned)
+    fwi.fwi_set_time_blocking(args.fwd_steps, args.adj_steps)
     stream = torch.cuda.Stream()  # graphs need a non-default stream
     torch.cuda.set_stream(stream)
     fwi.fwi_graphs_enable(bool(args.graphs))
@@ -477,6 +482,11 @@ def main():
     log("step %.1f ms; %.1f Gcell-steps/s physical, %.1f padded; fwd kernel %.1f us x %d, adj kernel %.1f us x %d" % (
         1e3 * elapsed / args.steps, value, pad_cells * nt * args.steps / elapsed / 1e9,
         1e3 * fwd_ms / max(fwd_n, 1), fwd_n, 1e3 * adj_ms / max(adj_n, 1), adj_n))
+    # two time steps per launch: the 2D keep-all schedule with an even step count (every
+    # launch of the timed sweep is then a two-step launch)
+    blk = cfg.ndim == 2 and ckpt == 0 and nt % 2 == 0
+    two_fwd = blk and args.fwd_steps == 2
+    two_adj = blk and args.adj_steps == 2
 
     # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
     # adjoint + imaging step: lt^{k+1}, lt^{k+2} read, lt^k write, W^{k-1} read = 16 B per
@@ -495,6 +505,15 @@ def main():
     if cfg.ndim == 2:
         adj_name = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)"
         fwd_name = "forward step (k_fwd2d<bz>)"
+        # per launch of two steps: u^{n-1}, u^n read, u^{n+1}, u^{n+2}, W^n, W^{n+1} written
+        # (24 B per simulation cell), c read once; adjoint: lt^{k+2}, lt^{k+1}, W^{k-1},
+        # W^{k-2} read, lt^k, lt^{k-1} written (24 B), c and the accumulator once (20 B)
+        if two_fwd:
+            fwd_bytes = pad_cells * 24 + samp_cells * 4
+            fwd_name = "two-step forward (k_fwd2d2<16>)"
+        if two_adj:
+            adj_bytes = pad_cells * 24 + samp_cells * 20
+            adj_name = "two-step adjoint+imaging (k_adj2d2<16>, per-sample imaging)"
     else:
         adj_name = "adjoint+imaging step (k_adj3d<16>, per-sample imaging)"
         fwd_name = "forward step (k_fwd3d<bz>)"
@@ -510,8 +529,10 @@ def main():
         try:
             tj = json.load(open(tfile))
             # counters are valid for the measured kernel sources, kernel and tile height only
+            two = two_adj if name == adj_name else two_fwd
+            rows = 16 if two else (tuned[0] if tuned is not None else None)
             if (tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name
-                    and tuned is not None and tj.get("tile_rows") == tuned[0]):
+                    and rows is not None and tj.get("tile_rows") == rows):
                 traffic = tj.get("bytes_per_launch")
         except (ValueError, OSError):
             traffic = None
@@ -553,6 +574,7 @@ def main():
                    "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
                    "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
                    "tile_rows": tuned[0] if tuned else None, "graphs": bool(args.graphs),
+                   "time_steps_per_launch": {"forward": 2 if two_fwd else 1, "adjoint": 2 if two_adj else 1},
                    "graph_captures_replays": list(gstats),
                    "padded_gcell_steps_per_s": round(pad_cells * nt * args.steps / elapsed / 1e9, 3),
                    "parallelism": "1 GPU"},

@@ -250,6 +250,21 @@ fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays);
  * later processes skip the timing.  The workspace content is overwritten.
  */
 fwi_status fwi_set_tile(int32_t ndim, int32_t bz);
+
+/*
+ * Time steps per launch of the 2D keep-all schedule (ckpt_every 0 or -1), process-wide, for
+ * the forward sweep (fwd_steps) and the adjoint sweep (adj_steps): 1 or 2 each; the default
+ * is 1 and 2.  With 2, one sweep advances the wavefield (or the adjoint field) by two steps
+ * of the discretized wave equation's recursion (Sec. 2), reading the two old levels once per
+ * two steps.  Each wavefront then covers a strip of 56 columns and 16 rows and also
+ * computes the first step on a 4-cell margin around it, the halo of the second.  The data
+ * and the imaging operands are the same as with 1 bit for bit.  The per-sample gradient
+ * sums the same FP64 products in another order.  An odd last step is launched alone.  3D
+ * and checkpointed schedules always take one step per launch.  The setting applies to
+ * calls that start after it (a captured graph keeps the setting it was captured with; the
+ * graph key includes it).  Returns FWI_E_ARG for other values.
+ */
+fwi_status fwi_set_time_blocking(int32_t fwd_steps, int32_t adj_steps);
 fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
                     const char *cache_path, int32_t *bz_out, double *ms_out);
 

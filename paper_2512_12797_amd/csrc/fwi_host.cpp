@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -162,6 +163,13 @@ struct Plan {
     std::vector<SampleDesc> samples;
     std::vector<Tile> tiles;
     std::vector<GTile> gtiles;  // adjoint strips (2D) or tiles (3D) of the samples' grids
+    // 2D, two time steps per launch: kStrip2 x kRows2 strips of every sim (forward) and of
+    // every sample (adjoint); their receiver event rows cover the first step's margins
+    std::vector<Tile> tiles2;
+    std::vector<GTile> gtiles2;
+    bool two = false;        // keep-all 2D schedule: forward with two steps per launch
+    bool two_adj = false;    // and the adjoint
+    int per_xcd2 = 0, per_xcd_g2 = 0, nw2 = 1;
     std::vector<EvRow> evrows;
     std::vector<int32_t> evvec;
     std::vector<SrcPos> src;
@@ -179,7 +187,8 @@ struct Plan {
     bool fwd_only = false;  // ckpt_every == -1: no adjoint state is kept
     int64_t wst_levels = 0, ck_slots = 0;
     int nchunk_res = 1, nchunk_fin = 1;
-    size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_gtiles = 0, t_evrows = 0, t_evvec = 0, t_src = 0, t_bytes = 0;
+    size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_gtiles = 0, t_tiles2 = 0, t_gtiles2 = 0, t_evrows = 0,
+           t_evvec = 0, t_src = 0, t_bytes = 0;
     size_t t_alloc = 0;  // table region reserved in the workspace (largest over tile heights)
     size_t o_status = 0, o_tables = 0, o_cf = 0, o_fields = 0, o_wst = 0, o_ck = 0, o_gacc = 0, o_rho = 0,
            o_part = 0, o_npart = 0, o_mis = 0, total = 0;
@@ -209,6 +218,10 @@ struct TileChoices {
     std::vector<std::pair<std::string, int>> tuned;
 };
 TileChoices g_tiles;
+
+// Time steps per launch of the 2D keep-all schedule (1 or 2), forward and adjoint,
+// process-wide.
+std::atomic<int> g_blocking_fwd{1}, g_blocking_adj{2};
 
 // Batch shape signature: dimensionality and the multiset of padded grid sizes.
 std::string shape_signature(const fwi_batch *b)
@@ -423,7 +436,58 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         T.ev_cnt++;
         i = j;
     }
-    if (p.tiles.size() >= (size_t)1 << 30) return fail(FWI_E_UNSUPPORTED, "too many tiles");
+    if (p.ndim == 2) {
+        // two-step strips: sim s covers tiles2[tile0b ..], z block then x strip; a receiver
+        // lands in every strip whose first-step rows and lanes (4-cell margins) hold it
+        std::vector<Ev> ev2;
+        for (int s = 0; s < b->nsim; ++s) {
+            const fwi_grid &g = b->grid[b->sample_of[s]];
+            SimDesc &S = p.sims[s];
+            S.tile0b = (int32_t)p.tiles2.size();
+            const int ntx = (S.N[2] + kStrip2 - 1) / kStrip2, ntz = (S.N[0] + kRows2 - 1) / kRows2;
+            for (int iz = 0; iz < ntz; ++iz)
+                for (int ix = 0; ix < ntx; ++ix) {
+                    Tile T;
+                    memset(&T, 0, sizeof T);
+                    T.sim = s;
+                    T.x0 = ix * kStrip2;
+                    T.z0 = iz * kRows2;
+                    p.tiles2.push_back(T);
+                }
+            for (int r = 0; r < S.nrec; ++r) {
+                const int32_t c = b->rec_cell[b->rec_ptr[s] + r];
+                const int px = c % g.nx + g.nb, pz = c / g.nx + g.nb;
+                for (int iz = (pz + kHalo) / kRows2 - 2; iz <= (pz + kHalo) / kRows2; ++iz) {
+                    if (iz < 0 || iz >= ntz || pz < iz * kRows2 - kHalo || pz >= iz * kRows2 + kRows2 + kHalo)
+                        continue;
+                    for (int ix = (px + kHalo) / kStrip2 - 2; ix <= (px + kHalo) / kStrip2; ++ix) {
+                        const int lx = px - (ix * kStrip2 - kHalo);
+                        if (ix < 0 || ix >= ntx || lx < 0 || lx >= kTileX) continue;
+                        ev2.push_back({S.tile0b + iz * ntx + ix, pz, lx, r});
+                    }
+                }
+            }
+        }
+        std::sort(ev2.begin(), ev2.end(), [](const Ev &a, const Ev &b) {
+            return a.tile != b.tile ? a.tile < b.tile : a.z < b.z;
+        });
+        for (size_t i = 0; i < ev2.size();) {
+            size_t j = i;
+            EvRow row{ev2[i].z, (int32_t)p.evvec.size()};
+            p.evvec.resize(p.evvec.size() + kTileX, -1);
+            Tile &T = p.tiles2[ev2[i].tile];
+            if (T.ev_cnt == 0) T.ev_beg = (int32_t)p.evrows.size();
+            while (j < ev2.size() && ev2[j].tile == ev2[i].tile && ev2[j].z == ev2[i].z) {
+                p.evvec[row.vec_off + ev2[j].slot] = ev2[j].r;
+                ++j;
+            }
+            p.evrows.push_back(row);
+            T.ev_cnt++;
+            i = j;
+        }
+    }
+    if (p.tiles.size() >= (size_t)1 << 30 || p.tiles2.size() >= (size_t)1 << 30)
+        return fail(FWI_E_UNSUPPORTED, "too many tiles");
     // imaging accumulators: one per sample, laid out like the coefficients (an adjoint
     // workgroup sweeps its strip or tile for every sim of the sample)
     p.grouped = true;
@@ -467,6 +531,27 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     // 2D: a workgroup runs 4 tiles (one per wavefront); 3D: one tile per workgroup
     const size_t nwg = p.ndim == 2 ? (p.tiles.size() + 3) / 4 : p.tiles.size();
     p.per_xcd = (int)((nwg + 7) / 8);
+    if (p.ndim == 2) {
+        for (int k = 0; k < b->nsample; ++k) {
+            const SampleDesc &Sm = p.samples[k];
+            const int ntx = (Sm.N[2] + kStrip2 - 1) / kStrip2, ntz = (Sm.N[0] + kRows2 - 1) / kRows2;
+            for (int iz = 0; iz < ntz; ++iz)
+                for (int ix = 0; ix < ntx; ++ix) {
+                    GTile G;
+                    memset(&G, 0, sizeof G);
+                    G.sample = k;
+                    G.x0 = ix * kStrip2;
+                    G.z0 = iz * kRows2;
+                    G.tix = iz * ntx + ix;  // the same strip in each of the sample's sims
+                    p.gtiles2.push_back(G);
+                }
+        }
+        // (on the 16-sample x 10-supergather workload 4 waves measured faster than 2, 5 or 8:
+        // 90.9 vs 108.9 / 121.6 / 125.7 us per two-step launch)
+        p.nw2 = std::min(grouped_waves(gmax, (int64_t)p.gtiles2.size()), 8);
+        p.per_xcd_g2 = (int)((p.gtiles2.size() + 7) / 8);
+        p.per_xcd2 = (int)(((p.tiles2.size() + 3) / 4 + 7) / 8);
+    }
     // table layout
     size_t o = 0;
     p.t_sims = o;
@@ -477,6 +562,10 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     o = align_up(o + p.tiles.size() * sizeof(Tile));
     p.t_gtiles = o;
     o = align_up(o + std::max<size_t>(1, p.gtiles.size()) * sizeof(GTile));
+    p.t_tiles2 = o;
+    o = align_up(o + std::max<size_t>(1, p.tiles2.size()) * sizeof(Tile));
+    p.t_gtiles2 = o;
+    o = align_up(o + std::max<size_t>(1, p.gtiles2.size()) * sizeof(GTile));
     p.t_evrows = o;
     o = align_up(o + std::max<size_t>(1, p.evrows.size()) * sizeof(EvRow));
     p.t_evvec = o;
@@ -496,7 +585,9 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.K = p.fwd_only ? 0 : t->ckpt_every;
     if (p.K > t->nt) p.K = t->nt;
     p.nseg = p.K > 0 ? (t->nt + p.K - 1) / p.K : 1;
-    p.nlev = p.K > 0 ? 4 : 2;
+    p.nlev = (p.K > 0 || p.ndim == 2) ? 4 : 2;
+    p.two = p.ndim == 2 && p.K == 0 && g_blocking_fwd.load() == 2;
+    p.two_adj = p.ndim == 2 && p.K == 0 && g_blocking_adj.load() == 2;
     p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.K : t->nt);
     p.ck_slots = p.K > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
     int64_t maxdata = 0;
@@ -568,6 +659,8 @@ fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
     memcpy(h + p.t_samples, p.samples.data(), p.samples.size() * sizeof(SampleDesc));
     memcpy(h + p.t_tiles, p.tiles.data(), p.tiles.size() * sizeof(Tile));
     if (!p.gtiles.empty()) memcpy(h + p.t_gtiles, p.gtiles.data(), p.gtiles.size() * sizeof(GTile));
+    if (!p.tiles2.empty()) memcpy(h + p.t_tiles2, p.tiles2.data(), p.tiles2.size() * sizeof(Tile));
+    if (!p.gtiles2.empty()) memcpy(h + p.t_gtiles2, p.gtiles2.data(), p.gtiles2.size() * sizeof(GTile));
     if (!p.evrows.empty()) memcpy(h + p.t_evrows, p.evrows.data(), p.evrows.size() * sizeof(EvRow));
     if (!p.evvec.empty()) memcpy(h + p.t_evvec, p.evvec.data(), p.evvec.size() * sizeof(int32_t));
     if (!p.src.empty()) memcpy(h + p.t_src, p.src.data(), p.src.size() * sizeof(SrcPos));
@@ -700,11 +793,14 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
     k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
     k.add(p.nchunk_res); k.add(p.nchunk_fin);
     k.add(p.grouped); k.add(p.bzg); k.add(p.nw); k.add(p.per_xcd_g); k.add(p.gcells);
+    k.add(p.two); k.add(p.two_adj); k.add(p.nw2); k.add(p.per_xcd2); k.add(p.per_xcd_g2);
+    k.add(p.tiles2.size()); k.add(p.gtiles2.size());
     const size_t ngt = p.gtiles.size();
     k.add(ngt);
     const size_t nt = p.tiles.size();
     k.add(nt);
-    const size_t offs[] = {p.t_sims, p.t_samples, p.t_tiles, p.t_gtiles, p.t_evrows, p.t_evvec, p.t_src, p.t_bytes,
+    const size_t offs[] = {p.t_sims, p.t_samples, p.t_tiles, p.t_gtiles, p.t_tiles2, p.t_gtiles2, p.t_evrows,
+                           p.t_evvec, p.t_src, p.t_bytes,
                            p.o_status, p.o_tables, p.o_cf, p.o_fields, p.o_wst, p.o_ck, p.o_gacc, p.o_rho,
                            p.o_part, p.o_npart, p.o_mis, p.total};
     k.bytes(offs, sizeof offs);
@@ -769,6 +865,8 @@ struct Dev {
     const SampleDesc *samples;
     const Tile *tiles;
     const GTile *gtiles;
+    const Tile *tiles2;
+    const GTile *gtiles2;
     const EvRow *evrows;
     const int32_t *evvec;
     const SrcPos *src;
@@ -793,6 +891,8 @@ Dev carve(const Plan &p, void *ws)
     d.samples = (const SampleDesc *)(tb + p.t_samples);
     d.tiles = (const Tile *)(tb + p.t_tiles);
     d.gtiles = (const GTile *)(tb + p.t_gtiles);
+    d.tiles2 = (const Tile *)(tb + p.t_tiles2);
+    d.gtiles2 = (const GTile *)(tb + p.t_gtiles2);
     d.evrows = (const EvRow *)(tb + p.t_evrows);
     d.evvec = (const int32_t *)(tb + p.t_evvec);
     d.src = (const SrcPos *)(tb + p.t_src);
@@ -830,6 +930,22 @@ StepArgs base_args(const Plan &p, const Dev &d)
     return a;
 }
 
+// Arguments of the two-steps-per-launch kernels: the two-step strip tables in place of the
+// one-step ones.
+StepArgs base_args2(const Plan &p, const Dev &d)
+{
+    StepArgs a = base_args(p, d);
+    a.tiles = d.tiles2;
+    a.ntiles = (int32_t)p.tiles2.size();
+    a.per_xcd = p.per_xcd2;
+    a.gtiles = d.gtiles2;
+    a.ngtiles = (int32_t)p.gtiles2.size();
+    a.per_xcd_g = p.per_xcd_g2;
+    a.nw = p.nw2;
+    a.rec_j2 = -1;
+    return a;
+}
+
 fwi_status prologue(const fwi_batch *b, const fwi_time *t, const double *kappa, void *ws, size_t ws_bytes, Plan &p)
 {
     fwi_status s = check_all(b, t, nullptr);
@@ -857,12 +973,48 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
     float *cur = d.lev[0], *prev = d.lev[1];
     RunTimer tm;
     HIP_TRY(tm.begin(0, st));
-    for (int n = 0; n < t->nt; ++n) {
+    auto slot = [&](int n) { return (n + 1) % t->rec_every == 0 ? (n + 1) / t->rec_every - 1 : -1; };
+    int n0 = 0;
+    if (p.two) {
+        // steps n+1, n+2 per launch: u^{n-1}, u^n are read from two levels and u^{n+1},
+        // u^{n+2} written to the other two; an odd last step runs alone below
+        StepArgs a2 = base_args2(p, d);
+        a2.dat = dat;
+        float *other[2] = {d.lev[2], d.lev[3]};
+        int64_t launches = 0;
+        for (; n0 + 1 < t->nt; n0 += 2) {
+            a2.cur = cur;
+            a2.prev = prev;
+            a2.next = other[0];
+            a2.next2 = other[1];
+            a2.fn = b->wavelet[n0];
+            a2.fn2 = b->wavelet[n0 + 1];
+            a2.rec_j = slot(n0);
+            a2.rec_j2 = slot(n0 + 1);
+            a2.wst = p.fwd_only ? nullptr : d.wst + (size_t)n0 * p.cells;
+            a2.wst2 = p.fwd_only ? nullptr : d.wst + (size_t)(n0 + 1) * p.cells;
+            HIP_TRY(launch_step2(a2, false, st));
+            float *op = prev, *oc = cur;
+            prev = other[0];
+            cur = other[1];
+            other[0] = op;
+            other[1] = oc;
+            ++launches;
+        }
+        if (n0 < t->nt) {
+            HIP_TRY(tm.end(launches));
+            HIP_TRY(tm.begin(0, st));
+        } else {
+            HIP_TRY(tm.end(launches));
+            return FWI_OK;
+        }
+    }
+    for (int n = n0; n < t->nt; ++n) {
         a.cur = cur;
         a.prev = prev;
         a.next = prev;  // in place over u^{n-1}
         a.fn = b->wavelet[n];
-        a.rec_j = (n + 1) % t->rec_every == 0 ? (n + 1) / t->rec_every - 1 : -1;
+        a.rec_j = slot(n);
         a.wst = (p.K == 0 && !p.fwd_only) ? d.wst + (size_t)n * p.cells : nullptr;
         a.cka = a.ckb = nullptr;
         if (p.K > 0 && (n + 1) % p.K == 0 && (n + 1) / p.K < p.nseg) {
@@ -873,7 +1025,7 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.ty, st));
         std::swap(cur, prev);
     }
-    HIP_TRY(tm.end(t->nt));
+    HIP_TRY(tm.end(t->nt - n0));
     return FWI_OK;
 }
 
@@ -903,11 +1055,41 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
     RunTimer tm;
     if (p.K == 0) {
         HIP_TRY(tm.begin(1, st));
-        for (int k = t->nt; k >= 1; --k) {
+        int k = t->nt;
+        if (p.two_adj) {
+            // steps k and k-1 per launch (lt^{k+2}, lt^{k+1} in; lt^k, lt^{k-1} out to the
+            // other two levels); an odd last step runs alone below
+            StepArgs a2 = base_args2(p, d);
+            a2.rho = rho;
+            a2.gacc = d.gacc;
+            float *other[2] = {d.lev[2], d.lev[3]};
+            int64_t launches = 0;
+            for (; k >= 2; k -= 2) {
+                a2.cur = lcur;
+                a2.prev = lprev;
+                a2.next = other[0];
+                a2.next2 = other[1];
+                a2.wimg = d.wst + (size_t)(k - 1) * p.cells;
+                a2.wimg2 = d.wst + (size_t)(k - 2) * p.cells;
+                a2.rec_j = k % t->rec_every == 0 ? k / t->rec_every - 1 : -1;
+                a2.rec_j2 = (k - 1) % t->rec_every == 0 ? (k - 1) / t->rec_every - 1 : -1;
+                HIP_TRY(launch_step2(a2, true, st));
+                float *op = lprev, *oc = lcur;
+                lprev = other[0];
+                lcur = other[1];
+                other[0] = op;
+                other[1] = oc;
+                ++launches;
+            }
+            HIP_TRY(tm.end(launches));
+            if (k >= 1) HIP_TRY(tm.begin(1, st));
+        }
+        const int k_single = k;
+        for (; k >= 1; --k) {
             fwi_status s = adj_step(k, d.wst + (size_t)(k - 1) * p.cells);
             if (s) return s;
         }
-        HIP_TRY(tm.end(t->nt));
+        if (!p.two_adj || k_single >= 1) HIP_TRY(tm.end(k_single));
     } else {
         float *P0 = d.lev[0], *P1 = d.lev[1];
         StepArgs f = base_args(p, d);
@@ -1203,6 +1385,15 @@ fwi_status fwi_set_tile(int32_t ndim, int32_t bz)
     if (bz != 0 && !valid_bz(ndim, bz)) return fail(FWI_E_ARG, "unsupported tile height %d", bz);
     std::lock_guard<std::mutex> lk(g_tiles.m);
     g_tiles.forced[ndim] = bz;
+    return FWI_OK;
+}
+
+fwi_status fwi_set_time_blocking(int32_t fwd_steps, int32_t adj_steps)
+{
+    if ((fwd_steps != 1 && fwd_steps != 2) || (adj_steps != 1 && adj_steps != 2))
+        return fail(FWI_E_ARG, "time steps per launch must be 1 or 2");
+    g_blocking_fwd.store(fwd_steps);
+    g_blocking_adj.store(adj_steps);
     return FWI_OK;
 }
 

@@ -12,6 +12,10 @@ namespace fwi {
 constexpr int kTileX = 64;   // one wavefront spans 64 consecutive x cells
 constexpr int kTileY3 = 8;   // 3D tile: 64 x 8 cells per xy plane
 constexpr int kHalo = 4;     // 8th-order stencil radius
+// Two time steps per launch (2D): a wavefront's 64 lanes hold columns x0 - 4 .. x0 + 59 of
+// a strip of kStrip2 columns; strips are kRows2 rows high (forward and adjoint alike).
+constexpr int kStrip2 = kTileX - 2 * kHalo;
+constexpr int kRows2 = 16;
 
 struct SimDesc {
     int64_t u_off;      // element offset of this sim in every field level
@@ -29,6 +33,7 @@ struct SimDesc {
     float w[3][5];      // stencil weights C_k / h_a^2, axes (z, y, x); zero for an unused axis
     float inv_vol;      // 1 / prod h
     int32_t tile0;      // index of this sim's first tile
+    int32_t tile0b;     // 2D: index of its first two-step strip
     double gmax[3];     // sponge gmax per axis (z, y, x); zero for an unused axis
     double dt;
 };
@@ -72,7 +77,9 @@ struct GTile {
 };
 
 // One row (2D: a grid row; 3D: an xy plane) of a tile that holds receivers.  vec_off
-// points at kTileX * ty entries of receiver indices (local to the sim) or -1.
+// points at kTileX * ty entries of receiver indices (local to the sim) or -1.  The event
+// rows of a two-step strip cover its rows z0 - 4 .. z0 + kRows2 + 3 and, entry l, column
+// x0 - 4 + l: the receivers of the margins the first step also computes.
 struct EvRow {
     int32_t z;
     int32_t vec_off;
@@ -92,10 +99,14 @@ struct StepArgs {
     const SrcPos *src;
     const float *cur;       // u^n (or lt^{k+1})
     const float *prev;      // u^{n-1} (or lt^{k+2})
-    float *next;            // u^{n+1} (or lt^k); may alias prev
+    float *next;            // u^{n+1} (or lt^k); may alias prev (one step per launch)
+    float *next2;           // two steps per launch: u^{n+2} (or lt^{k-1}); next and next2
+                            // alias neither cur nor prev
     const float *cf;        // per-sample c
     float *wst;             // imaging operand W^n = L u^n + q^n for this step (nullable)
+    float *wst2;            // two steps: W^{n+1} (nullable)
     const float *wimg;      // adjoint: W^{k-1} to image with
+    const float *wimg2;     // two steps: W^{k-2}
     float *cka, *ckb;       // checkpoint slots for u^{n+1}, u^n (nullable)
     float *dat;             // forward: recorded data (nullable)
     const float *rho;       // adjoint: residual
@@ -104,6 +115,8 @@ struct StepArgs {
     int32_t per_xcd;        // tiles per XCD chunk (grid = 8 * per_xcd)
     int32_t rec_j;          // recording slot j, or -1
     float fn;               // wavelet sample f[n] (forward)
+    int32_t rec_j2;         // two steps: slot of the second step, or -1
+    float fn2;              // two steps: f[n+1]
     // 2D adjoint with per-sample imaging
     const SampleDesc *samples;
     const GTile *gtiles;

@@ -3,9 +3,10 @@
 // Time stepping (both dims) streams each tile along z with a 9-deep register queue for
 // the z-derivative of the 8th-order Laplacian; the x (and y) neighbours come from an LDS
 // row/plane.  One wavefront covers 64 consecutive x cells, so every global access of a
-// row is a coalesced 256-byte segment.  One launch per time step covers every tile of
-// every simulation of the batch (grids may differ in size); the block -> tile map gives
-// each of the 8 XCDs a contiguous chunk of tiles so neighbouring tiles share an L2.
+// row is a coalesced 256-byte segment.  One launch per time step (2D: or per two time
+// steps) covers every tile of every simulation of the batch (grids may differ in size);
+// the block -> tile map gives each of the 8 XCDs a contiguous chunk of tiles so
+// neighbouring tiles share an L2.
 //
 // Scheme (per padded cell): u^{n+1} = a u^n - b u^{n-1} + c (L u^n + q^n), with
 // a = 2/(1+gamma dt), b = (1-gamma dt)/(1+gamma dt) computed from the cell index in
@@ -531,6 +532,470 @@ __global__ __launch_bounds__(1024) void k_adj2d(const StepArgs A)
 #pragma unroll
         for (int r = 0; r < BZ; ++r)
             bstore64(rG, (xin && r < nrow) ? 2 * (roff(z0 + r) + xo) : kOOB, g[r] + acc[r]);
+    }
+}
+
+// ------------------------------------------------ 2D, two time steps per launch
+//
+// One sweep advances the fields by two time steps, so u^{n-1}, u^n (or lt^{k+2}, lt^{k+1})
+// are read once per two steps.  Lane l of a wavefront holds column x0 - 4 + l of a strip
+// of kStrip2 columns.  The first step is evaluated on all 64 lanes and on the rows
+// z0 - 4 .. z0 + BZ + 3: its values in that 4-cell margin are the neighbours the second
+// step needs.  Every strip that needs them recomputes them from the same inputs with the
+// same instructions, so they equal the owner's bit for bit.  The second step runs 4 rows
+// behind the first, on the strip's own 56 lanes and BZ rows.  Every operand of a
+// first-step cell outside the grid reads 0 (poisoned offsets), so that cell comes out
+// exactly 0, the Dirichlet ghost the second step reads.  The two new levels go to
+// buffers that no strip reads during the launch.
+
+// Source term of one lane at row z: the lane's scanned source plus, when some lane of the
+// wave holds sources on several rows, the others at this row.
+__device__ __forceinline__ float src_term(const StepArgs &A, const LaneSrc &src, bool multi, int src_beg,
+                                          int src_cnt, int x, int z, float famp, float wv)
+{
+    if (z == src.z) wv += src.w * famp;
+    if (multi) {
+        float extra = 0.0f;
+        if (src.multi)
+            for (int s2 = 0; s2 < src_cnt; ++s2) {
+                const SrcPos p = A.src[src_beg + s2];
+                if (p.x == x && p.z == z && z != src.z) extra += p.w;
+            }
+        wv += extra * famp;
+    }
+    return wv;
+}
+
+constexpr int kNoRow = -(1 << 30);  // event cursor past its last row
+// Rows fetched ahead by the two-step sweeps.  The two-step forward runs at the same speed
+// with 4, 6 or 8 (it is bound by instruction issue and LDS round trips, not by memory
+// latency), and deeper queues only cost registers.
+constexpr int kPf2 = 4;
+
+template <int BZ, int PF>
+__global__ __launch_bounds__(256) void k_fwd2d2(const StepArgs A)
+{
+    constexpr int R1 = BZ + 2 * kHalo;  // rows of the first step
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd) * 4 + wave);
+    if (t >= A.ntiles) return;  // waves are independent: no workgroup barrier below
+    const Tile T = A.tiles[t];
+    const SimDesc &S = A.sims[T.sim];
+    const int Nx = S.N[2], Nz = S.N[0];
+    const int nz_phys = S.n[0], nx_phys = S.n[2], nb = S.nb;
+    const double gmz = S.gmax[0], gmx = S.gmax[2];
+    const int64_t u_off = S.u_off, d_off = S.d_off;
+    const int nrec = S.nrec, src_beg = S.src_beg, src_cnt = S.src_cnt;
+    const uint32_t fbytes = (uint32_t)Nz * (uint32_t)Nx * 4u;
+    const int x = T.x0 - kHalo + lane;
+    const bool xin = x >= 0 && x < Nx;
+    const bool mine = lane >= kHalo && lane < kHalo + kStrip2;  // the strip's own columns
+    const int z0 = T.z0;
+    const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
+    const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
+    const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
+    const rsrc_t rN2 = make_rsrc(A.next2 + u_off, fbytes);
+    const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
+    const rsrc_t rW = make_rsrc(A.wst ? A.wst + u_off : A.next, A.wst ? fbytes : 0);
+    const rsrc_t rW2 = make_rsrc(A.wst2 ? A.wst2 + u_off : A.next, A.wst2 ? fbytes : 0);
+    float *Dat1 = (A.dat && A.rec_j >= 0) ? A.dat + d_off + (int64_t)A.rec_j * nrec : nullptr;
+    float *Dat2 = (A.dat && A.rec_j2 >= 0) ? A.dat + d_off + (int64_t)A.rec_j2 * nrec : nullptr;
+    const EvRow *__restrict__ evrows = A.evrows;
+    const int32_t *__restrict__ evvec = A.evvec;
+    float wz[5], wx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        wz[k] = S.w[0][k];
+        wx[k] = S.w[2][k];
+    }
+    __shared__ float rows[4][2][kTileX + 2 * kHalo];   // u^n row with its x halo
+    __shared__ float rows1[4][2][kTileX + 2 * kHalo];  // u^{n+1} row (entries 4 .. 67)
+    if (lane < 2 * kHalo) {  // margins read only by lanes whose second step is discarded
+        const int m = lane < kHalo ? lane : kTileX + lane;
+        rows1[wave][0][m] = 0.0f;
+        rows1[wave][1][m] = 0.0f;
+    }
+
+    const double gx = sponge_axis(x, nx_phys, nb, gmx);
+    const double dt = S.dt;
+    float a_col, b_col;  // a, b of this column outside the z-sponge
+    {
+        double gam = 0.0;
+        gam = gam + gx;
+        sponge_ab(gam, dt, a_col, b_col);
+    }
+    const LaneSrc src = scan_sources_2d(A.src, src_beg, src_cnt, x, z0 - kHalo, z0 + BZ + kHalo);
+    const bool multi = __any(src.multi);
+    const float famp1 = A.fn * S.inv_vol, famp2 = A.fn2 * S.inv_vol;
+
+    const uint32_t xo = 4u * (uint32_t)min(max(x, 0), Nx - 1);
+    const int hx = lane < 4 ? T.x0 - 2 * kHalo + lane : T.x0 - kHalo + kTileX - 4 + lane;
+    const bool hl = lane < 8 && hx >= 0 && hx < Nx;
+    const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
+    const uint32_t rowb = 4u * (uint32_t)Nx;
+    auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
+    // every read of the first step is poisoned outside the grid (it must compute 0 there);
+    // stores and records are poisoned outside the strip's own columns
+    const uint32_t xb = xin ? xo : kPoison, hb = hl ? ho : kPoison;
+    const uint32_t sb = (xin && mine) ? xo : kPoison;
+    auto coff = [&](int zz) -> uint32_t { return roff(zz) + xb; };
+    auto hoff = [&](int zz) -> uint32_t { return roff(zz) + hb; };
+    auto soff = [&](int zz) -> uint32_t { return roff(zz) + sb; };
+
+    // u^n queue: q[k] holds row z0 - 8 + k; first-step queues: index k holds row z0 - 4 + k.
+    // Every queue is fetched PF rows ahead of the first step that reads it.
+    float q[R1 + 8 + PF], hq[R1 + PF], cq[R1 + PF], pq[R1 + PF], s1[R1], ra[R1], rb[R1];
+#pragma unroll
+    for (int k = 0; k < 8 + PF; ++k) q[k] = bload(rU, coff(z0 - 2 * kHalo + k));
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int zz = z0 - kHalo + k;
+        hq[k] = bload(rU, hoff(zz));
+        cq[k] = bload(rC, coff(zz));
+        pq[k] = bload(rP, coff(zz));
+    }
+    // receiver event rows of the strip from row z0 on (both steps record own rows only)
+    const bool rec = (Dat1 || Dat2) && T.ev_cnt > 0;
+    const int ev_end = T.ev_beg + T.ev_cnt;
+    int e1 = T.ev_beg;
+    int ez1 = kNoRow, eo1 = 0;
+    if (rec) {
+        while (e1 < ev_end) {
+            ez1 = __builtin_amdgcn_readfirstlane(evrows[e1].z);
+            if (ez1 >= z0) break;
+            ++e1;
+        }
+        if (e1 < ev_end)
+            eo1 = __builtin_amdgcn_readfirstlane(evrows[e1].vec_off);
+        else
+            ez1 = kNoRow;
+    }
+    int e2 = e1, ez2 = ez1, eo2 = eo1;
+
+#pragma unroll
+    for (int i = 0; i < R1; ++i) {
+        const int z1 = z0 - kHalo + i;
+        q[i + 8 + PF] = bload(rU, coff(z1 + kHalo + PF));
+        hq[i + PF] = bload(rU, hoff(z1 + PF));
+        cq[i + PF] = bload(rC, coff(z1 + PF));
+        pq[i + PF] = bload(rP, coff(z1 + PF));
+
+        // first step, row z1 (centre q[i + 4])
+        {
+            float *row = rows[wave][i & 1];
+            row[lane + kHalo] = q[i + 4];
+            if (lane < 4)
+                row[lane] = hq[i];
+            else if (lane < 8)
+                row[kTileX + lane] = hq[i];
+            wave_lds_sync();
+            float lx = wx[0] * q[i + 4];
+            lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+            lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+            lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+            lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+            float lz = wz[0] * q[i + 4];
+            lz += wz[1] * (q[i + 3] + q[i + 5]);
+            lz += wz[2] * (q[i + 2] + q[i + 6]);
+            lz += wz[3] * (q[i + 1] + q[i + 7]);
+            lz += wz[4] * (q[i + 0] + q[i + 8]);
+            float wv = lz + lx;
+            float a = a_col, b = b_col;
+            const double gz = sponge_axis(z1, nz_phys, nb, gmz);  // uniform
+            if (gz != 0.0) {
+                double gam = 0.0;
+                gam = gam + gz;
+                gam = gam + gx;
+                sponge_ab(gam, dt, a, b);
+            }
+            ra[i] = a;
+            rb[i] = b;
+            wv = src_term(A, src, multi, src_beg, src_cnt, x, z1, famp1, wv);
+            const float un = a * q[i + 4] - b * pq[i] + cq[i] * wv;
+            s1[i] = un;
+            if (i >= kHalo && i < BZ + kHalo) {  // the strip's own rows
+                bstore(rN, soff(z1), un);
+                if (A.wst) bstore(rW, soff(z1), wv);
+                if (z1 == ez1) {  // uniform
+                    if (Dat1) {
+                        const int rid = evvec[eo1 + lane];
+                        if (rid >= 0 && mine) Dat1[rid] = un;
+                    }
+                    ++e1;
+                    ez1 = e1 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e1].z) : kNoRow;
+                    eo1 = e1 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e1].vec_off) : 0;
+                }
+            }
+        }
+        // second step, row z2 = z1 - 4 (centre s1[i - 4]; u^n there is q[i], c is cq[i - 4])
+        if (i >= 2 * kHalo) {
+            const int z2 = z1 - kHalo;
+            float *row = rows1[wave][i & 1];
+            row[lane + kHalo] = s1[i - 4];
+            wave_lds_sync();
+            float lx = wx[0] * s1[i - 4];
+            lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+            lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+            lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+            lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+            float lz = wz[0] * s1[i - 4];
+            lz += wz[1] * (s1[i - 5] + s1[i - 3]);
+            lz += wz[2] * (s1[i - 6] + s1[i - 2]);
+            lz += wz[3] * (s1[i - 7] + s1[i - 1]);
+            lz += wz[4] * (s1[i - 8] + s1[i - 0]);
+            float wv = lz + lx;
+            wv = src_term(A, src, multi, src_beg, src_cnt, x, z2, famp2, wv);
+            const float un = ra[i - 4] * s1[i - 4] - rb[i - 4] * q[i] + cq[i - 4] * wv;
+            bstore(rN2, soff(z2), un);
+            if (A.wst2) bstore(rW2, soff(z2), wv);
+            if (z2 == ez2) {  // uniform
+                if (Dat2) {
+                    const int rid = evvec[eo2 + lane];
+                    if (rid >= 0 && mine) Dat2[rid] = un;
+                }
+                ++e2;
+                ez2 = e2 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e2].z) : kNoRow;
+                eo2 = e2 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e2].vec_off) : 0;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Adjoint steps k and k - 1 with the per-sample imaging sum, in one sweep.  A workgroup of
+// nw wavefronts owns one strip of a sample's grid (lanes as in the forward above); wave w
+// sweeps it for the sample's sims w, w + nw, ...  The first step (lt^k, residual slot of
+// step k injected on every lane and row it computes, margins included) and the second
+// (lt^{k-1}) add the exact FP64 products lt^k W^{k-1} and lt^{k-1} W^{k-2} of the strip's
+// own cells into registers; the waves' sums are then added in wave order through LDS and
+// wave 0 applies one read-modify-write of the sample's accumulator per two steps.
+template <int BZ, int PF>
+__global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
+{
+    constexpr int R1 = BZ + 2 * kHalo;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gt = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd_g));
+    if (gt >= A.ngtiles) return;  // uniform per block: nobody reaches the barriers below
+    const int nw = A.nw;
+    const GTile G = A.gtiles[gt];
+    const SampleDesc &Sm = A.samples[G.sample];
+    const int Nx = Sm.N[2], Nz = Sm.N[0];
+    const int nz_phys = Sm.n[0], nx_phys = Sm.n[2], nb = Sm.nb;
+    const double gmz = Sm.gmax[0], gmx = Sm.gmax[2];
+    const double dt = Sm.dt;
+    const int sim_beg = Sm.sim_beg, sim_cnt = Sm.sim_cnt;
+    const int64_t ncell = Sm.ncell, g_off = Sm.g_off;
+    const SimDesc &S0 = A.sims[sim_beg];
+    const int64_t u_off0 = S0.u_off;  // sims of a sample are consecutive, ncell apart
+    float wz[5], wx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        wz[k] = S0.w[0][k];
+        wx[k] = S0.w[2][k];
+    }
+    const uint32_t fbytes = (uint32_t)Nz * (uint32_t)Nx * 4u;
+    const int x = G.x0 - kHalo + lane;
+    const bool xin = x >= 0 && x < Nx;
+    const bool mine = lane >= kHalo && lane < kHalo + kStrip2;
+    const int z0 = G.z0;
+    const int nrow = min(BZ, Nz - z0);
+    const rsrc_t rC = make_rsrc(A.cf + Sm.c_off, fbytes);
+    const int rec_j1 = A.rec_j, rec_j2 = A.rec_j2;
+    const EvRow *__restrict__ evrows = A.evrows;
+    const int32_t *__restrict__ evvec = A.evvec;
+    const double gx = sponge_axis(x, nx_phys, nb, gmx);
+
+    const uint32_t xo = 4u * (uint32_t)min(max(x, 0), Nx - 1);
+    const int hx = lane < 4 ? G.x0 - 2 * kHalo + lane : G.x0 - kHalo + kTileX - 4 + lane;
+    const bool hl = lane < 8 && hx >= 0 && hx < Nx;
+    const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
+    const uint32_t rowb = 4u * (uint32_t)Nx;
+    auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
+
+    __shared__ float rows[8][2][kTileX + 2 * kHalo];
+    __shared__ float rows1[8][2][kTileX + 2 * kHalo];
+    __shared__ double red[BZ][kTileX];
+    __shared__ float2 abt[R1][kTileX];  // leapfrog a, b of the first step's cells
+
+    for (int r = wave; r < R1; r += nw) {
+        double gam = 0.0;
+        gam = gam + sponge_axis(z0 - kHalo + r, nz_phys, nb, gmz);
+        gam = gam + gx;
+        float a, b;
+        sponge_ab(gam, dt, a, b);
+        abt[r][lane] = make_float2(a, b);
+    }
+    if (lane < 2 * kHalo) {
+        const int m = lane < kHalo ? lane : kTileX + lane;
+        rows1[wave][0][m] = 0.0f;
+        rows1[wave][1][m] = 0.0f;
+    }
+    __syncthreads();
+
+    double acc[BZ];
+#pragma unroll
+    for (int r = 0; r < BZ; ++r) acc[r] = 0.0;
+
+    for (int j = wave; j < sim_cnt; j += nw) {
+        const int sim = sim_beg + j;
+        const int64_t u_off = u_off0 + (int64_t)j * ncell;
+        const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
+        const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
+        const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
+        const rsrc_t rN2 = make_rsrc(A.next2 + u_off, fbytes);
+        const rsrc_t rW = make_rsrc(A.wimg + u_off, fbytes);
+        const rsrc_t rW2 = make_rsrc(A.wimg2 + u_off, fbytes);
+        // lane offsets pass through an empty asm so that the row offsets built from them
+        // are recomputed per sim next to their loads, not hoisted out of the sim loop
+        uint32_t xs = xo, hs = ho;
+        int zs = z0;
+        asm volatile("" : "+v"(xs), "+v"(hs), "+s"(zs));
+        const uint32_t xb = xin ? xs : kPoison, hb = hl ? hs : kPoison;
+        const uint32_t sb = (xin && mine) ? xs : kPoison;
+        auto coff = [&](int zz) -> uint32_t { return roff(zz) + xb; };
+        auto hoff = [&](int zz) -> uint32_t { return roff(zz) + hb; };
+        auto soff = [&](int zz) -> uint32_t { return roff(zz) + sb; };
+        const int tile0b = __builtin_amdgcn_readfirstlane(A.sims[sim].tile0b);
+        const int nrec = __builtin_amdgcn_readfirstlane(A.sims[sim].nrec);
+        const int64_t d_off = A.sims[sim].d_off;
+        const int d_lo = __builtin_amdgcn_readfirstlane((int)(d_off & 0xFFFFFFFF));
+        const int d_hi = __builtin_amdgcn_readfirstlane((int)(d_off >> 32));
+        const int64_t d_off_u = (int64_t)(((uint64_t)(uint32_t)d_hi << 32) | (uint32_t)d_lo);
+
+        float q[R1 + 8 + PF], hq[R1 + PF], cq[R1 + PF], pq[R1 + PF], s1[R1], wq1[BZ], wq2[BZ];
+#pragma unroll
+        for (int k = 0; k < 8 + PF; ++k) q[k] = bload(rU, coff(zs - 2 * kHalo + k));
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int zz = zs - kHalo + k;
+            hq[k] = bload(rU, hoff(zz));
+            cq[k] = bload(rC, coff(zz));
+            pq[k] = bload(rP, coff(zz));
+        }
+        const float *Rho1 = rec_j1 >= 0 ? A.rho + d_off_u + (int64_t)rec_j1 * nrec : nullptr;
+        const float *Rho2 = rec_j2 >= 0 ? A.rho + d_off_u + (int64_t)rec_j2 * nrec : nullptr;
+        // receiver event rows of this sim's strip: the first step injects on all of them
+        // (margins included), the second from row z0 on
+        int e1 = 0, ev_end = 0, ez1 = kNoRow, eo1 = 0, e2 = 0, ez2 = kNoRow, eo2 = 0;
+        if (Rho1 || Rho2) {
+            const Tile &T = A.tiles[tile0b + G.tix];
+            e1 = __builtin_amdgcn_readfirstlane(T.ev_beg);
+            ev_end = e1 + __builtin_amdgcn_readfirstlane(T.ev_cnt);
+            if (e1 < ev_end) {
+                ez1 = __builtin_amdgcn_readfirstlane(evrows[e1].z);
+                eo1 = __builtin_amdgcn_readfirstlane(evrows[e1].vec_off);
+            }
+            e2 = e1;
+            while (e2 < ev_end) {
+                ez2 = __builtin_amdgcn_readfirstlane(evrows[e2].z);
+                if (ez2 >= z0) break;
+                ++e2;
+            }
+            if (e2 < ev_end)
+                eo2 = __builtin_amdgcn_readfirstlane(evrows[e2].vec_off);
+            else
+                ez2 = kNoRow;
+        }
+
+#pragma unroll
+        for (int i = 0; i < R1; ++i) {
+            const int z1 = zs - kHalo + i;
+            q[i + 8 + PF] = bload(rU, coff(z1 + kHalo + PF));
+            hq[i + PF] = bload(rU, hoff(z1 + PF));
+            cq[i + PF] = bload(rC, coff(z1 + PF));
+            pq[i + PF] = bload(rP, coff(z1 + PF));
+            // W^{k-1} of own row z0 + r is used at i = r + 4, W^{k-2} at i = r + 8: both are
+            // fetched 4 rows ahead (point operands: the clamped column)
+            if (i < BZ) wq1[i] = bload(rW, roff(zs + i) + xs);
+            if (i >= kHalo && i - kHalo < BZ) wq2[i - kHalo] = bload(rW2, roff(zs + i - kHalo) + xs);
+
+            {
+                float *row = rows[wave][i & 1];
+                row[lane + kHalo] = q[i + 4];
+                if (lane < 4)
+                    row[lane] = hq[i];
+                else if (lane < 8)
+                    row[kTileX + lane] = hq[i];
+                wave_lds_sync();
+                float lx = wx[0] * q[i + 4];
+                lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+                lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+                lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+                lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+                float lz = wz[0] * q[i + 4];
+                lz += wz[1] * (q[i + 3] + q[i + 5]);
+                lz += wz[2] * (q[i + 2] + q[i + 6]);
+                lz += wz[3] * (q[i + 1] + q[i + 7]);
+                lz += wz[4] * (q[i + 0] + q[i + 8]);
+                float wv = lz + lx;
+                const float2 ab = abt[i][lane];
+                if (z1 == ez1) {  // uniform
+                    const int rid = evvec[eo1 + lane];
+                    if (rid >= 0 && Rho1) wv += Rho1[rid];
+                    ++e1;
+                    ez1 = e1 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e1].z) : kNoRow;
+                    eo1 = e1 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e1].vec_off) : 0;
+                }
+                const float un = ab.x * q[i + 4] - ab.y * pq[i] + cq[i] * wv;
+                s1[i] = un;
+                if (i >= kHalo && i < BZ + kHalo) {
+                    bstore(rN, soff(z1), un);
+                    acc[i - kHalo] += (double)un * (double)wq1[i - kHalo];
+                }
+            }
+            if (i >= 2 * kHalo) {
+                const int z2 = z1 - kHalo;
+                float *row = rows1[wave][i & 1];
+                row[lane + kHalo] = s1[i - 4];
+                wave_lds_sync();
+                float lx = wx[0] * s1[i - 4];
+                lx += wx[1] * (row[lane + 3] + row[lane + 5]);
+                lx += wx[2] * (row[lane + 2] + row[lane + 6]);
+                lx += wx[3] * (row[lane + 1] + row[lane + 7]);
+                lx += wx[4] * (row[lane + 0] + row[lane + 8]);
+                float lz = wz[0] * s1[i - 4];
+                lz += wz[1] * (s1[i - 5] + s1[i - 3]);
+                lz += wz[2] * (s1[i - 6] + s1[i - 2]);
+                lz += wz[3] * (s1[i - 7] + s1[i - 1]);
+                lz += wz[4] * (s1[i - 8] + s1[i - 0]);
+                float wv = lz + lx;
+                const float2 ab = abt[i - kHalo][lane];
+                if (z2 == ez2) {  // uniform
+                    const int rid = evvec[eo2 + lane];
+                    if (rid >= 0 && Rho2) wv += Rho2[rid];
+                    ++e2;
+                    ez2 = e2 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e2].z) : kNoRow;
+                    eo2 = e2 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e2].vec_off) : 0;
+                }
+                const float un = ab.x * s1[i - 4] - ab.y * q[i] + cq[i - 4] * wv;
+                bstore(rN2, soff(z2), un);
+                acc[i - 2 * kHalo] += (double)un * (double)wq2[i - 2 * kHalo];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    for (int w = 1; w < nw; ++w) {
+        __syncthreads();
+        if (wave == w)
+#pragma unroll
+            for (int r = 0; r < BZ; ++r) red[r][lane] = acc[r];
+        __syncthreads();
+        if (wave == 0)
+#pragma unroll
+            for (int r = 0; r < BZ; ++r) acc[r] += red[r][lane];
+    }
+    if (wave == 0) {
+        const rsrc_t rG = make_rsrc(A.gacc + g_off, 2 * fbytes);
+        const bool own = xin && mine;
+        double g[BZ];
+#pragma unroll
+        for (int r = 0; r < BZ; ++r) g[r] = bload64(rG, (own && r < nrow) ? 2 * (roff(z0 + r) + xo) : kOOB);
+#pragma unroll
+        for (int r = 0; r < BZ; ++r)
+            bstore64(rG, (own && r < nrow) ? 2 * (roff(z0 + r) + xo) : kOOB, g[r] + acc[r]);
     }
 }
 
@@ -1230,6 +1695,21 @@ hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty
     if (a.ntiles <= 0) return hipSuccess;
     if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : fwd2d_dispatch(a, bz, st);
     return adjoint ? adj3d_dispatch(a, ty, st) : fwd3d_dispatch(a, bz, ty, st);
+}
+
+hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    if (!a.next2 || a.next2 == a.next || a.next == a.cur || a.next == a.prev || a.next2 == a.cur ||
+        a.next2 == a.prev)
+        return hipErrorInvalidValue;
+    if (adjoint) {
+        if (a.nw < 1 || a.nw > 8 || !a.wimg || !a.wimg2) return hipErrorInvalidValue;
+        k_adj2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd_g), 64 * a.nw, 0, st>>>(a);
+    } else {
+        k_fwd2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd), 256, 0, st>>>(a);  // 4 strips per workgroup
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(const SimDesc *sims, int nsim, int nt_rec, const float *d, const float *dobs, float *rho,

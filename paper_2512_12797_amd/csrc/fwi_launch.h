@@ -15,6 +15,8 @@ hipError_t launch_prep(const SampleDesc *smp, int nsample, int64_t max_cell, con
                        hipStream_t st);
 // one time step over every tile; bz = rows (2D) or planes (3D) per tile, ty = 3D tile height
 hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty, hipStream_t st);
+// two 2D time steps over every two-step strip (tables and nw of the two-step plan)
+hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st);
 hipError_t launch_residual(const SimDesc *sims, int nsim, int nt_rec, const float *d, const float *dobs, float *rho,
                            float inv_sigma2, double *partial, int nchunk, int *status, hipStream_t st);
 hipError_t launch_misfit_final(const double *partial, int nchunk, int nsim, double half_is2, double *misfit,

@@ -74,8 +74,9 @@ def lib():
         L.fwi_langevin.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                    C.c_uint64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
         L.fwi_poll_status.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
-        for name in ("fwi_graphs_enable", "fwi_graphs_stats", "fwi_set_tile", "fwi_tune"):
+        for name in ("fwi_graphs_enable", "fwi_graphs_stats", "fwi_set_tile", "fwi_tune", "fwi_set_time_blocking"):
             getattr(L, name).restype = C.c_int32
+        L.fwi_set_time_blocking.argtypes = [C.c_int32, C.c_int32]
         L.fwi_graphs_enable.argtypes = [C.c_int32]
         L.fwi_graphs_stats.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.fwi_set_tile.argtypes = [C.c_int32, C.c_int32]
@@ -322,6 +323,12 @@ def fwi_graphs_stats():
 
 def fwi_set_tile(ndim: int, bz: int):
     _ok(lib().fwi_set_tile(ndim, bz))
+
+
+def fwi_set_time_blocking(fwd_steps: int, adj_steps: int):
+    """Time steps per launch of the 2D keep-all forward and adjoint sweeps (1 or 2 each;
+    process-wide; default 1 and 2)."""
+    _ok(lib().fwi_set_time_blocking(fwd_steps, adj_steps))
 
 
 def fwi_tune(batch, time, v, ws, cache_path=None, stream=None):

@@ -243,7 +243,7 @@ def test_3d_configuration_full_size_properties(F):
 
 # ------------------------------------------------ graphs, tile heights, tuner
 
-def _edge_batch(F, seed, ckpt=0, nt=160):
+def _edge_batch(F, seed, ckpt=0, nt=160, R=2):
     """Uneven 2-sample batch whose encodings are redrawn per `seed`."""
     from paper_2512_12797_amd import problems
     cfg = W.C3
@@ -252,7 +252,7 @@ def _edge_batch(F, seed, ckpt=0, nt=160):
     wav = W.ricker(15.0, 1e-3, nt)
     batch, groups = problems.encoded_batch(cfg, grids, wav, seed=seed, step=seed, s=3, G=2,
                                            nshot_of=lambda g: 6)
-    time = F.time_axis(1e-3, nt, 2, ckpt)
+    time = F.time_axis(1e-3, nt, R, ckpt)
     models = [f32(W.salt_2d(g.nz, g.nx, seed=k + 5, vtop=1500, vbot=2800, vsalt=3500).ravel())
               for k, g in enumerate(grids)]
     return batch, groups, time, models
@@ -306,7 +306,9 @@ def test_graph_replays_equal_eager(F, ckpt):
 def test_results_identical_for_every_tile_height(F, ndim):
     say("case tile heights %dD" % ndim)
     if ndim == 2:
-        batch, groups, time, models = _edge_batch(F, 4, 0, 120)
+        # odd nt: with two time steps per launch the last forward and the first adjoint
+        # step run alone, at the forced tile height
+        batch, groups, time, models = _edge_batch(F, 4, 0, 123, R=3)
         cands = [8, 16, 32]
     else:
         g = F.Grid(nz=40, ny=13, nx=70, dz=20.0, dy=20.0, dx=20.0, nb=4, v_ref=3000.0, v_max=3300.0, ndim=3)
@@ -321,16 +323,21 @@ def test_results_identical_for_every_tile_height(F, ndim):
     v = dev(np.concatenate(models))
     dobs = dev(1e-4 * np.random.default_rng(2).standard_normal(nd))
     ws = F.alloc_workspace(batch, time)
-    outs = []
-    try:
-        for bz in cands:
-            F.fwi_set_tile(ndim, bz)
-            outs.append(_run(F, batch, time, v, dobs, [g[2] for g in groups], ws))
-    finally:
-        F.fwi_set_tile(ndim, 0)
-    for o in outs[1:]:
-        for a, b in zip(o, outs[0]):
-            assert np.array_equal(a, b)
+    # 2D: with one time step per launch every step runs at the forced tile height; with
+    # two the results must not depend on it either
+    for blocking in (((1, 1), (2, 2)) if ndim == 2 else ((1, 1),)):
+        outs = []
+        try:
+            F.fwi_set_time_blocking(*blocking)
+            for bz in cands:
+                F.fwi_set_tile(ndim, bz)
+                outs.append(_run(F, batch, time, v, dobs, [g[2] for g in groups], ws))
+        finally:
+            F.fwi_set_tile(ndim, 0)
+            F.fwi_set_time_blocking(1, 2)
+        for o in outs[1:]:
+            for a, b in zip(o, outs[0]):
+                assert np.array_equal(a, b)
 
 
 def test_tuner_and_cache(F, tmp_path):
