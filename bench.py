@@ -315,10 +315,10 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay each gradient as a captured HIP graph")
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
-    ap.add_argument("--fwd-steps", type=int, default=1, choices=[1, 2],
-                    help="2D keep-all schedule: time steps per forward launch")
-    ap.add_argument("--adj-steps", type=int, default=2, choices=[1, 2],
-                    help="2D keep-all schedule: time steps per adjoint launch")
+    ap.add_argument("--fwd-steps", type=int, default=0, choices=[0, 1, 2],
+                    help="2D keep-all schedule: time steps per forward launch (0: automatic, 1)")
+    ap.add_argument("--adj-steps", type=int, default=0, choices=[0, 1, 2],
+                    help="2D keep-all schedule: time steps per adjoint launch (0: the tuner's choice, else 2)")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
     ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
@@ -416,12 +416,12 @@ def main():
     tuned = None
     if args.tile:
         fwi.fwi_set_tile(cfg.ndim, args.tile)
-        tuned = (args.tile, float("nan"))
+        tuned = (args.tile, 0, float("nan"))
         log("tile height forced to %d" % args.tile)
     elif args.tune:
         cache = os.environ.get("FWI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "fwi_tune_cache.json"))
         tuned = fwi.fwi_tune(batch0, time_ax, v, ws, cache)
-        log("tuner: tile height %d, %.3f ms per gradient time step" % tuned)
+        log("tuner: tile height %d, adjoint steps per launch %d, %.3f ms per gradient time step" % tuned)
     fwi.fwi_set_time_blocking(args.fwd_steps, args.adj_steps)
     stream = torch.cuda.Stream()  # graphs need a non-default stream
     torch.cuda.set_stream(stream)
@@ -485,8 +485,9 @@ def main():
     # two time steps per launch: the 2D keep-all schedule with an even step count (every
     # launch of the timed sweep is then a two-step launch)
     blk = cfg.ndim == 2 and ckpt == 0 and nt % 2 == 0
+    adj_eff = args.adj_steps or (tuned[1] if tuned is not None and tuned[1] else 2)
     two_fwd = blk and args.fwd_steps == 2
-    two_adj = blk and args.adj_steps == 2
+    two_adj = blk and adj_eff == 2
 
     # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
     # adjoint + imaging step: lt^{k+1}, lt^{k+2} read, lt^k write, W^{k-1} read = 16 B per

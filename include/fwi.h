@@ -239,34 +239,43 @@ fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays);
 
 /*
  * Tile height of the step kernels: rows per 2D tile (8, 16, 32) or planes per 3D tile
- * (16, 32); the 2D adjoint sweeps strips of 8 rows when the tile height is 8 and of
- * 16 rows otherwise.  fwi_set_tile forces one for every batch of that dimensionality (0 returns
- * to automatic choice).  fwi_tune times one forward and one adjoint step of every candidate
- * on the caller's batch, model v (device) and workspace (>= fwi_workspace_size, whose
- * tables are sized for any candidate), keeps the fastest for this batch shape (the
- * multiset of padded grid sizes) for later calls, and returns it (bz_out, and the cost of
- * one gradient time step in ms_out; both nullable).  With cache_path (nullable) the choice
- * is read from / appended to a JSON-lines file ({"sig": ..., "bz": ..., "ms": ...}) so that
- * later processes skip the timing.  The workspace content is overwritten.
+ * (16, 32); the one-step 2D adjoint sweeps strips of 8 rows when the tile height is 8 and
+ * of 16 rows otherwise.  fwi_set_tile forces one for every batch of that dimensionality
+ * (0 returns to automatic choice).  fwi_tune times one forward and one adjoint step of
+ * every candidate on the caller's batch, model v (device) and workspace (>=
+ * fwi_workspace_size, whose tables are sized for any candidate); for 2D keep-all schedules
+ * of at least two steps it also times the two-step adjoint (see fwi_set_time_blocking).  It
+ * keeps the fastest combination for this batch shape (the multiset of padded grid sizes)
+ * for later calls and returns it: bz_out, adj_steps_out (1 or 2; 0 where the two-step
+ * adjoint does not apply) and the cost of one gradient time step in ms_out; all three are
+ * nullable.  With cache_path (nullable) the choice is read from / appended to a JSON-lines
+ * file ({"sig": ..., "bz": ..., "adj_steps": ..., "ms": ...}) so that later processes skip
+ * the timing.  The workspace content is overwritten.
  */
 fwi_status fwi_set_tile(int32_t ndim, int32_t bz);
+fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
+                    const char *cache_path, int32_t *bz_out, int32_t *adj_steps_out, double *ms_out);
 
 /*
  * Time steps per launch of the 2D keep-all schedule (ckpt_every 0 or -1), process-wide, for
- * the forward sweep (fwd_steps) and the adjoint sweep (adj_steps): 1 or 2 each; the default
- * is 1 and 2.  With 2, one sweep advances the wavefield (or the adjoint field) by two steps
- * of the discretized wave equation's recursion (Sec. 2), reading the two old levels once per
- * two steps.  Each wavefront then covers a strip of 56 columns and 16 rows and also
- * computes the first step on a 4-cell margin around it, the halo of the second.  The data
- * and the imaging operands are the same as with 1 bit for bit.  The per-sample gradient
- * sums the same FP64 products in another order.  An odd last step is launched alone.  3D
- * and checkpointed schedules always take one step per launch.  The setting applies to
- * calls that start after it (a captured graph keeps the setting it was captured with; the
- * graph key includes it).  Returns FWI_E_ARG for other values.
+ * the forward sweep (fwd_steps) and the adjoint sweep (adj_steps).  Each is 1 or 2 (forced),
+ * or 0 (automatic, the default).  Automatic means one forward step per launch, and for the
+ * adjoint the choice fwi_tune made for the batch shape, else two steps per launch.
+ *
+ * With 2, one sweep advances the wavefield (or the adjoint field) by two steps of the
+ * recursion of the discretized wave equation (Sec. 2). It reads the two old levels once
+ * per two steps. Each wavefront then covers a strip of 56 columns and 16 rows, and also
+ * computes the first step on a 4-cell margin around it: the halo of the second step.
+ *
+ * The data and the imaging operands are bit-identical to those of one step per launch.
+ * The per-sample gradient sums the same FP64 products in another order.
+ *
+ * An odd last step is launched alone.  3D and checkpointed schedules always take one step
+ * per launch.  The setting applies to calls that start after it.  A captured graph keeps
+ * the setting it was captured with (the graph key includes it).  Returns FWI_E_ARG for
+ * other values.
  */
 fwi_status fwi_set_time_blocking(int32_t fwd_steps, int32_t adj_steps);
-fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
-                    const char *cache_path, int32_t *bz_out, double *ms_out);
 
 #ifdef __cplusplus
 }

@@ -211,17 +211,36 @@ const int kBz2[] = {8, 16, 32};
 const int kBz3[] = {16, 32};
 
 // Process-wide tile choices: forced per dimensionality (fwi_set_tile) or tuned per batch
-// shape (fwi_tune).
+// shape (fwi_tune): the tile height and, for 2D keep-all batches, the adjoint's time steps
+// per launch (0: not tuned).
+struct TunedShape {
+    std::string sig;
+    int bz;
+    int adj;
+};
 struct TileChoices {
     std::mutex m;
     int forced[4] = {0, 0, 0, 0};
-    std::vector<std::pair<std::string, int>> tuned;
+    std::vector<TunedShape> tuned;
 };
 TileChoices g_tiles;
 
-// Time steps per launch of the 2D keep-all schedule (1 or 2), forward and adjoint,
-// process-wide.
-std::atomic<int> g_blocking_fwd{1}, g_blocking_adj{2};
+void set_tuned(const std::string &sig, int bz, int adj)
+{
+    std::lock_guard<std::mutex> lk(g_tiles.m);
+    for (auto &e : g_tiles.tuned)
+        if (e.sig == sig) {
+            e.bz = bz;
+            e.adj = adj;
+            return;
+        }
+    g_tiles.tuned.push_back({sig, bz, adj});
+}
+
+// Time steps per launch of the 2D keep-all schedule, forward and adjoint, process-wide:
+// 1 or 2 forced, 0 automatic (forward 1; adjoint the tuned choice for the batch shape,
+// else 2).
+std::atomic<int> g_blocking_fwd{0}, g_blocking_adj{0};
 
 // Batch shape signature: dimensionality and the multiset of padded grid sizes.
 std::string shape_signature(const fwi_batch *b)
@@ -265,8 +284,8 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
         }
         const std::string sig = shape_signature(b);
         for (auto &e : g_tiles.tuned)
-            if (e.first == sig && valid_bz(p.ndim, e.second)) {
-                p.bz = e.second;
+            if (e.sig == sig && valid_bz(p.ndim, e.bz)) {
+                p.bz = e.bz;
                 return;
             }
     }
@@ -586,8 +605,17 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     if (p.K > t->nt) p.K = t->nt;
     p.nseg = p.K > 0 ? (t->nt + p.K - 1) / p.K : 1;
     p.nlev = (p.K > 0 || p.ndim == 2) ? 4 : 2;
-    p.two = p.ndim == 2 && p.K == 0 && g_blocking_fwd.load() == 2;
-    p.two_adj = p.ndim == 2 && p.K == 0 && g_blocking_adj.load() == 2;
+    {
+        int fwd = g_blocking_fwd.load(), adj = g_blocking_adj.load();
+        if (p.ndim == 2 && p.K == 0 && adj == 0) {
+            const std::string sig = shape_signature(b);
+            std::lock_guard<std::mutex> lk(g_tiles.m);
+            for (auto &e : g_tiles.tuned)
+                if (e.sig == sig) adj = e.adj;
+        }
+        p.two = p.ndim == 2 && p.K == 0 && fwd == 2;
+        p.two_adj = p.ndim == 2 && p.K == 0 && (adj == 2 || adj == 0);
+    }
     p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.K : t->nt);
     p.ck_slots = p.K > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
     int64_t maxdata = 0;
@@ -1390,17 +1418,18 @@ fwi_status fwi_set_tile(int32_t ndim, int32_t bz)
 
 fwi_status fwi_set_time_blocking(int32_t fwd_steps, int32_t adj_steps)
 {
-    if ((fwd_steps != 1 && fwd_steps != 2) || (adj_steps != 1 && adj_steps != 2))
-        return fail(FWI_E_ARG, "time steps per launch must be 1 or 2");
+    if (fwd_steps < 0 || fwd_steps > 2 || adj_steps < 0 || adj_steps > 2)
+        return fail(FWI_E_ARG, "time steps per launch must be 0 (automatic), 1 or 2");
     g_blocking_fwd.store(fwd_steps);
     g_blocking_adj.store(adj_steps);
     return FWI_OK;
 }
 
 // Time one forward step and one adjoint step of every candidate tile height on the
-// caller's batch and workspace; keep the fastest for this batch shape.
+// caller's batch and workspace, and (2D keep-all schedules) the two-step adjoint; keep the
+// fastest combination for this batch shape.
 fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
-                    const char *cache_path, int32_t *bz_out, double *ms_out)
+                    const char *cache_path, int32_t *bz_out, int32_t *adj_steps_out, double *ms_out)
 {
     Plan p0;
     fwi_status s = prologue(b, t, nullptr, ws, ws_bytes, p0);
@@ -1408,34 +1437,33 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
     if (!v) return fail(FWI_E_ARG, "null model");
     hipStream_t st = (hipStream_t)stream;
     const std::string sig = shape_signature(b);
+    // the two-step adjoint is a candidate for 2D keep-all schedules of at least two steps
+    const bool try_two = p0.ndim == 2 && p0.K == 0 && !p0.fwd_only && t->nt >= 2;
     // a recorded choice for this shape wins
     if (cache_path && *cache_path) {
         FILE *f = fopen(cache_path, "r");
         if (f) {
             char line[4096];
             const std::string needle = "\"sig\": \"" + sig + "\"";
-            int found = 0;
+            int found = 0, adj = 0;
             double ms = 0;
             while (fgets(line, sizeof line, f)) {
                 if (!strstr(line, needle.c_str())) continue;
                 const char *q = strstr(line, "\"bz\": ");
+                const char *a = strstr(line, "\"adj_steps\": ");
                 const char *m = strstr(line, "\"ms\": ");
                 if (q && valid_bz(p0.ndim, atoi(q + 6))) {
                     found = atoi(q + 6);
+                    adj = a ? atoi(a + 13) : 0;
+                    if (adj != 1 && adj != 2) adj = 0;
                     ms = m ? atof(m + 6) : 0.0;
                 }
             }
             fclose(f);
             if (found) {
-                std::lock_guard<std::mutex> lk(g_tiles.m);
-                bool set = false;
-                for (auto &e : g_tiles.tuned)
-                    if (e.first == sig) {
-                        e.second = found;
-                        set = true;
-                    }
-                if (!set) g_tiles.tuned.push_back({sig, found});
+                set_tuned(sig, found, adj);
                 if (bz_out) *bz_out = found;
+                if (adj_steps_out) *adj_steps_out = adj;
                 if (ms_out) *ms_out = ms;
                 return FWI_OK;
             }
@@ -1446,16 +1474,23 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
         cand.assign(std::begin(kBz2), std::end(kBz2));
     else
         cand.assign(std::begin(kBz3), std::end(kBz3));
-    const int reps = 8;
+    // the timed launches stream through distinct imaging-operand levels, as a sweep does:
+    // with one level the fields stay in the 256 MB MALL and the kernels that move fewer
+    // bytes gain less than they do in a real sweep
+    const int reps = 16;
+    auto wlev = [&](const Plan &p, const Dev &d, int r) {
+        return d.wst + (size_t)(r % std::max<int64_t>(1, p.wst_levels)) * p.cells;
+    };
     hipEvent_t e0, e1, e2;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventCreate(&e2));
-    int best = 0;
-    double best_ms = 1e30;
-    for (int bz : cand) {
-        Plan p;
-        s = build_plan(b, t, nullptr, p, bz);
+    std::vector<double> fwd_ms(cand.size(), 0.0), adj_ms(cand.size(), 0.0);
+    Plan pl;  // plan of the last candidate: its two-step tables serve every tile height
+    for (size_t c = 0; c < cand.size(); ++c) {
+        Plan &p = pl;
+        p = Plan();
+        s = build_plan(b, t, nullptr, p, cand[c]);
         if (s) return s;
         Dev d = carve(p, ws);
         s = upload_tables(p, d.base + p.o_tables, st);
@@ -1465,8 +1500,6 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
         if (!p.fwd_only) HIP_TRY(launch_fill_f64(d.gacc, p.gcells, 0.0, st));
         StepArgs a = base_args(p, d);
         a.fn = 0.0f;
-        a.wst = p.fwd_only ? nullptr : d.wst;
-        a.wimg = p.fwd_only ? nullptr : d.wst;
         a.gacc = d.gacc;
         a.rho = d.rho;
         for (int pass = 0; pass < 2; ++pass) {  // first pass warms the caches
@@ -1475,6 +1508,7 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
             for (int r = 0; r < reps; ++r) {
                 a.cur = cur;
                 a.prev = a.next = prev;
+                a.wst = p.fwd_only ? nullptr : wlev(p, d, r);
                 HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.ty, st));
                 std::swap(cur, prev);
             }
@@ -1483,6 +1517,7 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
                 for (int r = 0; r < reps; ++r) {
                     a.cur = cur;
                     a.prev = a.next = prev;
+                    a.wimg = wlev(p, d, reps - 1 - r);
                     HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.ty, st));
                     std::swap(cur, prev);
                 }
@@ -1492,34 +1527,67 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
         float fms = 0, ams = 0;
         HIP_TRY(hipEventElapsedTime(&fms, e0, e1));
         HIP_TRY(hipEventElapsedTime(&ams, e1, e2));
-        // cost of one gradient time step: forward sweeps (two with recomputation) + adjoint
-        const double ms = (fms * (p.K > 0 ? 2.0 : 1.0) + ams) / reps;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = bz;
+        fwd_ms[c] = fms / reps;
+        adj_ms[c] = ams / reps;
+    }
+    // the two-step adjoint: reps launches of two steps, per time step
+    double adj2_ms = 1e30;
+    if (try_two) {
+        Dev d = carve(pl, ws);
+        StepArgs a = base_args2(pl, d);
+        a.rho = d.rho;
+        a.gacc = d.gacc;
+        for (int pass = 0; pass < 2; ++pass) {
+            float *cur = d.lev[0], *prev = d.lev[1], *o0 = d.lev[2], *o1 = d.lev[3];
+            HIP_TRY(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) {
+                a.cur = cur;
+                a.prev = prev;
+                a.next = o0;
+                a.next2 = o1;
+                a.wimg = wlev(pl, d, 2 * reps - 1 - 2 * r);
+                a.wimg2 = wlev(pl, d, 2 * reps - 2 - 2 * r);
+                HIP_TRY(launch_step2(a, true, st));
+                std::swap(prev, o0);
+                std::swap(cur, o1);
+            }
+            HIP_TRY(hipEventRecord(e1, st));
         }
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms2 = 0;
+        HIP_TRY(hipEventElapsedTime(&ms2, e0, e1));
+        adj2_ms = ms2 / (2.0 * reps);  // reps launches of two steps
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
-    {
-        std::lock_guard<std::mutex> lk(g_tiles.m);
-        bool set = false;
-        for (auto &e : g_tiles.tuned)
-            if (e.first == sig) {
-                e.second = best;
-                set = true;
-            }
-        if (!set) g_tiles.tuned.push_back({sig, best});
+    // cost of one gradient time step: forward sweeps (two with recomputation) + adjoint
+    int best = 0, best_adj = 0;
+    double best_ms = 1e30;
+    for (size_t c = 0; c < cand.size(); ++c) {
+        const double f = fwd_ms[c] * (p0.K > 0 ? 2.0 : 1.0);
+        if (f + adj_ms[c] < best_ms) {
+            best_ms = f + adj_ms[c];
+            best = cand[c];
+            best_adj = try_two ? 1 : 0;
+        }
+        if (try_two && f + adj2_ms < best_ms) {
+            best_ms = f + adj2_ms;
+            best = cand[c];
+            best_adj = 2;
+        }
     }
+    set_tuned(sig, best, best_adj);
     if (cache_path && *cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "{\"sig\": \"%s\", \"bz\": %d, \"ms\": %.6f}\n", sig.c_str(), best, best_ms);
+            fprintf(f, "{\"sig\": \"%s\", \"bz\": %d, \"adj_steps\": %d, \"ms\": %.6f}\n", sig.c_str(), best, best_adj,
+                    best_ms);
             fclose(f);
         }
     }
     if (bz_out) *bz_out = best;
+    if (adj_steps_out) *adj_steps_out = best_adj;
     if (ms_out) *ms_out = best_ms;
     return FWI_OK;
 }

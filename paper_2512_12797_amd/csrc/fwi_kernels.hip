@@ -681,15 +681,19 @@ __global__ __launch_bounds__(256) void k_fwd2d2(const StepArgs A)
         cq[i + PF] = bload(rC, coff(z1 + PF));
         pq[i + PF] = bload(rP, coff(z1 + PF));
 
+        // both steps' x rows go to LDS before one wave-scope fence: the second step's row
+        // (first-step row z1 - 4) was computed four iterations ago
+        float *row = rows[wave][i & 1];
+        float *row1 = rows1[wave][i & 1];
+        row[lane + kHalo] = q[i + 4];
+        if (lane < 4)
+            row[lane] = hq[i];
+        else if (lane < 8)
+            row[kTileX + lane] = hq[i];
+        if (i >= 2 * kHalo) row1[lane + kHalo] = s1[i - 4];
+        wave_lds_sync();
         // first step, row z1 (centre q[i + 4])
         {
-            float *row = rows[wave][i & 1];
-            row[lane + kHalo] = q[i + 4];
-            if (lane < 4)
-                row[lane] = hq[i];
-            else if (lane < 8)
-                row[kTileX + lane] = hq[i];
-            wave_lds_sync();
             float lx = wx[0] * q[i + 4];
             lx += wx[1] * (row[lane + 3] + row[lane + 5]);
             lx += wx[2] * (row[lane + 2] + row[lane + 6]);
@@ -731,9 +735,7 @@ __global__ __launch_bounds__(256) void k_fwd2d2(const StepArgs A)
         // second step, row z2 = z1 - 4 (centre s1[i - 4]; u^n there is q[i], c is cq[i - 4])
         if (i >= 2 * kHalo) {
             const int z2 = z1 - kHalo;
-            float *row = rows1[wave][i & 1];
-            row[lane + kHalo] = s1[i - 4];
-            wave_lds_sync();
+            const float *row = row1;
             float lx = wx[0] * s1[i - 4];
             lx += wx[1] * (row[lane + 3] + row[lane + 5]);
             lx += wx[2] * (row[lane + 2] + row[lane + 6]);
@@ -911,14 +913,17 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
             if (i < BZ) wq1[i] = bload(rW, roff(zs + i) + xs);
             if (i >= kHalo && i - kHalo < BZ) wq2[i - kHalo] = bload(rW2, roff(zs + i - kHalo) + xs);
 
+            // both steps' x rows go to LDS before one wave-scope fence
+            float *row = rows[wave][i & 1];
+            float *row1 = rows1[wave][i & 1];
+            row[lane + kHalo] = q[i + 4];
+            if (lane < 4)
+                row[lane] = hq[i];
+            else if (lane < 8)
+                row[kTileX + lane] = hq[i];
+            if (i >= 2 * kHalo) row1[lane + kHalo] = s1[i - 4];
+            wave_lds_sync();
             {
-                float *row = rows[wave][i & 1];
-                row[lane + kHalo] = q[i + 4];
-                if (lane < 4)
-                    row[lane] = hq[i];
-                else if (lane < 8)
-                    row[kTileX + lane] = hq[i];
-                wave_lds_sync();
                 float lx = wx[0] * q[i + 4];
                 lx += wx[1] * (row[lane + 3] + row[lane + 5]);
                 lx += wx[2] * (row[lane + 2] + row[lane + 6]);
@@ -947,9 +952,7 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
             }
             if (i >= 2 * kHalo) {
                 const int z2 = z1 - kHalo;
-                float *row = rows1[wave][i & 1];
-                row[lane + kHalo] = s1[i - 4];
-                wave_lds_sync();
+                const float *row = row1;
                 float lx = wx[0] * s1[i - 4];
                 lx += wx[1] * (row[lane + 3] + row[lane + 5]);
                 lx += wx[2] * (row[lane + 2] + row[lane + 6]);

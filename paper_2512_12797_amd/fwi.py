@@ -81,7 +81,8 @@ def lib():
         L.fwi_graphs_stats.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.fwi_set_tile.argtypes = [C.c_int32, C.c_int32]
         L.fwi_tune.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p, C.c_size_t,
-                               C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+                               C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]
         for name in ("fwi_timing_enable", "fwi_timing_read", "fwi_copy_probe"):
             getattr(L, name).restype = C.c_int32
         L.fwi_timing_enable.argtypes = [C.c_int32]
@@ -326,15 +327,17 @@ def fwi_set_tile(ndim: int, bz: int):
 
 
 def fwi_set_time_blocking(fwd_steps: int, adj_steps: int):
-    """Time steps per launch of the 2D keep-all forward and adjoint sweeps (1 or 2 each;
-    process-wide; default 1 and 2)."""
+    """Time steps per launch of the 2D keep-all forward and adjoint sweeps: 1 or 2 forced,
+    0 automatic (the default: forward 1, adjoint the tuned choice, else 2); process-wide."""
     _ok(lib().fwi_set_time_blocking(fwd_steps, adj_steps))
 
 
 def fwi_tune(batch, time, v, ws, cache_path=None, stream=None):
-    """Returns (tile height, ms per gradient time step)."""
+    """Returns (tile height, adjoint time steps per launch (0: not applicable),
+    ms per gradient time step)."""
     bz = C.c_int32(0)
+    adj = C.c_int32(0)
     ms = C.c_double(0.0)
     _ok(lib().fwi_tune(batch.c, C.byref(time), _ptr(v), _ptr(ws), ws.numel(), _stream(stream),
-                       cache_path.encode() if cache_path else None, C.byref(bz), C.byref(ms)))
-    return bz.value, ms.value
+                       cache_path.encode() if cache_path else None, C.byref(bz), C.byref(adj), C.byref(ms)))
+    return bz.value, adj.value, ms.value

@@ -132,3 +132,28 @@ def test_langevin_argument_checks(F):
                         C.c_float(1.0), C.c_float(2.0), C.c_float(1.0), None)
     assert st == F.FWI_E_ARG
     assert F.lib().fwi_status_string(F.FWI_E_CFL)
+
+
+def test_time_blocking_values(F):
+    # 0 (automatic), 1 or 2 time steps per launch for each sweep; anything else is rejected
+    # on the host
+    for bad in ((3, 0), (0, 3), (-1, 1), (1, -1)):
+        expect(F, F.FWI_E_ARG, F.fwi_set_time_blocking, *bad)
+    for ok in ((1, 1), (2, 2), (1, 2), (2, 1), (0, 0)):
+        F.fwi_set_time_blocking(*ok)
+
+
+def test_workspace_independent_of_time_blocking(F):
+    # 2D always reserves four field levels and the two-step strip tables, so a workspace
+    # sized under one setting serves every other
+    g, rec, wav = small(F)
+    b = F.Batch([g], [0], [([31], [1.0])], [rec], wav)
+    t = F.time_axis(1e-3, 100, 2, 0)
+    sizes = set()
+    try:
+        for mode in ((1, 1), (2, 2), (1, 2), (0, 0)):
+            F.fwi_set_time_blocking(*mode)
+            sizes.add(F.fwi_workspace_size(b, t))
+    finally:
+        F.fwi_set_time_blocking(0, 0)
+    assert len(sizes) == 1

@@ -334,7 +334,7 @@ def test_results_identical_for_every_tile_height(F, ndim):
                 outs.append(_run(F, batch, time, v, dobs, [g[2] for g in groups], ws))
         finally:
             F.fwi_set_tile(ndim, 0)
-            F.fwi_set_time_blocking(1, 2)
+            F.fwi_set_time_blocking(0, 0)
         for o in outs[1:]:
             for a, b in zip(o, outs[0]):
                 assert np.array_equal(a, b)
@@ -346,13 +346,14 @@ def test_tuner_and_cache(F, tmp_path):
     v = dev(np.concatenate(models))
     ws = F.alloc_workspace(batch, time)
     path = str(tmp_path / "tune.json")
-    bz, ms = F.fwi_tune(batch, time, v, ws, path)
-    say("  tuned bz %d, %.4f ms per gradient step" % (bz, ms))
+    bz, adj, ms = F.fwi_tune(batch, time, v, ws, path)
+    say("  tuned bz %d, adjoint steps per launch %d, %.4f ms per gradient step" % (bz, adj, ms))
     assert bz in ((8, 16, 32) if batch.grids[0].ndim == 2 else (16, 32)) and ms > 0
+    assert adj in (1, 2)  # 2D keep-all: both adjoints are candidates
     lines = open(path).read().strip().splitlines()
-    assert len(lines) == 1 and '"bz": %d' % bz in lines[0]
-    bz2, ms2 = F.fwi_tune(batch, time, v, ws, path)  # read back, no new line
-    assert bz2 == bz and abs(ms2 - ms) < 1e-5
+    assert len(lines) == 1 and '"bz": %d' % bz in lines[0] and '"adj_steps": %d' % adj in lines[0]
+    bz2, adj2, ms2 = F.fwi_tune(batch, time, v, ws, path)  # read back, no new line
+    assert bz2 == bz and adj2 == adj and abs(ms2 - ms) < 1e-5
     assert len(open(path).read().strip().splitlines()) == 1
     # the tuned choice is used and the result is still the oracle's
     nd = batch.data_size(time.nt // 2)
