@@ -257,8 +257,9 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
                     const char *cache_path, int32_t *bz_out, int32_t *adj_steps_out, double *ms_out);
 
 /*
- * Time steps per launch of the 2D keep-all schedule (ckpt_every 0 or -1), process-wide, for
- * the forward sweep (fwd_steps) and the adjoint sweep (adj_steps).  Each is 1 or 2 (forced),
+ * Time steps per launch of the 2D sweeps, process-wide: the forward sweep of the keep-all
+ * schedule (fwd_steps; ckpt_every 0 or -1) and the adjoint sweep of either schedule
+ * (adj_steps; with checkpoints, within each recomputed segment).  Each is 1 or 2 (forced),
  * or 0 (automatic, the default).  Automatic means one forward step per launch, and for the
  * adjoint the choice fwi_tune made for the batch shape, else two steps per launch.
  *
@@ -270,8 +271,9 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
  * The data and the imaging operands are bit-identical to those of one step per launch.
  * The per-sample gradient sums the same FP64 products in another order.
  *
- * An odd last step is launched alone.  3D and checkpointed schedules always take one step
- * per launch.  The setting applies to calls that start after it.  A captured graph keeps
+ * An odd last step (of the sweep, or of a segment) is launched alone.  3D takes one step
+ * per launch, and so does the recomputation of a checkpointed forward.  The setting applies
+ * to calls that start after it.  A captured graph keeps
  * the setting it was captured with (the graph key includes it).  Returns FWI_E_ARG for
  * other values.
  */

@@ -604,17 +604,19 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.K = p.fwd_only ? 0 : t->ckpt_every;
     if (p.K > t->nt) p.K = t->nt;
     p.nseg = p.K > 0 ? (t->nt + p.K - 1) / p.K : 1;
-    p.nlev = (p.K > 0 || p.ndim == 2) ? 4 : 2;
+    // levels: 2 (u^n, u^{n-1} updated in place), 4 with checkpoints (recomputation and
+    // adjoint), and in 2D two more for the output levels of two-step launches
+    p.nlev = (p.K > 0 ? 4 : 2) + (p.ndim == 2 ? 2 : 0);
     {
         int fwd = g_blocking_fwd.load(), adj = g_blocking_adj.load();
-        if (p.ndim == 2 && p.K == 0 && adj == 0) {
+        if (p.ndim == 2 && adj == 0) {
             const std::string sig = shape_signature(b);
             std::lock_guard<std::mutex> lk(g_tiles.m);
             for (auto &e : g_tiles.tuned)
                 if (e.sig == sig) adj = e.adj;
         }
         p.two = p.ndim == 2 && p.K == 0 && fwd == 2;
-        p.two_adj = p.ndim == 2 && p.K == 0 && (adj == 2 || adj == 0);
+        p.two_adj = p.ndim == 2 && (adj == 2 || adj == 0);
     }
     p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.K : t->nt);
     p.ck_slots = p.K > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
@@ -899,7 +901,7 @@ struct Dev {
     const int32_t *evvec;
     const SrcPos *src;
     float *cf;
-    float *lev[4];
+    float *lev[6];
     float *wst;
     float *ck;
     double *gacc;
@@ -925,7 +927,7 @@ Dev carve(const Plan &p, void *ws)
     d.evvec = (const int32_t *)(tb + p.t_evvec);
     d.src = (const SrcPos *)(tb + p.t_src);
     d.cf = (float *)(d.base + p.o_cf);
-    for (int l = 0; l < 4; ++l) d.lev[l] = l < p.nlev ? (float *)(d.base + p.o_fields) + (size_t)l * p.cells : nullptr;
+    for (int l = 0; l < 6; ++l) d.lev[l] = l < p.nlev ? (float *)(d.base + p.o_fields) + (size_t)l * p.cells : nullptr;
     d.wst = (float *)(d.base + p.o_wst);
     d.ck = (float *)(d.base + p.o_ck);
     d.gacc = (double *)(d.base + p.o_gacc);
@@ -1070,54 +1072,63 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
     a.rho = rho;
     a.gacc = d.gacc;
     float *lcur = L0, *lprev = L1;
+    auto slot = [&](int k) { return k % t->rec_every == 0 ? k / t->rec_every - 1 : -1; };
     auto adj_step = [&](int k, const float *wimg) -> fwi_status {
         a.cur = lcur;
         a.prev = lprev;
         a.next = lprev;
         a.wimg = wimg;
-        a.rec_j = k % t->rec_every == 0 ? k / t->rec_every - 1 : -1;
+        a.rec_j = slot(k);
         HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.ty, st));
         std::swap(lcur, lprev);
         return FWI_OK;
     };
+    // two steps per launch: lt^{k+2}, lt^{k+1} in; lt^k, lt^{k-1} out to the two spare
+    // levels (the last two of the 2D plan)
+    StepArgs a2 = base_args2(p, d);
+    a2.rho = rho;
+    a2.gacc = d.gacc;
+    float *spare[2] = {p.ndim == 2 ? d.lev[p.nlev - 2] : nullptr, p.ndim == 2 ? d.lev[p.nlev - 1] : nullptr};
     RunTimer tm;
-    if (p.K == 0) {
-        HIP_TRY(tm.begin(1, st));
-        int k = t->nt;
-        if (p.two_adj) {
-            // steps k and k-1 per launch (lt^{k+2}, lt^{k+1} in; lt^k, lt^{k-1} out to the
-            // other two levels); an odd last step runs alone below
-            StepArgs a2 = base_args2(p, d);
-            a2.rho = rho;
-            a2.gacc = d.gacc;
-            float *other[2] = {d.lev[2], d.lev[3]};
+    // adjoint steps k = hi .. lo + 1, imaging with W^{k-1} at wimg(k)
+    auto sweep = [&](int hi, int lo, auto wimg) -> fwi_status {
+        int k = hi;
+        if (p.two_adj && hi - lo >= 2) {
+            HIP_TRY(tm.begin(1, st));
             int64_t launches = 0;
-            for (; k >= 2; k -= 2) {
+            for (; k - 1 >= lo + 1; k -= 2) {
                 a2.cur = lcur;
                 a2.prev = lprev;
-                a2.next = other[0];
-                a2.next2 = other[1];
-                a2.wimg = d.wst + (size_t)(k - 1) * p.cells;
-                a2.wimg2 = d.wst + (size_t)(k - 2) * p.cells;
-                a2.rec_j = k % t->rec_every == 0 ? k / t->rec_every - 1 : -1;
-                a2.rec_j2 = (k - 1) % t->rec_every == 0 ? (k - 1) / t->rec_every - 1 : -1;
+                a2.next = spare[0];
+                a2.next2 = spare[1];
+                a2.wimg = wimg(k);
+                a2.wimg2 = wimg(k - 1);
+                a2.rec_j = slot(k);
+                a2.rec_j2 = slot(k - 1);
                 HIP_TRY(launch_step2(a2, true, st));
                 float *op = lprev, *oc = lcur;
-                lprev = other[0];
-                lcur = other[1];
-                other[0] = op;
-                other[1] = oc;
+                lprev = spare[0];
+                lcur = spare[1];
+                spare[0] = op;
+                spare[1] = oc;
                 ++launches;
             }
             HIP_TRY(tm.end(launches));
-            if (k >= 1) HIP_TRY(tm.begin(1, st));
         }
-        const int k_single = k;
-        for (; k >= 1; --k) {
-            fwi_status s = adj_step(k, d.wst + (size_t)(k - 1) * p.cells);
-            if (s) return s;
+        if (k >= lo + 1) {  // one step per launch (or an odd last step)
+            const int n1 = k - lo;
+            HIP_TRY(tm.begin(1, st));
+            for (; k >= lo + 1; --k) {
+                fwi_status s = adj_step(k, wimg(k));
+                if (s) return s;
+            }
+            HIP_TRY(tm.end(n1));
         }
-        if (!p.two_adj || k_single >= 1) HIP_TRY(tm.end(k_single));
+        return FWI_OK;
+    };
+    if (p.K == 0) {
+        fwi_status s = sweep(t->nt, 0, [&](int k) { return (const float *)(d.wst + (size_t)(k - 1) * p.cells); });
+        if (s) return s;
     } else {
         float *P0 = d.lev[0], *P1 = d.lev[1];
         StepArgs f = base_args(p, d);
@@ -1149,12 +1160,9 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
                 cur = next;
             }
             HIP_TRY(tm.end(ne - ns));
-            HIP_TRY(tm.begin(1, st));
-            for (int k = ne; k >= ns + 1; --k) {
-                fwi_status s = adj_step(k, d.wst + (size_t)(k - 1 - ns) * p.cells);
-                if (s) return s;
-            }
-            HIP_TRY(tm.end(ne - ns));
+            fwi_status s =
+                sweep(ne, ns, [&](int k) { return (const float *)(d.wst + (size_t)(k - 1 - ns) * p.cells); });
+            if (s) return s;
         }
     }
     HIP_TRY(launch_finalize(d.samples, d.sims, b->nsample, d.gacc, v, grad, d.npart, p.nchunk_fin, d.status, st));
@@ -1438,7 +1446,7 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
     hipStream_t st = (hipStream_t)stream;
     const std::string sig = shape_signature(b);
     // the two-step adjoint is a candidate for 2D keep-all schedules of at least two steps
-    const bool try_two = p0.ndim == 2 && p0.K == 0 && !p0.fwd_only && t->nt >= 2;
+    const bool try_two = p0.ndim == 2 && !p0.fwd_only && t->nt >= 2;
     // a recorded choice for this shape wins
     if (cache_path && *cache_path) {
         FILE *f = fopen(cache_path, "r");

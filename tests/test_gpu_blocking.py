@@ -39,7 +39,7 @@ def dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def strip_edge_problem(F, nt, R):
+def strip_edge_problem(F, nt, R, ckpt=0):
     """Two samples (one and three supergathers) on grids whose padded sizes are not
     multiples of the 56 x 16 strips.  Sources and receivers sit on the columns and rows
     where strips meet and inside the 4-cell margins the first step also computes,
@@ -66,7 +66,7 @@ def strip_edge_problem(F, nt, R):
     rec1 = np.array(rec1, dtype=np.int32)
     wav = W.ricker(20.0, 1e-3, nt)
     batch = F.Batch([g0, g1], [0, 1, 1, 1], s0 + s1, [rec0, rec1, rec1, rec1], wav)
-    time = F.time_axis(1e-3, nt, R, 0)
+    time = F.time_axis(1e-3, nt, R, ckpt)
     return batch, time, [m0, m1]
 
 
@@ -83,10 +83,12 @@ def run(F, blocking, batch, time, models, dobs, kappa, is2=2.0):
     return dpred.cpu().numpy(), mis.cpu().numpy(), grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("nt,R", [(160, 2), (161, 1), (99, 3)])
-def test_two_steps_equal_one_step(F, nt, R):
-    say("case two steps per launch vs one, nt=%d rec_every=%d" % (nt, R))
-    batch, time, models = strip_edge_problem(F, nt, R)
+# keep-all (even and odd nt) and checkpointed schedules (odd segments, a short last one):
+# with checkpoints the adjoint of every recomputed segment runs in pairs plus an odd step
+@pytest.mark.parametrize("nt,R,ckpt", [(160, 2, 0), (161, 1, 0), (99, 3, 0), (100, 2, 7), (99, 3, 10)])
+def test_two_steps_equal_one_step(F, nt, R, ckpt):
+    say("case two steps per launch vs one, nt=%d rec_every=%d ckpt_every=%d" % (nt, R, ckpt))
+    batch, time, models = strip_edge_problem(F, nt, R, ckpt)
     nd = batch.data_size(nt // R)
     dobs = 1e-4 * np.random.default_rng(nt).standard_normal(nd)
     kappa = [1.25, 0.5]
