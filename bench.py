@@ -497,9 +497,9 @@ def main():
     # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
     # 16 B per simulation cell (12 B when recomputing from checkpoints without a store),
     # plus c once per sample cell.
-    # with checkpoints the forward sweeps (first pass: 12 B; recomputation: 16 B) average
-    # to 14 B per simulation cell
-    fwd_bytes = pad_cells * (16 if ckpt == 0 else 14) + samp_cells * 4
+    # with checkpoints the forward sweeps (first pass: 12 B plus a checkpoint pair every K
+    # steps, 8/K B; recomputation: 16 B) average to 14 + 4/K B per simulation cell
+    fwd_bytes = pad_cells * (16 if ckpt == 0 else 14 + 4.0 / ckpt) + samp_cells * 4
     # adjoint + imaging: lt^{k+1}, lt^{k+2}, W^{k-1} read and lt^k written per simulation
     # cell; c read and the FP64 per-sample accumulator read + written per sample cell
     adj_bytes = pad_cells * 16 + samp_cells * 20
@@ -581,7 +581,7 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+                     "bytes_per_launch": int(round(nbytes)), "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
                      "copy_probe_GBs": round(copy_gbs, 1)},
     }
     if not args.no_cpu_baseline:
