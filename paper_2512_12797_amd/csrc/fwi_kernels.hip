@@ -242,9 +242,8 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
     const uint32_t ho = 4u * (uint32_t)min(max(hx, 0), Nx - 1);
     const uint32_t rowb = 4u * (uint32_t)Nx;
     auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
-    // wavefield reads and stores: lanes past the x edge (or not halo lanes) carry the
-    // poison bit, so they read 0 and drop their stores; point operands read the clamped
-    // column
+    // wavefield and point-operand reads and the stores: lanes past the x edge (or not halo
+    // lanes) carry the poison bit, so they read 0 (fetching nothing) and drop their stores
     const uint32_t xb = xin ? xo : kPoison, hb = hl ? ho : kPoison;
     auto coff = [&](int zz) -> uint32_t { return roff(zz) + xb; };
     auto hoff = [&](int zz) -> uint32_t { return roff(zz) + hb; };
@@ -256,8 +255,8 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
     for (int k = 0; k < PF; ++k) {
         const uint32_t o = roff(z0 + k);
         hq[k] = bload(rU, hoff(z0 + k));
-        cq[k] = bload(rC, o + xo);
-        pq[k] = bload(rP, o + xo);
+        cq[k] = bload(rC, o + xb);
+        pq[k] = bload(rP, o + xb);
     }
     // receiver event rows of this tile, kept in scalar registers (one row per z)
     const bool rec = rec_j >= 0 && T.ev_cnt > 0;
@@ -272,8 +271,8 @@ __global__ __launch_bounds__(256) void k_fwd2d(const StepArgs A)
         q[r + 12] = bload(rU, coff(z + 8));
         const uint32_t of = roff(z + PF);
         hq[r + PF] = bload(rU, hoff(z + PF));
-        cq[r + PF] = bload(rC, of + xo);
-        pq[r + PF] = bload(rP, of + xo);
+        cq[r + PF] = bload(rC, of + xb);
+        pq[r + PF] = bload(rP, of + xb);
 
         float *row = rows[wave][r & 1];
         row[lane + kHalo] = q[r + 4];
@@ -909,9 +908,10 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
             cq[i + PF] = bload(rC, coff(z1 + PF));
             pq[i + PF] = bload(rP, coff(z1 + PF));
             // W^{k-1} of own row z0 + r is used at i = r + 4, W^{k-2} at i = r + 8: both are
-            // fetched 4 rows ahead (point operands: the clamped column)
-            if (i < BZ) wq1[i] = bload(rW, roff(zs + i) + xs);
-            if (i >= kHalo && i - kHalo < BZ) wq2[i - kHalo] = bload(rW2, roff(zs + i - kHalo) + xs);
+            // fetched 4 rows ahead, by the strip's own lanes only (the margin lanes' products
+            // are never used, so their loads are poisoned and fetch nothing)
+            if (i < BZ) wq1[i] = bload(rW, roff(zs + i) + sb);
+            if (i >= kHalo && i - kHalo < BZ) wq2[i - kHalo] = bload(rW2, roff(zs + i - kHalo) + sb);
 
             // both steps' x rows go to LDS before one wave-scope fence
             float *row = rows[wave][i & 1];
