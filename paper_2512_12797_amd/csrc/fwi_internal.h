@@ -117,12 +117,12 @@ struct StepArgs {
     float fn;               // wavelet sample f[n] (forward)
     int32_t rec_j2;         // two steps: slot of the second step, or -1
     float fn2;              // two steps: f[n+1]
-    // 2D adjoint with per-sample imaging
+    // adjoint with per-sample imaging (2D strips; 3D tiles)
     const SampleDesc *samples;
     const GTile *gtiles;
     int32_t ngtiles;
     int32_t per_xcd_g;      // grouped tiles per XCD chunk
-    int32_t nw;             // wavefronts per grouped workgroup (1..16)
+    int32_t nw;             // wavefronts per grouped workgroup (1..16; two steps: 1..8)
     int32_t bzg;            // rows per grouped tile (8 or 16)
 };
 

@@ -567,7 +567,7 @@ __device__ __forceinline__ float src_term(const StepArgs &A, const LaneSrc &src,
 
 constexpr int kNoRow = -(1 << 30);  // event cursor past its last row
 // Rows fetched ahead by the two-step sweeps.  The two-step forward runs at the same speed
-// with 4, 6 or 8 (it is bound by instruction issue and LDS round trips, not by memory
+// with 4, 6 or 8 (at its occupancy it is limited by instruction issue, not by memory
 // latency), and deeper queues only cost registers.
 constexpr int kPf2 = 4;
 
