@@ -173,6 +173,7 @@ struct Plan {
     std::vector<EvRow> evrows;
     std::vector<int32_t> evvec;
     std::vector<SrcPos> src;
+    std::vector<int32_t> order;  // 3D forward launch order (tile indices)
     int64_t cells = 0;       // one field level, all sims
     int64_t coefs = 0;       // all samples' padded cells
     int64_t data = 0;        // all sims' data
@@ -188,7 +189,7 @@ struct Plan {
     int64_t wst_levels = 0, ck_slots = 0;
     int nchunk_res = 1, nchunk_fin = 1;
     size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_gtiles = 0, t_tiles2 = 0, t_gtiles2 = 0, t_evrows = 0,
-           t_evvec = 0, t_src = 0, t_bytes = 0;
+           t_evvec = 0, t_src = 0, t_order = 0, t_bytes = 0;
     size_t t_alloc = 0;  // table region reserved in the workspace (largest over tile heights)
     size_t o_status = 0, o_tables = 0, o_cf = 0, o_fields = 0, o_wst = 0, o_ck = 0, o_gacc = 0, o_rho = 0,
            o_part = 0, o_npart = 0, o_mis = 0, total = 0;
@@ -329,6 +330,12 @@ int grouped_waves(int g, int64_t ngt)
     int w = std::min(g, 4);
     while (w < std::min(g, 16) && ngt * w < 256 * 24) ++w;
     return w;
+}
+
+// index one past the last tile of sim s (its tiles are contiguous, sims in order)
+int s_tiles_end(const Plan &p, int s)
+{
+    return s + 1 < (int)p.sims.size() ? p.sims[s + 1].tile0 : (int)p.tiles.size();
 }
 
 fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p, int bz_override = 0,
@@ -507,6 +514,21 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     }
     if (p.tiles.size() >= (size_t)1 << 30 || p.tiles2.size() >= (size_t)1 << 30)
         return fail(FWI_E_UNSUPPORTED, "too many tiles");
+    if (p.ndim == 3) {
+        // forward launch order: sample by sample, tile position by position, the sample's
+        // sims (which share its geometry and coefficient grid) next to each other
+        p.order.reserve(p.tiles.size());
+        for (int k = 0; k < b->nsample; ++k) {
+            std::vector<int> sims_k;
+            for (int s = 0; s < b->nsim; ++s)
+                if (b->sample_of[s] == k) sims_k.push_back(s);
+            if (sims_k.empty()) continue;
+            const int per_sim = (s_tiles_end(p, sims_k[0]) - p.sims[sims_k[0]].tile0);
+            for (int i = 0; i < per_sim; ++i)
+                for (int s : sims_k) p.order.push_back(p.sims[s].tile0 + i);
+        }
+        if (p.order.size() != p.tiles.size()) return fail(FWI_E_ARG, "internal: tile order incomplete");
+    }
     // imaging accumulators: one per sample, laid out like the coefficients (an adjoint
     // workgroup sweeps its strip or tile for every sim of the sample)
     p.grouped = true;
@@ -591,6 +613,8 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     o = align_up(o + std::max<size_t>(1, p.evvec.size()) * sizeof(int32_t));
     p.t_src = o;
     o = align_up(o + std::max<size_t>(1, p.src.size()) * sizeof(SrcPos));
+    p.t_order = o;
+    o = align_up(o + std::max<size_t>(1, p.order.size()) * sizeof(int32_t));
     p.t_bytes = o;
     p.t_alloc = o;
     if (size_for_all_tiles) {
@@ -694,6 +718,7 @@ fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
     if (!p.evrows.empty()) memcpy(h + p.t_evrows, p.evrows.data(), p.evrows.size() * sizeof(EvRow));
     if (!p.evvec.empty()) memcpy(h + p.t_evvec, p.evvec.data(), p.evvec.size() * sizeof(int32_t));
     if (!p.src.empty()) memcpy(h + p.t_src, p.src.data(), p.src.size() * sizeof(SrcPos));
+    if (!p.order.empty()) memcpy(h + p.t_order, p.order.data(), p.order.size() * sizeof(int32_t));
     HIP_TRY(hipMemcpyAsync(dst, h, p.t_bytes, hipMemcpyHostToDevice, st));
     if (!g_stage.ev) HIP_TRY(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(g_stage.ev, st));
@@ -830,7 +855,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
     const size_t nt = p.tiles.size();
     k.add(nt);
     const size_t offs[] = {p.t_sims, p.t_samples, p.t_tiles, p.t_gtiles, p.t_tiles2, p.t_gtiles2, p.t_evrows,
-                           p.t_evvec, p.t_src, p.t_bytes,
+                           p.t_evvec, p.t_src, p.t_order, p.t_bytes,
                            p.o_status, p.o_tables, p.o_cf, p.o_fields, p.o_wst, p.o_ck, p.o_gacc, p.o_rho,
                            p.o_part, p.o_npart, p.o_mis, p.total};
     k.bytes(offs, sizeof offs);
@@ -900,6 +925,7 @@ struct Dev {
     const EvRow *evrows;
     const int32_t *evvec;
     const SrcPos *src;
+    const int32_t *order;
     float *cf;
     float *lev[6];
     float *wst;
@@ -926,6 +952,7 @@ Dev carve(const Plan &p, void *ws)
     d.evrows = (const EvRow *)(tb + p.t_evrows);
     d.evvec = (const int32_t *)(tb + p.t_evvec);
     d.src = (const SrcPos *)(tb + p.t_src);
+    d.order = p.order.empty() ? nullptr : (const int32_t *)(tb + p.t_order);
     d.cf = (float *)(d.base + p.o_cf);
     for (int l = 0; l < 6; ++l) d.lev[l] = l < p.nlev ? (float *)(d.base + p.o_fields) + (size_t)l * p.cells : nullptr;
     d.wst = (float *)(d.base + p.o_wst);
@@ -947,6 +974,7 @@ StepArgs base_args(const Plan &p, const Dev &d)
     a.evrows = d.evrows;
     a.evvec = d.evvec;
     a.src = d.src;
+    a.order = d.order;
     a.cf = d.cf;
     a.ntiles = (int32_t)p.tiles.size();
     a.per_xcd = p.per_xcd;

@@ -97,6 +97,7 @@ struct StepArgs {
     const EvRow *evrows;
     const int32_t *evvec;
     const SrcPos *src;
+    const int32_t *order;   // 3D forward: launch slot -> tile (nullable: identity)
     const float *cur;       // u^n (or lt^{k+1})
     const float *prev;      // u^{n-1} (or lt^{k+2})
     float *next;            // u^{n+1} (or lt^k); may alias prev (one step per launch)

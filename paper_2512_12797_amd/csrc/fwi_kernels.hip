@@ -1207,8 +1207,11 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
 template <int BZ>
 __global__ __launch_bounds__(64 * kTileY3) void k_fwd3d(const StepArgs A)
 {
-    const int t = xcd_tile(blockIdx.x, A.per_xcd);
-    if (t >= A.ntiles) return;  // uniform per block
+    const int slot = xcd_tile(blockIdx.x, A.per_xcd);
+    if (slot >= A.ntiles) return;  // uniform per block
+    // the launch order takes a sample's supergathers at one tile position in a row, so
+    // that the sample's coefficient grid is read from L2 by all but the first of them
+    const int t = A.order ? A.order[slot] : slot;
     const Tile T = A.tiles[t];
     const SimDesc &S = A.sims[T.sim];
     __shared__ Plane3 P;
