@@ -515,8 +515,12 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     if (p.tiles.size() >= (size_t)1 << 30 || p.tiles2.size() >= (size_t)1 << 30)
         return fail(FWI_E_UNSUPPORTED, "too many tiles");
     if (p.ndim == 3) {
-        // forward launch order: sample by sample, tile position by position, the sample's
-        // sims (which share its geometry and coefficient grid) next to each other
+        // forward launch order: sample by sample, in groups of up to kGroup of its sims
+        // (which share its geometry and coefficient grid), tile position by position with
+        // the group's sims next to each other.  Small groups keep the tiles that neighbour
+        // one another in y a few launch slots apart, so they run together and share their
+        // halo rows in L2 as well.
+        constexpr size_t kGroup = 4;
         p.order.reserve(p.tiles.size());
         for (int k = 0; k < b->nsample; ++k) {
             std::vector<int> sims_k;
@@ -524,8 +528,11 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
                 if (b->sample_of[s] == k) sims_k.push_back(s);
             if (sims_k.empty()) continue;
             const int per_sim = (s_tiles_end(p, sims_k[0]) - p.sims[sims_k[0]].tile0);
-            for (int i = 0; i < per_sim; ++i)
-                for (int s : sims_k) p.order.push_back(p.sims[s].tile0 + i);
+            for (size_t g0 = 0; g0 < sims_k.size(); g0 += kGroup) {
+                const size_t g1 = std::min(sims_k.size(), g0 + kGroup);
+                for (int i = 0; i < per_sim; ++i)
+                    for (size_t g = g0; g < g1; ++g) p.order.push_back(p.sims[sims_k[g]].tile0 + i);
+            }
         }
         if (p.order.size() != p.tiles.size()) return fail(FWI_E_ARG, "internal: tile order incomplete");
     }
