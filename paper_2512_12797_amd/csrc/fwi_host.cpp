@@ -169,7 +169,7 @@ struct Plan {
     std::vector<GTile> gtiles2;
     bool two = false;        // keep-all 2D schedule: forward with two steps per launch
     bool two_adj = false;    // and the adjoint
-    int per_xcd2 = 0, per_xcd_g2 = 0, nw2 = 1;
+    int per_xcd2 = 0, per_xcd_g2 = 0, nw2 = 1, sg2 = 1;
     std::vector<EvRow> evrows;
     std::vector<int32_t> evvec;
     std::vector<SrcPos> src;
@@ -597,7 +597,15 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         // (on the 16-sample x 10-supergather workload 4 waves measured faster than 2, 5 or 8:
         // 90.9 vs 108.9 / 121.6 / 125.7 us per two-step launch)
         p.nw2 = std::min(grouped_waves(gmax, (int64_t)p.gtiles2.size()), 8);
-        p.per_xcd_g2 = (int)((p.gtiles2.size() + 7) / 8);
+        // two strips per workgroup (half the waves on each) when that splits the largest
+        // sample's sims more evenly over its waves: 10 sims on 4 waves run 3 + 3 + 2 + 2,
+        // two idle waves waiting at the reduction; on 2 waves per strip, 5 + 5
+        p.sg2 = 1;
+        if (p.nw2 % 2 == 0) {
+            auto idle = [&](int w) { return (gmax + w - 1) / w * w - gmax; };
+            if (idle(p.nw2 / 2) < idle(p.nw2)) p.sg2 = 2;
+        }
+        p.per_xcd_g2 = (int)(((p.gtiles2.size() + p.sg2 - 1) / p.sg2 + 7) / 8);
         p.per_xcd2 = (int)(((p.tiles2.size() + 3) / 4 + 7) / 8);
     }
     // table layout
@@ -855,7 +863,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
     k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
     k.add(p.nchunk_res); k.add(p.nchunk_fin);
     k.add(p.grouped); k.add(p.bzg); k.add(p.nw); k.add(p.per_xcd_g); k.add(p.gcells);
-    k.add(p.two); k.add(p.two_adj); k.add(p.nw2); k.add(p.per_xcd2); k.add(p.per_xcd_g2);
+    k.add(p.two); k.add(p.two_adj); k.add(p.nw2); k.add(p.sg2); k.add(p.per_xcd2); k.add(p.per_xcd_g2);
     k.add(p.tiles2.size()); k.add(p.gtiles2.size());
     const size_t ngt = p.gtiles.size();
     k.add(ngt);
@@ -1007,6 +1015,7 @@ StepArgs base_args2(const Plan &p, const Dev &d)
     a.ngtiles = (int32_t)p.gtiles2.size();
     a.per_xcd_g = p.per_xcd_g2;
     a.nw = p.nw2;
+    a.sg = p.sg2;
     a.rec_j2 = -1;
     return a;
 }

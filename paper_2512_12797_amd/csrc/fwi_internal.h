@@ -125,6 +125,7 @@ struct StepArgs {
     int32_t per_xcd_g;      // grouped tiles per XCD chunk
     int32_t nw;             // wavefronts per grouped workgroup (1..16; two steps: 1..8)
     int32_t bzg;            // rows per grouped tile (8 or 16)
+    int32_t sg;             // two-step 2D adjoint: strips per workgroup (1 or 2)
 };
 
 }  // namespace fwi

@@ -765,22 +765,29 @@ __global__ __launch_bounds__(256) void k_fwd2d2(const StepArgs A)
 }
 
 // Adjoint steps k and k - 1 with the per-sample imaging sum, in one sweep.  A workgroup of
-// nw wavefronts owns one strip of a sample's grid (lanes as in the forward above); wave w
-// sweeps it for the sample's sims w, w + nw, ...  The first step (lt^k, residual slot of
-// step k injected on every lane and row it computes, margins included) and the second
-// (lt^{k-1}) add the exact FP64 products lt^k W^{k-1} and lt^{k-1} W^{k-2} of the strip's
-// own cells into registers; the waves' sums are then added in wave order through LDS and
-// wave 0 applies one read-modify-write of the sample's accumulator per two steps.
+// nw wavefronts owns sg (1 or 2) consecutive strips of the samples' grids (lanes as in the
+// forward above), nw / sg wavefronts per strip; local wave l of a strip sweeps it for the
+// strip's sample's sims l, l + nw / sg, ...  (Two strips per workgroup balance the waves
+// when a sample's sim count divides by nw / sg but not by nw.)  The first step (lt^k,
+// residual slot of step k injected on every lane and row it computes, margins included)
+// and the second (lt^{k-1}) add the exact FP64 products lt^k W^{k-1} and lt^{k-1} W^{k-2}
+// of the strip's own cells into registers; each strip's wave sums are then added in wave
+// order through LDS and its first wave applies one read-modify-write of the sample's
+// accumulator per two steps.
 template <int BZ, int PF>
 __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
 {
     constexpr int R1 = BZ + 2 * kHalo;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int gt = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd_g));
-    if (gt >= A.ngtiles) return;  // uniform per block: nobody reaches the barriers below
-    const int nw = A.nw;
-    const GTile G = A.gtiles[gt];
+    const int nw = A.nw, sg = A.sg;
+    const int wps = nw / sg;                 // waves per strip
+    const int sidx = wave / wps, wl = wave - sidx * wps;  // this wave's strip, its rank there
+    const int gt0 = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, A.per_xcd_g) * sg);
+    if (gt0 >= A.ngtiles) return;  // uniform per block: nobody reaches the barriers below
+    const int gt = gt0 + sidx;
+    const bool active = gt < A.ngtiles;  // uniform per wave; inactive waves only join the barriers
+    const GTile G = A.gtiles[active ? gt : gt0];
     const SampleDesc &Sm = A.samples[G.sample];
     const int Nx = Sm.N[2], Nz = Sm.N[0];
     const int nz_phys = Sm.n[0], nx_phys = Sm.n[2], nb = Sm.nb;
@@ -817,16 +824,16 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
 
     __shared__ float rows[8][2][kTileX + 2 * kHalo];
     __shared__ float rows1[8][2][kTileX + 2 * kHalo];
-    __shared__ double red[BZ][kTileX];
-    __shared__ float2 abt[R1][kTileX];  // leapfrog a, b of the first step's cells
+    __shared__ double red[2][BZ][kTileX];
+    __shared__ float2 abt[2][R1][kTileX];  // leapfrog a, b of each strip's first-step cells
 
-    for (int r = wave; r < R1; r += nw) {
+    for (int r = wl; r < R1 && active; r += wps) {
         double gam = 0.0;
         gam = gam + sponge_axis(z0 - kHalo + r, nz_phys, nb, gmz);
         gam = gam + gx;
         float a, b;
         sponge_ab(gam, dt, a, b);
-        abt[r][lane] = make_float2(a, b);
+        abt[sidx][r][lane] = make_float2(a, b);
     }
     if (lane < 2 * kHalo) {
         const int m = lane < kHalo ? lane : kTileX + lane;
@@ -839,7 +846,7 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
 #pragma unroll
     for (int r = 0; r < BZ; ++r) acc[r] = 0.0;
 
-    for (int j = wave; j < sim_cnt; j += nw) {
+    for (int j = wl; j < sim_cnt && active; j += wps) {
         const int sim = sim_beg + j;
         const int64_t u_off = u_off0 + (int64_t)j * ncell;
         const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
@@ -935,7 +942,7 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
                 lz += wz[3] * (q[i + 1] + q[i + 7]);
                 lz += wz[4] * (q[i + 0] + q[i + 8]);
                 float wv = lz + lx;
-                const float2 ab = abt[i][lane];
+                const float2 ab = abt[sidx][i][lane];
                 if (z1 == ez1) {  // uniform
                     const int rid = evvec[eo1 + lane];
                     if (rid >= 0 && Rho1) wv += Rho1[rid];
@@ -964,7 +971,7 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
                 lz += wz[3] * (s1[i - 7] + s1[i - 1]);
                 lz += wz[4] * (s1[i - 8] + s1[i - 0]);
                 float wv = lz + lx;
-                const float2 ab = abt[i - kHalo][lane];
+                const float2 ab = abt[sidx][i - kHalo][lane];
                 if (z2 == ez2) {  // uniform
                     const int rid = evvec[eo2 + lane];
                     if (rid >= 0 && Rho2) wv += Rho2[rid];
@@ -980,17 +987,18 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
         }
     }
 
-    for (int w = 1; w < nw; ++w) {
+    // each strip's wave sums, in wave order (every wave joins every barrier)
+    for (int w = 1; w < wps; ++w) {
         __syncthreads();
-        if (wave == w)
+        if (wl == w)
 #pragma unroll
-            for (int r = 0; r < BZ; ++r) red[r][lane] = acc[r];
+            for (int r = 0; r < BZ; ++r) red[sidx][r][lane] = acc[r];
         __syncthreads();
-        if (wave == 0)
+        if (wl == 0)
 #pragma unroll
-            for (int r = 0; r < BZ; ++r) acc[r] += red[r][lane];
+            for (int r = 0; r < BZ; ++r) acc[r] += red[sidx][r][lane];
     }
-    if (wave == 0) {
+    if (wl == 0 && active) {
         const rsrc_t rG = make_rsrc(A.gacc + g_off, 2 * fbytes);
         const bool own = xin && mine;
         double g[BZ];
@@ -1710,7 +1718,8 @@ hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st)
         a.next2 == a.prev)
         return hipErrorInvalidValue;
     if (adjoint) {
-        if (a.nw < 1 || a.nw > 8 || !a.wimg || !a.wimg2) return hipErrorInvalidValue;
+        if (a.nw < 1 || a.nw > 8 || (a.sg != 1 && a.sg != 2) || a.nw % a.sg || !a.wimg || !a.wimg2)
+            return hipErrorInvalidValue;
         k_adj2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd_g), 64 * a.nw, 0, st>>>(a);
     } else {
         k_fwd2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd), 256, 0, st>>>(a);  // 4 strips per workgroup

@@ -144,3 +144,33 @@ def test_two_steps_against_oracle(F):
         e = rel(gg[k], ogr[k])
         say("  sample %d gradient rel %.2e" % (k, e))
         assert e < TOL
+
+
+def test_two_strips_per_workgroup_odd_strip_count(F):
+    # one sample of 10 supergathers on a grid of 3 strips (52 x 42 padded): the two-step
+    # adjoint runs 8 waves per workgroup as two strips of 4 waves each (10 sims split
+    # 3+3+2+2 per strip, instead of 2+2+1+1+1+1+1+1 on one strip of 8 waves), and the last
+    # workgroup's second strip does not exist (its waves only join the barriers)
+    say("case two strips per workgroup, odd strip count")
+    g = F.Grid(nz=30, nx=40, dz=10.0, dx=10.0, nb=6, v_ref=3000.0, v_max=3300.0)
+    r = np.random.default_rng(5)
+    model = f32(r.uniform(1800, 3200, g.nphys))
+    rec = (np.arange(0, 40, 2) + 40).astype(np.int32)
+    srcs = [(r.integers(0, g.nphys, 2).astype(np.int32), r.choice([-1.0, 1.0], 2)) for _ in range(10)]
+    nt, R = 120, 2
+    batch = F.Batch([g], [0] * 10, srcs, [rec] * 10, W.ricker(15.0, 1e-3, nt))
+    time = F.time_axis(1e-3, nt, R, 0)
+    nd = batch.data_size(nt // R)
+    dobs = f32(1e-4 * np.random.default_rng(9).standard_normal(nd))
+    one = run(F, (1, 1), batch, time, [model], dobs, [0.75])
+    two = run(F, (1, 2), batch, time, [model], dobs, [0.75])
+    assert np.abs(one[2]).max() > 0
+    assert np.array_equal(one[0], two[0]) and np.array_equal(one[1], two[1])
+    e = rel(two[2].astype(np.float64), one[2].astype(np.float64))
+    say("  gradient rel %.2e" % e)
+    assert e < 1e-6
+    # and against the oracle
+    dp, mis, gr = two
+    truth_d = split_data(dobs, batch, nt // R)
+    odp, omis, ogr = oracle_batch_gradient(batch, 1e-3, nt, R, [model.ravel()], truth_d, 2.0, [0.75])
+    assert rel(gr.astype(np.float64), ogr[0]) < TOL
