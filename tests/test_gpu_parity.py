@@ -296,6 +296,42 @@ def test_3d_uneven_batch_per_sample_imaging(F):
         assert e < TOL
 
 
+def test_3d_launch_order_groups(F):
+    """3D batch of two samples with 5 and 2 supergathers on different grids: the forward's
+    launch order takes at most 4 of a sample's supergathers at a tile position (groups of
+    4 + 1, then 2), and every result matches the oracle."""
+    say("case 3d launch-order groups")
+    grids = [F.Grid(nz=22, ny=10, nx=37, dz=20.0, dy=20.0, dx=20.0, nb=4, v_ref=3500.0, v_max=3600.0, ndim=3),
+             F.Grid(nz=18, ny=13, nx=30, dz=20.0, dy=20.0, dx=20.0, nb=3, v_ref=3500.0, v_max=3600.0, ndim=3)]
+    r = np.random.default_rng(21)
+    sample_of = [0, 0, 0, 0, 0, 1, 1]
+    srcs, recs = [], []
+    for k in sample_of:
+        g = grids[k]
+        srcs.append((r.integers(0, g.nphys, 2).astype(np.int32), r.choice([-1.0, 1.0], 2)))
+        recs.append(np.array([(z * g.ny + y) * g.nx + x for z in (1, g.nz - 1) for y in range(0, g.ny, 4)
+                              for x in range(0, g.nx, 6)], dtype=np.int32))
+    nt, R = 80, 2
+    batch = F.Batch(grids, sample_of, srcs, recs, W.ricker(7.0, 2e-3, nt))
+    time = F.time_axis(2e-3, nt, R, 0)
+    models = [f32(r.uniform(1800, 3400, g.nphys)) for g in grids]
+    truths = [f32(m * 0.9) for m in models]
+    dobs = [f32(0.5 * d) for d in oracle_forward_sims(batch, 2e-3, nt, R, truths, coef_fp32=False)]
+    kappa = [0.7, 1.3]
+    dp, mis, gr, _ = run_gradient(F, batch, time, models, np.concatenate([d.ravel() for d in dobs]), 1.0, kappa)
+    odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, models, dobs, 1.0, kappa)
+    gdp = split_data(dp, batch, nt // R)
+    for s in range(batch.nsim):
+        e = rel(gdp[s], odp[s])
+        say("  sim %d (sample %d) data rel %.2e" % (s, sample_of[s], e))
+        assert e < TOL and abs(mis[s] / omis[s] - 1) < TOL
+    gs = split_model(gr, batch)
+    for k in range(2):
+        e = rel(gs[k], ogr[k])
+        say("  sample %d gradient rel %.2e" % (k, e))
+        assert e < TOL
+
+
 # ------------------------------------------------------ stored oracle golden
 
 def test_stored_oracle_golden(F):
