@@ -55,6 +55,7 @@ def lib():
         _lib = C.CDLL(build())
         _lib.orc_philox4x64.restype = None
         _lib.orc_normals.restype = None
+        _lib.orc_normals_key.restype = None
         _lib.orc_langevin.restype = None
     return _lib
 
@@ -276,6 +277,14 @@ def normals(seed, step, sample, n):
     """Langevin noise xi ~ N(0, I) for one sample at one step (counter-based, reproducible)."""
     out = np.zeros(int(n))
     lib().orc_normals(C.c_uint64(seed), C.c_uint64(step), C.c_uint64(sample), C.c_int64(n), _dp(out))
+    return out
+
+
+def normals_key(seed, tag, a, b, n):
+    """Standard normals of any counter-based stream: cells 4m..4m+3 from Philox(ctr = {m, a,
+    b, 0}, key = {seed, tag}) with Box-Muller (normals() is tag 0x4C414E47)."""
+    out = np.zeros(int(n))
+    lib().orc_normals_key(C.c_uint64(seed), C.c_uint64(tag), C.c_uint64(a), C.c_uint64(b), C.c_int64(n), _dp(out))
     return out
 
 

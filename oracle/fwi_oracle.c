@@ -586,11 +586,23 @@ static double u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 900719
  * Box-Muller on the word pairs (0,1) and (2,3): r = sqrt(-2 ln u_a), th = 2 pi u_b,
  * giving r cos th, r sin th.
  */
+void orc_normals_key(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, int64_t n, double *out);
+
 void orc_normals(uint64_t seed, uint64_t step, uint64_t sample, int64_t n, double *out)
 {
-    const uint64_t key[2] = {seed, 0x4C414E47ULL};
+    orc_normals_key(seed, 0x4C414E47ULL, step, sample, n, out);
+}
+
+/*
+ * The same construction for any stream: cells 4m..4m+3 use Philox(ctr = {m, a, b, 0},
+ * key = {seed, tag}) and Box-Muller as above (the diffusion re-noising uses tag 0x44415053
+ * with a = step, b = image).
+ */
+void orc_normals_key(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, int64_t n, double *out)
+{
+    const uint64_t key[2] = {seed, tag};
     for (int64_t m = 0; 4 * m < n; ++m) {
-        uint64_t ctr[4] = {(uint64_t)m, step, sample, 0}, w[4];
+        uint64_t ctr[4] = {(uint64_t)m, a, b, 0}, w[4];
         orc_philox4x64(ctr, key, w);
         double z[4];
         for (int p = 0; p < 2; ++p) {

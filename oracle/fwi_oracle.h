@@ -49,6 +49,8 @@ int orc_forward_batch(int nsim, const orc_grid *grids, const orc_time *t, const 
                       const int32_t *rec_ptr, const int32_t *rec_cell, double *const *d_out);
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 void orc_normals(uint64_t seed, uint64_t step, uint64_t sample, int64_t n, double *out);
+/* standard normals of the stream Philox(ctr = {m, a, b, 0}, key = {seed, tag}), Box-Muller */
+void orc_normals_key(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, int64_t n, double *out);
 void orc_langevin(int64_t n, double *z, const double *g, const double *xi, double eta, double nu, double lo,
                   double hi);
 int orc_draw_encoding(uint64_t seed, uint64_t step, uint64_t sample, int nshot, int s, int G, int32_t *grp_shot,
