@@ -19,6 +19,7 @@
 
 #include "fwi_internal.h"
 #include "fwi_launch.h"
+#include "philox.h"
 
 namespace fwi {
 
@@ -1550,29 +1551,6 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ d, int
 
 // --------------------------------------------------------------- Langevin
 
-// Philox4x64-10 (Salmon et al., SC 2011).
-__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ double u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
-
 // One thread per group of 4 cells of one sample's model (n cells at v, g, xi).
 __global__ __launch_bounds__(256) void k_langevin(int64_t n, float *__restrict__ v, const float *__restrict__ g,
                                                   const float *__restrict__ xi, uint64_t seed, uint64_t step,
@@ -1581,17 +1559,7 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, float *__restrict__
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (4 * m >= n) return;
     double z[4] = {0.0, 0.0, 0.0, 0.0};
-    if (xi == nullptr) {
-        uint64_t c[4] = {(uint64_t)m, step, sample, 0};
-        philox4x64(c, seed, 0x4C414E47ULL);
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const double r = sqrt(-2.0 * log(u01(c[2 * p])));
-            const double th = 6.283185307179586476925 * u01(c[2 * p + 1]);
-            z[2 * p] = r * cos(th);
-            z[2 * p + 1] = r * sin(th);
-        }
-    }
+    if (xi == nullptr) normals4((uint64_t)m, step, sample, seed, 0x4C414E47ULL, z);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t i = 4 * m + j;

@@ -157,3 +157,18 @@ def test_workspace_independent_of_time_blocking(F):
     finally:
         F.fwi_set_time_blocking(0, 0)
     assert len(sizes) == 1
+
+
+def test_daps_argument_checks(F):
+    # host-side checks of the diffusion outer loop's entry points: nothing is enqueued
+    from paper_2512_12797_amd import daps
+    L = daps._lib()
+    p = C.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert L.fwi_daps_mix(0, 10, p, None, p, p, p, 1500.0, 5000.0, 1, 0, p, None) == F.FWI_E_ARG
+    assert L.fwi_daps_mix(2, 10, None, None, p, p, p, 1500.0, 5000.0, 1, 0, p, None) == F.FWI_E_ARG
+    assert L.fwi_daps_mix(2, 10, p, None, p, p, p, 5000.0, 1500.0, 1, 0, p, None) == F.FWI_E_ARG
+    assert L.fwi_daps_mix(70000, 10, p, None, p, p, p, 1500.0, 5000.0, 1, 0, p, None) == F.FWI_E_ARG
+    assert L.fwi_daps_prep(2, 10, 8, 9, p, p, C.c_void_p(18), None, None) == F.FWI_E_ARG  # misaligned
+    assert L.fwi_daps_prep(2, 10, 8, 9, p, p, p, None, None) == F.FWI_E_ARG  # hp < h
+    assert L.fwi_daps_model(2, 10, 8, 10, 0, p, 1500.0, 5000.0, p, None) == F.FWI_E_ARG
+    assert b"model" in L.fwi_daps_last_error()

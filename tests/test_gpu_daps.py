@@ -1,0 +1,109 @@
+"""GPU: the diffusion outer loop's kernels (include/fwi_daps.h) against the FP64 oracle
+(oracle/daps.py), through the C ABI.
+
+fwi_daps_mix evaluates in FP64 and rounds once: it matches the oracle to FP32 rounding
+(the two normal streams share their construction; the device's log / cos / sin may differ
+from the host's in the last FP64 bits).  fwi_daps_prep's BF16 channels equal the oracle's
+values rounded to nearest even, bit for bit; fwi_daps_model matches exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import daps as D
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = 1350.0, 6600.0
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12797_amd import daps
+    return daps
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("terms", ["both", "z", "x", "inplace"])
+def test_mix_matches_oracle(M, terms):
+    say("case daps mix, %s" % terms)
+    r = np.random.default_rng(3)
+    nimg, n = 3, 1001  # n not a multiple of 4: a partial Philox block per image
+    z = f32(r.uniform(LO, HI, (nimg, n)))
+    x = f32(r.uniform(-1.2, 1.2, (nimg, n)))
+    c0 = f32(r.uniform(0.1, 1.0, nimg))
+    c1 = f32(r.uniform(0.0, 1.0, nimg))
+    sig = f32([0.3, 0.0, 0.02])
+    seed, step = 77, 5
+    zz = z if terms in ("both", "z", "inplace") else None
+    xx = x if terms in ("both", "x", "inplace") else None
+    ref = D.mix(zz, xx, c0, c1, sig, LO, HI, seed, step)
+    zt = dev(z) if zz is not None else None
+    xt = dev(x) if xx is not None else None
+    out = xt if terms == "inplace" else torch.empty(nimg, n, device="cuda")
+    M.fwi_daps_mix(nimg, n, zt, xt, dev(c0), dev(c1), dev(sig), LO, HI, seed, step, out)
+    got = out.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  max rel error %.2e" % err)
+    assert err < 2e-7
+    # the image with sig = 0 is deterministic
+    assert np.array_equal(got[1], f32(ref[1]))
+
+
+def test_forward_diffusion_statistics(M):
+    # q(x_t | x_0) with the kernel's own draws: mean sqrt(alpha_t) x0, variance 1 - alpha_t
+    sched = M.Schedule()
+    t = 40
+    n = 1 << 20
+    z = torch.full((1, n), 4000.0, device="cuda")
+    c0, c1, sig = (torch.tensor([v], dtype=torch.float32, device="cuda") for v in sched.forward(t))
+    out = torch.empty(1, n, device="cuda")
+    M.fwi_daps_mix(1, n, z, None, c0, c1, sig, LO, HI, 9, 0, out)
+    x0 = D.normalise(4000.0, LO, HI)
+    a = out.double()
+    assert abs(float(a.mean()) - np.sqrt(sched.alpha[t]) * x0) < 5 * np.sqrt((1 - sched.alpha[t]) / n)
+    assert abs(float(a.var()) / (1 - sched.alpha[t]) - 1) < 5 * np.sqrt(2.0 / n)
+
+
+@pytest.mark.parametrize("hp", [150, 152])
+def test_prep_matches_oracle(M, hp):
+    r = np.random.default_rng(4)
+    nimg, h, w = 2, 150, 40
+    x = f32(r.uniform(-1, 1, (nimg, h, w)))
+    level = f32([0.05, 0.3])
+    x16 = torch.empty(nimg, hp, w, 16, dtype=torch.int16, device="cuda")
+    res = torch.empty(nimg, hp, w, device="cuda")
+    M.fwi_daps_prep(nimg, h, w, hp, dev(x), dev(level), x16, res)
+    ch0, ch1, rref = D.prep(x, level, hp)
+    got = (x16.to(torch.int32) << 16).view(torch.float32).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[..., 0], U.bf16(ch0))
+    assert np.array_equal(got[..., 1], U.bf16(ch1))
+    assert np.all(got[..., 2:] == 0)
+    assert np.array_equal(res.cpu().numpy().astype(np.float64), rref)
+
+
+def test_model_matches_oracle(M):
+    r = np.random.default_rng(5)
+    nimg, h, w, hp, c = 2, 150, 40, 152, 32
+    pred = f32(r.uniform(-1.3, 1.3, (nimg, hp, w, c)))
+    v = torch.empty(nimg, h, w, device="cuda")
+    M.fwi_daps_model(nimg, h, w, hp, c, dev(pred), LO, HI, v)
+    ref = f32(D.to_model(pred[:, :h, :, 0], LO, HI))
+    assert np.array_equal(v.cpu().numpy().astype(np.float64), ref)
