@@ -250,6 +250,63 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
             "layers": rows, "weight_gradients": wrows}
 
 
+def daps_bench(torch, args):
+    """Diffusion-prior posterior sampling (the decoupled diffusion inference) against the
+    prior-free encoded Langevin chain, on the 2D encoded workload: 16 samples from the
+    smoothed start, the same number of encoded-gradient evaluations per sample.  The
+    predict-x0 network is trained here on seeded procedural thrust models (not the test
+    model's seed)."""
+    from paper_2512_12797_amd import chains, daps
+    sv = chains.Survey(seed=args.seed, log=log)
+    cfg = sv.cfg
+    nsample = 16
+    v0 = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
+    eta = args.daps_max_update / float(sv.full_gradient(v0[:1], 1).abs().max())
+    lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+    t0 = time.perf_counter()
+    models = daps.procedural_models(cfg, args.daps_models, seed0=20000)
+    log("prior training set: %d models in %.1f s" % (args.daps_models, time.perf_counter() - t0))
+    sched = daps.Schedule()
+    den = daps.Denoiser(cfg.nz, cfg.nx, cfg.nz + chains.PAD_ROWS, lo, hi, seed=0)
+    t1 = time.perf_counter()
+    hist = den.train(models, sched, args.daps_tstart, steps=args.daps_train, log=log)
+    t_train = time.perf_counter() - t1
+    del models
+    held = daps.procedural_models(cfg, 16, seed0=30000)
+    ts = sorted({1, max(1, args.daps_tstart // 4), max(1, args.daps_tstart // 2), args.daps_tstart})
+    ev = den.evaluate(held, sched, ts)
+    for t, noise, err in ev:
+        log("prior: level %d, noise %.1f m/s, clean-model estimate RMSE %.1f m/s" % (t, noise, err))
+    v, r_daps, wall, ngrad = daps.sample(sv, den, sched, args.daps_tstart, args.daps_k, eta, args.seed, nsample,
+                                         every=args.daps_every, renoise=args.daps_renoise)
+    log("daps: %d levels, %d steps every %d, %.1f s, posterior-mean RMSE %.1f -> %.1f m/s" % (
+        args.daps_tstart, args.daps_k, args.daps_every, wall, r_daps[0], r_daps[-1]))
+    r_enc, s_enc, _ = chains.run_chain(sv, "encoded", ngrad, eta, args.seed, nsample=nsample)
+    vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
+    per_sample = float((v.double() - vt).pow(2).mean(1).sqrt().mean())
+    start_rmse = float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2)))
+    log("encoded chain: %d steps, %.3f s per step, posterior-mean RMSE %.1f m/s" % (ngrad, s_enc, r_enc[-1]))
+    return {"metric": "posterior-mean RMSE after the same encoded-gradient evaluations", "unit": "m/s",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "f32 (network bf16)",
+            "workload": "2d-400x150-thrust-80shot: 16 samples from a start smoothed by %g cells; encoded gradients "
+                        "(10 supergathers of 8), Langevin eta=%.3e (largest first update %g m/s), nu=sqrt(2 eta)"
+                        % (sv.start_sigma, eta, args.daps_max_update),
+            "start_rmse_mps": round(start_rmse, 2), "gradient_evaluations_per_sample": ngrad,
+            "daps": {"levels": args.daps_tstart, "steps_per_guided_level": args.daps_k, "guide_every": args.daps_every,
+                     "renoise": args.daps_renoise, "T": sched.T,
+                     "posterior_mean_rmse_mps": round(r_daps[-1], 2), "mean_sample_rmse_mps": round(per_sample, 2),
+                     "rmse_per_level_sampled": [[args.daps_tstart - i, round(r_daps[i], 2)] for i in
+                                                range(0, len(r_daps), max(1, len(r_daps) // 20))],
+                     "wall_s": round(wall, 2),
+                     "samples_per_hour": round(nsample / wall * 3600, 1),
+                     "prior": {"models": args.daps_models, "train_steps": args.daps_train,
+                               "train_s": round(t_train, 1), "loss_first_last": [hist[0][1], hist[-1][1]],
+                               "heldout_level_noise_rmse_mps": [[t, round(n, 1), round(e, 1)] for t, n, e in ev]}},
+            "encoded_langevin": {"steps": ngrad, "posterior_mean_rmse_mps": round(r_enc[-1], 2),
+                                 "s_per_step": round(s_enc, 4),
+                                 "samples_per_hour": round(nsample / (ngrad * s_enc) * 3600, 1)}}
+
+
 def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e-3, G=1):
     """The learned preconditioner at the pair configuration's full scale: about 10k pairs
     (2500 seeded thrust / salt models on 256 x 256 patches at 10 m, 32 surface shots of a
@@ -320,7 +377,7 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=0, choices=[0, 1, 2],
                     help="2D keep-all schedule: time steps per adjoint launch (0: the tuner's choice, else 2)")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond"],
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond", "daps"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
                          "equal-error: posterior samples/hour of plain, encoded and preconditioned chains at equal "
                          "posterior-mean RMSE (several minutes); unet: the gradient preconditioner's network "
@@ -334,6 +391,14 @@ def main():
     ap.add_argument("--pc-steps", type=int, default=20000, help="precond: training steps (batch 8)")
     ap.add_argument("--pc-lr", type=float, default=1e-3, help="precond: initial Adam learning rate (cosine to 1/10)")
     ap.add_argument("--pc-G", type=int, default=1, help="precond: supergathers of 8 shots summed per encoded gradient")
+    ap.add_argument("--daps-tstart", type=int, default=20, help="daps: first diffusion level (of T = 1000)")
+    ap.add_argument("--daps-k", type=int, default=5, help="daps: Langevin steps per guided level")
+    ap.add_argument("--daps-every", type=int, default=1, help="daps: guidance at every this many levels")
+    ap.add_argument("--daps-renoise", default="marginal", choices=["posterior", "marginal", "mean"])
+    ap.add_argument("--daps-max-update", type=float, default=300.0,
+                    help="daps: eta is set so that the largest first update is this many m/s")
+    ap.add_argument("--daps-models", type=int, default=1024, help="daps: procedural models the prior is trained on")
+    ap.add_argument("--daps-train", type=int, default=8000, help="daps: denoiser training steps (batch 8)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the workload shards by posterior sample with no exchange "
@@ -350,6 +415,9 @@ def main():
     if args.workload == "precond":
         print(json.dumps(precond_bench(torch, args, nmodels=args.pc_models, steps=args.pc_steps, lr=args.pc_lr,
                                        G=args.pc_G)), flush=True)
+        return
+    if args.workload == "daps":
+        print(json.dumps(daps_bench(torch, args)), flush=True)
         return
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains

@@ -11,9 +11,14 @@ For a batch of posterior samples at diffusion level t, from t_start down to 1:
   (iii) re-noise: x_{t-1} ~ N(mu~_t(x_t, z), beta~_t) in the normalised space (Eq. renoise,
         fwi_daps_mix); at t = 1 the refined model is the sample.
 The chain starts from the last levels: x_{t_start} is the forward diffusion of the
-starting model (a warm start instead of pure noise).  The predict-x0 network is trained
-here, on the GPU network kernels, on seeded procedural models.  Python only arranges
-tensors and scalars and calls the library.
+starting model (a warm start instead of pure noise).  Guidance may be injected every few
+levels only (the synthetic experiments of Sec. 3 take 5 steps every 5 levels); a level
+without it re-noises the network's estimate.  The modified sampler of the proposed-framework
+table draws the Langevin noise with its own weight nu (sqrt(2 eta) by default) and makes
+the re-noise optional: `renoise` picks the posterior draw (the equation), the draw from
+q(x_{t-1} | z) (the table's line), or the posterior mean without noise.  The predict-x0
+network is trained here, on the GPU network kernels, on seeded procedural models.  Python
+only arranges tensors and scalars and calls the library.
 """
 from __future__ import annotations
 
@@ -135,7 +140,7 @@ class Denoiser:
             fwi_daps_model(b, self.h, self.w, self.hp, out.shape[-1], out, self.v_lo, self.v_hi, v[i:i + b])
         return v
 
-    def train(self, models, sched, t_max, steps=3000, batch=8, lr=2e-3, lr_final=2e-4, seed=0, log=None):
+    def train(self, models, sched, t_max, steps=3000, batch=8, lr=5e-4, lr_final=5e-5, seed=0, log=None):
         """Adam on the relative squared error of the clean-model estimate: for a random batch
         of models (device f32 [N, h, w], m/s) and random levels t in 1..t_max, x_t is their
         forward diffusion and the target their normalised clean version.  Returns losses."""
@@ -167,9 +172,25 @@ class Denoiser:
             self.net.adam_step(cur)
             if it % 100 == 0 or it == steps - 1:
                 hist.append((it, float(loss.item())))
-                if log:
+                if log and (it % 1000 == 0 or it == steps - 1):
                     log("denoiser step %d loss %.4f (%.1f s)" % (it, hist[-1][1], time.perf_counter() - t0))
         return hist
+
+    def evaluate(self, models, sched, ts, seed=1):
+        """RMSE (m/s) of the clean-model estimate from the forward diffusion of `models`
+        (device f32 [N, h, w], m/s) at each level in ts, with the noise level itself."""
+        N = models.shape[0]
+        hw = self.h * self.w
+        z = models.reshape(N, hw).contiguous()
+        xt = torch.empty(N, hw, device=self.dev)
+        out = []
+        for t in ts:
+            c0, c1, sig = _coefs(sched.forward(int(t)), N, self.dev)
+            fwi_daps_mix(N, hw, z, None, c0, c1, sig, self.v_lo, self.v_hi, seed, int(t), xt)
+            v = self.predict(xt.view(N, self.h, self.w), sig)
+            err = float((v.double().reshape(N, hw) - z.double()).pow(2).mean().sqrt())
+            out.append((int(t), sched.level(int(t)) * 0.5 * (self.v_hi - self.v_lo), err))
+        return out
 
 
 def procedural_models(cfg, n, seed0, device="cuda"):
@@ -180,11 +201,19 @@ def procedural_models(cfg, n, seed0, device="cuda"):
 
 # -------------------------------------------------------------------- sampler
 
-def sample(sv, den: Denoiser, sched: Schedule, t_start, K, eta, seed, nsample=16, langevin_bounds=None):
+RENOISE = ("posterior", "marginal", "mean")
+
+
+def sample(sv, den: Denoiser, sched: Schedule, t_start, K, eta, seed, nsample=16, every=1, nu=None,
+           renoise="posterior", langevin_bounds=None):
     """Decoupled diffusion inference of `nsample` posterior samples on the Survey `sv`
-    (chains.Survey: geometry, observed data, starting model).  Returns (samples, device
-    f32 [nsample, nphys]; posterior-mean RMSE after each level; wall seconds; gradient
-    evaluations per sample)."""
+    (chains.Survey: geometry, observed data, starting model): K Langevin steps at levels
+    t_start, t_start - every, ...; noise weight nu (default sqrt(2 eta)); re-noise mode
+    one of RENOISE.  Returns (samples, device f32 [nsample, nphys]; posterior-mean RMSE
+    after each level; wall seconds; gradient evaluations per sample)."""
+    if renoise not in RENOISE or every < 1 or K < 0:
+        raise ValueError("renoise must be one of %s, every >= 1, K >= 0" % (RENOISE,))
+    nu = math.sqrt(2 * eta) if nu is None else nu
     cfg = sv.cfg
     nz, nx = cfg.nz, cfg.nx
     nphys = sv.grid.nphys
@@ -204,14 +233,18 @@ def sample(sv, den: Denoiser, sched: Schedule, t_start, K, eta, seed, nsample=16
     for t in range(t_start, 0, -1):
         level = torch.full((nsample,), sched.level(t), device=dev)
         v = den.predict(x.view(nsample, nz, nx), level).reshape(nsample, nphys).contiguous()   # (i)
-        for _ in range(K):                                                                       # (ii)
+        for _ in range(K if (t_start - t) % every == 0 else 0):                                 # (ii)
             g = sv.encoded_gradient(v, nsample, seed, step)
-            fwi.fwi_langevin(off, v.reshape(-1), g.reshape(-1).contiguous(), None, seed, step, eta,
-                             math.sqrt(2 * eta), lo, hi)
+            fwi.fwi_langevin(off, v.reshape(-1), g.reshape(-1).contiguous(), None, seed, step, eta, nu, lo, hi)
             step += 1
         if t > 1:                                                                                 # (iii)
-            c0, c1, sig = _coefs(sched.posterior(t), nsample, dev)
-            fwi_daps_mix(nsample, nphys, v, x, c0, c1, sig, den.v_lo, den.v_hi, seed, t, x)
+            if renoise == "marginal":
+                c0, c1, sig = _coefs(sched.forward(t - 1), nsample, dev)
+            else:
+                c0, c1, sig = sched.posterior(t)
+                c0, c1, sig = _coefs((c0, c1, sig if renoise == "posterior" else 0.0), nsample, dev)
+            fwi_daps_mix(nsample, nphys, v, x if renoise != "marginal" else None, c0, c1, sig, den.v_lo, den.v_hi,
+                         seed, t, x)
         rmse.append(float((v.double().mean(0) - vt).pow(2).mean().sqrt()))
     torch.cuda.synchronize()
     return v, rmse, time.perf_counter() - t0, step

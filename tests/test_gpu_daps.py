@@ -107,3 +107,40 @@ def test_model_matches_oracle(M):
     M.fwi_daps_model(nimg, h, w, hp, c, dev(pred), LO, HI, v)
     ref = f32(D.to_model(pred[:, :h, :, 0], LO, HI))
     assert np.array_equal(v.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("renoise", ["posterior", "marginal", "mean"])
+def test_sampler_plumbing_with_identity_network(M, renoise):
+    # An untrained network returns its residual input (zero output layer), so with no
+    # Langevin steps every level is: v = model(x_t); x_{t-1} = re-noise(v, x_t).  The oracle
+    # replays that chain in FP64 with its own noise streams: this checks the warm start, the
+    # coefficients of each mode and the counter words of every draw.
+    from types import SimpleNamespace
+    say("case daps sampler plumbing, %s" % renoise)
+    nz, nx, ns, ts, seed = 14, 24, 3, 6, 21
+    r = np.random.default_rng(6)
+    vstart = 3000.0 + 1500.0 * r.random((nz, nx))
+    cfg = SimpleNamespace(nz=nz, nx=nx, vmin=2000.0, vmax=6000.0)
+    sv = SimpleNamespace(cfg=cfg, grid=SimpleNamespace(nphys=nz * nx), dev="cuda", vtrue=vstart + 50.0,
+                         vstart=vstart)
+    lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+    den = M.Denoiser(nz, nx, 16, lo, hi, seed=0)
+    sched = M.Schedule()
+    v, rmse, _, ngrad = M.sample(sv, den, sched, ts, 0, 1e-5, seed, nsample=ns, renoise=renoise)
+    beta, alpha = D.linear_schedule(1000, 1e-4, 0.02)
+    z0 = np.tile(f32(vstart).ravel(), (ns, 1))
+    x = D.mix(z0, None, [np.sqrt(alpha[ts])] * ns, [0.0] * ns, [np.sqrt(1 - alpha[ts])] * ns, lo, hi, seed, 1001)
+    for t in range(ts, 0, -1):
+        vo = D.to_model(x, lo, hi)
+        if t > 1:
+            if renoise == "marginal":
+                c = (np.sqrt(alpha[t - 1]), 0.0, np.sqrt(1 - alpha[t - 1]))
+            else:
+                c0, c1, bt = D.posterior(beta, alpha, t)
+                c = (c0, c1, np.sqrt(bt) if renoise == "posterior" else 0.0)
+            x = D.mix(vo, x if renoise != "marginal" else None, *([ci] * ns for ci in c), lo, hi, seed, t)
+    assert ngrad == 0 and len(rmse) == ts
+    got = v.cpu().numpy().astype(np.float64)
+    err = np.abs(got - vo).max()
+    say("  max abs error %.3e m/s" % err)
+    assert err < 5e-3
