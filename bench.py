@@ -252,10 +252,14 @@ def unet_bench(torch, args, b=8, n=256, chans=(32, 64, 128, 256)):
 
 def daps_bench(torch, args):
     """Diffusion-prior posterior sampling (the decoupled diffusion inference) against the
-    prior-free encoded Langevin chain, on the 2D encoded workload: 16 samples from the
-    smoothed start, the same number of encoded-gradient evaluations per sample.  The
-    predict-x0 network is trained here on seeded procedural thrust models (not the test
-    model's seed)."""
+    prior-free encoded chains, on the 2D encoded workload: 16 samples from the smoothed
+    start, the same number of encoded-gradient evaluations per sample for every sampler.
+    Each sampler runs with the stochastic Langevin refinement and with the deterministic
+    Adam guidance of the paper's experiments (the calibration ablation).  The predict-x0
+    network is trained here on seeded procedural thrust models (not the test model's
+    seed).  Reported per sampler: posterior-mean RMSE, mean sample RMSE, the mean
+    posterior standard deviation and the share of cells whose error lies within two of
+    them."""
     from paper_2512_12797_amd import chains, daps
     sv = chains.Survey(seed=args.seed, log=log)
     cfg = sv.cfg
@@ -277,34 +281,48 @@ def daps_bench(torch, args):
     ev = den.evaluate(held, sched, ts)
     for t, noise, err in ev:
         log("prior: level %d, noise %.1f m/s, clean-model estimate RMSE %.1f m/s" % (t, noise, err))
-    v, r_daps, wall, ngrad = daps.sample(sv, den, sched, args.daps_tstart, args.daps_k, eta, args.seed, nsample,
-                                         every=args.daps_every, renoise=args.daps_renoise)
-    log("daps: %d levels, %d steps every %d, %.1f s, posterior-mean RMSE %.1f -> %.1f m/s" % (
-        args.daps_tstart, args.daps_k, args.daps_every, wall, r_daps[0], r_daps[-1]))
-    r_enc, s_enc, _ = chains.run_chain(sv, "encoded", ngrad, eta, args.seed, nsample=nsample)
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
-    per_sample = float((v.double() - vt).pow(2).mean(1).sqrt().mean())
+
+    def stats(v, wall):
+        vd = v.double()
+        mean, std = vd.mean(0), vd.std(0)
+        return {"posterior_mean_rmse_mps": round(float((mean - vt).pow(2).mean().sqrt()), 2),
+                "mean_sample_rmse_mps": round(float((vd - vt).pow(2).mean(1).sqrt().mean()), 2),
+                "mean_posterior_std_mps": round(float(std.mean()), 2),
+                "within_2std": round(float(((mean - vt).abs() <= 2 * std).double().mean()), 3),
+                "wall_s": round(wall, 2), "samples_per_hour": round(nsample / wall * 3600, 1)}
+
+    runs = {}
+    ngrad = None
+    for guide in ("langevin", "adam"):
+        v, r_d, wall, ngrad = daps.sample(sv, den, sched, args.daps_tstart, args.daps_k, eta, args.seed, nsample,
+                                          every=args.daps_every, renoise=args.daps_renoise, guide=guide,
+                                          adam_lr=args.daps_lr, nu=None if guide == "langevin" else args.daps_adam_nu)
+        runs["daps_" + guide] = dict(stats(v, wall), rmse_per_level_sampled=[
+            [args.daps_tstart - i, round(r_d[i], 2)] for i in range(0, len(r_d), max(1, len(r_d) // 10))])
+        log("daps, %s guidance: %s" % (guide, runs["daps_" + guide]))
+    for guide in ("langevin", "adam"):
+        t2 = time.perf_counter()
+        r_e, s_e, _, v = chains.run_chain(sv, "encoded", ngrad, eta, args.seed, nsample=nsample,
+                                          nu=None if guide == "langevin" else args.daps_adam_nu,
+                                          adam_lr=args.daps_lr if guide == "adam" else None, keep_samples=True)
+        runs["encoded_" + guide] = dict(stats(v, time.perf_counter() - t2), s_per_step=round(s_e, 4))
+        log("encoded chain, %s guidance: %s" % (guide, runs["encoded_" + guide]))
     start_rmse = float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2)))
-    log("encoded chain: %d steps, %.3f s per step, posterior-mean RMSE %.1f m/s" % (ngrad, s_enc, r_enc[-1]))
     return {"metric": "posterior-mean RMSE after the same encoded-gradient evaluations", "unit": "m/s",
+            "value": runs["daps_langevin"]["posterior_mean_rmse_mps"],
             "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "f32 (network bf16)",
             "workload": "2d-400x150-thrust-80shot: 16 samples from a start smoothed by %g cells; encoded gradients "
-                        "(10 supergathers of 8), Langevin eta=%.3e (largest first update %g m/s), nu=sqrt(2 eta)"
-                        % (sv.start_sigma, eta, args.daps_max_update),
+                        "(10 supergathers of 8); Langevin eta=%.3e (largest first update %g m/s), nu=sqrt(2 eta); "
+                        "Adam rate %g m/s, nu=%g" % (sv.start_sigma, eta, args.daps_max_update, args.daps_lr,
+                                                      args.daps_adam_nu),
             "start_rmse_mps": round(start_rmse, 2), "gradient_evaluations_per_sample": ngrad,
             "daps": {"levels": args.daps_tstart, "steps_per_guided_level": args.daps_k, "guide_every": args.daps_every,
                      "renoise": args.daps_renoise, "T": sched.T,
-                     "posterior_mean_rmse_mps": round(r_daps[-1], 2), "mean_sample_rmse_mps": round(per_sample, 2),
-                     "rmse_per_level_sampled": [[args.daps_tstart - i, round(r_daps[i], 2)] for i in
-                                                range(0, len(r_daps), max(1, len(r_daps) // 20))],
-                     "wall_s": round(wall, 2),
-                     "samples_per_hour": round(nsample / wall * 3600, 1),
                      "prior": {"models": args.daps_models, "train_steps": args.daps_train,
                                "train_s": round(t_train, 1), "loss_first_last": [hist[0][1], hist[-1][1]],
                                "heldout_level_noise_rmse_mps": [[t, round(n, 1), round(e, 1)] for t, n, e in ev]}},
-            "encoded_langevin": {"steps": ngrad, "posterior_mean_rmse_mps": round(r_enc[-1], 2),
-                                 "s_per_step": round(s_enc, 4),
-                                 "samples_per_hour": round(nsample / (ngrad * s_enc) * 3600, 1)}}
+            "runs": runs}
 
 
 def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e-3, G=1):
@@ -397,6 +415,8 @@ def main():
     ap.add_argument("--daps-renoise", default="marginal", choices=["posterior", "marginal", "mean"])
     ap.add_argument("--daps-max-update", type=float, default=300.0,
                     help="daps: eta is set so that the largest first update is this many m/s")
+    ap.add_argument("--daps-lr", type=float, default=50.0, help="daps: Adam guidance rate, m/s")
+    ap.add_argument("--daps-adam-nu", type=float, default=0.0, help="daps: noise weight after an Adam step")
     ap.add_argument("--daps-models", type=int, default=1024, help="daps: procedural models the prior is trained on")
     ap.add_argument("--daps-train", type=int, default=8000, help="daps: denoiser training steps (batch 8)")
     args = ap.parse_args()

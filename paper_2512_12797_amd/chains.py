@@ -27,7 +27,7 @@ import torch
 
 import workloads as W
 
-from . import fwi, precond, problems
+from . import fwi, nn, precond, problems
 from .unet import UNet
 
 
@@ -144,11 +144,16 @@ def precondition(net, g_enc, v):
 
 # -------------------------------------------------------------------- chains
 
-def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16):
+def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None, adam_lr=None, keep_samples=False):
     """Langevin refinement of `nsample` samples from the smoothed start; returns the
     posterior-mean RMSE after each step, the mean wall time per step (direct launches,
     steps after the first: the first carries one-time host costs) and, for the
-    preconditioned form, how many samples kept the network's gradient at each step."""
+    preconditioned form, how many samples kept the network's gradient at each step (and
+    the samples themselves with keep_samples).  Noise weight nu (default sqrt(2 eta)).
+    With adam_lr the encoded gradient drives an Adam step of that rate (m/s) instead of
+    -eta g, its moments kept over the chain, followed by the nu-weighted noise and the
+    clamp (the guidance of the paper's experiments; nu = 0 makes it deterministic)."""
+    nu = math.sqrt(2 * eta) if nu is None else nu
     cfg = sv.cfg
     nz, nx = cfg.nz, cfg.nx
     v = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
@@ -156,6 +161,8 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16):
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
     lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
     rmse, kept = [], []
+    if adam_lr is not None:
+        m1, m2 = torch.zeros_like(v).reshape(-1), torch.zeros_like(v).reshape(-1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for t in range(steps):
@@ -170,11 +177,16 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16):
                 g, keep = precondition(net, g.view(nsample, nz, nx), v.view(nsample, nz, nx))
                 g = g.reshape(nsample, -1).contiguous()
                 kept.append(int(keep.sum()))
-        fwi.fwi_langevin(off, v.reshape(-1), g.reshape(-1).contiguous(), None, seed, t, eta, math.sqrt(2 * eta), lo,
-                         hi)
+        g = g.reshape(-1).contiguous()
+        if adam_lr is not None:
+            nn.adam(v.reshape(-1), g, m1, m2, adam_lr, 0.9, 0.999, 1e-8, t + 1)
+            fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, t, 0.0, nu, lo, hi)
+        else:
+            fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, t, eta, nu, lo, hi)
         rmse.append(float((v.double().mean(0) - vt).pow(2).mean().sqrt()))
     torch.cuda.synchronize()
-    return rmse, (time.perf_counter() - t0) / max(1, steps - 1), kept
+    out = (rmse, (time.perf_counter() - t0) / max(1, steps - 1), kept)
+    return out + (v,) if keep_samples else out
 
 
 def time_naive_plain(sv: Survey, v, ncall=8):

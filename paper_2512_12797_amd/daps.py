@@ -204,16 +204,23 @@ def procedural_models(cfg, n, seed0, device="cuda"):
 RENOISE = ("posterior", "marginal", "mean")
 
 
+GUIDE = ("langevin", "adam")
+
+
 def sample(sv, den: Denoiser, sched: Schedule, t_start, K, eta, seed, nsample=16, every=1, nu=None,
-           renoise="posterior", langevin_bounds=None):
+           renoise="posterior", guide="langevin", adam_lr=50.0, langevin_bounds=None):
     """Decoupled diffusion inference of `nsample` posterior samples on the Survey `sv`
-    (chains.Survey: geometry, observed data, starting model): K Langevin steps at levels
-    t_start, t_start - every, ...; noise weight nu (default sqrt(2 eta)); re-noise mode
-    one of RENOISE.  Returns (samples, device f32 [nsample, nphys]; posterior-mean RMSE
+    (chains.Survey: geometry, observed data, starting model): K refinement steps at levels
+    t_start, t_start - every, ...; re-noise mode one of RENOISE.  guide "langevin":
+    z <- clamp(z - eta g + nu xi), nu default sqrt(2 eta); guide "adam": an Adam step of
+    rate adam_lr (m/s) on the encoded gradient, moments restarted at each guided level,
+    then z <- clamp(z + nu xi), nu default 0 (the deterministic guidance of the paper's
+    experiments).  Returns (samples, device f32 [nsample, nphys]; posterior-mean RMSE
     after each level; wall seconds; gradient evaluations per sample)."""
-    if renoise not in RENOISE or every < 1 or K < 0:
-        raise ValueError("renoise must be one of %s, every >= 1, K >= 0" % (RENOISE,))
-    nu = math.sqrt(2 * eta) if nu is None else nu
+    if renoise not in RENOISE or guide not in GUIDE or every < 1 or K < 0:
+        raise ValueError("renoise must be one of %s, guide one of %s, every >= 1, K >= 0" % (RENOISE, GUIDE))
+    if nu is None:
+        nu = math.sqrt(2 * eta) if guide == "langevin" else 0.0
     cfg = sv.cfg
     nz, nx = cfg.nz, cfg.nx
     nphys = sv.grid.nphys
@@ -233,9 +240,15 @@ def sample(sv, den: Denoiser, sched: Schedule, t_start, K, eta, seed, nsample=16
     for t in range(t_start, 0, -1):
         level = torch.full((nsample,), sched.level(t), device=dev)
         v = den.predict(x.view(nsample, nz, nx), level).reshape(nsample, nphys).contiguous()   # (i)
-        for _ in range(K if (t_start - t) % every == 0 else 0):                                 # (ii)
-            g = sv.encoded_gradient(v, nsample, seed, step)
-            fwi.fwi_langevin(off, v.reshape(-1), g.reshape(-1).contiguous(), None, seed, step, eta, nu, lo, hi)
+        if guide == "adam":
+            m1, m2 = torch.zeros(nsample * nphys, device=dev), torch.zeros(nsample * nphys, device=dev)
+        for k in range(K if (t_start - t) % every == 0 else 0):                                 # (ii)
+            g = sv.encoded_gradient(v, nsample, seed, step).reshape(-1).contiguous()
+            if guide == "adam":
+                nn.adam(v.reshape(-1), g, m1, m2, adam_lr, 0.9, 0.999, 1e-8, k + 1)
+                fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, step, 0.0, nu, lo, hi)
+            else:
+                fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, step, eta, nu, lo, hi)
             step += 1
         if t > 1:                                                                                 # (iii)
             if renoise == "marginal":

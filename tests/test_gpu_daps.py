@@ -144,3 +144,54 @@ def test_sampler_plumbing_with_identity_network(M, renoise):
     err = np.abs(got - vo).max()
     say("  max abs error %.3e m/s" % err)
     assert err < 5e-3
+
+
+@pytest.mark.parametrize("guide,nu", [("langevin", 3.0), ("adam", 0.0), ("adam", 2.0)])
+def test_sampler_guidance_steps(M, guide, nu):
+    # The same identity-network chain with K = 2 refinement steps per level, the encoded
+    # gradient replaced by that of (1/2)|v - v_ref|^2 (a stand-in whose value the oracle
+    # can form): checks the Langevin and Adam guidance, the moment restart per level, the
+    # noise counters and the clamp against an FP64 replay.
+    import oracle
+    from types import SimpleNamespace
+    say("case daps sampler guidance, %s nu=%g" % (guide, nu))
+    nz, nx, ns, ts, K, seed = 14, 24, 3, 4, 2, 23
+    r = np.random.default_rng(8)
+    vstart = 3000.0 + 1500.0 * r.random((nz, nx))
+    vref = f32(vstart + r.normal(0.0, 80.0, (nz, nx)))
+    vref_t = dev(vref.ravel())
+    cfg = SimpleNamespace(nz=nz, nx=nx, vmin=2000.0, vmax=6000.0)
+    sv = SimpleNamespace(cfg=cfg, grid=SimpleNamespace(nphys=nz * nx), dev="cuda", vtrue=vref, vstart=vstart,
+                         encoded_gradient=lambda v, n, s, k: v.reshape(n, -1) - vref_t)
+    lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+    eta, lr = 0.1, 20.0
+    den = M.Denoiser(nz, nx, 16, lo, hi, seed=0)
+    v, _, _, ngrad = M.sample(sv, den, M.Schedule(), ts, K, eta, seed, nsample=ns, nu=nu, renoise="marginal",
+                              guide=guide, adam_lr=lr)
+    beta, alpha = D.linear_schedule(1000, 1e-4, 0.02)
+    z0 = np.tile(f32(vstart).ravel(), (ns, 1))
+    x = D.mix(z0, None, [np.sqrt(alpha[ts])] * ns, [0.0] * ns, [np.sqrt(1 - alpha[ts])] * ns, lo, hi, seed, 1001)
+    step = 0
+    for t in range(ts, 0, -1):
+        vo = D.to_model(x, lo, hi)
+        m1, m2 = np.zeros_like(vo), np.zeros_like(vo)
+        for k in range(K):
+            g = vo - vref.ravel()
+            for i in range(ns):
+                xi = oracle.normals(seed, step, i, vo.shape[1])
+                if guide == "adam":
+                    m1[i] = 0.9 * m1[i] + 0.1 * g[i]
+                    m2[i] = 0.999 * m2[i] + 0.001 * g[i] ** 2
+                    p = vo[i] - lr * (m1[i] / (1 - 0.9 ** (k + 1))) / (np.sqrt(m2[i] / (1 - 0.999 ** (k + 1))) + 1e-8)
+                    vo[i] = oracle.langevin(p, np.zeros_like(p), xi, 0.0, nu, lo, hi)
+                else:
+                    vo[i] = oracle.langevin(vo[i], g[i], xi, eta, nu, lo, hi)
+            step += 1
+        if t > 1:
+            x = D.mix(vo, None, [np.sqrt(alpha[t - 1])] * ns, [0.0] * ns, [np.sqrt(1 - alpha[t - 1])] * ns, lo, hi,
+                      seed, t)
+    assert ngrad == ts * K
+    got = v.cpu().numpy().astype(np.float64)
+    err = np.abs(got - vo).max()
+    say("  max abs error %.3e m/s" % err)
+    assert err < 2e-2
