@@ -284,13 +284,7 @@ def daps_bench(torch, args):
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
 
     def stats(v, wall):
-        vd = v.double()
-        mean, std = vd.mean(0), vd.std(0)
-        return {"posterior_mean_rmse_mps": round(float((mean - vt).pow(2).mean().sqrt()), 2),
-                "mean_sample_rmse_mps": round(float((vd - vt).pow(2).mean(1).sqrt().mean()), 2),
-                "mean_posterior_std_mps": round(float(std.mean()), 2),
-                "within_2std": round(float(((mean - vt).abs() <= 2 * std).double().mean()), 3),
-                "wall_s": round(wall, 2), "samples_per_hour": round(nsample / wall * 3600, 1)}
+        return posterior_stats(v, vt, wall, nsample)
 
     runs = {}
     ngrad = None
@@ -323,6 +317,43 @@ def daps_bench(torch, args):
                                "train_s": round(t_train, 1), "loss_first_last": [hist[0][1], hist[-1][1]],
                                "heldout_level_noise_rmse_mps": [[t, round(n, 1), round(e, 1)] for t, n, e in ev]}},
             "runs": runs}
+
+
+def posterior_stats(v, vt, wall, nsample):
+    """Posterior-mean and mean-sample RMSE, mean posterior standard deviation and the share
+    of cells whose posterior-mean error is within two standard deviations (metrics of a
+    batch of samples v, device [nsample, ncell], against the truth vt, f64)."""
+    vd = v.double()
+    mean, std = vd.mean(0), vd.std(0)
+    return {"posterior_mean_rmse_mps": round(float((mean - vt).pow(2).mean().sqrt()), 2),
+            "mean_sample_rmse_mps": round(float((vd - vt).pow(2).mean(1).sqrt().mean()), 2),
+            "mean_posterior_std_mps": round(float(std.mean()), 2),
+            "within_2std": round(float(((mean - vt).abs() <= 2 * std).double().mean()), 3),
+            "wall_s": round(wall, 2), "samples_per_hour": round(nsample / wall * 3600, 1)}
+
+
+def svgd_bench(torch, args):
+    """The SVGD baseline on the 2D encoded workload's survey: 16 particles from the
+    smoothed start (each perturbed by 20 m/s of seeded white noise), RBF kernel with the
+    median bandwidth, step set so that the largest first move is 300 m/s; with full-shot
+    gradients (the paper's baseline) and with the encoded estimate."""
+    from paper_2512_12797_amd import chains, svgd
+    sv = chains.Survey(seed=args.seed, log=log)
+    vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
+    runs = {}
+    for kind, steps in (("full", args.svgd_full_steps), ("encoded", args.svgd_enc_steps)):
+        x, r, wall = svgd.run(sv, steps, 300.0, args.seed, gradient=kind)
+        runs["svgd_" + kind] = dict(posterior_stats(x, vt, wall, 16), steps=steps, s_per_step=round(wall / steps, 4),
+                                    rmse_sampled=[[i + 1, round(r[i], 2)] for i in
+                                                  range(0, len(r), max(1, len(r) // 10))])
+        log("svgd, %s gradients, %d steps: %s" % (kind, steps, runs["svgd_" + kind]))
+    start_rmse = float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2)))
+    return {"metric": "posterior-mean RMSE", "unit": "m/s", "value": runs["svgd_full"]["posterior_mean_rmse_mps"],
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+            "workload": "2d-400x150-thrust-80shot: SVGD, 16 particles from a start smoothed by %g cells (+20 m/s "
+                        "seeded white noise each), RBF kernel, median bandwidth, largest first move 300 m/s"
+                        % sv.start_sigma,
+            "start_rmse_mps": round(start_rmse, 2), "runs": runs}
 
 
 def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e-3, G=1):
@@ -395,7 +426,7 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=0, choices=[0, 1, 2],
                     help="2D keep-all schedule: time steps per adjoint launch (0: the tuner's choice, else 2)")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond", "daps"],
+    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond", "daps", "svgd"],
                     help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
                          "equal-error: posterior samples/hour of plain, encoded and preconditioned chains at equal "
                          "posterior-mean RMSE (several minutes); unet: the gradient preconditioner's network "
@@ -416,6 +447,8 @@ def main():
     ap.add_argument("--daps-max-update", type=float, default=300.0,
                     help="daps: eta is set so that the largest first update is this many m/s")
     ap.add_argument("--daps-lr", type=float, default=50.0, help="daps: Adam guidance rate, m/s")
+    ap.add_argument("--svgd-full-steps", type=int, default=12, help="svgd: steps with full-shot gradients")
+    ap.add_argument("--svgd-enc-steps", type=int, default=100, help="svgd: steps with encoded gradients")
     ap.add_argument("--daps-adam-nu", type=float, default=0.0, help="daps: noise weight after an Adam step")
     ap.add_argument("--daps-models", type=int, default=1024, help="daps: procedural models the prior is trained on")
     ap.add_argument("--daps-train", type=int, default=8000, help="daps: denoiser training steps (batch 8)")
@@ -438,6 +471,9 @@ def main():
         return
     if args.workload == "daps":
         print(json.dumps(daps_bench(torch, args)), flush=True)
+        return
+    if args.workload == "svgd":
+        print(json.dumps(svgd_bench(torch, args)), flush=True)
         return
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains

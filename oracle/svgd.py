@@ -9,7 +9,8 @@ The paper restates no formula; this follows the cited method:
   * RBF kernel k(x, y) = exp(-|x - y|^2 / h);
   * bandwidth by the median heuristic h = med^2 / log n, med^2 read as the median of the
     squared pairwise distances over the pairs i < j (mean of the two middle values when
-    their number is even);
+    their number is even); h = 1 when it is undefined (one particle, or coincident
+    particles: median 0);
   * direction phi(x_i) = (1/n) sum_j [k(x_j, x_i) (-g_j) + grad_{x_j} k(x_j, x_i)], where
     grad_{x_j} k(x_j, x_i) = (2/h) (x_i - x_j) k(x_j, x_i) (the repulsive term);
   * step x_i <- clamp(x_i + eps phi(x_i), lo, hi).
@@ -32,10 +33,14 @@ def sq_distances(x):
 
 
 def bandwidth(D):
-    """Median heuristic: median of D over i < j, divided by log n (n >= 2)."""
+    """Median heuristic: median of D over i < j, divided by log n; 1 when that is not a
+    positive number (n = 1, or coincident particles)."""
     n = D.shape[0]
+    if n < 2:
+        return 1.0
     iu = np.triu_indices(n, 1)
-    return float(np.median(D[iu])) / np.log(n)
+    h = float(np.median(D[iu])) / np.log(n)
+    return h if 0.0 < h < np.inf else 1.0
 
 
 def direction(x, g, h=None):
@@ -46,7 +51,7 @@ def direction(x, g, h=None):
     n = x.shape[0]
     D = sq_distances(x)
     if h is None or h <= 0:
-        h = bandwidth(D) if n > 1 else 1.0
+        h = bandwidth(D)
     K = np.exp(-D / h)
     phi = np.zeros_like(x)
     for i in range(n):

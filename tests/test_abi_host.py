@@ -172,3 +172,32 @@ def test_daps_argument_checks(F):
     assert L.fwi_daps_prep(2, 10, 8, 9, p, p, p, None, None) == F.FWI_E_ARG  # hp < h
     assert L.fwi_daps_model(2, 10, 8, 10, 0, p, 1500.0, 5000.0, p, None) == F.FWI_E_ARG
     assert b"model" in L.fwi_daps_last_error()
+
+
+def test_svgd_argument_checks(F):
+    # host-side checks of the SVGD step: nothing is enqueued
+    from paper_2512_12797_amd import svgd
+    L = svgd._lib()
+    assert svgd.fwi_svgd_work_size(0, 10) == 0 and svgd.fwi_svgd_work_size(65, 10) == 0
+    assert svgd.fwi_svgd_work_size(16, 60000) == 8 * (120 * 15 + 256 + 2)
+    assert svgd.fwi_svgd_work_size(1, 5) == 8 * (1 + 2)
+    a, b, c = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)  # never dereferenced
+    w, nb = C.c_void_p(4 << 20), 1 << 20
+    ok = (4, 100, a, b, 0.1, 0.0, 1500.0, 5000.0, c, None, None, w, nb, None)
+
+    def call(**kw):
+        args = list(ok)
+        for k, v in kw.items():
+            args[{"n": 0, "N": 1, "x": 2, "g": 3, "eps": 4, "lo": 6, "hi": 7, "out": 8, "phi": 9, "w": 11,
+                  "nb": 12}[k]] = v
+        return L.fwi_svgd_step(*args)
+
+    assert call(n=0) == F.FWI_E_ARG and call(n=65) == F.FWI_E_ARG and call(N=0) == F.FWI_E_ARG
+    assert call(x=None) == F.FWI_E_ARG and call(out=None) == F.FWI_E_ARG
+    assert call(eps=-1.0) == F.FWI_E_ARG and call(eps=float("inf")) == F.FWI_E_ARG
+    assert call(lo=5000.0, hi=1500.0) == F.FWI_E_ARG
+    assert call(out=C.c_void_p((1 << 20) + 400)) == F.FWI_E_ARG  # x_out overlaps x (4 x 100 floats)
+    assert call(phi=a) == F.FWI_E_ARG
+    assert call(w=None) == F.FWI_E_WORKSPACE and call(w=C.c_void_p((4 << 20) + 4)) == F.FWI_E_WORKSPACE
+    assert call(nb=8) == F.FWI_E_WORKSPACE
+    assert b"work" in L.fwi_svgd_last_error()

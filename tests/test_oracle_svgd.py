@@ -75,3 +75,13 @@ def test_gaussian_target_moments(sd):
         x, _, _ = S.step(x, x / sd ** 2, 0.1 * sd ** 2, -1e9, 1e9)
     assert abs(x.mean()) < 0.02 * sd
     assert abs(x.std() / sd - 1.0) < 0.1
+
+
+def test_coincident_particles_fall_back_to_unit_bandwidth():
+    # identical particles: every distance is 0, the heuristic's h would be 0; h = 1 gives
+    # k = 1 everywhere and no repulsion, so the direction is minus the mean gradient
+    x = np.ones((3, 4))
+    g = np.arange(12.0).reshape(3, 4)
+    phi, K, h = S.direction(x, g)
+    assert h == 1.0 and np.all(K == 1.0)
+    assert np.allclose(phi, -np.tile(g.mean(0), (3, 1)), rtol=1e-15, atol=0)
