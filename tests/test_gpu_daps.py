@@ -195,3 +195,69 @@ def test_sampler_guidance_steps(M, guide, nu):
     err = np.abs(got - vo).max()
     say("  max abs error %.3e m/s" % err)
     assert err < 2e-2
+
+
+@pytest.mark.parametrize("nu", [0.0, 1.5])
+def test_prior_free_adam_chain(M, nu):
+    # chains.run_chain with Adam guidance: moments kept over the whole chain (bias
+    # correction with the step count), then the noise and the clamp; the stand-in gradient
+    # is that of (1/2)|v - v_ref|^2, replayed by the oracle in FP64
+    import oracle
+    from types import SimpleNamespace
+    from paper_2512_12797_amd import chains
+    say("case prior-free Adam chain, nu=%g" % nu)
+    nz, nx, ns, steps, seed, lr = 6, 10, 2, 5, 31, 15.0
+    r = np.random.default_rng(9)
+    vstart = 3000.0 + 1000.0 * r.random((nz, nx))
+    vref = f32(vstart + r.normal(0.0, 60.0, (nz, nx)))
+    vref_t = dev(vref.ravel())
+    cfg = SimpleNamespace(nz=nz, nx=nx, vmin=2000.0, vmax=6000.0)
+    sv = SimpleNamespace(cfg=cfg, grid=SimpleNamespace(nphys=nz * nx), dev="cuda", vtrue=vref, vstart=vstart,
+                         encoded_gradient=lambda v, n, s, k: v.reshape(n, -1) - vref_t)
+    rmse, _, _, v = chains.run_chain(sv, "encoded", steps, 1e-3, seed, nsample=ns, nu=nu, adam_lr=lr,
+                                     keep_samples=True)
+    lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+    vo = np.tile(f32(vstart).ravel(), (ns, 1))
+    m1, m2 = np.zeros_like(vo), np.zeros_like(vo)
+    for t in range(steps):
+        g = vo - vref.ravel()
+        m1 = 0.9 * m1 + 0.1 * g
+        m2 = 0.999 * m2 + 0.001 * g ** 2
+        p = vo - lr * (m1 / (1 - 0.9 ** (t + 1))) / (np.sqrt(m2 / (1 - 0.999 ** (t + 1))) + 1e-8)
+        for i in range(ns):
+            vo[i] = oracle.langevin(p[i], np.zeros_like(p[i]), oracle.normals(seed, t, i, p.shape[1]), 0.0, nu, lo,
+                                    hi)
+    err = np.abs(v.cpu().numpy().astype(np.float64) - vo).max()
+    say("  max abs error %.3e m/s" % err)
+    assert len(rmse) == steps and err < 1e-2
+
+
+def test_svgd_loop_against_oracle_steps():
+    # svgd.run's particle loop (start perturbation, step size from the first direction,
+    # buffer swap) with the full-shot gradient replaced by that of (1/2)|v - v_ref|^2
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from types import SimpleNamespace
+    from oracle import svgd as S
+    from paper_2512_12797_amd import svgd
+    say("case svgd loop")
+    nz, nx, n, steps, seed = 8, 12, 5, 4, 17
+    r = np.random.default_rng(10)
+    vstart = 3000.0 + 1000.0 * r.random((nz, nx))
+    vref = f32(vstart + r.normal(0.0, 60.0, (nz, nx)))
+    vref_t = dev(vref.ravel())
+    cfg = SimpleNamespace(nz=nz, nx=nx, vmin=2000.0, vmax=6000.0)
+    sv = SimpleNamespace(cfg=cfg, grid=SimpleNamespace(nphys=nz * nx), dev="cuda", vtrue=vref, vstart=vstart,
+                         full_gradient=lambda v, k: v.reshape(k, -1) - vref_t)
+    x, rmse, _ = svgd.run(sv, steps, 40.0, seed, n=n, gradient="full")
+    lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+    xo = f32(np.clip(vstart.ravel()[None, :] + np.random.default_rng(seed).normal(0.0, 20.0, (n, nz * nx)), lo, hi))
+    eps = None
+    for _ in range(steps):
+        g = xo - vref.ravel()
+        if eps is None:
+            eps = 40.0 / np.abs(S.direction(xo, g)[0]).max()
+        xo, _, _ = S.step(xo, g, eps, lo, hi)
+    err = np.abs(x.cpu().numpy().astype(np.float64) - xo).max()
+    say("  max abs error %.3e m/s" % err)
+    assert len(rmse) == steps and err < 1e-2
