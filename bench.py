@@ -284,7 +284,7 @@ def daps_bench(torch, args):
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
 
     def stats(v, wall):
-        return posterior_stats(v, vt, wall, nsample)
+        return posterior_stats(v, vt, wall, nsample, cfg.nz)
 
     runs = {}
     ngrad = None
@@ -295,6 +295,11 @@ def daps_bench(torch, args):
         runs["daps_" + guide] = dict(stats(v, wall), rmse_per_level_sampled=[
             [args.daps_tstart - i, round(r_d[i], 2)] for i in range(0, len(r_d), max(1, len(r_d) // 10))])
         log("daps, %s guidance: %s" % (guide, runs["daps_" + guide]))
+    # the prior alone (no refinement): the spread the data have to narrow
+    v, _, wall, _ = daps.sample(sv, den, sched, args.daps_tstart, 0, eta, args.seed, nsample,
+                                every=args.daps_every, renoise=args.daps_renoise)
+    runs["daps_prior_only"] = stats(v, wall)
+    log("daps, prior only: %s" % runs["daps_prior_only"])
     for guide in ("langevin", "adam"):
         t2 = time.perf_counter()
         r_e, s_e, _, v = chains.run_chain(sv, "encoded", ngrad, eta, args.seed, nsample=nsample,
@@ -319,16 +324,23 @@ def daps_bench(torch, args):
             "runs": runs}
 
 
-def posterior_stats(v, vt, wall, nsample):
+def posterior_stats(v, vt, wall, nsample, nz):
     """Posterior-mean and mean-sample RMSE, mean posterior standard deviation and the share
     of cells whose posterior-mean error is within two standard deviations (metrics of a
-    batch of samples v, device [nsample, ncell], against the truth vt, f64)."""
+    batch of samples v, device [nsample, ncell], against the truth vt, f64), and the
+    standard deviation and posterior-mean error by depth third (nz rows; the surface
+    acquisition illuminates the shallow third best)."""
     vd = v.double()
     mean, std = vd.mean(0), vd.std(0)
+    err = (mean - vt).abs()
+    thirds = [(0, nz // 3), (nz // 3, 2 * nz // 3), (2 * nz // 3, nz)]
+    sd2, er2 = std.view(nz, -1), err.view(nz, -1)
     return {"posterior_mean_rmse_mps": round(float((mean - vt).pow(2).mean().sqrt()), 2),
             "mean_sample_rmse_mps": round(float((vd - vt).pow(2).mean(1).sqrt().mean()), 2),
             "mean_posterior_std_mps": round(float(std.mean()), 2),
-            "within_2std": round(float(((mean - vt).abs() <= 2 * std).double().mean()), 3),
+            "within_2std": round(float((err <= 2 * std).double().mean()), 3),
+            "std_by_depth_third_mps": [round(float(sd2[a:b].mean()), 1) for a, b in thirds],
+            "abs_error_by_depth_third_mps": [round(float(er2[a:b].mean()), 1) for a, b in thirds],
             "wall_s": round(wall, 2), "samples_per_hour": round(nsample / wall * 3600, 1)}
 
 
@@ -343,7 +355,7 @@ def svgd_bench(torch, args):
     runs = {}
     for kind, steps in (("full", args.svgd_full_steps), ("encoded", args.svgd_enc_steps)):
         x, r, wall = svgd.run(sv, steps, 300.0, args.seed, gradient=kind)
-        runs["svgd_" + kind] = dict(posterior_stats(x, vt, wall, 16), steps=steps, s_per_step=round(wall / steps, 4),
+        runs["svgd_" + kind] = dict(posterior_stats(x, vt, wall, 16, sv.cfg.nz), steps=steps, s_per_step=round(wall / steps, 4),
                                     rmse_sampled=[[i + 1, round(r[i], 2)] for i in
                                                   range(0, len(r), max(1, len(r) // 10))])
         log("svgd, %s gradients, %d steps: %s" % (kind, steps, runs["svgd_" + kind]))
