@@ -33,7 +33,8 @@ size_t fwi_svgd_work_size(int32_t n, int64_t N);
  * One SVGD step for n particles (1 <= n <= 64) of N cells each:
  *   x, grad: device f32 [n][N] (particle j at x + j N);
  *   x_out:   device f32 [n][N], the moved particles; must not overlap x or grad;
- *   phi:     device f32 [n][N] or NULL, the direction (before eps and the clamp);
+ *   phi:     device f32 [n][N] or NULL, the direction (before eps and the clamp); must not
+ *            overlap x, grad or x_out;
  *   h_out:   device f64 [1] or NULL, the bandwidth used;
  *   eps >= 0 the step (eps = 0 leaves x_out = clamp(x) and still writes phi);
  *   h > 0 fixes the bandwidth, h <= 0 selects the median heuristic (n >= 2; with n = 1,
@@ -42,8 +43,8 @@ size_t fwi_svgd_work_size(int32_t n, int64_t N);
  * Distances, bandwidth, kernel and direction are computed in FP64 (distances summed in an
  * order fixed by N alone, so results are reproducible run to run); outputs rounded once.
  * FWI_E_ARG: null x, grad or x_out, n or N out of range, eps < 0 or not finite, v_hi <=
- * v_lo, x_out overlapping x or grad.  FWI_E_WORKSPACE: work null, misaligned or smaller
- * than fwi_svgd_work_size.
+ * v_lo, x_out or phi overlapping x, grad or each other.  FWI_E_WORKSPACE: work null,
+ * misaligned or smaller than fwi_svgd_work_size.
  */
 fwi_status fwi_svgd_step(int32_t n, int64_t N, const float *x, const float *grad, float eps, float h, float v_lo,
                          float v_hi, float *x_out, float *phi, double *h_out, void *work, size_t work_bytes,

@@ -182,9 +182,9 @@ fwi_status fwi_svgd_step(int32_t n, int64_t N, const float *x, const float *grad
     if (!(eps >= 0.0f) || !std::isfinite(eps)) return svgd_fail(FWI_E_ARG, "step: eps must be finite and >= 0");
     if (!(v_hi > v_lo)) return svgd_fail(FWI_E_ARG, "step: need v_hi > v_lo");
     const int64_t total = (int64_t)n * N;
-    if (overlaps(x_out, x, total) || overlaps(x_out, grad, total) || (phi && (overlaps(phi, x_out, total) ||
-                                                                             overlaps(phi, x, total))))
-        return svgd_fail(FWI_E_ARG, "step: x_out (and phi) must not overlap x or grad");
+    if (overlaps(x_out, x, total) || overlaps(x_out, grad, total) ||
+        (phi && (overlaps(phi, x_out, total) || overlaps(phi, x, total) || overlaps(phi, grad, total))))
+        return svgd_fail(FWI_E_ARG, "step: x_out and phi must not overlap x, grad or each other");
     if (!work || (uintptr_t)work % 8 || work_bytes < need)
         return svgd_fail(FWI_E_WORKSPACE, "step: work null, misaligned or under %zu bytes", need);
     hipStream_t s = (hipStream_t)stream;

@@ -197,7 +197,7 @@ def test_svgd_argument_checks(F):
     assert call(eps=-1.0) == F.FWI_E_ARG and call(eps=float("inf")) == F.FWI_E_ARG
     assert call(lo=5000.0, hi=1500.0) == F.FWI_E_ARG
     assert call(out=C.c_void_p((1 << 20) + 400)) == F.FWI_E_ARG  # x_out overlaps x (4 x 100 floats)
-    assert call(phi=a) == F.FWI_E_ARG
+    assert call(phi=a) == F.FWI_E_ARG and call(phi=b) == F.FWI_E_ARG and call(phi=c) == F.FWI_E_ARG
     assert call(w=None) == F.FWI_E_WORKSPACE and call(w=C.c_void_p((4 << 20) + 4)) == F.FWI_E_WORKSPACE
     assert call(nb=8) == F.FWI_E_WORKSPACE
     assert b"work" in L.fwi_svgd_last_error()
