@@ -2,9 +2,8 @@
  * fwi_daps.h -- C ABI of the diffusion outer loop around the Langevin refinement: the
  * decoupled diffusion inference of Sec. 2 ("Decoupled diffusion inference with encoded
  * shots data"): predict a clean model from the noisy state x_t with the predict-x0
- * network (Eq. x0-pred), refine it with the encoded-gradient Langevin steps (fwi.h), and
- * re-noise it to the next level with the DDPM posterior (Eqs. renoise, ddpm-posterior0,
- * ddpm-posterior).
+ * network (Eq. 7), refine it with the encoded-gradient Langevin steps (fwi.h), and
+ * re-noise it to the next level with the DDPM posterior (Eqs. 10-12).
  *
  * Models live in two spaces: physical velocities v (m/s) and the diffusion model's
  * normalised space x = 2 (v - v_lo) / (v_hi - v_lo) - 1 (in [-1, 1] for v in [v_lo, v_hi]).

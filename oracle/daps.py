@@ -5,8 +5,8 @@ Sec. 2, "Diffusion prior and reverse parameterization" and "Decoupled diffusion 
 with encoded shots data":
   * a variance schedule beta_t (t = 1..T) with alpha_t = prod_{s<=t} (1 - beta_s) and
     alpha_0 = 1; the forward diffusion q(x_t | x_0) = N(sqrt(alpha_t) x_0, (1 - alpha_t) I);
-  * the re-noise step (Eq. renoise): x_{t-1} ~ N(mu~_t(x_t, x_0), beta~_t I), with the DDPM
-    posterior variance (Eq. ddpm-posterior0) and mean (Eq. ddpm-posterior);
+  * the re-noise step (Eq. 10): x_{t-1} ~ N(mu~_t(x_t, x_0), beta~_t I), with the DDPM
+    posterior variance (Eq. 11) and mean (Eq. 12);
   * models normalised to [-1, 1] for the network; physical units for the likelihood.
 The noise of a draw is the counter-based stream of ``normals_key`` with tag DAPS_TAG
 (counter words a = step, b = image).
@@ -31,7 +31,7 @@ def linear_schedule(T, beta_1, beta_T):
 
 def posterior(beta, alpha, t):
     """(c_x0, c_xt, beta_tilde) of q(x_{t-1} | x_t, x_0) at level t >= 1:
-    mu~ = c_x0 x_0 + c_xt x_t (Eq. ddpm-posterior), beta~ (Eq. ddpm-posterior0)."""
+    mu~ = c_x0 x_0 + c_xt x_t (Eq. 12), beta~ (Eq. 11)."""
     bt, at, atm1 = beta[t], alpha[t], alpha[t - 1]
     c_x0 = np.sqrt(atm1) * bt / (1.0 - at)
     c_xt = np.sqrt(1.0 - bt) * (1.0 - atm1) / (1.0 - at)

@@ -3,12 +3,12 @@
 with encoded shots data"; the proposed-framework table).
 
 For a batch of posterior samples at diffusion level t, from t_start down to 1:
-  (i)   predict the clean model x0^ = g(x_t, t) (Eq. x0-pred) with the U-Net, in the
+  (i)   predict the clean model x0^ = g(x_t, t) (Eq. 7) with the U-Net, in the
         normalised space (input: x_t and its noise level sqrt(1 - alpha_t); the network's
         output is added to x_t), and map it to m/s (fwi_daps_prep, fwi_daps_model);
   (ii)  take K Langevin steps from it with the encoded-shot gradient (Eq. 6 estimate,
         fwi_gradient + fwi_langevin);
-  (iii) re-noise: x_{t-1} ~ N(mu~_t(x_t, z), beta~_t) in the normalised space (Eq. renoise,
+  (iii) re-noise: x_{t-1} ~ N(mu~_t(x_t, z), beta~_t) in the normalised space (Eq. 10,
         fwi_daps_mix); at t = 1 the refined model is the sample.
 The chain starts from the last levels: x_{t_start} is the forward diffusion of the
 starting model (a warm start instead of pure noise).  Guidance may be injected every few
