@@ -41,16 +41,17 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("terms", ["both", "z", "x", "inplace"])
-def test_mix_matches_oracle(M, terms):
-    say("case daps mix, %s" % terms)
+@pytest.mark.parametrize("terms,nimg,n", [("both", 3, 1001), ("z", 3, 1001), ("x", 3, 1001), ("inplace", 3, 1001),
+                                          ("both", 16, 60000)])
+def test_mix_matches_oracle(M, terms, nimg, n):
+    # 1001 cells: a partial Philox block per image; 16 x 60000: the 2D workload's samples
+    say("case daps mix, %s, %d x %d" % (terms, nimg, n))
     r = np.random.default_rng(3)
-    nimg, n = 3, 1001  # n not a multiple of 4: a partial Philox block per image
     z = f32(r.uniform(LO, HI, (nimg, n)))
     x = f32(r.uniform(-1.2, 1.2, (nimg, n)))
     c0 = f32(r.uniform(0.1, 1.0, nimg))
     c1 = f32(r.uniform(0.0, 1.0, nimg))
-    sig = f32([0.3, 0.0, 0.02])
+    sig = f32(([0.3, 0.0, 0.02] * nimg)[:nimg])
     seed, step = 77, 5
     zz = z if terms in ("both", "z", "inplace") else None
     xx = x if terms in ("both", "x", "inplace") else None
@@ -82,12 +83,13 @@ def test_forward_diffusion_statistics(M):
     assert abs(float(a.var()) / (1 - sched.alpha[t]) - 1) < 5 * np.sqrt(2.0 / n)
 
 
-@pytest.mark.parametrize("hp", [150, 152])
-def test_prep_matches_oracle(M, hp):
+@pytest.mark.parametrize("nimg,w,hp", [(2, 40, 150), (2, 40, 152), (8, 400, 152)])
+def test_prep_matches_oracle(M, nimg, w, hp):
+    say("case daps prep, %d x 150 x %d -> %d rows" % (nimg, w, hp))
     r = np.random.default_rng(4)
-    nimg, h, w = 2, 150, 40
+    h = 150
     x = f32(r.uniform(-1, 1, (nimg, h, w)))
-    level = f32([0.05, 0.3])
+    level = f32(r.uniform(0.01, 0.5, nimg))
     x16 = torch.empty(nimg, hp, w, 16, dtype=torch.int16, device="cuda")
     res = torch.empty(nimg, hp, w, device="cuda")
     M.fwi_daps_prep(nimg, h, w, hp, dev(x), dev(level), x16, res)
@@ -99,9 +101,10 @@ def test_prep_matches_oracle(M, hp):
     assert np.array_equal(res.cpu().numpy().astype(np.float64), rref)
 
 
-def test_model_matches_oracle(M):
+@pytest.mark.parametrize("nimg,w", [(2, 40), (8, 400)])
+def test_model_matches_oracle(M, nimg, w):
     r = np.random.default_rng(5)
-    nimg, h, w, hp, c = 2, 150, 40, 152, 32
+    h, hp, c = 150, 152, 32
     pred = f32(r.uniform(-1.3, 1.3, (nimg, hp, w, c)))
     v = torch.empty(nimg, h, w, device="cuda")
     M.fwi_daps_model(nimg, h, w, hp, c, dev(pred), LO, HI, v)
