@@ -372,7 +372,7 @@ def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e
     """The learned preconditioner at the pair configuration's full scale: about 10k pairs
     (2500 seeded thrust / salt models on 256 x 256 patches at 10 m, 32 surface shots of a
     10 Hz Ricker over 1500 steps, 4 encoded supergathers of 8 shots per model) generated by
-    the library, split 90 / 10 by model, the network trained on the first part and judged
+    the library, split 90 / 10 by model, the network trained on the first part and scored
     on the held-out part: relative L2 error to the full-shot gradient of the plain encoded
     gradient, of the network's estimate and of the guarded result."""
     from paper_2512_12797_amd import precond
