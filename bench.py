@@ -347,24 +347,28 @@ def posterior_stats(v, vt, wall, nsample, nz):
 def svgd_bench(torch, args):
     """The SVGD baseline on the 2D encoded workload's survey: 16 particles from the
     smoothed start (each perturbed by 20 m/s of seeded white noise), RBF kernel with the
-    median bandwidth, step set so that the largest first move is 300 m/s; with full-shot
-    gradients (the paper's baseline) and with the encoded estimate."""
+    median bandwidth, step set so that the largest first move is 300 m/s, or an Adam
+    ascent along the Stein direction at --daps-lr m/s; with full-shot gradients (the
+    paper's baseline) and with the encoded estimate."""
     from paper_2512_12797_amd import chains, svgd
     sv = chains.Survey(seed=args.seed, log=log)
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
     runs = {}
     for kind, steps in (("full", args.svgd_full_steps), ("encoded", args.svgd_enc_steps)):
-        x, r, wall = svgd.run(sv, steps, 300.0, args.seed, gradient=kind)
-        runs["svgd_" + kind] = dict(posterior_stats(x, vt, wall, 16, sv.cfg.nz), steps=steps, s_per_step=round(wall / steps, 4),
-                                    rmse_sampled=[[i + 1, round(r[i], 2)] for i in
-                                                  range(0, len(r), max(1, len(r) // 10))])
-        log("svgd, %s gradients, %d steps: %s" % (kind, steps, runs["svgd_" + kind]))
+        for step_rule in ("", "_adam"):
+            x, r, wall = svgd.run(sv, steps, 300.0, args.seed, gradient=kind,
+                                  adam_lr=args.daps_lr if step_rule else None)
+            name = "svgd_" + kind + step_rule
+            runs[name] = dict(posterior_stats(x, vt, wall, 16, sv.cfg.nz), steps=steps,
+                              s_per_step=round(wall / steps, 4),
+                              rmse_sampled=[[i + 1, round(r[i], 2)] for i in range(0, len(r), max(1, len(r) // 10))])
+            log("%s, %d steps: %s" % (name, steps, runs[name]))
     start_rmse = float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2)))
     return {"metric": "posterior-mean RMSE", "unit": "m/s", "value": runs["svgd_full"]["posterior_mean_rmse_mps"],
             "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "dtype": "f32",
             "workload": "2d-400x150-thrust-80shot: SVGD, 16 particles from a start smoothed by %g cells (+20 m/s "
-                        "seeded white noise each), RBF kernel, median bandwidth, largest first move 300 m/s"
-                        % sv.start_sigma,
+                        "seeded white noise each), RBF kernel, median bandwidth, largest first move 300 m/s "
+                        "(_adam runs: Adam ascent along the Stein direction at %g m/s)" % (sv.start_sigma, args.daps_lr),
             "start_rmse_mps": round(start_rmse, 2), "runs": runs}
 
 

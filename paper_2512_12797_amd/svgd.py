@@ -11,7 +11,7 @@ import time
 import numpy as np
 import torch
 
-from . import fwi
+from . import fwi, nn
 
 _bound = False
 
@@ -43,13 +43,15 @@ def fwi_svgd_step(n, N, x, grad, eps, h, v_lo, v_hi, x_out, phi=None, h_out=None
         raise fwi.FwiError(st, _lib().fwi_svgd_last_error().decode())
 
 
-def run(sv, steps, max_update, seed, n=16, gradient="full", init_sd=20.0, h=0.0):
+def run(sv, steps, max_update, seed, n=16, gradient="full", init_sd=20.0, h=0.0, adam_lr=None):
     """SVGD on the Survey `sv` (chains.Survey) from the smoothed start, each particle
     perturbed by seeded white noise of init_sd m/s (SVGD needs distinct particles: from
     coincident ones it moves them as one).  The step eps is set so that the largest
-    first move is max_update m/s.  gradient: "full" (every shot, the paper's baseline) or
-    "encoded" (Eq. 6 estimate).  Returns (particles, device f32 [n, nphys]; posterior-mean
-    RMSE after each step; wall seconds)."""
+    first move is max_update m/s; with adam_lr the Stein direction instead drives an Adam
+    ascent of that rate (m/s), moments kept over the run, then the clamp.  gradient:
+    "full" (every shot, the paper's baseline) or "encoded" (Eq. 6 estimate).  Returns
+    (particles, device f32 [n, nphys]; posterior-mean RMSE after each step; wall
+    seconds)."""
     cfg = sv.cfg
     nphys = sv.grid.nphys
     dev = sv.dev
@@ -63,6 +65,9 @@ def run(sv, steps, max_update, seed, n=16, gradient="full", init_sd=20.0, h=0.0)
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=dev)
     rmse = []
     eps = None
+    if adam_lr is not None:
+        m1, m2 = torch.zeros(n * nphys, device=dev), torch.zeros(n * nphys, device=dev)
+        off = np.arange(n + 1, dtype=np.int64) * nphys
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -71,6 +76,14 @@ def run(sv, steps, max_update, seed, n=16, gradient="full", init_sd=20.0, h=0.0)
         else:
             g = sv.encoded_gradient(x, n, seed, k)
         g = g.reshape(n, nphys).contiguous()
+        if adam_lr is not None:
+            # phi only (x2 receives the clamped x and is not used); Adam with rate -adam_lr
+            # on phi ascends along it; then the clamp in place
+            fwi_svgd_step(n, nphys, x, g, 0.0, h, lo, hi, x2, phi, None, work)
+            nn.adam(x.reshape(-1), phi.reshape(-1), m1, m2, -adam_lr, 0.9, 0.999, 1e-8, k + 1)
+            fwi.fwi_langevin(off, x.reshape(-1), phi.reshape(-1), None, seed, k, 0.0, 0.0, lo, hi)
+            rmse.append(float((x.double().mean(0) - vt).pow(2).mean().sqrt()))
+            continue
         if eps is None:
             fwi_svgd_step(n, nphys, x, g, 0.0, h, lo, hi, x2, phi, None, work)
             eps = max_update / float(phi.abs().max())

@@ -235,15 +235,17 @@ def test_prior_free_adam_chain(M, nu):
     assert len(rmse) == steps and err < 1e-2
 
 
-def test_svgd_loop_against_oracle_steps():
+@pytest.mark.parametrize("adam_lr", [None, 12.0])
+def test_svgd_loop_against_oracle_steps(adam_lr):
     # svgd.run's particle loop (start perturbation, step size from the first direction,
-    # buffer swap) with the full-shot gradient replaced by that of (1/2)|v - v_ref|^2
+    # buffer swap; or the Adam ascent along the Stein direction) with the full-shot
+    # gradient replaced by that of (1/2)|v - v_ref|^2
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from types import SimpleNamespace
     from oracle import svgd as S
     from paper_2512_12797_amd import svgd
-    say("case svgd loop")
+    say("case svgd loop, adam %s" % adam_lr)
     nz, nx, n, steps, seed = 8, 12, 5, 4, 17
     r = np.random.default_rng(10)
     vstart = 3000.0 + 1000.0 * r.random((nz, nx))
@@ -252,12 +254,20 @@ def test_svgd_loop_against_oracle_steps():
     cfg = SimpleNamespace(nz=nz, nx=nx, vmin=2000.0, vmax=6000.0)
     sv = SimpleNamespace(cfg=cfg, grid=SimpleNamespace(nphys=nz * nx), dev="cuda", vtrue=vref, vstart=vstart,
                          full_gradient=lambda v, k: v.reshape(k, -1) - vref_t)
-    x, rmse, _ = svgd.run(sv, steps, 40.0, seed, n=n, gradient="full")
+    x, rmse, _ = svgd.run(sv, steps, 40.0, seed, n=n, gradient="full", adam_lr=adam_lr)
     lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
     xo = f32(np.clip(vstart.ravel()[None, :] + np.random.default_rng(seed).normal(0.0, 20.0, (n, nz * nx)), lo, hi))
     eps = None
-    for _ in range(steps):
+    m1, m2 = np.zeros_like(xo), np.zeros_like(xo)
+    for k in range(steps):
         g = xo - vref.ravel()
+        if adam_lr is not None:
+            phi = S.direction(xo, g)[0]
+            m1 = 0.9 * m1 + 0.1 * phi
+            m2 = 0.999 * m2 + 0.001 * phi ** 2
+            xo = np.clip(xo + adam_lr * (m1 / (1 - 0.9 ** (k + 1))) / (np.sqrt(m2 / (1 - 0.999 ** (k + 1))) + 1e-8),
+                         lo, hi)
+            continue
         if eps is None:
             eps = 40.0 / np.abs(S.direction(xo, g)[0]).max()
         xo, _, _ = S.step(xo, g, eps, lo, hi)
