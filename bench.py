@@ -724,6 +724,16 @@ def main():
                      "bytes_per_launch": int(round(nbytes)), "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
                      "copy_probe_GBs": round(copy_gbs, 1)},
     }
+    # all step kernels of one gradient together (forward and adjoint sweeps): their
+    # algorithmic bytes over their summed live durations, and the share of the step's wall
+    # time they take
+    k_s = (fwd_ms + adj_ms) / 1e3
+    if k_s > 0 and fwd_n and adj_n:
+        all_gbs = (fwd_bytes * fwd_n + adj_bytes * adj_n) / k_s / 1e9
+        res["roofline_step_kernels"] = {
+            "bound": "hbm", "achieved": round(all_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(all_gbs / PEAK_HBM_GBS, 4), "of_copy_probe": round(all_gbs / copy_gbs, 3),
+            "kernel_ms_per_gradient": round(1e3 * k_s, 2), "share_of_step": round(k_s / (elapsed / args.steps), 4)}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         # the oracle keeps every wavefield of a simulation in host memory: the 3D sample is a
