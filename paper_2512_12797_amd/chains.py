@@ -144,7 +144,8 @@ def precondition(net, g_enc, v):
 
 # -------------------------------------------------------------------- chains
 
-def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None, adam_lr=None, keep_samples=False):
+def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None, adam_lr=None, keep_samples=False,
+              v0=None, step0=0):
     """Langevin refinement of `nsample` samples from the smoothed start; returns the
     posterior-mean RMSE after each step, the mean wall time per step (direct launches,
     steps after the first: the first carries one-time host costs) and, for the
@@ -152,11 +153,20 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
     the samples themselves with keep_samples).  Noise weight nu (default sqrt(2 eta)).
     With adam_lr the encoded gradient drives an Adam step of that rate (m/s) instead of
     -eta g, its moments kept over the chain, followed by the nu-weighted noise and the
-    clamp (the guidance of the paper's experiments; nu = 0 makes it deterministic)."""
+    clamp (the guidance of the paper's experiments; nu = 0 makes it deterministic).
+    Resume: v0 (device f32 [nsample, nphys]) and step0 continue a chain saved after step0
+    steps; the encodings and the noise are counter-based (seed, step, sample), so the
+    continuation equals the uninterrupted chain bit for bit (not for the Adam form, whose
+    moments are not part of the saved state)."""
     nu = math.sqrt(2 * eta) if nu is None else nu
+    if step0 and adam_lr is not None:
+        raise ValueError("the Adam form cannot resume: its moments are not saved")
     cfg = sv.cfg
     nz, nx = cfg.nz, cfg.nx
-    v = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
+    if v0 is None:
+        v = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
+    else:
+        v = v0.reshape(nsample, -1).clone()
     off = np.arange(nsample + 1, dtype=np.int64) * sv.grid.nphys
     vt = torch.tensor(sv.vtrue.ravel(), dtype=torch.float64, device=sv.dev)
     lo, hi = cfg.vmin * 0.9, cfg.vmax * 1.1
@@ -172,7 +182,7 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
         if form == "plain":
             g = sv.full_gradient(v, nsample)
         else:
-            g = sv.encoded_gradient(v, nsample, seed, t)
+            g = sv.encoded_gradient(v, nsample, seed, step0 + t)
             if form == "preconditioned":
                 g, keep = precondition(net, g.view(nsample, nz, nx), v.view(nsample, nz, nx))
                 g = g.reshape(nsample, -1).contiguous()
@@ -182,11 +192,24 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
             nn.adam(v.reshape(-1), g, m1, m2, adam_lr, 0.9, 0.999, 1e-8, t + 1)
             fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, t, 0.0, nu, lo, hi)
         else:
-            fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, t, eta, nu, lo, hi)
+            fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, step0 + t, eta, nu, lo, hi)
         rmse.append(float((v.double().mean(0) - vt).pow(2).mean().sqrt()))
     torch.cuda.synchronize()
     out = (rmse, (time.perf_counter() - t0) / max(1, steps - 1), kept)
     return out + (v,) if keep_samples else out
+
+
+def save_state(path, v, step, seed):
+    """Chain state after `step` steps: the samples (device or host f32 [nsample, nphys]),
+    the step count and the seed, as an .npz of plain arrays (no pickled objects)."""
+    np.savez(path, v=np.ascontiguousarray(v.detach().cpu().numpy() if torch.is_tensor(v) else v, dtype=np.float32),
+             step=np.int64(step), seed=np.int64(seed))
+
+
+def load_state(path, device="cuda"):
+    """(samples as device f32 [nsample, nphys], step, seed) saved by save_state."""
+    with np.load(path, allow_pickle=False) as z:
+        return torch.tensor(z["v"], device=device), int(z["step"]), int(z["seed"])
 
 
 def time_naive_plain(sv: Survey, v, ncall=8):
