@@ -19,6 +19,7 @@ launch pattern, decides the trajectory).
 """
 from __future__ import annotations
 
+import json
 import math
 import time
 
@@ -145,7 +146,7 @@ def precondition(net, g_enc, v):
 # -------------------------------------------------------------------- chains
 
 def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None, adam_lr=None, keep_samples=False,
-              v0=None, step0=0):
+              v0=None, step0=0, log_jsonl=None):
     """Langevin refinement of `nsample` samples from the smoothed start; returns the
     posterior-mean RMSE after each step, the mean wall time per step (direct launches,
     steps after the first: the first carries one-time host costs) and, for the
@@ -157,7 +158,9 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
     Resume: v0 (device f32 [nsample, nphys]) and step0 continue a chain saved after step0
     steps; the encodings and the noise are counter-based (seed, step, sample), so the
     continuation equals the uninterrupted chain bit for bit (not for the Adam form, whose
-    moments are not part of the saved state)."""
+    moments are not part of the saved state).  log_jsonl: a file that receives one JSON
+    line per step (step, posterior-mean RMSE, mean posterior standard deviation, PDE solves
+    per sample so far, seconds since the start)."""
     nu = math.sqrt(2 * eta) if nu is None else nu
     if step0 and adam_lr is not None:
         raise ValueError("the Adam form cannot resume: its moments are not saved")
@@ -194,6 +197,14 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
         else:
             fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, step0 + t, eta, nu, lo, hi)
         rmse.append(float((v.double().mean(0) - vt).pow(2).mean().sqrt()))
+        if log_jsonl:
+            # one forward and one adjoint solve per shot (plain) or per supergather (encoded)
+            per_step = 2 * len(sv.shots) // (1 if form == "plain" else sv.cfg.shots_per_group)
+            with open(log_jsonl, "a") as f:
+                f.write(json.dumps({"step": step0 + t, "posterior_mean_rmse_mps": rmse[-1],
+                                    "mean_posterior_std_mps": float(v.double().std(0).mean()) if nsample > 1 else 0.0,
+                                    "pde_solves_per_sample": (step0 + t + 1) * per_step,
+                                    "elapsed_s": time.perf_counter() - t0}) + "\n")
     torch.cuda.synchronize()
     out = (rmse, (time.perf_counter() - t0) / max(1, steps - 1), kept)
     return out + (v,) if keep_samples else out
