@@ -16,21 +16,32 @@ from . import fwi
 
 class _FwiData(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, v, batch, time, ws):
-        nt_rec = time.nt // time.rec_every
-        d = torch.empty(batch.data_size(nt_rec), dtype=torch.float32, device=v.device)
+    def forward(ctx, v, op):
+        nt_rec = op.time.nt // op.time.rec_every
+        d = torch.empty(op.batch.data_size(nt_rec), dtype=torch.float32, device=v.device)
         vd = v.detach().contiguous()
-        fwi.fwi_forward(batch, time, vd, d, ws)
+        fwi.fwi_forward(op.batch, op.time, vd, d, op.ws)
+        op._calls += 1
+        op._holds = op._calls  # the workspace now holds the state of this forward
         ctx.save_for_backward(vd)
-        ctx.batch, ctx.time, ctx.ws = batch, time, ws
+        ctx.op, ctx.token = op, op._calls
         return d
 
     @staticmethod
     def backward(ctx, grad_d):
         (v,) = ctx.saved_tensors
+        op = ctx.op
+        if op._holds != ctx.token:
+            # a later forward on the same operator replaced this one's checkpoints (or
+            # imaging operands): recompute them from the saved model first
+            nt_rec = op.time.nt // op.time.rec_every
+            scratch = torch.empty(op.batch.data_size(nt_rec), dtype=torch.float32, device=v.device)
+            fwi.fwi_forward(op.batch, op.time, v, scratch, op.ws)
+            op._holds = ctx.token
+            op.replays += 1
         grad = torch.empty_like(v)
-        fwi.fwi_adjoint(ctx.batch, ctx.time, v, grad_d.contiguous().float(), None, grad, None, ctx.ws)
-        return grad, None, None, None
+        fwi.fwi_adjoint(op.batch, op.time, v, grad_d.contiguous().float(), None, grad, None, op.ws)
+        return grad, None
 
 
 class FwiOperator:
@@ -38,17 +49,22 @@ class FwiOperator:
 
     ``ckpt_every`` (time axis) selects the schedule: 0 keeps every imaging operand, K >= 1
     keeps checkpoints every K steps and recomputes each segment in the backward pass.
-    The workspace is allocated once and reused; one forward must be followed by its
-    backward before the next forward (the workspace holds that forward's state).
+    The workspace is allocated once and reused.  It holds the state of the most recent
+    forward; a backward through an earlier output (two forwards in one loss, a probe
+    taken before backward, gradcheck) first re-runs that output's forward from its saved
+    model (counted in ``replays``), so every backward sees its own forward's state.
     """
 
     def __init__(self, batch: fwi.Batch, time, device="cuda"):
         self.batch, self.time = batch, time
         fwi.fwi_check(batch, time)
         self.ws = fwi.alloc_workspace(batch, time, device)
+        self._calls = 0      # forwards run so far
+        self._holds = 0      # which of them the workspace holds
+        self.replays = 0     # forwards re-run by a backward
 
     def __call__(self, v: torch.Tensor) -> torch.Tensor:
-        return _FwiData.apply(v, self.batch, self.time, self.ws)
+        return _FwiData.apply(v, self)
 
     def split(self, d: torch.Tensor):
         """Per-simulation views [nt_rec][nrec] of a flat data tensor."""

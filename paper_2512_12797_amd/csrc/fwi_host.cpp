@@ -701,28 +701,26 @@ size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz)
 
 // ----------------------------------------------------------- host staging
 
+// The tables of a call are staged in host memory and copied to the workspace with one
+// asynchronous copy.  Each thread owns two pinned staging buffers used in turn, so a call
+// waits only for the upload two calls back on the same thread (its buffer is then free
+// again) and calls from distinct threads never wait for each other.
 struct Stager {
-    std::mutex m;
-    void *host = nullptr;
-    size_t cap = 0;
-    hipEvent_t ev = nullptr;
-    bool pending = false;
+    struct Slot {
+        void *host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Slot slot[2];
+    int next = 0;
+    // no destructor: a thread's buffers stay until the process ends (releasing them at
+    // thread or process exit could run after the HIP runtime has shut down)
 };
-Stager g_stage;
+thread_local Stager t_stage;
 
-fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
+void fill_tables(const Plan &p, uint8_t *h)
 {
-    std::lock_guard<std::mutex> lk(g_stage.m);
-    if (g_stage.pending) HIP_TRY(hipEventSynchronize(g_stage.ev));
-    g_stage.pending = false;
-    if (g_stage.cap < p.t_bytes) {
-        if (g_stage.host) HIP_TRY(hipHostFree(g_stage.host));
-        g_stage.host = nullptr;
-        g_stage.cap = 0;
-        HIP_TRY(hipHostMalloc(&g_stage.host, p.t_bytes, hipHostMallocDefault));
-        g_stage.cap = p.t_bytes;
-    }
-    uint8_t *h = (uint8_t *)g_stage.host;
     memset(h, 0, p.t_bytes);
     memcpy(h + p.t_sims, p.sims.data(), p.sims.size() * sizeof(SimDesc));
     memcpy(h + p.t_samples, p.samples.data(), p.samples.size() * sizeof(SampleDesc));
@@ -734,10 +732,27 @@ fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
     if (!p.evvec.empty()) memcpy(h + p.t_evvec, p.evvec.data(), p.evvec.size() * sizeof(int32_t));
     if (!p.src.empty()) memcpy(h + p.t_src, p.src.data(), p.src.size() * sizeof(SrcPos));
     if (!p.order.empty()) memcpy(h + p.t_order, p.order.data(), p.order.size() * sizeof(int32_t));
-    HIP_TRY(hipMemcpyAsync(dst, h, p.t_bytes, hipMemcpyHostToDevice, st));
-    if (!g_stage.ev) HIP_TRY(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(g_stage.ev, st));
-    g_stage.pending = true;
+}
+
+fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
+{
+    Stager &g = t_stage;
+    Stager::Slot &sl = g.slot[g.next];
+    g.next ^= 1;
+    if (sl.pending) HIP_TRY(hipEventSynchronize(sl.ev));
+    sl.pending = false;
+    if (sl.cap < p.t_bytes) {
+        if (sl.host) HIP_TRY(hipHostFree(sl.host));
+        sl.host = nullptr;
+        sl.cap = 0;
+        HIP_TRY(hipHostMalloc(&sl.host, p.t_bytes, hipHostMallocDefault));
+        sl.cap = p.t_bytes;
+    }
+    fill_tables(p, (uint8_t *)sl.host);
+    HIP_TRY(hipMemcpyAsync(dst, sl.host, p.t_bytes, hipMemcpyHostToDevice, st));
+    if (!sl.ev) HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(sl.ev, st));
+    sl.pending = true;
     return FWI_OK;
 }
 
@@ -829,7 +844,8 @@ struct GraphCache {
     std::mutex m;
     bool on = false;
     struct Entry {
-        uint64_t key;
+        uint64_t key;        // hash of `full`, compared first
+        std::string full;    // every byte that went into the key
         hipGraphExec_t exec;
         uint64_t used;
     };
@@ -840,11 +856,15 @@ struct GraphCache {
 GraphCache g_graphs;
 constexpr size_t kMaxGraphs = 8;
 
+// Graph key: the bytes of every value that reaches a kernel argument, kept whole (a cached
+// graph is replayed only on a byte-for-byte match) and hashed (FNV-1a) for a quick compare.
 struct KeyHash {
-    uint64_t h = 1469598103934665603ULL;  // FNV-1a
+    uint64_t h = 1469598103934665603ULL;
+    std::string full;
     void bytes(const void *p, size_t n)
     {
         const uint8_t *c = (const uint8_t *)p;
+        full.append((const char *)c, n);
         for (size_t i = 0; i < n; ++i) {
             h ^= c[i];
             h *= 1099511628211ULL;
@@ -882,7 +902,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
 void destroy_entry(GraphCache::Entry &e) { (void)hipGraphExecDestroy(e.exec); }
 
 template <class Body>
-fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
+fwi_status run_maybe_graph(const KeyHash &key, hipStream_t st, Body body)
 {
     bool use;
     {
@@ -892,7 +912,7 @@ fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
     if (!use) return body(st);
     std::lock_guard<std::mutex> lk(g_graphs.m);
     for (auto &e : g_graphs.entries)
-        if (e.key == key) {
+        if (e.key == key.h && e.full == key.full) {
             e.used = ++g_graphs.tick;
             g_graphs.replays++;
             HIP_TRY(hipGraphLaunch(e.exec, st));
@@ -902,7 +922,7 @@ fwi_status run_maybe_graph(uint64_t key, hipStream_t st, Body body)
     fwi_status s = body(st);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(st, &graph);
-    GraphCache::Entry ent{key, nullptr, 0};
+    GraphCache::Entry ent{key.h, key.full, nullptr, 0};
     if (s || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         return s ? s : fail(FWI_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -1268,7 +1288,7 @@ fwi_status fwi_forward(const fwi_batch *b, const fwi_time *t, const float *v, fl
     k.add(1);
     k.add(v); k.add(d_pred); k.add(ws); k.add(st);
     hash_plan(k, p, b, t);
-    return run_maybe_graph(k.h, st, [&](hipStream_t s2) { return run_forward(p, d, b, t, v, d_pred ? d_pred : d.rho, s2); });
+    return run_maybe_graph(k, st, [&](hipStream_t s2) { return run_forward(p, d, b, t, v, d_pred ? d_pred : d.rho, s2); });
 }
 
 fwi_status fwi_adjoint(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_res,
@@ -1287,7 +1307,7 @@ fwi_status fwi_adjoint(const fwi_batch *b, const fwi_time *t, const float *v, co
     k.add(2);
     k.add(v); k.add(d_res); k.add(grad); k.add(grad_norm); k.add(ws); k.add(st);
     hash_plan(k, p, b, t);
-    return run_maybe_graph(k.h, st, [&](hipStream_t s2) -> fwi_status {
+    return run_maybe_graph(k, st, [&](hipStream_t s2) -> fwi_status {
         HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, s2));
         return run_adjoint(p, d, b, t, v, d_res, grad, grad_norm, s2);
     });
@@ -1313,7 +1333,7 @@ fwi_status fwi_gradient(const fwi_batch *b, const fwi_time *t, const float *v, c
     k.add(v); k.add(d_obs); k.add(inv_sigma2); k.add(d_pred); k.add(misfit); k.add(grad); k.add(grad_norm);
     k.add(ws); k.add(st);
     hash_plan(k, p, b, t);
-    return run_maybe_graph(k.h, st, [&](hipStream_t s2) -> fwi_status {
+    return run_maybe_graph(k, st, [&](hipStream_t s2) -> fwi_status {
         fwi_status r = run_forward(p, d, b, t, v, dat, s2);
         if (r) return r;
         HIP_TRY(launch_residual(d.sims, b->nsim, p.nt_rec, dat, d_obs, d.rho, inv_sigma2, d.part, p.nchunk_res,

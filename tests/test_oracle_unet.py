@@ -77,3 +77,91 @@ def test_bf16_rounding():
     assert r[2] == 1.0 + 2 ** -7  # round up
     assert abs(r[3] + 3.140625) < 1e-12
     assert r[4] == 0.0
+
+
+# ---------------------------------------------------- input preparation and the guard
+
+def test_prep_input_hand_computed_scale_and_padding():
+    """RMS scale over the image's own h x w cells (padded rows never count), BF16 inputs,
+    zero rows below h, and scale 1 for an all-zero image."""
+    g = np.array([[[3.0, 4.0], [0.0, 0.0]],        # RMS sqrt(25 / 4) = 2.5 over the 2 x 2 image
+                  [[0.0, 0.0], [0.0, 0.0]]])       # all zero: scale 1
+    v = np.array([[[3000.0, 2500.0], [3500.0, 2000.0]]] * 2)
+    x, res, scale = U.prep_input(g, v, 4, 2500.0, 1000.0)
+    assert x.shape == (2, 4, 2, 2) and res.shape == (2, 4, 2)
+    assert scale[0] == 2.5 and scale[1] == 1.0      # an RMS over the 4 padded rows would be 1.768
+    assert np.array_equal(res[0, :2], [[1.2, 1.6], [0.0, 0.0]])
+    # 1.2 and 1.6 rounded to BF16 (8 significant bits): 154/128 and 205/128
+    assert np.array_equal(x[0, :2, :, 0], [[154 / 128, 205 / 128], [0.0, 0.0]])
+    assert np.array_equal(x[0, :2, :, 1], [[0.5, 0.0], [1.0, -0.5]])
+    assert not x[:, 2:].any() and not res[:, 2:].any()
+    assert not x[1, :, :, 0].any()
+    # no model: channel 1 stays zero
+    x2, _, _ = U.prep_input(g, None, 2, 0.0, 1.0)
+    assert not x2[..., 1].any()
+
+
+def test_prep_input_scale_equivariance_and_given_scale():
+    r = np.random.default_rng(5)
+    g = r.standard_normal((3, 5, 7))
+    x, res, scale = U.prep_input(g, None, 8, 0.0, 1.0)
+    xs, ress, scales = U.prep_input(4.0 * g, None, 8, 0.0, 1.0)
+    assert np.allclose(scales, 4.0 * scale, rtol=1e-15)
+    assert np.allclose(ress, res, rtol=1e-14, atol=0) and np.array_equal(xs, x)
+    # a given scale replaces the RMS
+    _, res2, scale2 = U.prep_input(g, None, 5, 0.0, 1.0, scale=np.array([2.0, 4.0, 0.5]))
+    assert np.array_equal(scale2, [2.0, 4.0, 0.5])
+    assert np.array_equal(res2[1], g[1] / 4.0)
+
+
+def _guard_case(p, g, hp=3, scale=2.0, junk=7.0):
+    """pred0 rows of a padded height hp (rows past h hold junk the guard must ignore)."""
+    g = np.asarray(g, dtype=np.float64)[None]
+    pred0 = np.full((1, hp, g.shape[2]), junk)
+    pred0[0, :g.shape[1]] = np.asarray(p, dtype=np.float64) / scale
+    return pred0, np.array([scale]), g
+
+
+def test_guard_thresholds_are_inclusive():
+    """p = (3, 9; 3, 1) has |p| = 10.  Against g = (2, 0; 0, 0): cos = 0.3, |p|/|g| = 5;
+    against g = (50, 0; 0, 0): cos = 0.3, |p|/|g| = 0.2.  All exact in FP64, so the
+    bounds cos >= 0.3 and 0.2 <= ratio <= 5 are hit exactly: kept; one ulp past: fallback."""
+    p = [[3.0, 9.0], [3.0, 1.0]]
+    for gv, lo, hi in (([[2.0, 0.0], [0.0, 0.0]], 0.2, 5.0), ([[50.0, 0.0], [0.0, 0.0]], 0.2, 5.0)):
+        pred0, sc, g = _guard_case(p, gv)
+        out, keep = U.guard(pred0, sc, g, 0.3, lo, hi)
+        assert keep[0] and np.array_equal(out[0], p)
+        # one ulp stricter in each threshold that is active: the plain gradient comes back
+        ratio = 10.0 / np.abs(g).max()
+        strict = [(np.nextafter(0.3, 1.0), lo, hi)]
+        if ratio == hi:
+            strict.append((0.3, lo, np.nextafter(hi, 0.0)))
+        else:
+            strict.append((0.3, np.nextafter(lo, 1.0), hi))
+        for c, l, h in strict:
+            out, keep = U.guard(pred0, sc, g, c, l, h)
+            assert not keep[0] and np.array_equal(out[0], g[0])
+
+
+def test_guard_zero_norms_fall_back():
+    p = [[3.0, 9.0], [3.0, 1.0]]
+    # zero plain gradient: the network output is never kept (the ratio is undefined)
+    pred0, sc, g = _guard_case(p, [[0.0, 0.0], [0.0, 0.0]])
+    out, keep = U.guard(pred0, sc, g, -1.0, 0.0, np.inf)
+    assert not keep[0] and not out.any()
+    # zero network output: fall back to g even with the loosest thresholds
+    pred0, sc, g = _guard_case([[0.0, 0.0], [0.0, 0.0]], [[1.0, 2.0], [3.0, 4.0]])
+    out, keep = U.guard(pred0, sc, g, -1.0, 0.0, np.inf)
+    assert not keep[0] and np.array_equal(out[0], g[0])
+
+
+def test_guard_per_image_decision_and_scale():
+    """Two images in one call, one kept and one rejected (cosine -0.3 < 0), each decided on
+    its own; the kept output is scale * pred0."""
+    p0 = np.array([[3.0, 9.0], [3.0, 1.0]])
+    g = np.array([[[2.0, 0.0], [0.0, 0.0]], [[-2.0, 0.0], [0.0, 0.0]]])
+    pred0 = np.full((2, 4, 2), -3.0)
+    pred0[:, :2] = p0 / 8.0
+    out, keep = U.guard(pred0, np.array([8.0, 8.0]), g, 0.0, 0.2, 5.0)
+    assert list(keep) == [True, False]
+    assert np.array_equal(out[0], p0) and np.array_equal(out[1], g[1])
