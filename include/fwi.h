@@ -161,6 +161,33 @@ fwi_status fwi_gradient(const fwi_batch *b, const fwi_time *t, const float *v, c
                         float inv_sigma2, const double *kappa, float *d_pred, double *misfit, float *grad,
                         float *grad_norm, void *ws, size_t ws_bytes, void *stream);
 
+/* Largest workspace the allocation-free gradient can use, in bytes. */
+#define FWI_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/*
+ * fwi_gradient_noalloc -- fwi_gradient for callers that cannot allocate memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Arguments, outputs and arithmetic are those of fwi_gradient without the workspace
+ * arguments: the workspace is a device array of FWI_NOALLOC_MAX_BYTES that the library
+ * holds on every GPU it runs on (from the loading of the library until the process ends),
+ * taken on the current device.
+ *   Size: a batch whose fwi_workspace_size exceeds FWI_NOALLOC_MAX_BYTES is rejected with
+ *   FWI_E_WORKSPACE before anything is enqueued.  Other errors as fwi_gradient.
+ *   The call allocates no device or pinned host memory (its tables are copied from host
+ *   heap memory), never replays or records a graph (fwi_graphs_enable does not apply)
+ *   and takes no kernel timings (fwi_timing_enable does not apply).
+ *   Sharing: every call on one GPU uses that GPU's one array, and each call starts by
+ *   clearing what must start at zero.  Calls ordered on one stream are fine; calls that
+ *   overlap in time on one GPU (other streams, other threads) race and give undefined
+ *   results.  fwi_forward / fwi_adjoint / fwi_gradient on caller workspaces are unaffected.
+ *   Device findings (non-finite values, a model outside (0, v_max]) cannot be polled for
+ *   this call (fwi_poll_status needs a caller workspace); non-finite values propagate to
+ *   the outputs.
+ */
+fwi_status fwi_gradient_noalloc(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_obs,
+                                float inv_sigma2, const double *kappa, float *d_pred, double *misfit, float *grad,
+                                float *grad_norm, void *stream);
+
 /*
  * Encoded observed data (Eq. 4): d_enc[g] = sum_{k in grp_ptr[g]..grp_ptr[g+1]-1}
  * grp_w[k] d_shots[grp_shot[k]], each item n_per_shot floats.

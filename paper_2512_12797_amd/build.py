@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwi_mi355.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["fwi_kernels.hip", "fwi_host.cpp", "nn_kernels.hip", "daps_kernels.hip", "svgd_kernels.hip"]
+SOURCES = ["fwi_kernels.hip", "fwi_host.cpp", "fwi_static.hip", "nn_kernels.hip", "daps_kernels.hip", "svgd_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code: some of their forms have given
 # wrong results now and then on this hardware; hipcc -O3 would otherwise emit them by itself

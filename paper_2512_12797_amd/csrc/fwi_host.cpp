@@ -18,6 +18,11 @@
 #include "fwi_internal.h"
 #include "fwi_launch.h"
 
+namespace fwi {
+// device array of the allocation-free gradient (fwi_static.hip)
+hipError_t noalloc_scratch(void **ptr, size_t *bytes);
+}  // namespace fwi
+
 using namespace fwi;
 
 namespace {
@@ -704,7 +709,9 @@ size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz)
 // The tables of a call are staged in host memory and copied to the workspace with one
 // asynchronous copy.  Each thread owns two pinned staging buffers used in turn, so a call
 // waits only for the upload two calls back on the same thread (its buffer is then free
-// again) and calls from distinct threads never wait for each other.
+// again) and calls from distinct threads never wait for each other.  Allocation-free
+// calls stage in host heap memory with a pageable copy instead (the runtime consumes the
+// source before the copy call returns).
 struct Stager {
     struct Slot {
         void *host = nullptr;
@@ -714,6 +721,7 @@ struct Stager {
     };
     Slot slot[2];
     int next = 0;
+    std::vector<uint8_t> heap;  // allocation-free calls
     // no destructor: a thread's buffers stay until the process ends (releasing them at
     // thread or process exit could run after the HIP runtime has shut down)
 };
@@ -734,9 +742,15 @@ void fill_tables(const Plan &p, uint8_t *h)
     if (!p.order.empty()) memcpy(h + p.t_order, p.order.data(), p.order.size() * sizeof(int32_t));
 }
 
-fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st)
+fwi_status upload_tables(const Plan &p, uint8_t *dst, hipStream_t st, bool noalloc = false)
 {
     Stager &g = t_stage;
+    if (noalloc) {
+        g.heap.resize(p.t_bytes);
+        fill_tables(p, g.heap.data());
+        HIP_TRY(hipMemcpyAsync(dst, g.heap.data(), p.t_bytes, hipMemcpyHostToDevice, st));
+        return FWI_OK;
+    }
     Stager::Slot &sl = g.slot[g.next];
     g.next ^= 1;
     if (sl.pending) HIP_TRY(hipEventSynchronize(sl.ev));
@@ -786,6 +800,9 @@ hipError_t pooled_event(hipEvent_t *ev)
     return hipSuccess;
 }
 
+// Set for the duration of an allocation-free call: its launches take no timing events.
+thread_local bool t_untimed = false;
+
 // One timed run of launches; inactive when timing is off or the stream is being captured
 // (the runtime gives no elapsed time for events recorded by graph replays).
 struct RunTimer {
@@ -795,6 +812,7 @@ struct RunTimer {
 
     hipError_t begin(int k, hipStream_t s)
     {
+        if (t_untimed) return hipSuccess;
         {
             std::lock_guard<std::mutex> lk(g_timing.m);
             if (!g_timing.on) return hipSuccess;
@@ -1234,6 +1252,46 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
     return FWI_OK;
 }
 
+// fwi_gradient on a given workspace; `noalloc`: stage tables without pinned memory, no
+// graph replay or capture, no timing (the allocation-free entry point)
+fwi_status gradient_call(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_obs, float inv_sigma2,
+                         const double *kappa, float *d_pred, double *misfit, float *grad, float *grad_norm, void *ws,
+                         size_t ws_bytes, hipStream_t st, bool noalloc)
+{
+    Plan p;
+    fwi_status s = prologue(b, t, kappa, ws, ws_bytes, p);
+    if (s) return s;
+    if (!v || !d_obs || !grad) return fail(FWI_E_ARG, "null model, observed data or gradient");
+    if (p.fwd_only) return fail(FWI_E_ARG, "ckpt_every = -1 keeps no adjoint state");
+    if (!std::isfinite(inv_sigma2) || !(inv_sigma2 > 0)) return fail(FWI_E_ARG, "inv_sigma2 must be > 0");
+    Dev d = carve(p, ws);
+    s = upload_tables(p, d.base + p.o_tables, st, noalloc);
+    if (s) return s;
+    float *dat = d_pred ? d_pred : d.rho;
+    auto body = [&](hipStream_t s2) -> fwi_status {
+        fwi_status r = run_forward(p, d, b, t, v, dat, s2);
+        if (r) return r;
+        HIP_TRY(launch_residual(d.sims, b->nsim, p.nt_rec, dat, d_obs, d.rho, inv_sigma2, d.part, p.nchunk_res,
+                                d.status, s2));
+        HIP_TRY(launch_misfit_final(d.part, p.nchunk_res, b->nsim, 0.5 * (double)inv_sigma2,
+                                    misfit ? misfit : d.mis, s2));
+        return run_adjoint(p, d, b, t, v, d.rho, grad, grad_norm, s2);
+    };
+    if (noalloc) {
+        struct Untimed {
+            Untimed() { t_untimed = true; }
+            ~Untimed() { t_untimed = false; }
+        } untimed;
+        return body(st);
+    }
+    KeyHash k;
+    k.add(3);
+    k.add(v); k.add(d_obs); k.add(inv_sigma2); k.add(d_pred); k.add(misfit); k.add(grad); k.add(grad_norm);
+    k.add(ws); k.add(st);
+    hash_plan(k, p, b, t);
+    return run_maybe_graph(k, st, body);
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1317,31 +1375,27 @@ fwi_status fwi_gradient(const fwi_batch *b, const fwi_time *t, const float *v, c
                         float inv_sigma2, const double *kappa, float *d_pred, double *misfit, float *grad,
                         float *grad_norm, void *ws, size_t ws_bytes, void *stream)
 {
-    Plan p;
-    fwi_status s = prologue(b, t, kappa, ws, ws_bytes, p);
+    return gradient_call(b, t, v, d_obs, inv_sigma2, kappa, d_pred, misfit, grad, grad_norm, ws, ws_bytes,
+                         (hipStream_t)stream, false);
+}
+
+fwi_status fwi_gradient_noalloc(const fwi_batch *b, const fwi_time *t, const float *v, const float *d_obs,
+                                float inv_sigma2, const double *kappa, float *d_pred, double *misfit, float *grad,
+                                float *grad_norm, void *stream)
+{
+    if (!b || !t) return fail(FWI_E_ARG, "null batch or time axis");
+    size_t need = 0;
+    fwi_status s = fwi_workspace_size(b, t, &need);
     if (s) return s;
-    if (!v || !d_obs || !grad) return fail(FWI_E_ARG, "null model, observed data or gradient");
-    if (p.fwd_only) return fail(FWI_E_ARG, "ckpt_every = -1 keeps no adjoint state");
-    if (!std::isfinite(inv_sigma2) || !(inv_sigma2 > 0)) return fail(FWI_E_ARG, "inv_sigma2 must be > 0");
-    hipStream_t st = (hipStream_t)stream;
-    Dev d = carve(p, ws);
-    s = upload_tables(p, d.base + p.o_tables, st);
-    if (s) return s;
-    float *dat = d_pred ? d_pred : d.rho;
-    KeyHash k;
-    k.add(3);
-    k.add(v); k.add(d_obs); k.add(inv_sigma2); k.add(d_pred); k.add(misfit); k.add(grad); k.add(grad_norm);
-    k.add(ws); k.add(st);
-    hash_plan(k, p, b, t);
-    return run_maybe_graph(k, st, [&](hipStream_t s2) -> fwi_status {
-        fwi_status r = run_forward(p, d, b, t, v, dat, s2);
-        if (r) return r;
-        HIP_TRY(launch_residual(d.sims, b->nsim, p.nt_rec, dat, d_obs, d.rho, inv_sigma2, d.part, p.nchunk_res,
-                                d.status, s2));
-        HIP_TRY(launch_misfit_final(d.part, p.nchunk_res, b->nsim, 0.5 * (double)inv_sigma2,
-                                    misfit ? misfit : d.mis, s2));
-        return run_adjoint(p, d, b, t, v, d.rho, grad, grad_norm, s2);
-    });
+    void *ws = nullptr;
+    size_t cap = 0;
+    hipError_t e = noalloc_scratch(&ws, &cap);
+    if (e != hipSuccess) return fail(FWI_E_HIP, "device array of the allocation-free gradient: %s", hipGetErrorString(e));
+    if (need > cap)
+        return fail(FWI_E_WORKSPACE, "the batch needs a %zu-byte workspace; the allocation-free gradient holds %zu",
+                    need, cap);
+    return gradient_call(b, t, v, d_obs, inv_sigma2, kappa, d_pred, misfit, grad, grad_norm, ws, cap,
+                         (hipStream_t)stream, true);
 }
 
 fwi_status fwi_encode(const float *d_shots, int32_t nshot, int64_t n_per_shot, int32_t ngrp, const int32_t *grp_ptr,

@@ -67,6 +67,10 @@ def lib():
         L.fwi_gradient.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p, C.c_float,
                                    C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_size_t, C.c_void_p]
+        L.fwi_gradient_noalloc.restype = C.c_int32
+        L.fwi_gradient_noalloc.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p,
+                                           C.c_float, C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]
         L.fwi_encode.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_int32, C.c_void_p, C.c_void_p]
         L.fwi_draw_encoding.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
@@ -264,6 +268,27 @@ def fwi_gradient(batch, time, v, d_obs, inv_sigma2, kappa, d_pred, misfit, grad,
     _ok(lib().fwi_gradient(batch.c, C.byref(time), _ptr(v), _ptr(d_obs), C.c_float(inv_sigma2),
                            k[1] if k else None, _ptr(d_pred), _ptr(misfit), _ptr(grad), _ptr(grad_norm),
                            _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def fwi_gradient_noalloc(batch, time, v, d_obs, inv_sigma2, kappa, d_pred, misfit, grad, grad_norm,
+                         stream=None):
+    """fwi_gradient on the library's own device array (FWI_NOALLOC_MAX_BYTES): no workspace."""
+    import torch
+    _check_f32(v, batch.model_size, "v")
+    nd = batch.data_size(time.nt // time.rec_every)
+    _check_f32(d_obs, nd, "d_obs")
+    if d_pred is not None:
+        _check_f32(d_pred, nd, "d_pred")
+    if misfit is not None and (misfit.dtype != torch.float64 or misfit.numel() < batch.nsim):
+        raise ValueError("misfit: need a float64 device tensor with nsim elements")
+    _check_f32(grad, batch.model_size, "grad")
+    k = _kappa(kappa, batch.nsample)
+    _ok(lib().fwi_gradient_noalloc(batch.c, C.byref(time), _ptr(v), _ptr(d_obs), C.c_float(inv_sigma2),
+                                   k[1] if k else None, _ptr(d_pred), _ptr(misfit), _ptr(grad), _ptr(grad_norm),
+                                   _stream(stream)))
+
+
+NOALLOC_MAX_BYTES = 64 << 20  # FWI_NOALLOC_MAX_BYTES
 
 
 def fwi_encode(d_shots, grp_ptr, grp_shot, grp_w, d_enc, stream=None):
