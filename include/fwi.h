@@ -280,6 +280,37 @@ fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays);
  * the timing.  The workspace content is overwritten.
  */
 fwi_status fwi_set_tile(int32_t ndim, int32_t bz);
+
+/*
+ * Width of the 3D step kernels' tiles, process-wide: 64 cells (8 rows per tile, one row
+ * per wavefront) or 32 cells (16 rows per tile, two rows per wavefront); 0 (the default)
+ * picks per batch the width that leaves fewer lanes idle over its padded grids (x extent
+ * rounded up to the width, y extent to the tile's rows).  Results are identical for both
+ * widths; only the speed differs.  The workspace size covers either width.
+ */
+fwi_status fwi_set_tile_width(int32_t wx);
+
+/*
+ * Checkpointed schedules (ckpt_every = K >= 1): recomputation of a segment beside the
+ * adjoint of the segment after it, process-wide (default off).  While the adjoint sweeps
+ * segment s on the caller's stream, segment s - 1 is recomputed on a library-owned side
+ * stream (one per device, default priority) into a second ring of K imaging-operand
+ * levels; events order every ring write after the adjoint sweep that last read it, and
+ * the caller's stream waits for the side stream before it reads a segment, so a call is
+ * still complete when its stream's work is.  Results are identical with and without the
+ * overlap.  The workspace then holds 2K instead of K imaging levels (fwi_workspace_size
+ * follows the setting at the time it is called; change it before sizing workspaces).
+ * Graph capture includes the side stream's work.  fwi_gradient_noalloc never overlaps.
+ */
+fwi_status fwi_set_overlap(int32_t on);
+
+/*
+ * Tile shape the step kernels would use for (b, t) under the current process-wide
+ * settings (forced or tuned tile height, tile width): bz = rows per 2D tile or planes per
+ * 3D tile, wx = tile width in cells (64 in 2D; 64 or 32 in 3D).  Host-only; both outputs
+ * nullable.
+ */
+fwi_status fwi_tile_shape(const fwi_batch *b, const fwi_time *t, int32_t *bz, int32_t *wx);
 fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void *ws, size_t ws_bytes, void *stream,
                     const char *cache_path, int32_t *bz_out, int32_t *adj_steps_out, double *ms_out);
 

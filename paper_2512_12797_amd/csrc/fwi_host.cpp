@@ -164,6 +164,7 @@ fwi_status check_all(const fwi_batch *b, const fwi_time *t, double *worst)
 struct Plan {
     int ndim = 2;
     int bz = 32, ty = 8;
+    int wx = kTileX;  // 3D tile width: 64 or 32 cells (ty = 8 * 64 / wx rows)
     std::vector<SimDesc> sims;
     std::vector<SampleDesc> samples;
     std::vector<Tile> tiles;
@@ -191,6 +192,7 @@ struct Plan {
     // layout
     int nlev = 2, K = 0, nseg = 1;
     bool fwd_only = false;  // ckpt_every == -1: no adjoint state is kept
+    bool overlap = false;   // checkpoints: recompute the next segment beside the current adjoint
     int64_t wst_levels = 0, ck_slots = 0;
     int nchunk_res = 1, nchunk_fin = 1;
     size_t t_sims = 0, t_samples = 0, t_tiles = 0, t_gtiles = 0, t_tiles2 = 0, t_gtiles2 = 0, t_evrows = 0,
@@ -243,6 +245,12 @@ void set_tuned(const std::string &sig, int bz, int adj)
     g_tiles.tuned.push_back({sig, bz, adj});
 }
 
+// 3D tile width forced process-wide (fwi_set_tile_width): 0 automatic, 32 or 64.
+std::atomic<int> g_width3{0};
+
+// Overlap of recomputation and adjoint in checkpointed schedules (fwi_set_overlap).
+std::atomic<int> g_overlap{0};
+
 // Time steps per launch of the 2D keep-all schedule, forward and adjoint, process-wide:
 // 1 or 2 forced, 0 automatic (forward 1; adjoint the tuned choice for the batch shape,
 // else 2).
@@ -275,9 +283,29 @@ bool valid_bz(int ndim, int bz)
     return bz == 16 || bz == 32;
 }
 
-void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
+// 3D tile width: 32-wide tiles (two rows per wavefront, 16 rows per tile) when they leave
+// fewer lanes idle over the batch's grids than 64-wide ones (8 rows per tile), unless a
+// width is forced.
+int pick_width3(const fwi_batch *b)
 {
-    p.ty = p.ndim == 3 ? kTileY3 : 1;
+    const int forced = g_width3.load();
+    if (forced == 32 || forced == 64) return forced;
+    int64_t lanes[2] = {0, 0};
+    for (int s = 0; s < b->nsim; ++s) {
+        const fwi_grid &g = b->grid[b->sample_of[s]];
+        const int64_t Nx = g.nx + 2 * g.nb, Ny = g.ny + 2 * g.nb;
+        for (int i = 0; i < 2; ++i) {
+            const int64_t wx = i == 0 ? 64 : 32, ty = 8 * (64 / wx);
+            lanes[i] += ((Nx + wx - 1) / wx) * wx * ((Ny + ty - 1) / ty) * ty;
+        }
+    }
+    return lanes[1] < lanes[0] ? 32 : 64;
+}
+
+void pick_tiles(Plan &p, const fwi_batch *b, int bz_override, int wx_override)
+{
+    p.wx = p.ndim == 3 ? (wx_override == 32 || wx_override == 64 ? wx_override : pick_width3(b)) : kTileX;
+    p.ty = p.ndim == 3 ? 8 * (kTileX / p.wx) : 1;
     if (valid_bz(p.ndim, bz_override)) {
         p.bz = bz_override;
         return;
@@ -301,7 +329,7 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
         for (int s = 0; s < b->nsim; ++s) {
             const fwi_grid &g = b->grid[b->sample_of[s]];
             int64_t Nx = g.nx + 2 * g.nb, Nz = g.nz + 2 * g.nb, Ny = p.ndim == 3 ? g.ny + 2 * g.nb : 1;
-            n += ((Nx + kTileX - 1) / kTileX) * ((Nz + bz - 1) / bz) * ((Ny + p.ty - 1) / p.ty);
+            n += ((Nx + p.wx - 1) / p.wx) * ((Nz + bz - 1) / bz) * ((Ny + p.ty - 1) / p.ty);
         }
         return n;
     };
@@ -322,7 +350,7 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override)
     }
 }
 
-size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz);
+size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz, int wx);
 
 // Wavefronts per workgroup of the per-sample 2D adjoint for samples of up to g sims and
 // ngt strips.  Four waves (fewer for smaller samples) pack the kernel's occupancy (six
@@ -344,12 +372,13 @@ int s_tiles_end(const Plan &p, int s)
 }
 
 fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa, Plan &p, int bz_override = 0,
-                      bool size_for_all_tiles = true)
+                      bool size_for_all_tiles = true, int wx_override = 0, bool no_overlap = false)
 {
     p.ndim = b->grid[0].ndim;
-    pick_tiles(p, b, bz_override);
+    pick_tiles(p, b, bz_override, wx_override);
     p.nt_rec = t->nt / t->rec_every;
     const int TYt = p.ndim == 3 ? p.ty : 1;
+    const int WXt = p.ndim == 3 ? p.wx : kTileX;  // tile width
     // samples
     p.samples.resize(b->nsample);
     for (int k = 0; k < b->nsample; ++k) {
@@ -412,7 +441,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         p.cells += Sm.ncell;
         p.data += (int64_t)p.nt_rec * S.nrec;
         // tiles: z block, then y block, then x strip
-        const int ntx = (S.N[2] + kTileX - 1) / kTileX;
+        const int ntx = (S.N[2] + WXt - 1) / WXt;
         const int nty = (S.N[1] + TYt - 1) / TYt;
         const int ntz = (S.N[0] + p.bz - 1) / p.bz;
         const int tile0 = (int)p.tiles.size();
@@ -422,7 +451,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
                     Tile T;
                     memset(&T, 0, sizeof T);
                     T.sim = s;
-                    T.x0 = ix * kTileX;
+                    T.x0 = ix * WXt;
                     T.y0 = iy * TYt;
                     T.z0 = iz * p.bz;
                     p.tiles.push_back(T);
@@ -432,8 +461,8 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
             const int32_t c = b->rec_cell[b->rec_ptr[s] + r];
             const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
             const int px = ix + g.nb, py = iy + nby, pz = iz + g.nb;
-            const int tl = tile0 + ((pz / p.bz) * nty + py / TYt) * ntx + px / kTileX;
-            evs.push_back({tl, pz, (py % TYt) * kTileX + px % kTileX, r});
+            const int tl = tile0 + ((pz / p.bz) * nty + py / TYt) * ntx + px / WXt;
+            evs.push_back({tl, pz, (py % TYt) * WXt + px % WXt, r});
         }
     }
     for (int s = 0; s < b->nsim; ++s) {
@@ -452,7 +481,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     std::sort(evs.begin(), evs.end(), [](const Ev &a, const Ev &b) {
         return a.tile != b.tile ? a.tile < b.tile : a.z < b.z;
     });
-    const int vec = kTileX * TYt;
+    const int vec = WXt * TYt;
     for (size_t i = 0; i < evs.size();) {
         size_t j = i;
         EvRow row{evs[i].z, (int32_t)p.evvec.size()};
@@ -562,7 +591,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.bzg = p.ndim == 2 ? (p.bz == 8 ? 8 : 16) : 16;
     for (int k = 0; k < (p.grouped ? b->nsample : 0); ++k) {
         const SampleDesc &Sm = p.samples[k];
-        const int ntx = (Sm.N[2] + kTileX - 1) / kTileX;
+        const int ntx = (Sm.N[2] + WXt - 1) / WXt;
         const int nty = (Sm.N[1] + TYt - 1) / TYt;
         const int ntz = (Sm.N[0] + p.bzg - 1) / p.bzg;
         for (int iz = 0; iz < ntz; ++iz)
@@ -572,14 +601,14 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
                     GTile G;
                     memset(&G, 0, sizeof G);
                     G.sample = k;
-                    G.x0 = ix * kTileX;
+                    G.x0 = ix * WXt;
                     G.y0 = iy * TYt;
                     G.z0 = z0;
                     G.tix = ((z0 / p.bz) * nty + iy) * ntx + ix;
                     p.gtiles.push_back(G);
                 }
     }
-    p.nw = p.ndim == 2 ? grouped_waves(gmax, (int64_t)p.gtiles.size()) : kTileY3;
+    p.nw = p.ndim == 2 ? grouped_waves(gmax, (int64_t)p.gtiles.size()) : 8;  // 3D: 8 wavefronts
     p.per_xcd_g = (int)((p.gtiles.size() + 7) / 8);
     // 2D: a workgroup runs 4 tiles (one per wavefront); 3D: one tile per workgroup
     const size_t nwg = p.ndim == 2 ? (p.tiles.size() + 3) / 4 : p.tiles.size();
@@ -639,9 +668,10 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     p.t_alloc = o;
     if (size_for_all_tiles) {
         if (p.ndim == 2)
-            for (int c : kBz2) p.t_alloc = std::max(p.t_alloc, plan_tables_bytes(b, t, c));
+            for (int c : kBz2) p.t_alloc = std::max(p.t_alloc, plan_tables_bytes(b, t, c, 0));
         else
-            for (int c : kBz3) p.t_alloc = std::max(p.t_alloc, plan_tables_bytes(b, t, c));
+            for (int c : kBz3)
+                for (int w : {32, 64}) p.t_alloc = std::max(p.t_alloc, plan_tables_bytes(b, t, c, w));
     }
     // workspace layout
     p.fwd_only = t->ckpt_every < 0;
@@ -662,7 +692,10 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         p.two = p.ndim == 2 && p.K == 0 && fwd == 2;
         p.two_adj = p.ndim == 2 && (adj == 2 || adj == 0);
     }
-    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.K : t->nt);
+    // with overlap the recomputation writes one of two rings of K imaging levels while the
+    // adjoint reads the other
+    p.overlap = !p.fwd_only && p.K > 0 && p.K < t->nt && !no_overlap && g_overlap.load();
+    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? (p.overlap ? 2 * p.K : p.K) : t->nt);
     p.ck_slots = p.K > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
     int64_t maxdata = 0;
     for (auto &S : p.sims) maxdata = std::max(maxdata, (int64_t)p.nt_rec * S.nrec);
@@ -697,10 +730,10 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     return FWI_OK;
 }
 
-size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz)
+size_t plan_tables_bytes(const fwi_batch *b, const fwi_time *t, int bz, int wx)
 {
     Plan q;
-    if (build_plan(b, t, nullptr, q, bz, false)) return 0;
+    if (build_plan(b, t, nullptr, q, bz, false, wx)) return 0;
     return q.t_bytes;
 }
 
@@ -897,7 +930,7 @@ struct KeyHash {
 
 void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
 {
-    k.add(p.ndim); k.add(p.bz); k.add(p.ty); k.add(p.per_xcd); k.add(p.cells); k.add(p.coefs); k.add(p.data);
+    k.add(p.ndim); k.add(p.bz); k.add(p.ty); k.add(p.wx); k.add(p.per_xcd); k.add(p.cells); k.add(p.coefs); k.add(p.data);
     k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
     k.add(p.nchunk_res); k.add(p.nchunk_fin);
     k.add(p.grouped); k.add(p.bzg); k.add(p.nw); k.add(p.per_xcd_g); k.add(p.gcells);
@@ -965,6 +998,42 @@ fwi_status run_maybe_graph(const KeyHash &key, hipStream_t st, Body body)
 }
 
 // ------------------------------------------------------------- the schedule
+
+// The side stream of overlapped schedules: one per device, created on first use (default
+// priority, non-blocking), and the calling thread's events that order it with the caller's
+// stream.
+hipError_t side_stream(hipStream_t *out)
+{
+    static std::mutex m;
+    static std::vector<hipStream_t> streams;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(m);
+    if ((size_t)dev >= streams.size()) streams.resize((size_t)dev + 1, nullptr);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
+struct SideEvents {
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // start, recomputed x2, imaged x2
+};
+thread_local SideEvents t_side;
+
+hipError_t side_events(hipEvent_t **ev)
+{
+    for (auto &e : t_side.ev)
+        if (!e) {
+            hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (r != hipSuccess) return r;
+        }
+    *ev = t_side.ev;
+    return hipSuccess;
+}
 
 struct Dev {
     uint8_t *base;
@@ -1058,11 +1127,12 @@ StepArgs base_args2(const Plan &p, const Dev &d)
     return a;
 }
 
-fwi_status prologue(const fwi_batch *b, const fwi_time *t, const double *kappa, void *ws, size_t ws_bytes, Plan &p)
+fwi_status prologue(const fwi_batch *b, const fwi_time *t, const double *kappa, void *ws, size_t ws_bytes, Plan &p,
+                    bool no_overlap = false)
 {
     fwi_status s = check_all(b, t, nullptr);
     if (s) return s;
-    s = build_plan(b, t, kappa, p);
+    s = build_plan(b, t, kappa, p, 0, true, 0, no_overlap);
     if (s) return s;
     if (!ws) return fail(FWI_E_WORKSPACE, "null workspace");
     if ((uintptr_t)ws % kAlign) return fail(FWI_E_WORKSPACE, "workspace not 256-byte aligned");
@@ -1134,7 +1204,7 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
             a.cka = d.ck + (size_t)(2 * (slot - 1)) * p.cells;
             a.ckb = d.ck + (size_t)(2 * (slot - 1) + 1) * p.cells;
         }
-        HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.ty, st));
+        HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.wx, st));
         std::swap(cur, prev);
     }
     HIP_TRY(tm.end(t->nt - n0));
@@ -1161,7 +1231,7 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         a.next = lprev;
         a.wimg = wimg;
         a.rec_j = slot(k);
-        HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.ty, st));
+        HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.wx, st));
         std::swap(lcur, lprev);
         return FWI_OK;
     };
@@ -1212,20 +1282,36 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         fwi_status s = sweep(t->nt, 0, [&](int k) { return (const float *)(d.wst + (size_t)(k - 1) * p.cells); });
         if (s) return s;
     } else {
+        // checkpoint segments, last to first: recompute the segment from its checkpoint (its
+        // imaging operands into a ring of K levels), then sweep the adjoint over it.  With
+        // overlap, segment sg - 1 is recomputed on the side stream into the other ring while
+        // the adjoint of segment sg runs on `st`; events order each ring's writes after the
+        // adjoint that last read it.
         float *P0 = d.lev[0], *P1 = d.lev[1];
         StepArgs f = base_args(p, d);
-        for (int sg = p.nseg - 1; sg >= 0; --sg) {
+        hipStream_t rs = st;  // stream of the recomputation
+        hipEvent_t *ev = nullptr;
+        if (p.overlap) {
+            HIP_TRY(side_stream(&rs));
+            HIP_TRY(side_events(&ev));
+            HIP_TRY(hipEventRecord(ev[0], st));  // the forward, residual and fills come first
+            HIP_TRY(hipStreamWaitEvent(rs, ev[0], 0));
+        }
+        auto ring = [&](int sg) { return d.wst + (size_t)(p.overlap ? (sg & 1) * p.K : 0) * p.cells; };
+        auto recompute = [&](int sg) -> fwi_status {
             const int ns = sg * p.K, ne = std::min(ns + p.K, t->nt);
+            float *W = ring(sg);
             const float *cur, *prev;
             if (sg == 0) {
-                HIP_TRY(launch_fill_f32(P0, 2 * p.cells, 0.0f, st));
+                HIP_TRY(launch_fill_f32(P0, 2 * p.cells, 0.0f, rs));
                 cur = P0;
                 prev = P1;
             } else {
                 cur = d.ck + (size_t)(2 * (sg - 1)) * p.cells;
                 prev = d.ck + (size_t)(2 * (sg - 1) + 1) * p.cells;
             }
-            HIP_TRY(tm.begin(0, st));
+            RunTimer tr;
+            HIP_TRY(tr.begin(0, rs));
             for (int n = ns; n < ne; ++n) {
                 float *next;
                 if (prev == P0 || prev == P1)
@@ -1236,15 +1322,36 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
                 f.prev = prev;
                 f.next = next;
                 f.fn = b->wavelet[n];
-                f.wst = d.wst + (size_t)(n - ns) * p.cells;
-                HIP_TRY(launch_step(f, p.ndim, false, p.bz, p.ty, st));
+                f.wst = W + (size_t)(n - ns) * p.cells;
+                HIP_TRY(launch_step(f, p.ndim, false, p.bz, p.wx, rs));
                 prev = cur;
                 cur = next;
             }
-            HIP_TRY(tm.end(ne - ns));
-            fwi_status s =
-                sweep(ne, ns, [&](int k) { return (const float *)(d.wst + (size_t)(k - 1 - ns) * p.cells); });
+            HIP_TRY(tr.end(ne - ns));
+            if (p.overlap) HIP_TRY(hipEventRecord(ev[1 + (sg & 1)], rs));
+            return FWI_OK;
+        };
+        fwi_status s = recompute(p.nseg - 1);
+        if (s) return s;
+        for (int sg = p.nseg - 1; sg >= 0; --sg) {
+            const int ns = sg * p.K, ne = std::min(ns + p.K, t->nt);
+            if (p.overlap) {
+                if (sg >= 1) {
+                    // ring (sg - 1) & 1 was last read by the adjoint of segment sg + 1
+                    if (sg + 1 <= p.nseg - 1) HIP_TRY(hipStreamWaitEvent(rs, ev[3 + ((sg + 1) & 1)], 0));
+                    s = recompute(sg - 1);
+                    if (s) return s;
+                }
+                HIP_TRY(hipStreamWaitEvent(st, ev[1 + (sg & 1)], 0));
+            }
+            float *W = ring(sg);
+            s = sweep(ne, ns, [&](int k) { return (const float *)(W + (size_t)(k - 1 - ns) * p.cells); });
             if (s) return s;
+            if (p.overlap) HIP_TRY(hipEventRecord(ev[3 + (sg & 1)], st));
+            if (!p.overlap && sg >= 1) {
+                s = recompute(sg - 1);
+                if (s) return s;
+            }
         }
     }
     HIP_TRY(launch_finalize(d.samples, d.sims, b->nsample, d.gacc, v, grad, d.npart, p.nchunk_fin, d.status, st));
@@ -1259,7 +1366,7 @@ fwi_status gradient_call(const fwi_batch *b, const fwi_time *t, const float *v, 
                          size_t ws_bytes, hipStream_t st, bool noalloc)
 {
     Plan p;
-    fwi_status s = prologue(b, t, kappa, ws, ws_bytes, p);
+    fwi_status s = prologue(b, t, kappa, ws, ws_bytes, p, noalloc);
     if (s) return s;
     if (!v || !d_obs || !grad) return fail(FWI_E_ARG, "null model, observed data or gradient");
     if (p.fwd_only) return fail(FWI_E_ARG, "ckpt_every = -1 keeps no adjoint state");
@@ -1385,8 +1492,14 @@ fwi_status fwi_gradient_noalloc(const fwi_batch *b, const fwi_time *t, const flo
 {
     if (!b || !t) return fail(FWI_E_ARG, "null batch or time axis");
     size_t need = 0;
-    fwi_status s = fwi_workspace_size(b, t, &need);
-    if (s) return s;
+    {
+        Plan q;
+        fwi_status s = check_all(b, t, nullptr);
+        if (s) return s;
+        s = build_plan(b, t, nullptr, q, 0, true, 0, true);
+        if (s) return s;
+        need = q.total;
+    }
     void *ws = nullptr;
     size_t cap = 0;
     hipError_t e = noalloc_scratch(&ws, &cap);
@@ -1396,6 +1509,24 @@ fwi_status fwi_gradient_noalloc(const fwi_batch *b, const fwi_time *t, const flo
                     need, cap);
     return gradient_call(b, t, v, d_obs, inv_sigma2, kappa, d_pred, misfit, grad, grad_norm, ws, cap,
                          (hipStream_t)stream, true);
+}
+
+fwi_status fwi_set_overlap(int32_t on)
+{
+    g_overlap.store(on ? 1 : 0);
+    return FWI_OK;
+}
+
+fwi_status fwi_tile_shape(const fwi_batch *b, const fwi_time *t, int32_t *bz, int32_t *wx)
+{
+    fwi_status s = check_all(b, t, nullptr);
+    if (s) return s;
+    Plan p;
+    s = build_plan(b, t, nullptr, p, 0, false);
+    if (s) return s;
+    if (bz) *bz = p.bz;
+    if (wx) *wx = p.wx;
+    return FWI_OK;
 }
 
 fwi_status fwi_encode(const float *d_shots, int32_t nshot, int64_t n_per_shot, int32_t ngrp, const int32_t *grp_ptr,
@@ -1542,6 +1673,13 @@ fwi_status fwi_set_tile(int32_t ndim, int32_t bz)
     return FWI_OK;
 }
 
+fwi_status fwi_set_tile_width(int32_t wx)
+{
+    if (wx != 0 && wx != 32 && wx != 64) return fail(FWI_E_ARG, "unsupported 3D tile width %d", wx);
+    g_width3.store(wx);
+    return FWI_OK;
+}
+
 fwi_status fwi_set_time_blocking(int32_t fwd_steps, int32_t adj_steps)
 {
     if (fwd_steps < 0 || fwd_steps > 2 || adj_steps < 0 || adj_steps > 2)
@@ -1635,7 +1773,7 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
                 a.cur = cur;
                 a.prev = a.next = prev;
                 a.wst = p.fwd_only ? nullptr : wlev(p, d, r);
-                HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.ty, st));
+                HIP_TRY(launch_step(a, p.ndim, false, p.bz, p.wx, st));
                 std::swap(cur, prev);
             }
             HIP_TRY(hipEventRecord(e1, st));
@@ -1644,7 +1782,7 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
                     a.cur = cur;
                     a.prev = a.next = prev;
                     a.wimg = wlev(p, d, reps - 1 - r);
-                    HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.ty, st));
+                    HIP_TRY(launch_step(a, p.ndim, true, p.bz, p.wx, st));
                     std::swap(cur, prev);
                 }
             HIP_TRY(hipEventRecord(e2, st));

@@ -9,8 +9,7 @@
 
 namespace fwi {
 
-constexpr int kTileX = 64;   // one wavefront spans 64 consecutive x cells
-constexpr int kTileY3 = 8;   // 3D tile: 64 x 8 cells per xy plane
+constexpr int kTileX = 64;   // one wavefront spans 64 consecutive x cells (3D: 64 or 32 per row)
 constexpr int kHalo = 4;     // 8th-order stencil radius
 // Two time steps per launch (2D): a wavefront's 64 lanes hold columns x0 - 4 .. x0 + 59 of
 // a strip of kStrip2 columns; strips are kRows2 rows high (forward and adjoint alike).
@@ -77,7 +76,8 @@ struct GTile {
 };
 
 // One row (2D: a grid row; 3D: an xy plane) of a tile that holds receivers.  vec_off
-// points at kTileX * ty entries of receiver indices (local to the sim) or -1.  The event
+// points at 64 * (rows per tile / rows per wavefront) entries of receiver indices (local
+// to the sim) or -1, one per lane of the workgroup: entry (y - y0) * width + (x - x0).  The event
 // rows of a two-step strip cover its rows z0 - 4 .. z0 + kRows2 + 3 and, entry l, column
 // x0 - 4 + l: the receivers of the margins the first step also computes.
 struct EvRow {

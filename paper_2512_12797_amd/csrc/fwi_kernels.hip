@@ -1013,52 +1013,145 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
 
 // ------------------------------------------------------------ 3D stepping
 
-// 3D step.  Block: 64 x kTileY3 threads, one wavefront per row of a 64 x kTileY3 (x, y)
-// tile, streamed along z.  The xy plane (tile plus a 4-cell halo in x and y) goes through
-// a double-buffered LDS plane with one barrier per plane: each wave writes its own row,
-// waves 0..7 also one y-halo row each and lanes 0..7 of every wave the row's x-halo
-// cells.  The z-derivative comes from a register queue that runs 8 planes ahead, and the
-// halo and point operands are fetched 4 planes ahead with unconditional buffer loads.
+// 3D step.  A workgroup of kWaves3 = 8 wavefronts owns a tile of WX x-cells (WX = 64 or
+// 32), TY = 8 * RW rows (RW = 64 / WX rows per wavefront) and BZ planes, and streams it
+// along z.  Wavefront w holds rows w * RW .. w * RW + RW - 1, lane l the cell
+// (l % WX, l / WX) of them.  The host picks the width that leaves fewer lanes idle on the
+// batch's grids: a padded x extent of 220 cells runs on 224 lanes per row with 32-wide
+// tiles instead of 256 with 64-wide ones.  The xy plane (tile plus a 4-cell halo in x
+// and y) goes through a double-buffered LDS plane with one barrier per plane: every
+// wavefront writes its own cells, the first 8 / RW wavefronts one y-halo row each per
+// lane row, lanes with l % WX < 8 the x-halo cells of their row.  The z-derivative comes
+// from a register queue that runs 8 planes ahead; halo and point operands are fetched 4
+// planes ahead with unconditional buffer loads.
 //
-// The step is VALU-bound rather than HBM-bound (25-point stencil, one cell per lane), so
-// the sweep keeps instructions per cell low: the plane loop is fully unrolled (queues
-// shift by register renaming, no moves), every lane offset carries a poison bit instead
-// of a per-access select, and the sponge coefficients a, b of planes outside the z-sponge
-// are computed once per column.
+// The sweep is bound by instruction issue, not by HBM bandwidth: its time follows the
+// number of lanes it runs, not the bytes it moves.  So it keeps instructions per cell low:
+// the plane loop is fully unrolled (queues shift by register renaming), every lane offset
+// carries a poison bit instead of a per-access select, the sponge coefficients a, b of
+// planes outside the z-sponge are computed once per column, the optional stores are fixed
+// per kernel instance (MODE) instead of tested per plane, and source terms are looked for
+// only in tiles that hold sources.
 
-struct Plane3 {
-    float v[2][kTileY3 + 2 * kHalo][kTileX + 2 * kHalo];
+constexpr int kWaves3 = 8;  // wavefronts per 3D workgroup
+
+// Stores of a forward launch besides u^{n+1}: none, the checkpoint pair (u^{n+1}, u^n),
+// or the imaging operand W^n = L u^n + q^n.
+enum : int { kStorePlain = 0, kStoreCkpt = 1, kStoreImage = 2 };
+
+// Cells into the sponge of padded index p on an axis with n physical cells (0 inside).
+__device__ __forceinline__ int sponge_depth(int p, int n, int nb)
+{
+    return p < nb ? nb - p : (p > nb + n - 1 ? p - (nb + n - 1) : 0);
+}
+// gmax (d/nb)^2, rounded exactly as sponge_axis rounds it (d != 0)
+__device__ __forceinline__ double sponge_of_depth(int d, int nb, double gmax)
+{
+#pragma clang fp contract(off)
+    double r = (double)d / (double)nb;
+    return gmax * r * r;
+}
+
+// Lane geometry of a 3D tile shared by the forward and adjoint sweeps.
+template <int WX>
+struct Lanes3 {
+    static constexpr int RW = kTileX / WX;       // rows per wavefront
+    static constexpr int TY = kWaves3 * RW;      // rows per tile
+    static constexpr int NHW = 2 * kHalo / RW;   // wavefronts that load the 8 y-halo rows
+    static constexpr int LX = WX + 2 * kHalo;    // LDS row length
+    static constexpr int LY = TY + 2 * kHalo + RW;  // LDS rows (+ RW spare rows)
+    int lc, ry, x, y;        // lane's column and row in the tile, cell coordinates
+    bool in;                 // the cell lies in the grid
+    uint32_t col, cb;        // byte offset of (y, x) in a plane; poisoned copy for loads
+    uint32_t hyb, hxb;       // poisoned offsets of the lane's y- and x-halo cells
+    int hrow, hcol, hxrow;   // LDS row of the y-halo cell, column and row of the x-halo cell
+    __device__ __forceinline__ Lanes3(int tx0, int ty0, int Nx, int Ny)
+    {
+        const int lane = threadIdx.x & 63;
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lr = lane / WX;
+        lc = lane % WX;
+        ry = w * RW + lr;
+        x = tx0 + lc;
+        y = ty0 + ry;
+        in = x < Nx && y < Ny;
+        col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
+        cb = in ? col : kPoison;
+        // y halo: rows ty0-4 .. ty0-1, then ty0+TY .. ty0+TY+3, RW per wavefront; the
+        // other wavefronts load nothing and write a spare LDS row
+        const int hr = w * RW + lr;
+        const bool hw = w < NHW;
+        const int hy = hr < kHalo ? ty0 - kHalo + hr : ty0 + TY + hr - kHalo;
+        hrow = hw ? (hr < kHalo ? hr : TY + hr) : TY + 2 * kHalo + lr;
+        const bool hyl = hw && x < Nx && hy >= 0 && hy < Ny;
+        hyb = hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1)) : kPoison;
+        // x halo of the lane's row: columns tx0-4 .. tx0-1 (lc 0..3), tx0+WX .. +3 (lc 4..7);
+        // the other lanes load nothing and write a spare LDS row
+        const int hxx = lc < kHalo ? tx0 - kHalo + lc : tx0 + WX + lc - kHalo;
+        hcol = lc < kHalo ? lc : WX + lc;
+        hxrow = lc < 2 * kHalo ? ry + kHalo : TY + 2 * kHalo + lr;
+        if (lc >= 2 * kHalo) hcol = lc;
+        const bool hxl = lc < 2 * kHalo && y < Ny && hxx >= 0 && hxx < Nx;
+        hxb = hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
+    }
 };
 
-// One sim's forward sweep of one 3D tile (origin x0, y0, z0).  S supplies the grid,
-// weights and sources; u_off / d_off / nrec locate the sim's fields and data; the receiver
-// event planes are ev_beg .. ev_beg + ev_cnt.
-template <int BZ>
-__device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int64_t u_off, int64_t d_off, int nrec,
-                                        int tx0, int ty0, int z0, int ev_beg, int ev_cnt, Plane3 &P)
+// The 8th-order Laplacian of one cell from the LDS plane (x and y) and the z queue
+// qq[0..8] (qq[4] = the cell), summed per axis and then z + y + x.
+template <int LX>
+__device__ __forceinline__ float lap3(const float (*L)[LX], int ly, int lx, const float *qq, const float *wx,
+                                      const float *wy, const float *wz)
 {
-    static_assert(kTileY3 >= 8, "one y-halo row per wave needs at least 8 waves");
+    float sx = wx[0] * qq[4];
+    sx += wx[1] * (L[ly][lx - 1] + L[ly][lx + 1]);
+    sx += wx[2] * (L[ly][lx - 2] + L[ly][lx + 2]);
+    sx += wx[3] * (L[ly][lx - 3] + L[ly][lx + 3]);
+    sx += wx[4] * (L[ly][lx - 4] + L[ly][lx + 4]);
+    float sy = wy[0] * qq[4];
+    sy += wy[1] * (L[ly - 1][lx] + L[ly + 1][lx]);
+    sy += wy[2] * (L[ly - 2][lx] + L[ly + 2][lx]);
+    sy += wy[3] * (L[ly - 3][lx] + L[ly + 3][lx]);
+    sy += wy[4] * (L[ly - 4][lx] + L[ly + 4][lx]);
+    float sz = wz[0] * qq[4];
+    sz += wz[1] * (qq[3] + qq[5]);
+    sz += wz[2] * (qq[2] + qq[6]);
+    sz += wz[3] * (qq[1] + qq[7]);
+    sz += wz[4] * (qq[0] + qq[8]);
+    return sz + sy + sx;
+}
+
+// 3D forward step: one tile of one sim per workgroup.  MODE selects the extra stores.
+template <int WX, int BZ, int MODE>
+__global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
+{
+    using G = Lanes3<WX>;
     constexpr int PF = 4;
+    const int slot = xcd_tile(blockIdx.x, A.per_xcd);
+    if (slot >= A.ntiles) return;  // uniform per block
+    // the launch order takes a sample's supergathers at one tile position in a row, so
+    // that the sample's coefficient grid is read from L2 by all but the first of them
+    const int t = A.order ? A.order[slot] : slot;
+    const Tile T = A.tiles[t];
+    const SimDesc &S = A.sims[T.sim];
+    __shared__ float V[2][G::LY][G::LX];
     const int Nx = S.N[2], Ny = S.N[1], Nz = S.N[0];
     const int nz_phys = S.n[0], ny_phys = S.n[1], nx_phys = S.n[2], nb = S.nb;
-    const double gmz = S.gmax[0], gmy = S.gmax[1], gmx = S.gmax[2];
+    const double gmz = S.gmax[0];
     const int src_beg = S.src_beg, src_cnt = S.src_cnt;
     const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
     const uint32_t fbytes = pbytes * (uint32_t)Nz;
-    const int lane = threadIdx.x & 63;
-    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's row (uniform)
-    const int x = tx0 + lane;
-    const int y = ty0 + ty;
-    const int z1 = min(z0 + BZ, Nz);
+    const int z0 = T.z0;
+    const G g(T.x0, T.y0, Nx, Ny);
+    const int64_t u_off = S.u_off;
     const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
     const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
     const rsrc_t rN = make_rsrc(A.next + u_off, fbytes);
     const rsrc_t rC = make_rsrc(A.cf + S.c_off, fbytes);
-    const rsrc_t rW = make_rsrc(A.wst ? A.wst + u_off : A.next, A.wst ? fbytes : 0);
-    const rsrc_t rKa = make_rsrc(A.cka ? A.cka + u_off : A.next, A.cka ? fbytes : 0);
-    const rsrc_t rKb = make_rsrc(A.ckb ? A.ckb + u_off : A.next, A.ckb ? fbytes : 0);
+    const rsrc_t rW = make_rsrc(MODE == kStoreImage ? A.wst + u_off : A.next, MODE == kStoreImage ? fbytes : 0);
+    const rsrc_t rKa = make_rsrc(MODE == kStoreCkpt ? A.cka + u_off : A.next, MODE == kStoreCkpt ? fbytes : 0);
+    const rsrc_t rKb = make_rsrc(MODE == kStoreCkpt ? A.ckb + u_off : A.next, MODE == kStoreCkpt ? fbytes : 0);
     const int rec_j = A.rec_j;
-    float *Dat = (A.dat && rec_j >= 0) ? A.dat + d_off + (int64_t)rec_j * nrec : nullptr;
+    float *Dat = (A.dat && rec_j >= 0) ? A.dat + S.d_off + (int64_t)rec_j * S.nrec : nullptr;
     const EvRow *__restrict__ evrows = A.evrows;
     const int32_t *__restrict__ evvec = A.evvec;
 
@@ -1070,8 +1163,8 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
         wx[k] = S.w[2][k];
     }
     const double dt = S.dt;
-    const double gx = sponge_axis(x, nx_phys, nb, gmx);
-    const double gy = sponge_axis(y, ny_phys, nb, gmy);  // uniform per wave
+    const double gx = sponge_axis(g.x, nx_phys, nb, S.gmax[2]);
+    const double gy = sponge_axis(g.y, ny_phys, nb, S.gmax[1]);
     float a_col, b_col;  // a, b of this column outside the z-sponge
     {
         double gam = 0.0;
@@ -1079,32 +1172,18 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
         gam = gam + gx;
         sponge_ab(gam, dt, a_col, b_col);
     }
-
     auto poff = [&](int zz) -> uint32_t { return (uint32_t)zz * pbytes; };  // zz < 0 wraps out of range
-    const bool in = x < Nx && y < Ny;
-    const uint32_t col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
-    const uint32_t cb = in ? col : kPoison;          // own cell
-    // y-halo row of waves 0..7: rows y0-4 .. y0-1, then y0+TY .. y0+TY+3
-    const int hy = ty < 4 ? ty0 - kHalo + ty : ty0 + kTileY3 + ty - 4;
-    const int hrow = ty < 4 ? ty : kTileY3 + ty;  // its LDS row
-    const bool hyl = ty < 8 && x < Nx && hy >= 0 && hy < Ny;
-    const uint32_t hyb =
-        hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1)) : kPoison;
-    // x-halo of this row: lanes 0..3 left of the tile, 4..7 right of it
-    const int hxx = lane < 4 ? tx0 - kHalo + lane : tx0 + kTileX - 4 + lane;
-    const int hcol = lane < 4 ? lane : kTileX + lane;  // its LDS column
-    const bool hxl = lane < 8 && y < Ny && hxx >= 0 && hxx < Nx;
-    const uint32_t hxb =
-        hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
+    const uint32_t cb = g.cb, hyb = g.hyb, hxb = g.hxb;
 
     // sources in this thread's column
+    const int z1 = min(z0 + BZ, Nz);
     int sz = -1;
     float sw = 0.0f;
     bool smulti = false;
     const float famp = A.fn * S.inv_vol;
     for (int s = 0; s < src_cnt; ++s) {
         const SrcPos p = A.src[src_beg + s];
-        if (p.x != x || p.y != y || p.z < z0 || p.z >= z1) continue;
+        if (p.x != g.x || p.y != g.y || p.z < z0 || p.z >= z1) continue;
         if (sz < 0 || sz == p.z) {
             sz = p.z;
             sw += p.w;
@@ -1112,6 +1191,7 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
             smulti = true;
         }
     }
+    const bool has_src = __syncthreads_or(sz >= 0);
     const bool multi = __syncthreads_or(smulti);
 
     // queues indexed by plane (the plane loop is fully unrolled)
@@ -1126,11 +1206,11 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
         cq[k] = bload(rC, pz + cb);
         pq[k] = bload(rP, pz + cb);
     }
-    const bool rec = rec_j >= 0 && ev_cnt > 0;
-    int ev = ev_beg;
-    const int ev_end = ev_beg + ev_cnt;
-    int ev_z = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
-    int ev_off = rec ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
+    int ev = T.ev_beg;
+    const int ev_end = T.ev_beg + T.ev_cnt;
+    int ev_z = (rec_j >= 0 && ev < ev_end) ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
+    int ev_off = (rec_j >= 0 && ev < ev_end) ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
+    const int ly = g.ry + kHalo, lx = g.lc + kHalo;
 
     // planes below the grid are swept too: their loads read 0 and their stores fall
     // outside the buffers, so the tile needs no plane guard
@@ -1147,62 +1227,47 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
             pq[r + PF] = bload(rP, pz + cb);
         }
         // ---- plane z into LDS
-        float(*V)[kTileX + 2 * kHalo] = P.v[r & 1];
-        V[ty + kHalo][lane + kHalo] = q[r + 4];
-        if (ty < 8) V[hrow][lane + kHalo] = hyq[r];
-        if (lane < 8) V[ty + kHalo][hcol] = hxq[r];
+        float(*L)[G::LX] = V[r & 1];
+        L[ly][lx] = q[r + 4];
+        L[g.hrow][lx] = hyq[r];
+        L[g.hxrow][g.hcol] = hxq[r];
         __syncthreads();
 
-        const int ly = ty + kHalo, lx = lane + kHalo;
         const float *qq = &q[r];  // qq[4] is plane z
-        float sx = wx[0] * qq[4];
-        sx += wx[1] * (V[ly][lx - 1] + V[ly][lx + 1]);
-        sx += wx[2] * (V[ly][lx - 2] + V[ly][lx + 2]);
-        sx += wx[3] * (V[ly][lx - 3] + V[ly][lx + 3]);
-        sx += wx[4] * (V[ly][lx - 4] + V[ly][lx + 4]);
-        float sy = wy[0] * qq[4];
-        sy += wy[1] * (V[ly - 1][lx] + V[ly + 1][lx]);
-        sy += wy[2] * (V[ly - 2][lx] + V[ly + 2][lx]);
-        sy += wy[3] * (V[ly - 3][lx] + V[ly + 3][lx]);
-        sy += wy[4] * (V[ly - 4][lx] + V[ly + 4][lx]);
-        float szz = wz[0] * qq[4];
-        szz += wz[1] * (qq[3] + qq[5]);
-        szz += wz[2] * (qq[2] + qq[6]);
-        szz += wz[3] * (qq[1] + qq[7]);
-        szz += wz[4] * (qq[0] + qq[8]);
-        float wv = szz + sy + sx;
+        float wv = lap3<G::LX>(L, ly, lx, qq, wx, wy, wz);
         float a = a_col, b = b_col;
-        const double gz = sponge_axis(z, nz_phys, nb, gmz);  // uniform
-        if (gz != 0.0) {
+        if ((unsigned)(z - nb) >= (unsigned)nz_phys) {  // uniform: a z-sponge plane
             double gam = 0.0;
-            gam = gam + gz;
+            gam = gam + sponge_of_depth(sponge_depth(z, nz_phys, nb), nb, gmz);
             gam = gam + gy;
             gam = gam + gx;
             sponge_ab(gam, dt, a, b);
         }
-        const bool evrow = z == ev_z;  // uniform
-        if (z == sz) wv += sw * famp;
-        if (multi) {
-            float extra = 0.0f;
-            if (in)
-                for (int s = 0; s < src_cnt; ++s) {
-                    const SrcPos p = A.src[src_beg + s];
-                    if (p.x == x && p.y == y && p.z == z && z != sz) extra += p.w;
-                }
-            wv += extra * famp;
+        if (has_src) {  // uniform
+            if (z == sz) wv += sw * famp;
+            if (multi) {
+                float extra = 0.0f;
+                if (g.in)
+                    for (int s = 0; s < src_cnt; ++s) {
+                        const SrcPos p = A.src[src_beg + s];
+                        if (p.x == g.x && p.y == g.y && p.z == z && z != sz) extra += p.w;
+                    }
+                wv += extra * famp;
+            }
         }
         const uint32_t o = poff(z) + cb;
         const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
         bstore(rN, o, un);
-        // optional outputs: uniform branches skip the instructions when absent
-        if (A.wst) bstore(rW, o, wv);
-        if (A.cka) bstore(rKa, o, un);
-        if (A.ckb) bstore(rKb, o, qq[4]);
-        if (evrow && Dat) {
-            const int rid = evvec[ev_off + ty * kTileX + lane];
-            if (rid >= 0) Dat[rid] = un;
+        if (MODE == kStoreImage) bstore(rW, o, wv);
+        if (MODE == kStoreCkpt) {
+            bstore(rKa, o, un);
+            bstore(rKb, o, qq[4]);
         }
-        if (evrow) {
+        if (z == ev_z) {  // uniform
+            if (Dat) {
+                const int rid = evvec[ev_off + threadIdx.x];
+                if (rid >= 0) Dat[rid] = un;
+            }
             ++ev;
             ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
             ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
@@ -1212,44 +1277,29 @@ __device__ __forceinline__ void sweep3d(const StepArgs &A, const SimDesc &S, int
     }
 }
 
-// 3D forward step: one tile of one sim per workgroup.
-template <int BZ>
-__global__ __launch_bounds__(64 * kTileY3) void k_fwd3d(const StepArgs A)
+// 3D adjoint + imaging step with the imaging sum taken per sample.  A workgroup (lanes as
+// in the forward) owns one WX x TY x BZ tile of a sample's grid and sweeps it for each of
+// the sample's sims in turn; every thread keeps the FP64 sum over sims of its cells' exact
+// products lt^k W^{k-1} in LDS and applies one read-modify-write to the sample's
+// accumulator at the end, so the accumulator costs 16 B per sample cell and step instead
+// of 16 B per sim cell.  Per cell the sum runs over the sims in order and then into the
+// accumulator step by step: the result does not depend on tile shapes or the schedule.
+// Consecutive sims reuse the double-buffered plane without an extra barrier: a slot is
+// rewritten only after every wave has passed the barrier of the plane that follows its
+// last read.
+template <int WX, int BZ>
+__global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
 {
-    const int slot = xcd_tile(blockIdx.x, A.per_xcd);
-    if (slot >= A.ntiles) return;  // uniform per block
-    // the launch order takes a sample's supergathers at one tile position in a row, so
-    // that the sample's coefficient grid is read from L2 by all but the first of them
-    const int t = A.order ? A.order[slot] : slot;
-    const Tile T = A.tiles[t];
-    const SimDesc &S = A.sims[T.sim];
-    __shared__ Plane3 P;
-    sweep3d<BZ>(A, S, S.u_off, S.d_off, S.nrec, T.x0, T.y0, T.z0, T.ev_beg, T.ev_cnt, P);
-}
-
-// 3D adjoint + imaging step with the imaging sum taken per sample.  A workgroup (one
-// wavefront per tile row, as in the forward) owns one 64 x kTileY3 x BZ tile of a sample's
-// grid and sweeps it for each of the sample's sims in turn; every thread keeps the FP64
-// sum over sims of its cells' exact products lt^k W^{k-1} in LDS and applies one
-// read-modify-write to the sample's accumulator at the end, so the accumulator costs 16 B
-// per sample cell and step instead of 16 B per sim cell.  Per cell the sum runs over the
-// sims in order and then into the accumulator step by step: the result does not depend on
-// tile heights or the schedule.  Consecutive sims reuse the double-buffered plane without
-// an extra barrier: a slot is rewritten only after every wave has passed the barrier of
-// the plane that follows its last read.
-template <int BZ>
-__global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
-{
-    static_assert(kTileY3 >= 8, "one y-halo row per wave needs at least 8 waves");
+    using G = Lanes3<WX>;
     constexpr int PF = 4;
     const int gt = xcd_tile(blockIdx.x, A.per_xcd_g);
     if (gt >= A.ngtiles) return;  // uniform per block
     // sample-level descriptors are read before the first store (scalar loads)
-    const GTile G = A.gtiles[gt];
-    const SampleDesc &Sm = A.samples[G.sample];
+    const GTile GT = A.gtiles[gt];
+    const SampleDesc &Sm = A.samples[GT.sample];
     const int Nx = Sm.N[2], Ny = Sm.N[1], Nz = Sm.N[0];
     const int nz_phys = Sm.n[0], ny_phys = Sm.n[1], nx_phys = Sm.n[2], nb = Sm.nb;
-    const double gmz = Sm.gmax[0], gmy = Sm.gmax[1], gmx = Sm.gmax[2];
+    const double gmz = Sm.gmax[0];
     const double dt = Sm.dt;
     const int sim_beg = Sm.sim_beg, sim_cnt = Sm.sim_cnt;
     if (sim_cnt == 0) return;  // uniform per block: a sample without sims adds nothing
@@ -1265,18 +1315,15 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
     }
     const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
     const uint32_t fbytes = pbytes * (uint32_t)Nz;
-    const int lane = threadIdx.x & 63;
-    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's row (uniform)
-    const int tx0 = G.x0, ty0 = G.y0, z0 = G.z0;
-    const int x = tx0 + lane;
-    const int y = ty0 + ty;
+    const int z0 = GT.z0;
+    const G g(GT.x0, GT.y0, Nx, Ny);
     const rsrc_t rC = make_rsrc(A.cf + Sm.c_off, fbytes);
     const int rec_j = A.rec_j;
     const EvRow *__restrict__ evrows = A.evrows;
     const int32_t *__restrict__ evvec = A.evvec;
 
-    const double gx = sponge_axis(x, nx_phys, nb, gmx);
-    const double gy = sponge_axis(y, ny_phys, nb, gmy);  // uniform per wave
+    const double gx = sponge_axis(g.x, nx_phys, nb, Sm.gmax[2]);
+    const double gy = sponge_axis(g.y, ny_phys, nb, Sm.gmax[1]);
     float a_col, b_col;  // a, b of this column outside the z-sponge
     {
         double gam = 0.0;
@@ -1285,22 +1332,10 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
         sponge_ab(gam, dt, a_col, b_col);
     }
     auto poff = [&](int zz) -> uint32_t { return (uint32_t)zz * pbytes; };  // zz < 0 wraps out of range
-    const bool in = x < Nx && y < Ny;
-    const uint32_t col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
-    const uint32_t cb = in ? col : kPoison;
-    const int hy = ty < 4 ? ty0 - kHalo + ty : ty0 + kTileY3 + ty - 4;
-    const int hrow = ty < 4 ? ty : kTileY3 + ty;
-    const bool hyl = ty < 8 && x < Nx && hy >= 0 && hy < Ny;
-    const uint32_t hyb =
-        hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1)) : kPoison;
-    const int hxx = lane < 4 ? tx0 - kHalo + lane : tx0 + kTileX - 4 + lane;
-    const int hcol = lane < 4 ? lane : kTileX + lane;
-    const bool hxl = lane < 8 && y < Ny && hxx >= 0 && hxx < Nx;
-    const uint32_t hxb =
-        hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
+    const int ly = g.ry + kHalo, lx = g.lc + kHalo;
 
-    __shared__ Plane3 P;
-    __shared__ double red[BZ][kTileY3][kTileX];
+    __shared__ float V[2][G::LY][G::LX];
+    __shared__ double red[BZ][G::TY][WX];
 
     for (int j = 0; j < sim_cnt; ++j) {
         const int sim = sim_beg + j;
@@ -1311,7 +1346,7 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
         const rsrc_t rW = make_rsrc(A.wimg + u_off, fbytes);
         // lane offsets pass through an empty asm so that the plane offsets built from them
         // are recomputed per sim next to their loads, not hoisted out of the sim loop
-        uint32_t cbs = cb, hybs = hyb, hxbs = hxb;
+        uint32_t cbs = g.cb, hybs = g.hyb, hxbs = g.hxb;
         asm volatile("" : "+v"(cbs), "+v"(hybs), "+v"(hxbs));
         // per-sim fields read after stores: vector loads, made uniform explicitly
         const int tile0 = __builtin_amdgcn_readfirstlane(A.sims[sim].tile0);
@@ -1325,7 +1360,7 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
         // sim tile may be taller than BZ)
         int ev = 0, ev_end = 0, ev_z = -1, ev_off = 0;
         if (rec_j >= 0) {
-            const Tile &T = A.tiles[tile0 + G.tix];
+            const Tile &T = A.tiles[tile0 + GT.tix];
             ev = __builtin_amdgcn_readfirstlane(T.ev_beg);
             ev_end = ev + __builtin_amdgcn_readfirstlane(T.ev_cnt);
             while (ev < ev_end) {
@@ -1365,41 +1400,24 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
                 pq[r + PF] = bload(rP, pz + cbs);
                 wq[r + PF] = bload(rW, pz + cbs);
             }
-            float(*V)[kTileX + 2 * kHalo] = P.v[r & 1];
-            V[ty + kHalo][lane + kHalo] = q[r + 4];
-            if (ty < 8) V[hrow][lane + kHalo] = hyq[r];
-            if (lane < 8) V[ty + kHalo][hcol] = hxq[r];
+            float(*L)[G::LX] = V[r & 1];
+            L[ly][lx] = q[r + 4];
+            L[g.hrow][lx] = hyq[r];
+            L[g.hxrow][g.hcol] = hxq[r];
             __syncthreads();
 
-            const int ly = ty + kHalo, lx = lane + kHalo;
             const float *qq = &q[r];  // qq[4] is plane z
-            float sx = wx[0] * qq[4];
-            sx += wx[1] * (V[ly][lx - 1] + V[ly][lx + 1]);
-            sx += wx[2] * (V[ly][lx - 2] + V[ly][lx + 2]);
-            sx += wx[3] * (V[ly][lx - 3] + V[ly][lx + 3]);
-            sx += wx[4] * (V[ly][lx - 4] + V[ly][lx + 4]);
-            float sy = wy[0] * qq[4];
-            sy += wy[1] * (V[ly - 1][lx] + V[ly + 1][lx]);
-            sy += wy[2] * (V[ly - 2][lx] + V[ly + 2][lx]);
-            sy += wy[3] * (V[ly - 3][lx] + V[ly + 3][lx]);
-            sy += wy[4] * (V[ly - 4][lx] + V[ly + 4][lx]);
-            float szz = wz[0] * qq[4];
-            szz += wz[1] * (qq[3] + qq[5]);
-            szz += wz[2] * (qq[2] + qq[6]);
-            szz += wz[3] * (qq[1] + qq[7]);
-            szz += wz[4] * (qq[0] + qq[8]);
-            float wv = szz + sy + sx;
+            float wv = lap3<G::LX>(L, ly, lx, qq, wx, wy, wz);
             float a = a_col, b = b_col;
-            const double gz = sponge_axis(z, nz_phys, nb, gmz);  // uniform
-            if (gz != 0.0) {
+            if ((unsigned)(z - nb) >= (unsigned)nz_phys) {  // uniform: a z-sponge plane
                 double gam = 0.0;
-                gam = gam + gz;
+                gam = gam + sponge_of_depth(sponge_depth(z, nz_phys, nb), nb, gmz);
                 gam = gam + gy;
                 gam = gam + gx;
                 sponge_ab(gam, dt, a, b);
             }
             if (z == ev_z) {  // uniform
-                const int rid = evvec[ev_off + ty * kTileX + lane];
+                const int rid = evvec[ev_off + threadIdx.x];
                 if (rid >= 0) wv += Rho[rid];
                 ++ev;
                 ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
@@ -1408,7 +1426,7 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
             const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
             bstore(rN, poff(z) + cbs, un);
             const double pr = (double)un * (double)wq[r];  // the product of two floats is exact in FP64
-            red[r][ty][lane] = j == 0 ? pr : red[r][ty][lane] + pr;
+            red[r][g.ry][g.lc] = j == 0 ? pr : red[r][g.ry][g.lc] + pr;
             // keep each plane's loads in its own plane (prefetch distance PF planes)
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -1416,11 +1434,11 @@ __global__ __launch_bounds__(64 * kTileY3) void k_adj3d(const StepArgs A)
     // one read-modify-write of the sample's accumulator per cell (cells outside the grid:
     // poisoned or out-of-range offsets, so the load reads 0 and the store is dropped)
     const rsrc_t rG = make_rsrc(A.gacc + g_off, 2 * fbytes);
-    const uint32_t cb2 = in ? 2u * col : kPoison;
+    const uint32_t cb2 = g.in ? 2u * g.col : kPoison;
 #pragma unroll
     for (int r = 0; r < BZ; ++r) {
         const uint32_t o = 2u * poff(z0 + r) + cb2;
-        bstore64(rG, o, bload64(rG, o) + red[r][ty][lane]);
+        bstore64(rG, o, bload64(rG, o) + red[r][g.ry][g.lc]);
     }
 }
 
@@ -1574,13 +1592,13 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, float *__restrict__
 
 // ------------------------------------------------------------- copy probe
 
-// Plain streaming copy (16-byte vectors): the achievable-bandwidth reference and the
-// calibration kernel for hardware byte counters.
+// Plain streaming copy: one 16-byte vector per thread, one short-lived workgroup per 4 KB
+// (measured faster than grid-stride loops, which keep fewer requests in flight per
+// wavefront).  The achievable-bandwidth reference and the byte-counter calibration kernel.
 __global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ s, float4 *__restrict__ d, int64_t n4)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n4; i += stride) d[i] = s[i];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) d[i] = s[i];
 }
 
 // ------------------------------------------------------------ launchers
@@ -1594,7 +1612,9 @@ static inline int blocks_for(int64_t n, int bs, int cap)
 hipError_t launch_copy(const float *src, float *dst, int64_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    k_copy<<<blocks_for(n / 4, 256, 256 * 8 * 8), 256, 0, st>>>((const float4 *)src, (float4 *)dst, n / 4);
+    const int64_t nb = (n / 4 + 255) / 256;
+    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    k_copy<<<(unsigned)nb, 256, 0, st>>>((const float4 *)src, (float4 *)dst, n / 4);
     return hipGetLastError();
 }
 
@@ -1640,23 +1660,44 @@ static hipError_t fwd2d_dispatch(const StepArgs &a, int bz, hipStream_t st)
     return hipGetLastError();
 }
 
-static hipError_t fwd3d_dispatch(const StepArgs &a, int bz, int ty, hipStream_t st)
+template <int WX, int BZ>
+static void fwd3d_mode(const StepArgs &a, dim3 grid, hipStream_t st)
+{
+    if (a.cka)
+        k_fwd3d<WX, BZ, kStoreCkpt><<<grid, 64 * kWaves3, 0, st>>>(a);
+    else if (a.wst)
+        k_fwd3d<WX, BZ, kStoreImage><<<grid, 64 * kWaves3, 0, st>>>(a);
+    else
+        k_fwd3d<WX, BZ, kStorePlain><<<grid, 64 * kWaves3, 0, st>>>(a);
+}
+
+static hipError_t fwd3d_dispatch(const StepArgs &a, int bz, int wx, hipStream_t st)
 {
     dim3 grid(8 * a.per_xcd);
-    if (ty != kTileY3) return hipErrorInvalidValue;
-    switch (bz) {
-    case 16: k_fwd3d<16><<<grid, 64 * kTileY3, 0, st>>>(a); break;
-    case 32: k_fwd3d<32><<<grid, 64 * kTileY3, 0, st>>>(a); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (a.cka && a.wst) return hipErrorInvalidValue;  // one extra store kind per launch
+    if (wx == 64 && bz == 16)
+        fwd3d_mode<64, 16>(a, grid, st);
+    else if (wx == 64 && bz == 32)
+        fwd3d_mode<64, 32>(a, grid, st);
+    else if (wx == 32 && bz == 16)
+        fwd3d_mode<32, 16>(a, grid, st);
+    else if (wx == 32 && bz == 32)
+        fwd3d_mode<32, 32>(a, grid, st);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-static hipError_t adj3d_dispatch(const StepArgs &a, int ty, hipStream_t st)
+static hipError_t adj3d_dispatch(const StepArgs &a, int wx, hipStream_t st)
 {
     dim3 grid(8 * a.per_xcd_g);  // one workgroup per tile of a sample's grid
-    if (ty != kTileY3 || a.bzg != 16) return hipErrorInvalidValue;
-    k_adj3d<16><<<grid, 64 * kTileY3, 0, st>>>(a);
+    if (a.bzg != 16) return hipErrorInvalidValue;
+    if (wx == 64)
+        k_adj3d<64, 16><<<grid, 64 * kWaves3, 0, st>>>(a);
+    else if (wx == 32)
+        k_adj3d<32, 16><<<grid, 64 * kWaves3, 0, st>>>(a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1672,11 +1713,11 @@ static hipError_t adj2d_dispatch(const StepArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty, hipStream_t st)
+hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int wx, hipStream_t st)
 {
     if (a.ntiles <= 0) return hipSuccess;
     if (ndim == 2) return adjoint ? adj2d_dispatch(a, st) : fwd2d_dispatch(a, bz, st);
-    return adjoint ? adj3d_dispatch(a, ty, st) : fwd3d_dispatch(a, bz, ty, st);
+    return adjoint ? adj3d_dispatch(a, wx, st) : fwd3d_dispatch(a, bz, wx, st);
 }
 
 hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st)

@@ -13,8 +13,9 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t st);
 hipError_t launch_prep(const SampleDesc *smp, int nsample, int64_t max_cell, const float *v, float *cf, int *status,
                        hipStream_t st);
-// one time step over every tile; bz = rows (2D) or planes (3D) per tile, ty = 3D tile height
-hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int ty, hipStream_t st);
+// one time step over every tile; bz = rows (2D) or planes (3D) per tile, wx = 3D tile width
+// (64 or 32 cells; the tile is 8 * 64 / wx rows high)
+hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int wx, hipStream_t st);
 // two 2D time steps over every two-step strip (tables and nw of the two-step plan)
 hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st);
 hipError_t launch_residual(const SimDesc *sims, int nsim, int nt_rec, const float *d, const float *dobs, float *rho,

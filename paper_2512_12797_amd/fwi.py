@@ -84,6 +84,13 @@ def lib():
         L.fwi_graphs_enable.argtypes = [C.c_int32]
         L.fwi_graphs_stats.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.fwi_set_tile.argtypes = [C.c_int32, C.c_int32]
+        L.fwi_set_tile_width.restype = C.c_int32
+        L.fwi_set_tile_width.argtypes = [C.c_int32]
+        L.fwi_set_overlap.restype = C.c_int32
+        L.fwi_set_overlap.argtypes = [C.c_int32]
+        L.fwi_tile_shape.restype = C.c_int32
+        L.fwi_tile_shape.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]
         L.fwi_tune.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p, C.c_size_t,
                                C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]
@@ -349,6 +356,23 @@ def fwi_graphs_stats():
 
 def fwi_set_tile(ndim: int, bz: int):
     _ok(lib().fwi_set_tile(ndim, bz))
+
+
+def fwi_set_tile_width(wx: int):
+    """3D tile width: 64, 32, or 0 for the automatic choice."""
+    _ok(lib().fwi_set_tile_width(wx))
+
+
+def fwi_tile_shape(batch, time):
+    """(tile height or planes, tile width) the step kernels would use for this batch."""
+    bz, wx = C.c_int32(0), C.c_int32(0)
+    _ok(lib().fwi_tile_shape(batch.c, C.byref(time), C.byref(bz), C.byref(wx)))
+    return bz.value, wx.value
+
+
+def fwi_set_overlap(on: bool):
+    """Checkpointed schedules: recompute the next segment beside the current adjoint."""
+    _ok(lib().fwi_set_overlap(1 if on else 0))
 
 
 def fwi_set_time_blocking(fwd_steps: int, adj_steps: int):

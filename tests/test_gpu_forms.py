@@ -362,6 +362,55 @@ def _run(F, batch, time, v, dobs, kappa, ws, stream=None):
     return dpred.cpu().numpy(), mis.cpu().numpy(), grad.cpu().numpy()
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_overlapped_recomputation_is_bitwise_sequential(F, ndim):
+    """Checkpointed schedules with the recomputation of segment s - 1 beside the adjoint of
+    segment s (side stream, two imaging rings) give the sequential schedule's results bit
+    for bit, directly and as a replayed graph, and match the oracle.  nt = 97 with
+    checkpoints every 6 steps leaves a short last segment."""
+    say("case overlapped recomputation %dD" % ndim)
+    if ndim == 2:
+        batch, groups, _, models = _edge_batch(F, 3, 6, nt=97, R=1)
+        time = F.time_axis(1e-3, 97, 1, 6)
+    else:
+        g = F.Grid(nz=14, ny=11, nx=30, dz=20.0, dy=20.0, dx=20.0, nb=3, v_ref=3500.0, v_max=3850.0, ndim=3)
+        r0 = np.random.default_rng(5)
+        srcs = [(r0.integers(0, g.nphys, 2).astype(np.int32), [1.0, -1.0]) for _ in range(3)]
+        rec = np.arange(0, g.nphys, 7, dtype=np.int32)
+        batch = F.Batch([g], [0, 0, 0], srcs, [rec] * 3, W.ricker(9.0, 2e-3, 97))
+        groups = [(None, None, 1.0)]
+        models = [f32(r0.uniform(1800, 3400, g.nphys))]
+        time = F.time_axis(2e-3, 97, 1, 6)
+    kappa = [gr[2] for gr in groups]
+    r = np.random.default_rng(2)
+    dobs_np = [f32(1e-3 * r.standard_normal((97, batch.nrec[s]))) for s in range(batch.nsim)]
+    dobs = dev(np.concatenate([d.ravel() for d in dobs_np]))
+    v = dev(np.concatenate(models))
+    side = torch.cuda.Stream()
+    outs = []
+    try:
+        for ov, graphs in ((False, False), (True, False), (True, True)):
+            F.fwi_set_overlap(ov)
+            F.fwi_graphs_enable(graphs)
+            ws = F.alloc_workspace(batch, time)
+            for _ in range(2 if graphs else 1):  # capture, then replay
+                outs.append(_run(F, batch, time, v, dobs, kappa, ws, stream=side if graphs else None))
+            del ws
+    finally:
+        F.fwi_set_overlap(False)
+        F.fwi_graphs_enable(False)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    dt = 1e-3 if ndim == 2 else 2e-3
+    _, omis, ogr = oracle_batch_gradient(batch, dt, 97, 1, models, dobs_np, 2.0, kappa)
+    gg = split_model(outs[0][2].astype(np.float64), batch)
+    for k in range(batch.nsample):
+        e = rel(gg[k], ogr[k])
+        say("  sample %d gradient rel %.2e" % (k, e))
+        assert e < TOL
+
+
 @pytest.mark.parametrize("ckpt", [0, 6])
 def test_graph_replays_equal_eager(F, ckpt):
     say("case graph replays ckpt=%d" % ckpt)

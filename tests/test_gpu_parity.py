@@ -204,9 +204,9 @@ def test_determinism(F):
 
 # --------------------------------------------------------------------- 3D
 
-@pytest.mark.parametrize("ckpt", [0, 6])
-def test_3d_parity(F, ckpt):
-    say("case 3d ckpt_every=%d" % ckpt)
+@pytest.mark.parametrize("ckpt,wx", [(0, 32), (6, 32), (0, 64), (6, 64)])
+def test_3d_parity(F, ckpt, wx):
+    say("case 3d ckpt_every=%d tile width %d" % (ckpt, wx))
     g = F.Grid(nz=18, ny=21, nx=70, dz=20.0, dy=22.0, dx=25.0, nb=5, v_ref=3500.0, v_max=3600.0, ndim=3)
     cfg = W.C5
     m = f32(W.layered_salt_3d(18, 21, 70, seed=4, vmin=1500, vmax=3500).ravel())
@@ -226,7 +226,11 @@ def test_3d_parity(F, ckpt):
     # half-amplitude observed data keeps the residual ratio near 1 (well-conditioned
     # d - d_obs) despite the short record being dominated by direct arrivals
     dobs = [f32(0.5 * d) for d in oracle_forward_sims(batch, 2e-3, nt, R, [truth], coef_fp32=False)]
-    dp, mis, gr, gn = run_gradient(F, batch, time, [m], np.concatenate([d.ravel() for d in dobs]), 1.0, [1.0])
+    try:
+        F.fwi_set_tile_width(wx)
+        dp, mis, gr, gn = run_gradient(F, batch, time, [m], np.concatenate([d.ravel() for d in dobs]), 1.0, [1.0])
+    finally:
+        F.fwi_set_tile_width(0)
     odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, [m], dobs, 1.0, [1.0])
     gdp = split_data(dp, batch, nt // R)
     for s in range(2):
@@ -244,8 +248,9 @@ def test_3d_uneven_batch_per_sample_imaging(F):
     """Two 3D samples of different grid sizes with 3 and 1 supergathers, receivers on planes
     through the whole depth, against the oracle, with 16- and 32-plane forward tiles (the
     adjoint sweeps 16-plane tiles of each sample's grid for all of its supergathers; under
-    32-plane forward tiles it skips the receiver events above its first plane) -- and the
-    two tile heights bit-identical."""
+    32-plane forward tiles it skips the receiver events above its first plane) and tiles
+    64 and 32 cells wide (one and two rows per wavefront) -- and all four tile shapes
+    bit-identical."""
     say("case 3d uneven batch")
     grids = [F.Grid(nz=30, ny=9, nx=40, dz=20.0, dy=22.0, dx=25.0, nb=4, v_ref=3500.0, v_max=3600.0, ndim=3),
              F.Grid(nz=20, ny=12, nx=70, dz=20.0, dy=22.0, dx=25.0, nb=3, v_ref=3500.0, v_max=3600.0, ndim=3)]
@@ -275,12 +280,16 @@ def test_3d_uneven_batch_per_sample_imaging(F):
     outs = []
     try:
         for bz in (16, 32):
-            F.fwi_set_tile(3, bz)
-            outs.append(run_gradient(F, batch, time, models, flat, 1.0, kappa))
+            for wx in (64, 32):
+                F.fwi_set_tile(3, bz)
+                F.fwi_set_tile_width(wx)
+                outs.append(run_gradient(F, batch, time, models, flat, 1.0, kappa))
     finally:
         F.fwi_set_tile(3, 0)
-    for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(a, b)
+        F.fwi_set_tile_width(0)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
     dp, mis, gr, _ = outs[0]
     odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, models, dobs, 1.0, kappa)
     gdp = split_data(dp, batch, nt // R)
@@ -296,11 +305,12 @@ def test_3d_uneven_batch_per_sample_imaging(F):
         assert e < TOL
 
 
-def test_3d_launch_order_groups(F):
+@pytest.mark.parametrize("wx", [32, 64])
+def test_3d_launch_order_groups(F, wx):
     """3D batch of two samples with 5 and 2 supergathers on different grids: the forward's
     launch order takes at most 4 of a sample's supergathers at a tile position (groups of
     4 + 1, then 2), and every result matches the oracle."""
-    say("case 3d launch-order groups")
+    say("case 3d launch-order groups, tile width %d" % wx)
     grids = [F.Grid(nz=22, ny=10, nx=37, dz=20.0, dy=20.0, dx=20.0, nb=4, v_ref=3500.0, v_max=3600.0, ndim=3),
              F.Grid(nz=18, ny=13, nx=30, dz=20.0, dy=20.0, dx=20.0, nb=3, v_ref=3500.0, v_max=3600.0, ndim=3)]
     r = np.random.default_rng(21)
@@ -318,7 +328,11 @@ def test_3d_launch_order_groups(F):
     truths = [f32(m * 0.9) for m in models]
     dobs = [f32(0.5 * d) for d in oracle_forward_sims(batch, 2e-3, nt, R, truths, coef_fp32=False)]
     kappa = [0.7, 1.3]
-    dp, mis, gr, _ = run_gradient(F, batch, time, models, np.concatenate([d.ravel() for d in dobs]), 1.0, kappa)
+    try:
+        F.fwi_set_tile_width(wx)
+        dp, mis, gr, _ = run_gradient(F, batch, time, models, np.concatenate([d.ravel() for d in dobs]), 1.0, kappa)
+    finally:
+        F.fwi_set_tile_width(0)
     odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, models, dobs, 1.0, kappa)
     gdp = split_data(dp, batch, nt // R)
     for s in range(batch.nsim):
