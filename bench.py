@@ -1,14 +1,15 @@
 #!/usr/bin/env python3
 """Benchmark: encoded-shot FWI gradient + Langevin update on one MI355X.
 
-Workload (one "step" = one Langevin refinement of every posterior sample): 2D
-400 x 150 grid at 20 m (440 x 190 with the 20-cell sponge), 80 surface shots of a 6 Hz
-Ricker wavelet and 400 receivers, 2000 recorded samples at 2 ms from 4000 internal
-steps of 1 ms; 16 posterior samples, each drawing 10 supergathers of 8 shots with
-+-1 polarity per step (160 simulations in one launch per time step).  Per step: draw
+Default workload (one "step" = one Langevin refinement of every posterior sample): 3D
+200 x 200 x 100 grid at 25 m (220 x 220 x 120 with the 10-cell sponge), 64 surface shots
+of a 4 Hz Ricker wavelet on an 8 x 8 lattice and 2500 receivers, 1500 steps of 2 ms; 8
+posterior samples, each drawing 4 supergathers of 16 shots with +-1 polarity per step (32
+simulations in one launch per time step), checkpoints every 10 steps.  Per step: draw
 encodings (host), encode observed data, forward + misfit + adjoint-state gradient,
-Langevin update.  Inputs are seeded synthetic (folded-layer thrust model, smoothed
-start, 1 % Gaussian noise) and resident in HBM before the timed region.
+Langevin update.  Inputs are seeded synthetic (dipping layers with a salt body, smoothed
+start, 1 % Gaussian noise) and resident in HBM before the timed region.  The 2D encoded
+workload (400 x 150, 16 samples x 10 supergathers) follows as an extra record.
 
 Prints one JSON line.  Metric: physical cell-steps of the complete forward + adjoint
 gradient per second (Gcell-steps/s).
@@ -45,8 +46,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Host core count and CPU model (for the CPU baseline's record)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu": model}
+
+
 def cpu_baseline(batch, grid, wav, nt_sample, R, vstart, cfg):
-    """Time the oracle (as it stands) on one sample's supergathers for nt_sample steps."""
+    """Time the oracle (as it stands) on one posterior sample's supergathers for nt_sample
+    internal steps: a bounded sample of the workload, reported as a rate."""
     import oracle
     sims = [s for s in range(batch.nsim) if batch.sample_of[s] == 0]
     og = oracle.Grid(nz=grid.nz, nx=grid.nx, dz=grid.dz, dx=grid.dx, nb=grid.nb, v_ref=grid.v_ref, ny=grid.ny,
@@ -63,7 +79,9 @@ def cpu_baseline(batch, grid, wav, nt_sample, R, vstart, cfg):
         rp[i + 1] = rp[i] + (b - a)
     r = np.random.default_rng(99)
     dobs = [r.standard_normal((nt_sample // R, rp[i + 1] - rp[i])) for i in range(len(sims))]
-    threads = min(len(sims), int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
+    host = host_cpu()
+    # the oracle runs its simulations in parallel (OpenMP, one thread per simulation)
+    threads = min(len(sims), int(os.environ.get("OMP_NUM_THREADS", host["nproc"] or 1)), host["nproc"] or 1)
     t0 = time.perf_counter()
     oracle.gradient_batch([og] * len(sims), [vstart.ravel()] * len(sims), cfg.dt, nt_sample, R, sp,
                           np.array(sc, dtype=np.int32), np.array(sw, dtype=np.float64), wav[:nt_sample].astype(np.float64),
@@ -72,8 +90,359 @@ def cpu_baseline(batch, grid, wav, nt_sample, R, vstart, cfg):
     cells = len(sims) * grid.nphys * nt_sample
     return {"value": cells / dt / 1e9, "unit": "Gcell-steps/s", "cores": threads, "kind": "oracle",
             "sample": "FP64 oracle gradient (forward + misfit + adjoint + imaging) of one posterior sample's "
-                      "%d supergathers over the first %d of the %d internal steps, OpenMP over supergathers; "
-                      "%.1f s wall" % (len(sims), nt_sample, cfg.nt, dt)}
+                      "%d supergathers over the first %d of the %d internal steps (physical cell-steps over wall "
+                      "time, a bounded sample of the workload), one OpenMP thread per supergather; %.1f s wall"
+                      % (len(sims), nt_sample, cfg.nt, dt),
+            "host": host}
+
+
+_COPY_GBS = []
+
+
+def copy_probe(torch, fwi, dev):
+    """Achievable streaming bandwidth on this GPU: the library's copy kernel over 1 GiB."""
+    if _COPY_GBS:
+        return _COPY_GBS[0]
+    n4 = 1 << 28  # floats per buffer (1 GiB)
+    a = torch.empty(n4, device=dev)
+    b = torch.empty(n4, device=dev)
+    fwi.fwi_copy_probe(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        fwi.fwi_copy_probe(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * 4 * n4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    _COPY_GBS.append(gbs)
+    return gbs
+
+
+def gradient_bench(torch, fwi, problems, args, cfg, steps, warmup, with_cpu):
+    """Encoded-shot gradient + Langevin update of every posterior sample of `cfg`, timed
+    over `steps` refinement steps after `warmup`; returns the bench record."""
+    dev = torch.device("cuda:0")
+    nt = args.nt or cfg.nt
+    R = cfg.rec_every
+    nt_rec = nt // R
+    grid = problems.grid_of(cfg)
+    wav = W.ricker(cfg.freq, cfg.dt, nt)
+    if cfg.ndim == 2:
+        vtrue = W.thrust_2d(cfg.nz, cfg.nx, seed=args.seed)
+        vstart = np.clip(W.smooth(vtrue, 16.0), cfg.vmin, cfg.vmax)
+    else:
+        vtrue = W.layered_salt_3d(cfg.nz, cfg.ny, cfg.nx, seed=args.seed, vmin=cfg.vmin, vmax=cfg.vmax)
+        vstart = np.clip(W.smooth(vtrue, 8.0), cfg.vmin, cfg.vmax)
+    shots = problems.shot_cells(cfg, grid)
+
+    # ---- observed data: forward of the true model, one simulation per shot (setup)
+    t_setup = time.perf_counter()
+    obs_batch = problems.single_shot_batch(cfg, grid, shots, wav)
+    tf = fwi.time_axis(cfg.dt, nt, R, -1)
+    ws_obs = fwi.alloc_workspace(obs_batch, tf)
+    d_shots = torch.empty(cfg.nshot, nt_rec, len(problems.receiver_cells(cfg, grid)), device=dev)
+    fwi.fwi_forward(obs_batch, tf, torch.tensor(vtrue.ravel(), dtype=torch.float32, device=dev), d_shots, ws_obs)
+    fwi.fwi_poll_status(ws_obs)
+    del ws_obs
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    rms = float(d_shots.pow(2).mean().sqrt())
+    sigma = 0.01 * rms
+    d_shots += sigma * torch.randn(d_shots.shape, generator=gen, device=dev)
+    inv_sigma2 = 1.0 / sigma ** 2
+
+    # ---- the sampler state
+    batch0, groups0 = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, args.seed, 0)
+    v = torch.tensor(np.tile(vstart.ravel(), cfg.nsample), dtype=torch.float32, device=dev)
+    nsim = batch0.nsim
+    d_enc = torch.empty(nsim, nt_rec, d_shots.shape[2], device=dev)
+    grad = torch.empty(batch0.model_size, device=dev)
+    gnorm = torch.empty(cfg.nsample, device=dev)
+    misfit = torch.empty(nsim, dtype=torch.float64, device=dev)
+
+    fwi.fwi_set_overlap(bool(args.overlap))
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if args.ckpt == "auto":
+        ckpt = 0
+        for k in (0, 10, 15, 20, 30, 50, 100):
+            need = fwi.fwi_workspace_size(batch0, fwi.time_axis(cfg.dt, nt, R, k))
+            if need < free - (8 << 30):
+                ckpt = k
+                break
+    else:
+        ckpt = int(args.ckpt)
+    time_ax = fwi.time_axis(cfg.dt, nt, R, ckpt)
+    ws = fwi.alloc_workspace(batch0, time_ax)
+    log("[%s] setup %.1f s; workspace %.1f GB (ckpt_every=%d); free %.1f of %.1f GB" % (
+        cfg.name, time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, free / 1e9, total / 1e9))
+
+    fwi.fwi_set_tile_width(args.tile_width)
+    tuned = None
+    if args.tile:
+        fwi.fwi_set_tile(cfg.ndim, args.tile)
+        tuned = (args.tile, 0, float("nan"))
+        log("tile height forced to %d" % args.tile)
+    elif args.tune:
+        cache = os.environ.get("FWI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "fwi_tune_cache.json"))
+        tuned = fwi.fwi_tune(batch0, time_ax, v, ws, cache)
+        log("tuner: tile height %d, adjoint steps per launch %d, %.3f ms per gradient time step" % tuned)
+    fwi.fwi_set_time_blocking(args.fwd_steps, args.adj_steps)
+    stream = torch.cuda.Stream()  # graphs need a non-default stream
+    prev_stream = torch.cuda.current_stream()
+    torch.cuda.set_stream(stream)
+    fwi.fwi_graphs_enable(bool(args.graphs))
+    eta = [1e-3]
+    v_lo, v_hi = cfg.vmin * 0.9, cfg.vmax * 1.1
+
+    def step(t):
+        batch, groups = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, args.seed, t)
+        ptr, shot, w = problems.encode_tables(groups, cfg.shots_per_group)
+        gp = torch.from_numpy(ptr).to(dev, non_blocking=True)
+        gs = torch.from_numpy(shot).to(dev, non_blocking=True)
+        gw = torch.from_numpy(w).to(dev, non_blocking=True)
+        fwi.fwi_encode(d_shots, gp, gs, gw, d_enc)
+        kappa = [g[2] for g in groups]
+        fwi.fwi_gradient(batch, time_ax, v, d_enc, inv_sigma2, kappa, None, misfit, grad, gnorm, ws)
+        fwi.fwi_langevin(batch.model_off, v, grad, None, args.seed, t, eta[0], math.sqrt(2 * eta[0]), v_lo, v_hi)
+
+    for t in range(warmup):
+        step(t)
+        if t == 0:
+            gmax = float(grad.abs().max())
+            eta[0] = 10.0 / gmax if gmax > 0 else 1e-3  # ~10 m/s per refinement step
+    fwi.fwi_poll_status(ws)
+    torch.cuda.synchronize()
+
+    # kernel durations: HIP events around every step launch of the timed region when the
+    # launches are direct; graph replays cannot be timed per kernel, so with graphs the same
+    # step is repeated once, untimed, with direct launches and events
+    fwi.fwi_timing_read(0, True)
+    fwi.fwi_timing_read(1, True)
+    fwi.fwi_timing_enable(not args.graphs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(warmup, warmup + steps):
+        step(t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwi.fwi_timing_enable(False)
+    fwi.fwi_poll_status(ws)
+    elapsed = t1 - t0
+    gstats = fwi.fwi_graphs_stats()
+    if args.graphs:
+        fwi.fwi_graphs_enable(False)
+        fwi.fwi_timing_enable(True)
+        step(warmup + steps)
+        torch.cuda.synchronize()
+        fwi.fwi_timing_enable(False)
+    fwd_ms, fwd_n = fwi.fwi_timing_read(0, True)
+    adj_ms, adj_n = fwi.fwi_timing_read(1, True)
+    torch.cuda.set_stream(prev_stream)
+
+    ny_pad = cfg.ny + 2 * cfg.nb if cfg.ndim == 3 else 1
+    phys_cells = nsim * cfg.nz * cfg.ny * cfg.nx
+    pad_cells = nsim * (cfg.nz + 2 * cfg.nb) * ny_pad * (cfg.nx + 2 * cfg.nb)
+    samp_cells = cfg.nsample * (cfg.nz + 2 * cfg.nb) * ny_pad * (cfg.nx + 2 * cfg.nb)
+    cell_steps = phys_cells * nt * steps
+    value = cell_steps / elapsed / 1e9
+    log("[%s] step %.1f ms; %.1f Gcell-steps/s physical, %.1f padded; fwd kernel %.1f us x %d, adj kernel %.1f us "
+        "x %d" % (cfg.name, 1e3 * elapsed / steps, value, pad_cells * nt * steps / elapsed / 1e9,
+                  1e3 * fwd_ms / max(fwd_n, 1), fwd_n, 1e3 * adj_ms / max(adj_n, 1), adj_n))
+    # two time steps per launch: the 2D keep-all schedule with an even step count (every
+    # launch of the timed sweep is then a two-step launch)
+    blk = cfg.ndim == 2 and ckpt == 0 and nt % 2 == 0
+    adj_eff = args.adj_steps or (tuned[1] if tuned is not None and tuned[1] else 2)
+    two_fwd = blk and args.fwd_steps == 2
+    two_adj = blk and adj_eff == 2
+    width = fwi.fwi_tile_shape(batch0, time_ax)[1] if cfg.ndim == 3 else None
+
+    # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
+    # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
+    # 16 B per simulation cell, plus c once per sample cell; with checkpoints the forward
+    # sweeps (first pass: 12 B plus a checkpoint pair every K steps, 8/K B; recomputation:
+    # 16 B) average to 14 + 4/K B per simulation cell
+    fwd_bytes = pad_cells * (16 if ckpt == 0 else 14 + 4.0 / ckpt) + samp_cells * 4
+    # adjoint + imaging: lt^{k+1}, lt^{k+2}, W^{k-1} read and lt^k written per simulation
+    # cell; c read and the FP64 per-sample accumulator read + written per sample cell
+    adj_bytes = pad_cells * 16 + samp_cells * 20
+    if cfg.ndim == 2:
+        adj_name = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)"
+        fwd_name = "forward step (k_fwd2d<bz>)"
+        # per launch of two steps: u^{n-1}, u^n read, u^{n+1}, u^{n+2}, W^n, W^{n+1} written
+        # (24 B per simulation cell), c read once; adjoint: lt^{k+2}, lt^{k+1}, W^{k-1},
+        # W^{k-2} read, lt^k, lt^{k-1} written (24 B), c and the accumulator once (20 B)
+        if two_fwd:
+            fwd_bytes = pad_cells * 24 + samp_cells * 4
+            fwd_name = "two-step forward (k_fwd2d2<16>)"
+        if two_adj:
+            adj_bytes = pad_cells * 24 + samp_cells * 20
+            adj_name = "two-step adjoint+imaging (k_adj2d2<16>, per-sample imaging)"
+    else:
+        adj_name = "adjoint+imaging step (k_adj3d<%d,16>, per-sample imaging)" % width
+        fwd_name = "forward step (k_fwd3d<%d,bz>)" % width
+    if adj_ms >= fwd_ms:
+        name, nbytes, ms, n = adj_name, adj_bytes, adj_ms, adj_n
+    else:
+        name, nbytes, ms, n = fwd_name, fwd_bytes, fwd_ms, fwd_n
+    avg_s = ms / max(n, 1) / 1e3
+    achieved = nbytes / avg_s / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s.json" % ("2d" if cfg.ndim == 2 else "3d"))
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            # counters are valid for the measured kernel sources, kernel and tile height only
+            two = two_adj if name == adj_name else two_fwd
+            rows = 16 if two else (tuned[0] if tuned is not None else None)
+            if (tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name
+                    and rows is not None and tj.get("tile_rows") == rows):
+                traffic = tj.get("bytes_per_launch")
+        except (ValueError, OSError):
+            traffic = None
+    copy_gbs = copy_probe(torch, fwi, dev)
+
+    if cfg.ndim == 3:
+        wl = ("3d-200x200x100-salt-64shot-s16: 8 samples x 4 supergathers (+-1) of 16 shots, %d steps of 2 ms, "
+              "gradient + Langevin" % nt)
+    else:
+        wl = ("2d-400x150-thrust-80shot-s8: 16 samples x 10 supergathers (+-1) of 8 shots, %d steps of 1 ms, "
+              "gradient + Langevin" % nt)
+    res = {
+        "metric": "Gcell-steps/s fwd+adjoint FWI gradient",
+        "value": round(value, 3),
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(1e3 * elapsed / steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl,
+                   "grid": [cfg.nz, cfg.ny, cfg.nx] if cfg.ndim == 3 else [cfg.nz, cfg.nx],
+                   "padded": [cfg.nz + 2 * cfg.nb, ny_pad, cfg.nx + 2 * cfg.nb] if cfg.ndim == 3 else
+                             [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
+                   "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
+                   "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
+                   "tile_rows": tuned[0] if tuned else None, "tile_width": width, "graphs": bool(args.graphs),
+                   "time_steps_per_launch": {"forward": 2 if two_fwd else 1, "adjoint": 2 if two_adj else 1},
+                   "graph_captures_replays": list(gstats),
+                   "padded_gcell_steps_per_s": round(pad_cells * nt * steps / elapsed / 1e9, 3),
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": int(round(nbytes)), "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+                     "copy_probe_GBs": round(copy_gbs, 1)},
+    }
+    # all step kernels of one gradient together (forward and adjoint sweeps): their
+    # algorithmic bytes over their summed live durations, and the share of the step's wall
+    # time they take
+    k_s = (fwd_ms + adj_ms) / 1e3
+    if k_s > 0 and fwd_n and adj_n:
+        all_gbs = (fwd_bytes * fwd_n + adj_bytes * adj_n) / k_s / 1e9
+        res["roofline_step_kernels"] = {
+            "bound": "hbm", "achieved": round(all_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(all_gbs / PEAK_HBM_GBS, 4), "of_copy_probe": round(all_gbs / copy_gbs, 3),
+            "kernel_ms_per_gradient": round(1e3 * k_s, 2), "share_of_step": round(k_s / (elapsed / steps), 4),
+            "forward_avg_us": round(1e3 * fwd_ms / max(fwd_n, 1), 2),
+            "adjoint_avg_us": round(1e3 * adj_ms / max(adj_n, 1), 2)}
+    del ws
+    torch.cuda.empty_cache()
+    if with_cpu:
+        log("cpu baseline ...")
+        # the oracle keeps every wavefield of a simulation in host memory: the 3D sample is a
+        # short window of steps (5.8 M cells x 8 B per step and simulation)
+        cpu_nt = args.cpu_steps or (nt if cfg.ndim == 2 else 60)
+        res["cpu_baseline"] = cpu_baseline(batch0, grid, wav, min(cpu_nt, nt), R, vstart, cfg)
+    return res
+
+
+def uneven_bench(torch, fwi, problems, args):
+    """The uneven batch in one launch per time step: 32 samples round-robin over 256x128,
+    512x200 and 800x200 grids (10 m, 20-cell sponge), salt models, one supergather of 8
+    shots per sample, 2000 steps of 1 ms, checkpoints every 10 steps; the encoded gradient
+    of every sample timed over `steps` calls after `warmup`."""
+    dev = torch.device("cuda:0")
+    cfg = W.C3
+    nt = args.nt or cfg.nt
+    sizes = list(W.C3_SIZES)
+    grids = [fwi.Grid(nz=sizes[k % 3][0], nx=sizes[k % 3][1], dz=cfg.h, dx=cfg.h, nb=cfg.nb, v_ref=cfg.vmax,
+                      v_max=cfg.vmax * 1.1) for k in range(cfg.nsample)]
+    wav = W.ricker(cfg.freq, cfg.dt, nt)
+    nshot_of = lambda g: max(cfg.shots_per_group, g.nx // 16)  # noqa: E731
+    truth = [W.salt_2d(g.nz, g.nx, seed=args.seed + k).ravel() for k, g in enumerate(grids)]
+    start = [W.smooth(m.reshape(g.nz, g.nx), 10.0).ravel() for m, g in zip(truth, grids)]
+    batch, groups = problems.encoded_batch(cfg, grids, wav, seed=args.seed, step=0, s=cfg.shots_per_group, G=1,
+                                           nshot_of=nshot_of)
+    ckpt = 10 if args.ckpt == "auto" else int(args.ckpt)
+    time_ax = fwi.time_axis(cfg.dt, nt, 1, ckpt)
+    # observed data: the library's forward of the true models (setup)
+    tf = fwi.time_axis(cfg.dt, nt, 1, -1)
+    ws = fwi.alloc_workspace(batch, tf)
+    dobs = torch.empty(batch.data_size(nt), device=dev)
+    fwi.fwi_forward(batch, tf, torch.tensor(np.concatenate(truth), dtype=torch.float32, device=dev), dobs, ws)
+    fwi.fwi_poll_status(ws)
+    del ws
+    fwi.fwi_set_overlap(bool(args.overlap))
+    ws = fwi.alloc_workspace(batch, time_ax)
+    v = torch.tensor(np.concatenate(start), dtype=torch.float32, device=dev)
+    grad = torch.empty(batch.model_size, device=dev)
+    mis = torch.empty(batch.nsim, dtype=torch.float64, device=dev)
+    kappa = [g[2] for g in groups]
+    bz, wx = fwi.fwi_tile_shape(batch, time_ax)
+    stream = torch.cuda.Stream()
+    prev_stream = torch.cuda.current_stream()
+    torch.cuda.set_stream(stream)
+    fwi.fwi_graphs_enable(bool(args.graphs))
+    for _ in range(args.warmup):
+        fwi.fwi_gradient(batch, time_ax, v, dobs, 1.0, kappa, None, mis, grad, None, ws)
+    fwi.fwi_poll_status(ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwi.fwi_gradient(batch, time_ax, v, dobs, 1.0, kappa, None, mis, grad, None, ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwi.fwi_graphs_enable(False)
+    fwi.fwi_timing_read(0, True)
+    fwi.fwi_timing_read(1, True)
+    fwi.fwi_timing_enable(True)
+    fwi.fwi_gradient(batch, time_ax, v, dobs, 1.0, kappa, None, mis, grad, None, ws)
+    torch.cuda.synchronize()
+    fwi.fwi_timing_enable(False)
+    fwd_ms, fwd_n = fwi.fwi_timing_read(0, True)
+    adj_ms, adj_n = fwi.fwi_timing_read(1, True)
+    torch.cuda.set_stream(prev_stream)
+    pad = sum((g.nz + 2 * g.nb) * (g.nx + 2 * g.nb) for g in grids)   # one simulation per sample
+    phys = sum(g.nz * g.nx for g in grids)
+    value = phys * nt * args.steps / elapsed / 1e9
+    # bytes per launch as in the 2D and 3D lines: forward 14 + 4/K B per simulation cell
+    # (first pass and recomputation averaged) + 4 B per sample cell; adjoint 16 + 20 B
+    fwd_bytes = pad * (14 + 4.0 / ckpt + 4)
+    adj_bytes = pad * (16 + 20)
+    fwd_us, adj_us = 1e3 * fwd_ms / max(fwd_n, 1), 1e3 * adj_ms / max(adj_n, 1)
+    if adj_ms >= fwd_ms:
+        name, nbytes, us, n = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)", adj_bytes, adj_us, adj_n
+    else:
+        name, nbytes, us, n = "forward step (k_fwd2d<bz>)", fwd_bytes, fwd_us, fwd_n
+    achieved = nbytes / (us / 1e6) / 1e9
+    log("[uneven] %.1f ms per gradient; %.1f Gcell-steps/s physical; fwd %.1f us x %d, adj %.1f us x %d" % (
+        1e3 * elapsed / args.steps, value, fwd_us, fwd_n, adj_us, adj_n))
+    return {"metric": "Gcell-steps/s fwd+adjoint FWI gradient", "value": round(value, 3), "unit": "Gcell-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(1e3 * elapsed / args.steps, 2), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "2d-uneven-256x128/512x200/800x200-salt: 32 samples x 1 supergather of 8 shots, "
+                                   "%d steps of 1 ms, gradient only, one launch per time step over all grids" % nt,
+                       "nsim": batch.nsim, "schedule": "checkpoint every %d" % ckpt, "tile_rows": bz,
+                       "graphs": bool(args.graphs), "padded_cells": pad, "parallelism": "1 GPU"},
+            "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                         "bytes_per_launch": int(round(nbytes)), "avg_launch_us": round(us, 2), "launches": n}}
 
 
 PEAK_BF16_TFLOPS = 2500.0  # dense MFMA, BF16
@@ -437,13 +806,20 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay each gradient as a captured HIP graph")
     ap.add_argument("--tune", type=int, default=1, help="pick the tile height with the library's tuner")
     ap.add_argument("--tile", type=int, default=0, help="force this tile height (rows per tile); 0: tuner or heuristic")
+    ap.add_argument("--overlap", type=int, default=0, help="checkpoints: recompute beside the adjoint (0/1)")
+    ap.add_argument("--tile-width", type=int, default=0, choices=[0, 32, 64],
+                    help="3D tile width in cells (0: the library's choice by idle lanes)")
     ap.add_argument("--fwd-steps", type=int, default=0, choices=[0, 1, 2],
                     help="2D keep-all schedule: time steps per forward launch (0: automatic, 1)")
     ap.add_argument("--adj-steps", type=int, default=0, choices=[0, 1, 2],
                     help="2D keep-all schedule: time steps per adjoint launch (0: the tuner's choice, else 2)")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: all)")
-    ap.add_argument("--workload", default="2d", choices=["2d", "3d", "equal-error", "unet", "precond", "daps", "svgd"],
-                    help="2d: 400x150, 160 simulations (the reported line); 3d: 200x200x100, 32 simulations; "
+    ap.add_argument("--no-extra", action="store_true", help="3d: skip the 2D workload's extra record")
+    ap.add_argument("--workload", default="3d",
+                    choices=["2d", "3d", "uneven", "equal-error", "unet", "precond", "daps", "svgd"],
+                    help="3d: 200x200x100, 32 simulations (the reported line; the 2D workload follows as an extra "
+                         "record); 2d: 400x150, 160 simulations; uneven: 32 samples on 256x128 / 512x200 / 800x200 "
+                         "grids in one launch per step (checkpoints every 10); "
                          "equal-error: posterior samples/hour of plain, encoded and preconditioned chains at equal "
                          "posterior-mean RMSE (several minutes); unet: the gradient preconditioner's network "
                          "(inference, training step, per-layer convolution rooflines); precond: ~10k solver-made "
@@ -498,248 +874,18 @@ def main():
         res.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32"})
         print(json.dumps(res), flush=True)
         return
-    dev = torch.device("cuda:0")
+    if args.workload == "uneven":
+        print(json.dumps(uneven_bench(torch, fwi, problems, args)), flush=True)
+        return
     cfg = W.C2 if args.workload == "2d" else W.C5
-    nt = args.nt or cfg.nt
-    R = cfg.rec_every
-    nt_rec = nt // R
-    grid = problems.grid_of(cfg)
-    wav = W.ricker(cfg.freq, cfg.dt, nt)
-    if cfg.ndim == 2:
-        vtrue = W.thrust_2d(cfg.nz, cfg.nx, seed=args.seed)
-        vstart = np.clip(W.smooth(vtrue, 16.0), cfg.vmin, cfg.vmax)
-    else:
-        vtrue = W.layered_salt_3d(cfg.nz, cfg.ny, cfg.nx, seed=args.seed, vmin=cfg.vmin, vmax=cfg.vmax)
-        vstart = np.clip(W.smooth(vtrue, 8.0), cfg.vmin, cfg.vmax)
-    shots = problems.shot_cells(cfg, grid)
-
-    # ---- observed data: forward of the true model, one simulation per shot (setup)
-    t_setup = time.perf_counter()
-    obs_batch = problems.single_shot_batch(cfg, grid, shots, wav)
-    tf = fwi.time_axis(cfg.dt, nt, R, -1)
-    ws_obs = fwi.alloc_workspace(obs_batch, tf)
-    d_shots = torch.empty(cfg.nshot, nt_rec, len(problems.receiver_cells(cfg, grid)), device=dev)
-    fwi.fwi_forward(obs_batch, tf, torch.tensor(vtrue.ravel(), dtype=torch.float32, device=dev), d_shots, ws_obs)
-    fwi.fwi_poll_status(ws_obs)
-    del ws_obs
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(args.seed)
-    rms = float(d_shots.pow(2).mean().sqrt())
-    sigma = 0.01 * rms
-    d_shots += sigma * torch.randn(d_shots.shape, generator=gen, device=dev)
-    inv_sigma2 = 1.0 / sigma ** 2
-
-    # ---- the sampler state
-    batch0, groups0 = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, args.seed, 0)
-    v = torch.tensor(np.tile(vstart.ravel(), cfg.nsample), dtype=torch.float32, device=dev)
-    nsim = batch0.nsim
-    d_enc = torch.empty(nsim, nt_rec, d_shots.shape[2], device=dev)
-    grad = torch.empty(batch0.model_size, device=dev)
-    gnorm = torch.empty(cfg.nsample, device=dev)
-    misfit = torch.empty(nsim, dtype=torch.float64, device=dev)
-
-    free, total = torch.cuda.mem_get_info()
-    if args.ckpt == "auto":
-        ckpt = 0
-        for k in (0, 10, 15, 20, 30, 50, 100):
-            need = fwi.fwi_workspace_size(batch0, fwi.time_axis(cfg.dt, nt, R, k))
-            if need < free - (8 << 30):
-                ckpt = k
-                break
-    else:
-        ckpt = int(args.ckpt)
-    time_ax = fwi.time_axis(cfg.dt, nt, R, ckpt)
-    ws = fwi.alloc_workspace(batch0, time_ax)
-    log("setup %.1f s; workspace %.1f GB (ckpt_every=%d); free %.1f of %.1f GB" % (
-        time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, free / 1e9, total / 1e9))
-
-    tuned = None
-    if args.tile:
-        fwi.fwi_set_tile(cfg.ndim, args.tile)
-        tuned = (args.tile, 0, float("nan"))
-        log("tile height forced to %d" % args.tile)
-    elif args.tune:
-        cache = os.environ.get("FWI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "fwi_tune_cache.json"))
-        tuned = fwi.fwi_tune(batch0, time_ax, v, ws, cache)
-        log("tuner: tile height %d, adjoint steps per launch %d, %.3f ms per gradient time step" % tuned)
-    fwi.fwi_set_time_blocking(args.fwd_steps, args.adj_steps)
-    stream = torch.cuda.Stream()  # graphs need a non-default stream
-    torch.cuda.set_stream(stream)
-    fwi.fwi_graphs_enable(bool(args.graphs))
-    eta = [1e-3]
-    v_lo, v_hi = cfg.vmin * 0.9, cfg.vmax * 1.1
-
-    def step(t):
-        batch, groups = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, args.seed, t)
-        ptr, shot, w = problems.encode_tables(groups, cfg.shots_per_group)
-        gp = torch.from_numpy(ptr).to(dev, non_blocking=True)
-        gs = torch.from_numpy(shot).to(dev, non_blocking=True)
-        gw = torch.from_numpy(w).to(dev, non_blocking=True)
-        fwi.fwi_encode(d_shots, gp, gs, gw, d_enc)
-        kappa = [g[2] for g in groups]
-        fwi.fwi_gradient(batch, time_ax, v, d_enc, inv_sigma2, kappa, None, misfit, grad, gnorm, ws)
-        fwi.fwi_langevin(batch.model_off, v, grad, None, args.seed, t, eta[0], math.sqrt(2 * eta[0]), v_lo, v_hi)
-
-    for t in range(args.warmup):
-        step(t)
-        if t == 0:
-            gmax = float(grad.abs().max())
-            eta[0] = 10.0 / gmax if gmax > 0 else 1e-3  # ~10 m/s per refinement step
-    fwi.fwi_poll_status(ws)
-    torch.cuda.synchronize()
-
-    # kernel durations: HIP events around every step launch of the timed region when the
-    # launches are direct; graph replays cannot be timed per kernel, so with graphs the same
-    # step is repeated once, untimed, with direct launches and events
-    fwi.fwi_timing_read(0, True)
-    fwi.fwi_timing_read(1, True)
-    fwi.fwi_timing_enable(not args.graphs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(args.warmup, args.warmup + args.steps):
-        step(t)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fwi.fwi_timing_enable(False)
-    fwi.fwi_poll_status(ws)
-    elapsed = t1 - t0
-    gstats = fwi.fwi_graphs_stats()
-    if args.graphs:
-        fwi.fwi_graphs_enable(False)
-        fwi.fwi_timing_enable(True)
-        step(args.warmup + args.steps)
-        torch.cuda.synchronize()
-        fwi.fwi_timing_enable(False)
-    fwd_ms, fwd_n = fwi.fwi_timing_read(0, True)
-    adj_ms, adj_n = fwi.fwi_timing_read(1, True)
-
-    ny_pad = cfg.ny + 2 * cfg.nb if cfg.ndim == 3 else 1
-    phys_cells = nsim * cfg.nz * cfg.ny * cfg.nx
-    pad_cells = nsim * (cfg.nz + 2 * cfg.nb) * ny_pad * (cfg.nx + 2 * cfg.nb)
-    samp_cells = cfg.nsample * (cfg.nz + 2 * cfg.nb) * ny_pad * (cfg.nx + 2 * cfg.nb)
-    cell_steps = phys_cells * nt * args.steps
-    value = cell_steps / elapsed / 1e9
-    log("step %.1f ms; %.1f Gcell-steps/s physical, %.1f padded; fwd kernel %.1f us x %d, adj kernel %.1f us x %d" % (
-        1e3 * elapsed / args.steps, value, pad_cells * nt * args.steps / elapsed / 1e9,
-        1e3 * fwd_ms / max(fwd_n, 1), fwd_n, 1e3 * adj_ms / max(adj_n, 1), adj_n))
-    # two time steps per launch: the 2D keep-all schedule with an even step count (every
-    # launch of the timed sweep is then a two-step launch)
-    blk = cfg.ndim == 2 and ckpt == 0 and nt % 2 == 0
-    adj_eff = args.adj_steps or (tuned[1] if tuned is not None and tuned[1] else 2)
-    two_fwd = blk and args.fwd_steps == 2
-    two_adj = blk and adj_eff == 2
-
-    # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
-    # adjoint + imaging step: lt^{k+1}, lt^{k+2} read, lt^k write, W^{k-1} read = 16 B per
-    # simulation cell; c read and the FP64 imaging accumulator read+written: 2D sums a
-    # sample's supergathers in one workgroup (4 + 16 B per sample cell), 3D keeps one
-    # accumulator per simulation (16 B per simulation cell, 4 B per sample cell).
-    # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
-    # 16 B per simulation cell (12 B when recomputing from checkpoints without a store),
-    # plus c once per sample cell.
-    # with checkpoints the forward sweeps (first pass: 12 B plus a checkpoint pair every K
-    # steps, 8/K B; recomputation: 16 B) average to 14 + 4/K B per simulation cell
-    fwd_bytes = pad_cells * (16 if ckpt == 0 else 14 + 4.0 / ckpt) + samp_cells * 4
-    # adjoint + imaging: lt^{k+1}, lt^{k+2}, W^{k-1} read and lt^k written per simulation
-    # cell; c read and the FP64 per-sample accumulator read + written per sample cell
-    adj_bytes = pad_cells * 16 + samp_cells * 20
-    if cfg.ndim == 2:
-        adj_name = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)"
-        fwd_name = "forward step (k_fwd2d<bz>)"
-        # per launch of two steps: u^{n-1}, u^n read, u^{n+1}, u^{n+2}, W^n, W^{n+1} written
-        # (24 B per simulation cell), c read once; adjoint: lt^{k+2}, lt^{k+1}, W^{k-1},
-        # W^{k-2} read, lt^k, lt^{k-1} written (24 B), c and the accumulator once (20 B)
-        if two_fwd:
-            fwd_bytes = pad_cells * 24 + samp_cells * 4
-            fwd_name = "two-step forward (k_fwd2d2<16>)"
-        if two_adj:
-            adj_bytes = pad_cells * 24 + samp_cells * 20
-            adj_name = "two-step adjoint+imaging (k_adj2d2<16>, per-sample imaging)"
-    else:
-        adj_name = "adjoint+imaging step (k_adj3d<16>, per-sample imaging)"
-        fwd_name = "forward step (k_fwd3d<bz>)"
-    if adj_ms >= fwd_ms:
-        name, nbytes, ms, n = adj_name, adj_bytes, adj_ms, adj_n
-    else:
-        name, nbytes, ms, n = fwd_name, fwd_bytes, fwd_ms, fwd_n
-    avg_s = ms / max(n, 1) / 1e3
-    achieved = nbytes / avg_s / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
-    if os.path.exists(tfile):
-        try:
-            tj = json.load(open(tfile))
-            # counters are valid for the measured kernel sources, kernel and tile height only
-            two = two_adj if name == adj_name else two_fwd
-            rows = 16 if two else (tuned[0] if tuned is not None else None)
-            if (tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name
-                    and rows is not None and tj.get("tile_rows") == rows):
-                traffic = tj.get("bytes_per_launch")
-        except (ValueError, OSError):
-            traffic = None
-
-    # ---- copy probe: achievable bandwidth for context
-    n4 = 1 << 28  # 1 GiB per buffer
-    a = torch.empty(n4, device=dev)
-    b = torch.empty(n4, device=dev)
-    fwi.fwi_copy_probe(a, b)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        fwi.fwi_copy_probe(a, b)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * 4 * n4 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del a, b
-
-    res = {
-        "metric": "Gcell-steps/s fwd+adjoint FWI gradient",
-        "value": round(value, 3),
-        "unit": "Gcell-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": ("2d-400x150-thrust-80shot-s8: 16 samples x 10 supergathers (+-1), "
-                                "%d steps of 1 ms, gradient + Langevin" % nt) if cfg.ndim == 2 else
-                               ("3d-200x200x100-salt-64shot-s16: 8 samples x 4 supergathers (+-1), "
-                                "%d steps of 2 ms, gradient + Langevin" % nt),
-                   "grid": [cfg.nz, cfg.ny, cfg.nx] if cfg.ndim == 3 else [cfg.nz, cfg.nx],
-                   "padded": [cfg.nz + 2 * cfg.nb, ny_pad, cfg.nx + 2 * cfg.nb] if cfg.ndim == 3 else
-                             [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
-                   "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
-                   "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
-                   "tile_rows": tuned[0] if tuned else None, "graphs": bool(args.graphs),
-                   "time_steps_per_launch": {"forward": 2 if two_fwd else 1, "adjoint": 2 if two_adj else 1},
-                   "graph_captures_replays": list(gstats),
-                   "padded_gcell_steps_per_s": round(pad_cells * nt * args.steps / elapsed / 1e9, 3),
-                   "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": int(round(nbytes)), "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
-                     "copy_probe_GBs": round(copy_gbs, 1)},
-    }
-    # all step kernels of one gradient together (forward and adjoint sweeps): their
-    # algorithmic bytes over their summed live durations, and the share of the step's wall
-    # time they take
-    k_s = (fwd_ms + adj_ms) / 1e3
-    if k_s > 0 and fwd_n and adj_n:
-        all_gbs = (fwd_bytes * fwd_n + adj_bytes * adj_n) / k_s / 1e9
-        res["roofline_step_kernels"] = {
-            "bound": "hbm", "achieved": round(all_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(all_gbs / PEAK_HBM_GBS, 4), "of_copy_probe": round(all_gbs / copy_gbs, 3),
-            "kernel_ms_per_gradient": round(1e3 * k_s, 2), "share_of_step": round(k_s / (elapsed / args.steps), 4)}
-    if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        # the oracle keeps every wavefield of a simulation in host memory: the 3D sample is a
-        # short window of steps (5.8 M cells x 8 B per step and simulation)
-        cpu_nt = args.cpu_steps or (nt if cfg.ndim == 2 else 60)
-        res["cpu_baseline"] = cpu_baseline(batch0, grid, wav, min(cpu_nt, nt), R, vstart, cfg)
+    res = gradient_bench(torch, fwi, problems, args, cfg, args.steps, args.warmup, not args.no_cpu_baseline)
+    if args.workload == "3d" and not args.no_extra and not args.nt:
+        # the 2D encoded workload as a second record (its own measurement, not the value)
+        r2 = gradient_bench(torch, fwi, problems, args, W.C2, min(args.steps, 10), min(args.warmup, 3), False)
+        res["extra_workloads"] = {
+            r2["config"]["workload"]: {k: r2[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup")} |
+            {"roofline": r2["roofline"], "roofline_step_kernels": r2.get("roofline_step_kernels"),
+             "config": r2["config"]}}
     print(json.dumps(res), flush=True)
 
 
