@@ -283,9 +283,10 @@ bool valid_bz(int ndim, int bz)
     return bz == 16 || bz == 32;
 }
 
-// 3D tile width: 32-wide tiles (two rows per wavefront, 16 rows per tile) when they leave
-// fewer lanes idle over the batch's grids than 64-wide ones (8 rows per tile), unless a
-// width is forced.
+// 3D tile width: 64 cells (8 rows per tile) unless 32-wide tiles (two rows per wavefront,
+// 16 rows per tile) would run fewer than half the lanes over the batch's grids, or a width
+// is forced.  (On the 220 x 220 x 120 padded grid 32-wide tiles run 12 % fewer lanes but
+// measured 11 % slower: a 64-wide row segment is two whole 128-byte lines.)
 int pick_width3(const fwi_batch *b)
 {
     const int forced = g_width3.load();
@@ -299,7 +300,7 @@ int pick_width3(const fwi_batch *b)
             lanes[i] += ((Nx + wx - 1) / wx) * wx * ((Ny + ty - 1) / ty) * ty;
         }
     }
-    return lanes[1] < lanes[0] ? 32 : 64;
+    return 2 * lanes[1] < lanes[0] ? 32 : 64;
 }
 
 void pick_tiles(Plan &p, const fwi_batch *b, int bz_override, int wx_override)

@@ -8,7 +8,7 @@ The paper's velocity models and data are not available, so seeded stand-ins with
 shapes and value ranges of its workloads are used (2D ocean-bottom-node synthetics:
 fixed-spread receivers and sources one cell below the surface, Ricker wavelet,
 smoothed-truth starting model, "Posterior sampling using 2D ocean-bottom node synthetic
-data"; 3D upscaling study, Table 3).
+data"; 3D upscaling study, Table 2).
 """
 from __future__ import annotations
 
