@@ -75,12 +75,14 @@ fwi_status check_grid(const fwi_grid &g, int i)
     if (g.nb > 0 && !(g.v_ref > 0)) return fail(FWI_E_ARG, "grid %d: v_ref must be > 0", i);
     if (g.nb > 0 && !(g.refl > 0 && g.refl < 1)) return fail(FWI_E_ARG, "grid %d: refl must be in (0,1)", i);
     if (!(g.v_max > 0) || !std::isfinite(g.v_max)) return fail(FWI_E_ARG, "grid %d: v_max must be > 0", i);
-    const int64_t N = (int64_t)(g.nz + 2 * g.nb) * (g.ndim == 3 ? g.ny + 2 * g.nb : 1) * (g.nx + 2 * g.nb);
+    // x extent with the row pitch (3D rows are padded to kRowAlign cells)
+    const int64_t PX = g.ndim == 3 ? (g.nx + 2 * g.nb + kRowAlign - 1) / kRowAlign * kRowAlign : g.nx + 2 * g.nb;
+    const int64_t N = (int64_t)(g.nz + 2 * g.nb) * (g.ndim == 3 ? g.ny + 2 * g.nb : 1) * PX;
     // fields are addressed through 32-bit byte offsets (FP64 accumulators: 8 bytes/cell)
     if (N >= (int64_t)1 << 28) return fail(FWI_E_UNSUPPORTED, "grid %d: more than 2^28 padded cells", i);
     // the sweeps address up to 80 rows (2D) / planes (3D) past the grid with offsets that
     // must stay below bit 31 even when doubled (out-of-grid lanes carry bit 31)
-    const int64_t slice = (int64_t)4 * (g.ndim == 3 ? (int64_t)(g.ny + 2 * g.nb) * (g.nx + 2 * g.nb) : g.nx + 2 * g.nb);
+    const int64_t slice = (int64_t)4 * (g.ndim == 3 ? (int64_t)(g.ny + 2 * g.nb) * PX : PX);
     if ((int64_t)(g.nz + 2 * g.nb + 80) * slice > (int64_t)1 << 30)
         return fail(FWI_E_UNSUPPORTED, "grid %d: (padded nz + 80) x row or plane bytes exceeds 2^30", i);
     return FWI_OK;
@@ -403,7 +405,8 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         S.v_max = g.v_max;
         S.kappa = kappa ? kappa[k] : 1.0;
         S.nphys = (int64_t)g.nz * g.ny * g.nx;
-        S.ncell = (int64_t)S.N[0] * S.N[1] * S.N[2];
+        S.px = g.ndim == 3 ? (S.N[2] + kRowAlign - 1) / kRowAlign * kRowAlign : S.N[2];
+        S.ncell = (int64_t)S.N[0] * S.N[1] * S.px;
         S.sim_beg = -1;
         p.coefs += S.ncell;
         p.max_cell = std::max(p.max_cell, S.ncell);
@@ -432,6 +435,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
         }
         S.nb = g.nb;
         S.ndim = g.ndim;
+        S.px = Sm.px;
         S.nrec = b->rec_ptr[s + 1] - b->rec_ptr[s];
         S.src_beg = b->src_ptr[s];
         S.src_cnt = b->src_ptr[s + 1] - b->src_ptr[s];

@@ -4,6 +4,11 @@
 // (physical grid plus nb sponge cells on every face) per field level, packed one after
 // the other at SimDesc::u_off.  Per-sample arrays (the leapfrog coefficient c = dt^2 v^2 /
 // (1 + gamma dt)) are packed at SampleDesc::c_off.  x is the fastest axis, then y, then z.
+// Rows are px cells apart: in 3D the padded x extent rounded up to kRowAlign cells (128
+// bytes), so that every row starts on a cache line and a 64-cell tile row covers two whole
+// lines; the columns past the padded extent hold zeros, written by the step kernels so
+// that they store whole lines (a partly written line costs an extra fetch).  In 2D px is
+// the padded x extent.
 #pragma once
 #include <stdint.h>
 
@@ -15,6 +20,7 @@ constexpr int kHalo = 4;     // 8th-order stencil radius
 // a strip of kStrip2 columns; strips are kRows2 rows high (forward and adjoint alike).
 constexpr int kStrip2 = kTileX - 2 * kHalo;
 constexpr int kRows2 = 16;
+constexpr int kRowAlign = 32;  // 3D row pitch granule (cells)
 
 struct SimDesc {
     int64_t u_off;      // element offset of this sim in every field level
@@ -29,6 +35,7 @@ struct SimDesc {
     int32_t src_cnt;    // number of sources
     int32_t sample;     // owning sample
     int32_t ndim;
+    int32_t px;         // row pitch (cells)
     float w[3][5];      // stencil weights C_k / h_a^2, axes (z, y, x); zero for an unused axis
     float inv_vol;      // 1 / prod h
     int32_t tile0;      // index of this sim's first tile
@@ -54,7 +61,7 @@ struct SampleDesc {
     int64_t ncell;      // padded cells
     int64_t g_off;      // element offset of its first imaging accumulator slot
     int32_t g_cnt;      // accumulator slots (padded grids of ncell cells, consecutive)
-    int32_t pad0;
+    int32_t px;         // row pitch (cells)
 };
 
 struct Tile {

@@ -78,12 +78,16 @@ __global__ void k_prep(const SampleDesc *__restrict__ smp, const float *__restri
     const SampleDesc S = smp[blockIdx.y];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int Nx = S.N[2], Ny = S.N[1];
+    const int Nx = S.N[2], Ny = S.N[1], P = S.px;
     const int nby = S.ndim == 3 ? S.nb : 0;
     int bad = 0;
     for (; i < S.ncell; i += stride) {
-        int px = (int)(i % Nx);
-        int64_t r = i / Nx;
+        int px = (int)(i % P);
+        int64_t r = i / P;
+        if (px >= Nx) {  // row pitch padding
+            cf[S.c_off + i] = 0.0f;
+            continue;
+        }
         int py = (int)(r % Ny);
         int pz = (int)(r / Ny);
         int ix = min(max(px - S.nb, 0), S.n[2] - 1);
@@ -1062,10 +1066,12 @@ struct Lanes3 {
     static constexpr int LY = TY + 2 * kHalo + RW;  // LDS rows (+ RW spare rows)
     int lc, ry, x, y;        // lane's column and row in the tile, cell coordinates
     bool in;                 // the cell lies in the grid
-    uint32_t col, cb;        // byte offset of (y, x) in a plane; poisoned copy for loads
+    bool row;                // the cell lies in a row of the grid (x below the row pitch)
+    uint32_t col, cb, sb;    // byte offset of (y, x) in a plane; poisoned copies for loads
+                             // (cells of the grid) and for stores (cells of its rows)
     uint32_t hyb, hxb;       // poisoned offsets of the lane's y- and x-halo cells
     int hrow, hcol, hxrow;   // LDS row of the y-halo cell, column and row of the x-halo cell
-    __device__ __forceinline__ Lanes3(int tx0, int ty0, int Nx, int Ny)
+    __device__ __forceinline__ Lanes3(int tx0, int ty0, int Nx, int Ny, int P)
     {
         const int lane = threadIdx.x & 63;
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1075,8 +1081,10 @@ struct Lanes3 {
         x = tx0 + lc;
         y = ty0 + ry;
         in = x < Nx && y < Ny;
-        col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1));
+        row = x < P && y < Ny;
+        col = 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)P + (uint32_t)min(x, P - 1));
         cb = in ? col : kPoison;
+        sb = row ? col : kPoison;
         // y halo: rows ty0-4 .. ty0-1, then ty0+TY .. ty0+TY+3, RW per wavefront; the
         // other wavefronts load nothing and write a spare LDS row
         const int hr = w * RW + lr;
@@ -1084,7 +1092,7 @@ struct Lanes3 {
         const int hy = hr < kHalo ? ty0 - kHalo + hr : ty0 + TY + hr - kHalo;
         hrow = hw ? (hr < kHalo ? hr : TY + hr) : TY + 2 * kHalo + lr;
         const bool hyl = hw && x < Nx && hy >= 0 && hy < Ny;
-        hyb = hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)Nx + (uint32_t)min(x, Nx - 1)) : kPoison;
+        hyb = hyl ? 4u * ((uint32_t)min(max(hy, 0), Ny - 1) * (uint32_t)P + (uint32_t)min(x, Nx - 1)) : kPoison;
         // x halo of the lane's row: columns tx0-4 .. tx0-1 (lc 0..3), tx0+WX .. +3 (lc 4..7);
         // the other lanes load nothing and write a spare LDS row
         const int hxx = lc < kHalo ? tx0 - kHalo + lc : tx0 + WX + lc - kHalo;
@@ -1092,7 +1100,7 @@ struct Lanes3 {
         hxrow = lc < 2 * kHalo ? ry + kHalo : TY + 2 * kHalo + lr;
         if (lc >= 2 * kHalo) hcol = lc;
         const bool hxl = lc < 2 * kHalo && y < Ny && hxx >= 0 && hxx < Nx;
-        hxb = hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)Nx + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
+        hxb = hxl ? 4u * ((uint32_t)min(y, Ny - 1) * (uint32_t)P + (uint32_t)min(max(hxx, 0), Nx - 1)) : kPoison;
     }
 };
 
@@ -1138,10 +1146,10 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
     const int nz_phys = S.n[0], ny_phys = S.n[1], nx_phys = S.n[2], nb = S.nb;
     const double gmz = S.gmax[0];
     const int src_beg = S.src_beg, src_cnt = S.src_cnt;
-    const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
+    const uint32_t pbytes = 4u * (uint32_t)S.px * (uint32_t)Ny;
     const uint32_t fbytes = pbytes * (uint32_t)Nz;
     const int z0 = T.z0;
-    const G g(T.x0, T.y0, Nx, Ny);
+    const G g(T.x0, T.y0, Nx, Ny, S.px);
     const int64_t u_off = S.u_off;
     const rsrc_t rU = make_rsrc(A.cur + u_off, fbytes);
     const rsrc_t rP = make_rsrc(A.prev + u_off, fbytes);
@@ -1173,7 +1181,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
         sponge_ab(gam, dt, a_col, b_col);
     }
     auto poff = [&](int zz) -> uint32_t { return (uint32_t)zz * pbytes; };  // zz < 0 wraps out of range
-    const uint32_t cb = g.cb, hyb = g.hyb, hxb = g.hxb;
+    const uint32_t cb = g.cb, sb = g.sb, hyb = g.hyb, hxb = g.hxb;
 
     // sources in this thread's column
     const int z1 = min(z0 + BZ, Nz);
@@ -1255,13 +1263,15 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
                 wv += extra * famp;
             }
         }
-        const uint32_t o = poff(z) + cb;
-        const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
+        // stores cover the whole row pitch (zeros past the grid's rows), so that every
+        // line is written whole
+        const uint32_t o = poff(z) + sb;
+        const float un = g.in ? a * qq[4] - b * pq[r] + cq[r] * wv : 0.0f;
         bstore(rN, o, un);
-        if (MODE == kStoreImage) bstore(rW, o, wv);
+        if (MODE == kStoreImage) bstore(rW, o, g.in ? wv : 0.0f);
         if (MODE == kStoreCkpt) {
             bstore(rKa, o, un);
-            bstore(rKb, o, qq[4]);
+            bstore(rKb, o, qq[4]);  // 0 past the grid (its loads are poisoned)
         }
         if (z == ev_z) {  // uniform
             if (Dat) {
@@ -1313,10 +1323,10 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
         wy[k] = S0.w[1][k];
         wx[k] = S0.w[2][k];
     }
-    const uint32_t pbytes = 4u * (uint32_t)Nx * (uint32_t)Ny;
+    const uint32_t pbytes = 4u * (uint32_t)Sm.px * (uint32_t)Ny;
     const uint32_t fbytes = pbytes * (uint32_t)Nz;
     const int z0 = GT.z0;
-    const G g(GT.x0, GT.y0, Nx, Ny);
+    const G g(GT.x0, GT.y0, Nx, Ny, Sm.px);
     const rsrc_t rC = make_rsrc(A.cf + Sm.c_off, fbytes);
     const int rec_j = A.rec_j;
     const EvRow *__restrict__ evrows = A.evrows;
@@ -1346,8 +1356,8 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
         const rsrc_t rW = make_rsrc(A.wimg + u_off, fbytes);
         // lane offsets pass through an empty asm so that the plane offsets built from them
         // are recomputed per sim next to their loads, not hoisted out of the sim loop
-        uint32_t cbs = g.cb, hybs = g.hyb, hxbs = g.hxb;
-        asm volatile("" : "+v"(cbs), "+v"(hybs), "+v"(hxbs));
+        uint32_t cbs = g.cb, sbs = g.sb, hybs = g.hyb, hxbs = g.hxb;
+        asm volatile("" : "+v"(cbs), "+v"(sbs), "+v"(hybs), "+v"(hxbs));
         // per-sim fields read after stores: vector loads, made uniform explicitly
         const int tile0 = __builtin_amdgcn_readfirstlane(A.sims[sim].tile0);
         const int nrec = __builtin_amdgcn_readfirstlane(A.sims[sim].nrec);
@@ -1424,7 +1434,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
                 ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
             }
             const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
-            bstore(rN, poff(z) + cbs, un);
+            bstore(rN, poff(z) + sbs, g.in ? un : 0.0f);  // whole lines, as in the forward
             const double pr = (double)un * (double)wq[r];  // the product of two floats is exact in FP64
             red[r][g.ry][g.lc] = j == 0 ? pr : red[r][g.ry][g.lc] + pr;
             // keep each plane's loads in its own plane (prefetch distance PF planes)
@@ -1434,11 +1444,11 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
     // one read-modify-write of the sample's accumulator per cell (cells outside the grid:
     // poisoned or out-of-range offsets, so the load reads 0 and the store is dropped)
     const rsrc_t rG = make_rsrc(A.gacc + g_off, 2 * fbytes);
-    const uint32_t cb2 = g.in ? 2u * g.col : kPoison;
+    const uint32_t cb2 = g.in ? 2u * g.col : kPoison, sb2 = g.row ? 2u * g.col : kPoison;
 #pragma unroll
     for (int r = 0; r < BZ; ++r) {
-        const uint32_t o = 2u * poff(z0 + r) + cb2;
-        bstore64(rG, o, bload64(rG, o) + red[r][g.ry][g.lc]);
+        const uint32_t o = 2u * poff(z0 + r);
+        bstore64(rG, o + sb2, bload64(rG, o + cb2) + red[r][g.ry][g.lc]);  // 0 past the grid
     }
 }
 
@@ -1516,7 +1526,7 @@ __global__ __launch_bounds__(256) void k_finalize(const SampleDesc *__restrict__
             const double *g = gacc + S.g_off + (int64_t)s * S.ncell;
             for (int pz = zl; pz <= zh; ++pz)
                 for (int py = yl; py <= yh; ++py) {
-                    const int64_t base = ((int64_t)pz * Ny + py) * Nx;
+                    const int64_t base = ((int64_t)pz * Ny + py) * S.px;
                     for (int px = xl; px <= xh; ++px) sum += g[base + px];
                 }
         }
