@@ -421,12 +421,17 @@ def uneven_bench(torch, fwi, problems, args):
     phys = sum(g.nz * g.nx for g in grids)
     value = phys * nt * args.steps / elapsed / 1e9
     # bytes per launch as in the 2D and 3D lines: forward 14 + 4/K B per simulation cell
-    # (first pass and recomputation averaged) + 4 B per sample cell; adjoint 16 + 20 B
+    # (first pass and recomputation averaged) + 4 B per sample cell; adjoint 16 + 20 B per
+    # launch of one step, 24 + 20 B per launch of two (the timed gradient's launch count
+    # tells which)
     fwd_bytes = pad * (14 + 4.0 / ckpt + 4)
-    adj_bytes = pad * (16 + 20)
+    adj_two = adj_n > 0 and 2 * adj_n <= nt
+    adj_bytes = pad * ((24 if adj_two else 16) + 20)
+    adj_name = ("two-step adjoint+imaging (k_adj2d2<16>, per-sample imaging)" if adj_two else
+                "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)")
     fwd_us, adj_us = 1e3 * fwd_ms / max(fwd_n, 1), 1e3 * adj_ms / max(adj_n, 1)
     if adj_ms >= fwd_ms:
-        name, nbytes, us, n = "adjoint+imaging step (k_adj2d<bzg>, per-sample imaging)", adj_bytes, adj_us, adj_n
+        name, nbytes, us, n = adj_name, adj_bytes, adj_us, adj_n
     else:
         name, nbytes, us, n = "forward step (k_fwd2d<bz>)", fwd_bytes, fwd_us, fwd_n
     achieved = nbytes / (us / 1e6) / 1e9
