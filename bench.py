@@ -393,6 +393,7 @@ def uneven_bench(torch, fwi, problems, args):
     grad = torch.empty(batch.model_size, device=dev)
     mis = torch.empty(batch.nsim, dtype=torch.float64, device=dev)
     kappa = [g[2] for g in groups]
+    fwi.fwi_set_time_blocking(args.fwd_steps, args.adj_steps)
     bz, wx = fwi.fwi_tile_shape(batch, time_ax)
     stream = torch.cuda.Stream()
     prev_stream = torch.cuda.current_stream()
@@ -760,6 +761,7 @@ def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pairs = precond.make_pairs(cfg, nmodels, enc_per_model, seed=args.seed, models_per_batch=6,
+                               with_coverage=bool(args.pc_coverage),
                                log=lambda m: log(m) if ("%d models" % nmodels in m or m.count("00 models")) else None)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
@@ -768,20 +770,34 @@ def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e
     cell_steps = float(pairs["solves"]) * npad * npad * cfg.nt
     mid = pairs["model_id"].numpy()
     held = mid >= int(round(0.9 * nmodels))
-    train_idx = np.nonzero(~held)[0]
+    val = ~held & (mid >= int(round(0.8 * nmodels)))   # fits the guard's blend weight
+    train_idx = np.nonzero(~held & ~val)[0]
+    val_idx = torch.from_numpy(np.nonzero(val)[0]).to("cuda")
     test_idx = torch.from_numpy(np.nonzero(held)[0]).to("cuda")
     net = UNet(seed=args.seed)
     t1 = time.perf_counter()
     hist = precond.train(net, pairs, train_idx, steps=steps, batch=8, lr=lr, lr_final=lr / 10, seed=args.seed,
-                         log=lambda m: log(m) if m.startswith("train step") and int(m.split()[2]) % 2000 == 0 else None)
+                         log=lambda m: log(m) if m.startswith("validation") or (
+                             m.startswith("train step") and int(m.split()[2]) % 2000 == 0) else None,
+                         val_idx=val_idx, val_every=args.pc_val_every)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     x, res, tg = pairs["x16"][test_idx], pairs["res"][test_idx], pairs["target"][test_idx]
     plain = precond.rel_err(res, tg)
     out = precond.predict(net, x, res)
     netw = precond.rel_err(precond.channel0(out), tg)
-    guarded, keep = precond.guard(out, torch.ones(x.shape[0], device="cuda"), res)
+    vres, vtg = pairs["res"][val_idx], pairs["target"][val_idx]
+    alpha = precond.fit_blend(precond.channel0(precond.predict(net, pairs["x16"][val_idx], vres)), vres, vtg)
+    guarded, keep = precond.guard(out, torch.ones(x.shape[0], device="cuda"), res, alpha=alpha)
     guard_err = precond.rel_err(guarded, tg)
+    unblended, _ = precond.guard(out, torch.ones(x.shape[0], device="cuda"), res)
+    unblended_err = precond.rel_err(unblended, tg)
+    # the same scores on 1000 training pairs: under- or over-fitting
+    tr = torch.from_numpy(np.random.default_rng(args.seed).choice(train_idx, size=min(1000, len(train_idx)),
+                                                                  replace=False)).to("cuda")
+    tr_plain = precond.rel_err(pairs["res"][tr], pairs["target"][tr])
+    tr_net = precond.rel_err(precond.channel0(precond.predict(net, pairs["x16"][tr], pairs["res"][tr])),
+                             pairs["target"][tr])
     return {"metric": "held-out relative L2 error to the full-shot gradient (plain encoded -> preconditioned)",
             "value": round(float(netw.mean()), 4), "unit": "relative L2", "higher_is_better": False, "n_gpus": 1,
             "dtype": "f32 solver, bf16 network (fp32 accumulate)", "data": "synthetic",
@@ -791,8 +807,14 @@ def precond_bench(torch, args, nmodels=2500, enc_per_model=4, steps=20000, lr=1e
                        "train_steps": steps, "batch": 8, "lr": lr},
             "plain_encoded_error": round(float(plain.mean()), 4), "network_error": round(float(netw.mean()), 4),
             "guarded_error": round(float(guard_err.mean()), 4), "guard_kept": round(float(keep.float().mean()), 3),
+            "guard_blend_alpha": round(alpha, 4), "guarded_error_alpha1": round(float(unblended_err.mean()), 4),
+            "early_stop_step": net.val_best, "validation_error_by_step": [[s_, round(e_, 4)] for s_, e_ in net.val_hist],
+            "heldout_guarded_worse_fraction": round(float(np.mean(guard_err > plain)), 3),
+            "validation_pairs": int(val_idx.numel()),
             "median_plain_network_guarded": [round(float(np.median(x)), 4) for x in (plain, netw, guard_err)],
             "heldout_improved_fraction": round(float(np.mean(netw < plain)), 3),
+            "train_subset_plain_network": [round(float(tr_plain.mean()), 4), round(float(tr_net.mean()), 4)],
+            "shot_coverage_channel": bool(args.pc_coverage),
             "final_train_loss": round(hist[-1][1], 5),
             "pair_generation_s": round(t_pairs, 1), "pairs_per_s": round(npairs / t_pairs, 1),
             "pair_generation_padded_gcell_steps_per_s": round(cell_steps / t_pairs / 1e9, 1),
@@ -830,13 +852,19 @@ def main():
                          "(inference, training step, per-layer convolution rooflines); precond: ~10k solver-made "
                          "training pairs at 256^2, training, held-out error against the plain encoded gradient "
                          "(about 10 minutes)")
-    ap.add_argument("--plain-steps", type=int, default=20, help="equal-error: plain-chain steps that set the target")
-    ap.add_argument("--max-steps", type=int, default=60, help="equal-error: steps of the encoded chains")
+    ap.add_argument("--plain-steps", type=int, default=300,
+                    help="equal-error: most plain-chain steps (the chain stops at the target: 0.9 x the start RMSE)")
+    ap.add_argument("--max-steps", type=int, default=400, help="equal-error: most steps of the encoded chains")
     ap.add_argument("--net-seeds", type=int, default=3, help="equal-error: networks trained (seeds 0..n-1)")
+    ap.add_argument("--chain-log", default=None, help="equal-error: directory for each chain's per-step JSONL log")
     ap.add_argument("--pc-models", type=int, default=2500, help="precond: seeded models (4 pairs each)")
-    ap.add_argument("--pc-steps", type=int, default=20000, help="precond: training steps (batch 8)")
-    ap.add_argument("--pc-lr", type=float, default=1e-3, help="precond: initial Adam learning rate (cosine to 1/10)")
+    ap.add_argument("--pc-steps", type=int, default=1500,
+                    help="precond: training steps (batch 8; the best validation point is kept)")
+    ap.add_argument("--pc-lr", type=float, default=3e-4, help="precond: initial Adam learning rate (cosine to 1/10)")
     ap.add_argument("--pc-G", type=int, default=1, help="precond: supergathers of 8 shots summed per encoded gradient")
+    ap.add_argument("--pc-coverage", type=int, default=1, help="precond: shot-coverage input channel (0/1)")
+    ap.add_argument("--pc-val-every", type=int, default=100,
+                    help="precond: training steps between validation scores (early stopping)")
     ap.add_argument("--daps-tstart", type=int, default=20, help="daps: first diffusion level (of T = 1000)")
     ap.add_argument("--daps-k", type=int, default=5, help="daps: Langevin steps per guided level")
     ap.add_argument("--daps-every", type=int, default=1, help="daps: guidance at every this many levels")
@@ -875,6 +903,7 @@ def main():
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains
         res = chains.equal_error(seed=args.seed, plain_steps=args.plain_steps, max_steps=args.max_steps,
+                                 log_dir=args.chain_log,
                                  net_seeds=tuple(range(args.net_seeds)), log=log)
         res.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32"})
         print(json.dumps(res), flush=True)

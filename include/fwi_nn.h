@@ -145,12 +145,14 @@ fwi_status fwi_nn_prep(const float *g, const float *v, int32_t nimg, int32_t h, 
  * Guarded use of the network's gradient: p_i = scale_i * channel 0 of pred (device f32
  * [nimg][hp][w][c]) over the first h rows is kept when its cosine with the plain gradient
  * g_i (device f32 [nimg][h][w]) is >= cos_min and |p_i|/|g_i| lies in [ratio_lo,
- * ratio_hi] (FP64 statistics, fixed order); otherwise g_i is used.  out: device f32
- * [nimg][h][w]; keep: device int32 [nimg] (1 = network output kept).
+ * ratio_hi] (FP64 statistics, fixed order); otherwise g_i is used.  A kept image gives
+ * g_i + alpha (p_i - g_i) in FP32 (alpha = 1: p_i exactly; alpha = 0: g_i), alpha in
+ * [0, 1], a blend weight fitted on validation pairs.  out: device f32 [nimg][h][w]; keep:
+ * device int32 [nimg] (1 = network output kept).  FWI_E_ARG for alpha outside [0, 1].
  */
 fwi_status fwi_nn_guard(const float *pred, int32_t c, const float *scale, const float *g, int32_t nimg, int32_t h,
-                        int32_t w, int32_t hp, float cos_min, float ratio_lo, float ratio_hi, float *out,
-                        int32_t *keep, void *stream);
+                        int32_t w, int32_t hp, float cos_min, float ratio_lo, float ratio_hi, float alpha,
+                        float *out, int32_t *keep, void *stream);
 
 /* Thread-local detail of the last non-OK status returned by an fwi_nn_* call. */
 const char *fwi_nn_last_error(void);

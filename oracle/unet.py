@@ -204,9 +204,10 @@ def prep_input(g, v, hp, v_shift, v_scale, scale=None):
     return bf16(x), res, scale
 
 
-def guard(pred0, scale, g, cos_min, ratio_lo, ratio_hi):
+def guard(pred0, scale, g, cos_min, ratio_lo, ratio_hi, alpha=1.0):
     """Guarded gradient: p = scale * pred0 (first h rows of [N, hp, W]) is kept when
-    cos(p, g) >= cos_min and |p|/|g| is in [ratio_lo, ratio_hi], else g is used."""
+    cos(p, g) >= cos_min and |p|/|g| is in [ratio_lo, ratio_hi], else g is used.  A kept
+    image is blended with the plain one, g + alpha (p - g) (alpha = 1: p itself)."""
     g = np.asarray(g, dtype=np.float64)
     n, h, w = g.shape
     p = np.asarray(pred0, dtype=np.float64)[:, :h] * np.asarray(scale, dtype=np.float64)[:, None, None]
@@ -216,4 +217,5 @@ def guard(pred0, scale, g, cos_min, ratio_lo, ratio_hi):
         cos = (pf * gf).sum(1) / (pn * gn)
         ratio = pn / gn
     keep = (pn > 0) & (gn > 0) & (cos >= cos_min) & (ratio >= ratio_lo) & (ratio <= ratio_hi)
-    return np.where(keep[:, None, None], p, g), keep
+    kept = p if alpha == 1.0 else g + alpha * (p - g)
+    return np.where(keep[:, None, None], kept, g), keep

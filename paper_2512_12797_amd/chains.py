@@ -9,11 +9,13 @@ Three gradient estimators drive the same clean-space Langevin refinement (Eqs. 8
 * preconditioned: the encoded estimate mapped by the learned U-Net towards the
   full-shot gradient, with the plain-gradient guard.
 
-The target posterior-mean RMSE (m/s against the true model, physical grid) is the one the
-plain chain reaches after a fixed number of steps; each form's wall time to reach it is
-its number of steps times its measured time per step, and samples per hour follow.  The
-plain form is timed two ways: as a naive solver (one simulation per launch, samples one
-after the other; extrapolated from a few timed calls) and batched like the encoded form.
+The target posterior-mean RMSE (m/s against the true model, physical grid) is a fixed
+fraction of the starting RMSE (0.9: a 10 % reduction); the plain chain runs until it
+reaches it, which sets its step count.  Each form's wall time to the target is its number
+of steps times its measured time per step, and samples per hour follow.  The plain form
+is timed two ways: as a naive solver (one simulation per launch, samples one after the
+other; one sample's full step of 80 single-shot gradient calls timed, times 16 samples)
+and batched like the encoded form.
 Each chain's trajectory is computed with the batched library (the estimator, not the
 launch pattern, decides the trajectory).
 """
@@ -21,6 +23,7 @@ from __future__ import annotations
 
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -136,17 +139,18 @@ def make_pairs(sv: Survey, ntruth=32, fractions=(0.0, 0.35, 0.7), nenc=2, seed0=
     return {"x16": torch.cat(xs), "res": torch.cat(rs), "target": torch.cat(tgs)}
 
 
-def precondition(net, g_enc, v):
-    """Network estimate of the full-shot gradient, guarded by the plain encoded one."""
+def precondition(net, g_enc, v, alpha=1.0):
+    """Network estimate of the full-shot gradient, guarded by the plain encoded one and
+    blended with it by alpha (fitted on validation pairs)."""
     S, nz, nx = g_enc.shape
     x16, res, scale = precond.prepare(g_enc, v, nz + PAD_ROWS)
-    return precond.guard(precond.predict(net, x16, res), scale, g_enc)
+    return precond.guard(precond.predict(net, x16, res), scale, g_enc, alpha=alpha)
 
 
 # -------------------------------------------------------------------- chains
 
 def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None, adam_lr=None, keep_samples=False,
-              v0=None, step0=0, log_jsonl=None):
+              v0=None, step0=0, log_jsonl=None, stop_below=None, elapsed0=0.0, alpha=1.0):
     """Langevin refinement of `nsample` samples from the smoothed start; returns the
     posterior-mean RMSE after each step, the mean wall time per step (direct launches,
     steps after the first: the first carries one-time host costs) and, for the
@@ -160,7 +164,9 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
     continuation equals the uninterrupted chain bit for bit (not for the Adam form, whose
     moments are not part of the saved state).  log_jsonl: a file that receives one JSON
     line per step (step, posterior-mean RMSE, mean posterior standard deviation, PDE solves
-    per sample so far, seconds since the start)."""
+    per sample so far, seconds since the chain's start: elapsed0, the time a resumed chain
+    had already run, plus this call's wall time).  stop_below: end the chain after the first
+    step whose posterior-mean RMSE is at or below it."""
     nu = math.sqrt(2 * eta) if nu is None else nu
     if step0 and adam_lr is not None:
         raise ValueError("the Adam form cannot resume: its moments are not saved")
@@ -177,7 +183,7 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
     if adam_lr is not None:
         m1, m2 = torch.zeros_like(v).reshape(-1), torch.zeros_like(v).reshape(-1)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    t0 = t_log = time.perf_counter()  # t0 restarts after the first step (timing), t_log never
     for t in range(steps):
         if t == 1:
             torch.cuda.synchronize()
@@ -187,7 +193,7 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
         else:
             g = sv.encoded_gradient(v, nsample, seed, step0 + t)
             if form == "preconditioned":
-                g, keep = precondition(net, g.view(nsample, nz, nx), v.view(nsample, nz, nx))
+                g, keep = precondition(net, g.view(nsample, nz, nx), v.view(nsample, nz, nx), alpha)
                 g = g.reshape(nsample, -1).contiguous()
                 kept.append(int(keep.sum()))
         g = g.reshape(-1).contiguous()
@@ -197,6 +203,7 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
         else:
             fwi.fwi_langevin(off, v.reshape(-1), g, None, seed, step0 + t, eta, nu, lo, hi)
         rmse.append(float((v.double().mean(0) - vt).pow(2).mean().sqrt()))
+        done = stop_below is not None and rmse[-1] <= stop_below
         if log_jsonl:
             # one forward and one adjoint solve per shot (plain) or per supergather (encoded)
             per_step = 2 * len(sv.shots) // (1 if form == "plain" else sv.cfg.shots_per_group)
@@ -204,9 +211,11 @@ def run_chain(sv: Survey, form, steps, eta, seed, net=None, nsample=16, nu=None,
                 f.write(json.dumps({"step": step0 + t, "posterior_mean_rmse_mps": rmse[-1],
                                     "mean_posterior_std_mps": float(v.double().std(0).mean()) if nsample > 1 else 0.0,
                                     "pde_solves_per_sample": (step0 + t + 1) * per_step,
-                                    "elapsed_s": time.perf_counter() - t0}) + "\n")
+                                    "elapsed_s": elapsed0 + time.perf_counter() - t_log}) + "\n")
+        if done:
+            break
     torch.cuda.synchronize()
-    out = (rmse, (time.perf_counter() - t0) / max(1, steps - 1), kept)
+    out = (rmse, (time.perf_counter() - t0) / max(1, len(rmse) - 1), kept)
     return out + (v,) if keep_samples else out
 
 
@@ -223,10 +232,12 @@ def load_state(path, device="cuda"):
         return torch.tensor(z["v"], device=device), int(z["step"]), int(z["seed"])
 
 
-def time_naive_plain(sv: Survey, v, ncall=8):
+def time_naive_plain(sv: Survey, v, ncall=None):
     """Seconds per Langevin step of a naive plain solver: every shot of every sample its
-    own gradient call (one simulation per launch), one after the other; extrapolated from
-    `ncall` timed calls."""
+    own gradient call (one simulation per launch), one after the other.  Times `ncall`
+    calls (default: every shot, one sample's whole step) and scales to all shots of the
+    16 samples."""
+    ncall = ncall or len(sv.shots)
     cfg = sv.cfg
     calls = []
     for s in range(ncall):
@@ -252,9 +263,13 @@ def first_reaching(rmse, target):
     return None
 
 
-def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=1500, max_update=30.0,
-                start_sigma=6.0, net_seeds=(0,), log=print):
-    """The whole comparison; returns a dict (one JSON object)."""
+def equal_error(seed=1000, plain_steps=300, max_steps=400, ntruth=32, train_steps=1500, max_update=30.0,
+                start_sigma=6.0, net_seeds=(0,), target_frac=0.9, log=print, log_dir=None):
+    """The whole comparison; returns a dict (one JSON object).  log_dir: a directory that
+    receives each chain's per-step JSONL log (run_chain's log_jsonl)."""
+    def jl(name):
+        return None if log_dir is None else os.path.join(log_dir, "chain_%s.jsonl" % name)
+
     sv = Survey(seed=seed, start_sigma=start_sigma, log=log)
     nsample = 16
     v0 = torch.tensor(np.tile(sv.vstart.ravel(), nsample), dtype=torch.float32, device=sv.dev).view(nsample, -1)
@@ -263,28 +278,40 @@ def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=
     log("eta %.3e" % eta)
 
     naive_s = time_naive_plain(sv, v0)
-    log("plain, naive solver: %.1f s per step (extrapolated)" % naive_s)
-    r_plain, s_plain, _ = run_chain(sv, "plain", plain_steps, eta, seed)
-    target = r_plain[-1]
-    log("plain: %d steps, %.2f s per step, RMSE %.1f -> %.1f m/s" % (plain_steps, s_plain, r_plain[0], target))
-    r_enc, s_enc, _ = run_chain(sv, "encoded", max_steps, eta, seed)
-    log("encoded: %.3f s per step, RMSE after %d steps %.1f" % (s_enc, max_steps, r_enc[-1]))
+    log("plain, naive solver: %.1f s per step (one sample's 80 calls timed)" % naive_s)
+    start_rmse = float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2)))
+    target = target_frac * start_rmse
+    r_plain, s_plain, _ = run_chain(sv, "plain", plain_steps, eta, seed, stop_below=target, log_jsonl=jl("plain"))
+    log("plain: %d steps, %.2f s per step, RMSE %.1f -> %.1f m/s (target %.1f)" % (
+        len(r_plain), s_plain, start_rmse, r_plain[-1], target))
+    r_enc, s_enc, _ = run_chain(sv, "encoded", max_steps, eta, seed, stop_below=target, log_jsonl=jl("encoded"))
+    log("encoded: %.3f s per step, %d steps, RMSE %.1f" % (s_enc, len(r_enc), r_enc[-1]))
 
     t0 = time.perf_counter()
     pairs = make_pairs(sv, ntruth=ntruth)
     P = pairs["x16"].shape[0]
     log("pairs: %d in %.1f s" % (P, time.perf_counter() - t0))
+    # pairs come truth by truth (P / ntruth each): the last 4 truths validate (early
+    # stopping and the guard's blend weight)
+    per_truth = P // ntruth
+    val_idx = torch.arange((ntruth - 4) * per_truth, P, device=sv.dev)
+    train_idx = np.arange((ntruth - 4) * per_truth)
     runs = []
     for ns in net_seeds:
         t1 = time.perf_counter()
         net = UNet(chans=(32, 64, 128, 256), seed=ns)
-        hist = precond.train(net, pairs, np.arange(P), steps=train_steps, batch=8, lr=2e-3, lr_final=2e-4,
-                             seed=ns, log=log)
+        hist = precond.train(net, pairs, train_idx, steps=train_steps, batch=8, lr=1e-3, lr_final=1e-4,
+                             seed=ns, log=log, val_idx=val_idx, val_every=100)
+        vres = pairs["res"][val_idx]
+        alpha = precond.fit_blend(precond.channel0(precond.predict(net, pairs["x16"][val_idx], vres)), vres,
+                                  pairs["target"][val_idx])
         t_train = time.perf_counter() - t1
-        r_pre, s_pre, kept = run_chain(sv, "preconditioned", max_steps, eta, seed, net=net)
+        log("network seed %d: validation best after %s steps, blend weight %.3f" % (ns, net.val_best, alpha))
+        r_pre, s_pre, kept = run_chain(sv, "preconditioned", max_steps, eta, seed, net=net, stop_below=target,
+                                       log_jsonl=jl("preconditioned_%d" % ns), alpha=alpha)
         log("preconditioned (network seed %d): %.3f s per step, reaches the target after %s steps" %
             (ns, s_pre, first_reaching(r_pre, target)))
-        runs.append((ns, r_pre, s_pre, kept, t_train, hist))
+        runs.append((ns, r_pre, s_pre, kept, t_train, hist, alpha, net.val_best, net.val_hist))
     del pairs
 
     def entry(rmse, s_step, label):
@@ -298,17 +325,20 @@ def equal_error(seed=1000, plain_steps=20, max_steps=60, ntruth=32, train_steps=
         "metric": "posterior samples/hour at equal posterior-mean RMSE", "unit": "samples/hour",
         "workload": "2d-400x150-thrust-80shot: 16 samples from a start smoothed by %g cells, Langevin eta=%.3e "
                     "(largest first update %g m/s), nu=sqrt(2 eta)" % (start_sigma, eta, max_update),
-        "target_rmse_mps": round(target, 2), "start_rmse_mps": round(float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2))), 2),
-        "plain_steps": plain_steps,
+        "target_rmse_mps": round(target, 2), "start_rmse_mps": round(start_rmse, 2), "target_fraction": target_frac,
+        "plain_steps": len(r_plain),
         "forms": {
-            "plain_naive": {**entry(r_plain, naive_s, "one simulation per launch, samples in turn; extrapolated "
-                                                      "from 8 timed single-shot gradients"), "rmse": None},
+            "plain_naive": {**entry(r_plain, naive_s, "one simulation per launch, samples in turn; one sample's "
+                                                      "80 single-shot gradient calls timed, x 16 samples"),
+                            "rmse": None},
             "plain_batched": entry(r_plain, s_plain, "measured: 2 samples x 80 single-shot simulations per launch"),
             "encoded": entry(r_enc, s_enc, "measured: 16 samples x 10 supergathers of 8 in one launch per step"),
             "preconditioned": [
                 {**entry(r_pre, s_pre, "measured: encoded + U-Net inference + guard"), "network_seed": ns,
                  "network_kept_fraction": round(float(np.mean(kept)) / nsample, 3) if kept else None,
-                 "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]]}
-                for ns, r_pre, s_pre, kept, t_train, hist in runs],
+                 "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]],
+                 "blend_alpha": round(alpha, 4), "early_stop_step": vbest,
+                 "validation_error_by_step": [[s_, round(e_, 4)] for s_, e_ in vhist]}
+                for ns, r_pre, s_pre, kept, t_train, hist, alpha, vbest, vhist in runs],
         },
     }

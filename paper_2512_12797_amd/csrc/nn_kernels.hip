@@ -797,14 +797,16 @@ __global__ __launch_bounds__(256) void k_guard_stats(const float *__restrict__ p
 }
 
 // out[i][y][x] = keep_i ? pred[i][y][x][0] * scale_i : g[i][y][x]  (physical rows only).
+// kept images: g + alpha (p - g), with alpha = 1 giving p exactly
 __global__ void k_guard_write(const float *__restrict__ pred, int C, const float *__restrict__ scale,
-                              const float *__restrict__ g, int nimg, int h, int w, int hp,
+                              const float *__restrict__ g, int nimg, int h, int w, int hp, float alpha,
                               const int32_t *__restrict__ keep, float *__restrict__ out)
 {
     const int64_t hw = (int64_t)h * w, total = (int64_t)nimg * hw;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t img = i / hw, k = i % hw;
-        out[i] = keep[img] ? pred[((int64_t)img * hp * w + k) * C] * scale[img] : g[i];
+        const float p = pred[((int64_t)img * hp * w + k) * C] * scale[img];
+        out[i] = keep[img] ? (alpha == 1.0f ? p : fmaf(alpha, p - g[i], g[i])) : g[i];
     }
 }
 
@@ -1163,16 +1165,17 @@ fwi_status fwi_nn_prep(const float *g, const float *v, int32_t nimg, int32_t h, 
 }
 
 fwi_status fwi_nn_guard(const float *pred, int32_t c, const float *scale, const float *g, int32_t nimg, int32_t h,
-                        int32_t w, int32_t hp, float cos_min, float ratio_lo, float ratio_hi, float *out,
-                        int32_t *keep, void *stream)
+                        int32_t w, int32_t hp, float cos_min, float ratio_lo, float ratio_hi, float alpha,
+                        float *out, int32_t *keep, void *stream)
 {
     if (!pred || !scale || !g || !out || !keep || c < 1 || nimg < 1 || h < 1 || w < 1 || hp < h)
         return nn_fail(FWI_E_ARG, "guard: bad arguments");
+    if (!(alpha >= 0.0f && alpha <= 1.0f)) return nn_fail(FWI_E_ARG, "guard: alpha %g outside [0, 1]", (double)alpha);
     hipStream_t st = (hipStream_t)stream;
     k_guard_stats<<<nimg, 256, 0, st>>>(pred, c, scale, g, h, w, hp, cos_min, ratio_lo, ratio_hi, keep);
     NN_TRY(hipGetLastError());
     const int64_t n = (int64_t)nimg * h * w;
-    k_guard_write<<<grid_for(n), 256, 0, st>>>(pred, c, scale, g, nimg, h, w, hp, keep, out);
+    k_guard_write<<<grid_for(n), 256, 0, st>>>(pred, c, scale, g, nimg, h, w, hp, alpha, keep, out);
     NN_TRY(hipGetLastError());
     return FWI_OK;
 }

@@ -42,7 +42,7 @@ def lib():
             "fwi_nn_to_bf16": [P, C.c_int64, P, P],
             "fwi_nn_prep": [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, P, P, P, P, P],
             "fwi_nn_guard": [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float,
-                             C.c_float, P, P, P],
+                             C.c_float, C.c_float, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -153,6 +153,6 @@ def prep(g, v, nimg, h, w, hp, v_shift, v_scale, scale_in=None, scale_out=None, 
                           _p(res), _s()))
 
 
-def guard(pred, c, scale, g, nimg, h, w, hp, cos_min, ratio_lo, ratio_hi, out, keep):
-    _ok(lib().fwi_nn_guard(_p(pred), c, _p(scale), _p(g), nimg, h, w, hp, cos_min, ratio_lo, ratio_hi, _p(out),
-                           _p(keep), _s()))
+def guard(pred, c, scale, g, nimg, h, w, hp, cos_min, ratio_lo, ratio_hi, out, keep, alpha=1.0):
+    _ok(lib().fwi_nn_guard(_p(pred), c, _p(scale), _p(g), nimg, h, w, hp, cos_min, ratio_lo, ratio_hi, alpha,
+                           _p(out), _p(keep), _s()))

@@ -21,7 +21,8 @@ import torch
 
 from . import nn
 
-IN_CH = 16  # network input channels (2 used: normalised gradient, normalised model)
+IN_CH = 16  # network input channels (padded)
+IN_USED = 3  # channels in use: normalised gradient, normalised model, shot coverage
 
 
 def _pad(c, m):
@@ -59,7 +60,7 @@ class UNet:
         self.enc = []
         for i, c in enumerate(chans):
             cin = IN_CH if i == 0 else chans[i - 1]
-            cin_real = 2 if i == 0 else chans[i - 1]
+            cin_real = IN_USED if i == 0 else chans[i - 1]
             self.enc.append((Conv(cin, c, cin_real, c, rng, device), Conv(c, c, c, c, rng, device)))
         self.dec = [None] * (self.L - 1)
         for i in range(self.L - 2, -1, -1):
@@ -80,7 +81,7 @@ class UNet:
         return ls
 
     def nparams(self):
-        return sum(l.cout_real * 9 * (l.cin if l is not self.enc[0][0] else 2) + l.cout_real for l in self.layers())
+        return sum(l.cout_real * 9 * (l.cin if l is not self.enc[0][0] else IN_USED) + l.cout_real for l in self.layers())
 
     # ------------------------------------------------------------ forward
     def forward(self, x16, res, n, h, w, keep=False):

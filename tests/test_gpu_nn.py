@@ -338,6 +338,37 @@ def test_guard_matches_oracle():
     assert rel(out.cpu().numpy(), oo) < 1e-6
 
 
+def test_guard_blend_matches_oracle():
+    """Blend weights 0.25 and 0 on kept images (and none on rejected ones), against the
+    oracle; a weight outside [0, 1] is refused."""
+    from paper_2512_12797_amd import nn
+    r = np.random.default_rng(13)
+    n, h, w, hp, C = 3, 20, 40, 24, 32
+    g = r.standard_normal((n, h, w)).astype(np.float32)
+    scale = r.uniform(0.5, 2.0, n).astype(np.float32)
+    pred = np.zeros((n, hp, w, C), dtype=np.float32)
+    base = g / scale[:, None, None]
+    pred[0, :h, :, 0] = base[0] + 0.3 * r.standard_normal((h, w))   # kept
+    pred[1, :h, :, 0] = -base[1]                                      # rejected
+    pred[2, :h, :, 0] = 1.5 * base[2] + 0.2 * r.standard_normal((h, w))  # kept
+    args = (torch.tensor(pred, device="cuda"), C, torch.tensor(scale, device="cuda"), torch.tensor(g, device="cuda"),
+            n, h, w, hp, 0.3, 0.2, 5.0)
+    for alpha in (0.25, 0.0):
+        out = torch.empty(n, h, w, device="cuda")
+        keep = torch.empty(n, dtype=torch.int32, device="cuda")
+        nn.guard(*args, out, keep, alpha=alpha)
+        oo, okeep = U.guard(pred[..., 0], scale, g, 0.3, 0.2, 5.0, alpha=alpha)
+        assert list(keep.cpu().numpy().astype(bool)) == list(okeep) == [True, False, True]
+        if alpha == 0.0:
+            assert np.array_equal(out.cpu().numpy(), g)
+        else:
+            assert rel(out.cpu().numpy(), oo) < 1e-6
+    from paper_2512_12797_amd import fwi
+    with pytest.raises(fwi.FwiError):
+        nn.guard(*args, torch.empty(n, h, w, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"),
+                 alpha=1.5)
+
+
 def test_guard_exact_thresholds():
     """Cases that sit exactly on the guard's bounds (cosine 0.5, norm ratio 0.25 and 4, all
     exact in FP32 and FP64: p = (1, 1; 1, 1) with |p| = 2 against g = (8, 0; 0, 0) and

@@ -30,10 +30,12 @@ def test_chain_resume_is_bitwise(tmp_path):
     assert step0 == 2 and seed0 == seed and torch.equal(v0, v_half)
     log = str(tmp_path / "chain.jsonl")
     _, _, _, v_res = chains.run_chain(sv, "encoded", 2, eta, seed0, nsample=ns, keep_samples=True, v0=v0,
-                                      step0=step0, log_jsonl=log)
+                                      step0=step0, log_jsonl=log, elapsed0=5.0)
     import json
     recs = [json.loads(l) for l in open(log)]
     assert [r["step"] for r in recs] == [2, 3]
+    # seconds since the chain's start: the resumed run continues from the 5 s it had run
+    assert 5.0 < recs[0]["elapsed_s"] < recs[1]["elapsed_s"]
     # 80 shots in supergathers of 8: 10 encoded forward + adjoint pairs per step
     assert [r["pde_solves_per_sample"] for r in recs] == [60, 80]
     assert not torch.equal(v_half, v_full)  # the last two steps moved the samples

@@ -155,6 +155,22 @@ def test_guard_zero_norms_fall_back():
     assert not keep[0] and np.array_equal(out[0], g[0])
 
 
+def test_guard_blend_weight():
+    """A kept image with blend weight alpha is g + alpha (p - g): p = (3, 9; 3, 1), g =
+    (2, 0; 0, 0) (cos 0.3, ratio 5: kept) gives (2.25, 2.25; 0.75, 0.25) at alpha = 1/4,
+    g itself at alpha = 0 and p at alpha = 1; a rejected image stays g at any alpha."""
+    p = [[3.0, 9.0], [3.0, 1.0]]
+    pred0, sc, g = _guard_case(p, [[2.0, 0.0], [0.0, 0.0]])
+    out, keep = U.guard(pred0, sc, g, 0.3, 0.2, 5.0, alpha=0.25)
+    assert keep[0] and np.array_equal(out[0], [[2.25, 2.25], [0.75, 0.25]])
+    out, _ = U.guard(pred0, sc, g, 0.3, 0.2, 5.0, alpha=0.0)
+    assert np.array_equal(out[0], g[0])
+    out, _ = U.guard(pred0, sc, g, 0.3, 0.2, 5.0, alpha=1.0)
+    assert np.array_equal(out[0], p)
+    out, keep = U.guard(pred0, sc, g, np.nextafter(0.3, 1.0), 0.2, 5.0, alpha=0.25)
+    assert not keep[0] and np.array_equal(out[0], g[0])
+
+
 def test_guard_per_image_decision_and_scale():
     """Two images in one call, one kept and one rejected (cosine -0.3 < 0), each decided on
     its own; the kept output is scale * pred0."""
