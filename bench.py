@@ -852,9 +852,13 @@ def main():
                          "(inference, training step, per-layer convolution rooflines); precond: ~10k solver-made "
                          "training pairs at 256^2, training, held-out error against the plain encoded gradient "
                          "(about 10 minutes)")
+    ap.add_argument("--ee-forms", default="plain,encoded,preconditioned",
+                    help="equal-error: chains to run (comma-separated; the target depends on the start only)")
+    ap.add_argument("--ee-max-update", type=float, default=100.0,
+                    help="equal-error: the largest first plain update (m/s), which sets eta for every form")
     ap.add_argument("--plain-steps", type=int, default=300,
                     help="equal-error: most plain-chain steps (the chain stops at the target: 0.9 x the start RMSE)")
-    ap.add_argument("--max-steps", type=int, default=400, help="equal-error: most steps of the encoded chains")
+    ap.add_argument("--max-steps", type=int, default=300, help="equal-error: most steps of the encoded chains")
     ap.add_argument("--net-seeds", type=int, default=3, help="equal-error: networks trained (seeds 0..n-1)")
     ap.add_argument("--chain-log", default=None, help="equal-error: directory for each chain's per-step JSONL log")
     ap.add_argument("--pc-models", type=int, default=2500, help="precond: seeded models (4 pairs each)")
@@ -903,7 +907,8 @@ def main():
     if args.workload == "equal-error":
         from paper_2512_12797_amd import chains
         res = chains.equal_error(seed=args.seed, plain_steps=args.plain_steps, max_steps=args.max_steps,
-                                 log_dir=args.chain_log,
+                                 log_dir=args.chain_log, max_update=args.ee_max_update,
+                                 forms=tuple(args.ee_forms.split(",")),
                                  net_seeds=tuple(range(args.net_seeds)), log=log)
         res.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32"})
         print(json.dumps(res), flush=True)

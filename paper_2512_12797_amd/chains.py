@@ -263,10 +263,13 @@ def first_reaching(rmse, target):
     return None
 
 
-def equal_error(seed=1000, plain_steps=300, max_steps=400, ntruth=32, train_steps=1500, max_update=30.0,
-                start_sigma=6.0, net_seeds=(0,), target_frac=0.9, log=print, log_dir=None):
+def equal_error(seed=1000, plain_steps=300, max_steps=300, ntruth=32, train_steps=1500, max_update=100.0,
+                start_sigma=6.0, net_seeds=(0,), target_frac=0.9, log=print, log_dir=None,
+                forms=("plain", "encoded", "preconditioned")):
     """The whole comparison; returns a dict (one JSON object).  log_dir: a directory that
-    receives each chain's per-step JSONL log (run_chain's log_jsonl)."""
+    receives each chain's per-step JSONL log (run_chain's log_jsonl).  forms: the chains to
+    run (the target depends only on the start, so the forms can also run in separate
+    calls and their records be put side by side)."""
     def jl(name):
         return None if log_dir is None else os.path.join(log_dir, "chain_%s.jsonl" % name)
 
@@ -277,26 +280,31 @@ def equal_error(seed=1000, plain_steps=300, max_steps=400, ntruth=32, train_step
     eta = max_update / float(g0.abs().max())  # the largest first update, m/s; all forms alike
     log("eta %.3e" % eta)
 
-    naive_s = time_naive_plain(sv, v0)
-    log("plain, naive solver: %.1f s per step (one sample's 80 calls timed)" % naive_s)
     start_rmse = float(np.sqrt(np.mean((sv.vstart - sv.vtrue) ** 2)))
     target = target_frac * start_rmse
-    r_plain, s_plain, _ = run_chain(sv, "plain", plain_steps, eta, seed, stop_below=target, log_jsonl=jl("plain"))
-    log("plain: %d steps, %.2f s per step, RMSE %.1f -> %.1f m/s (target %.1f)" % (
-        len(r_plain), s_plain, start_rmse, r_plain[-1], target))
-    r_enc, s_enc, _ = run_chain(sv, "encoded", max_steps, eta, seed, stop_below=target, log_jsonl=jl("encoded"))
-    log("encoded: %.3f s per step, %d steps, RMSE %.1f" % (s_enc, len(r_enc), r_enc[-1]))
+    out_forms = {}
+    if "plain" in forms:
+        naive_s = time_naive_plain(sv, v0)
+        log("plain, naive solver: %.1f s per step (one sample's 80 calls timed)" % naive_s)
+        r_plain, s_plain, _ = run_chain(sv, "plain", plain_steps, eta, seed, stop_below=target, log_jsonl=jl("plain"))
+        log("plain: %d steps, %.2f s per step, RMSE %.1f -> %.1f m/s (target %.1f)" % (
+            len(r_plain), s_plain, start_rmse, r_plain[-1], target))
+    if "encoded" in forms:
+        r_enc, s_enc, _ = run_chain(sv, "encoded", max_steps, eta, seed, stop_below=target, log_jsonl=jl("encoded"))
+        log("encoded: %.3f s per step, %d steps, RMSE %.1f" % (s_enc, len(r_enc), r_enc[-1]))
+    runs = []
+    if "preconditioned" not in forms:
+        net_seeds = ()
 
-    t0 = time.perf_counter()
-    pairs = make_pairs(sv, ntruth=ntruth)
-    P = pairs["x16"].shape[0]
-    log("pairs: %d in %.1f s" % (P, time.perf_counter() - t0))
+    pairs = make_pairs(sv, ntruth=ntruth) if net_seeds else None
+    P = pairs["x16"].shape[0] if net_seeds else 0
+    if net_seeds:
+        log("pairs: %d in %.1f s" % (P, time.perf_counter() - t0))
     # pairs come truth by truth (P / ntruth each): the last 4 truths validate (early
     # stopping and the guard's blend weight)
     per_truth = P // ntruth
     val_idx = torch.arange((ntruth - 4) * per_truth, P, device=sv.dev)
     train_idx = np.arange((ntruth - 4) * per_truth)
-    runs = []
     for ns in net_seeds:
         t1 = time.perf_counter()
         net = UNet(chans=(32, 64, 128, 256), seed=ns)
@@ -321,24 +329,27 @@ def equal_error(seed=1000, plain_steps=300, max_steps=400, ntruth=32, train_step
                 "samples_per_hour": None if wall is None else round(nsample / wall * 3600, 1), "timing": label,
                 "rmse": [round(r, 2) for r in rmse]}
 
+    if "plain" in forms:
+        out_forms["plain_naive"] = {**entry(r_plain, naive_s, "one simulation per launch, samples in turn; one "
+                                                              "sample's 80 single-shot gradient calls timed, x 16 "
+                                                              "samples"), "rmse": None}
+        out_forms["plain_batched"] = entry(r_plain, s_plain, "measured: 2 samples x 80 single-shot simulations per "
+                                                             "launch")
+    if "encoded" in forms:
+        out_forms["encoded"] = entry(r_enc, s_enc, "measured: 16 samples x 10 supergathers of 8 in one launch per step")
+    if runs:
+        out_forms["preconditioned"] = [
+            {**entry(r_pre, s_pre, "measured: encoded + U-Net inference + guard"), "network_seed": ns,
+             "network_kept_fraction": round(float(np.mean(kept)) / nsample, 3) if kept else None,
+             "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]],
+             "blend_alpha": round(alpha, 4), "early_stop_step": vbest,
+             "validation_error_by_step": [[s_, round(e_, 4)] for s_, e_ in vhist]}
+            for ns, r_pre, s_pre, kept, t_train, hist, alpha, vbest, vhist in runs]
     return {
         "metric": "posterior samples/hour at equal posterior-mean RMSE", "unit": "samples/hour",
         "workload": "2d-400x150-thrust-80shot: 16 samples from a start smoothed by %g cells, Langevin eta=%.3e "
                     "(largest first update %g m/s), nu=sqrt(2 eta)" % (start_sigma, eta, max_update),
         "target_rmse_mps": round(target, 2), "start_rmse_mps": round(start_rmse, 2), "target_fraction": target_frac,
-        "plain_steps": len(r_plain),
-        "forms": {
-            "plain_naive": {**entry(r_plain, naive_s, "one simulation per launch, samples in turn; one sample's "
-                                                      "80 single-shot gradient calls timed, x 16 samples"),
-                            "rmse": None},
-            "plain_batched": entry(r_plain, s_plain, "measured: 2 samples x 80 single-shot simulations per launch"),
-            "encoded": entry(r_enc, s_enc, "measured: 16 samples x 10 supergathers of 8 in one launch per step"),
-            "preconditioned": [
-                {**entry(r_pre, s_pre, "measured: encoded + U-Net inference + guard"), "network_seed": ns,
-                 "network_kept_fraction": round(float(np.mean(kept)) / nsample, 3) if kept else None,
-                 "training_s": round(t_train, 1), "train_loss_first_last": [hist[0][1], hist[-1][1]],
-                 "blend_alpha": round(alpha, 4), "early_stop_step": vbest,
-                 "validation_error_by_step": [[s_, round(e_, 4)] for s_, e_ in vhist]}
-                for ns, r_pre, s_pre, kept, t_train, hist, alpha, vbest, vhist in runs],
-        },
+        "plain_steps": len(r_plain) if "plain" in forms else None,
+        "forms": out_forms,
     }

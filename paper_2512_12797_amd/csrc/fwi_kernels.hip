@@ -1454,6 +1454,19 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
 
 // ---------------------------------------------------------- misfit/residual
 
+// Sum of one double per thread of a 256-thread block in a fixed order: each wavefront
+// folds its 64 lanes with cross-lane moves (offsets 32, 16, ..., 1), then thread 0 adds
+// the four wavefront sums in wave order.  The result is valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return threadIdx.x == 0 ? ((part[0] + part[1]) + part[2]) + part[3] : 0.0;
+}
+
 // Block (chunk, sim): rho = (d - d_obs) inv_sigma2 and a partial sum of (d - d_obs)^2.
 __global__ __launch_bounds__(256) void k_residual(const SimDesc *__restrict__ sims, int nt_rec,
                                                   const float *d, const float *__restrict__ dobs,
@@ -1474,14 +1487,8 @@ __global__ __launch_bounds__(256) void k_residual(const SimDesc *__restrict__ si
         rho[S.d_off + i] = r * inv_sigma2;
         acc += (double)r * (double)r;
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * nchunk + blockIdx.x] = red[0];
+    const double sum = block_sum256(acc);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * nchunk + blockIdx.x] = sum;
     if (bad) atomicOr(status, 2);
 }
 
@@ -1536,14 +1543,8 @@ __global__ __launch_bounds__(256) void k_finalize(const SampleDesc *__restrict__
         grad[S.m_off + i] = gv;
         acc2 += (double)gv * (double)gv;
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = acc2;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * nchunk + blockIdx.x] = red[0];
+    const double sum = block_sum256(acc2);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * nchunk + blockIdx.x] = sum;
     if (bad) atomicOr(status, 4);
 }
 

@@ -775,29 +775,33 @@ __global__ __launch_bounds__(256) void k_guard_stats(const float *__restrict__ p
         spp += p * p;
         sgg += q * q;
     }
-    __shared__ double r0[256], r1[256], r2[256];
-    r0[threadIdx.x] = spg;
-    r1[threadIdx.x] = spp;
-    r2[threadIdx.x] = sgg;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            r0[threadIdx.x] += r0[threadIdx.x + o];
-            r1[threadIdx.x] += r1[threadIdx.x + o];
-            r2[threadIdx.x] += r2[threadIdx.x + o];
-        }
-        __syncthreads();
+    // fixed-order sums: cross-lane folds within each wavefront, then the four wavefront
+    // sums in wave order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        spg += __shfl_down(spg, o, 64);
+        spp += __shfl_down(spp, o, 64);
+        sgg += __shfl_down(sgg, o, 64);
     }
+    __shared__ double part[3][4];
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = spg;
+        part[1][threadIdx.x >> 6] = spp;
+        part[2][threadIdx.x >> 6] = sgg;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const double pn = sqrt(r1[0]), gn = sqrt(r2[0]);
-        const bool ok = pn > 0.0 && gn > 0.0 && r0[0] / (pn * gn) >= (double)cos_min && pn / gn >= (double)ratio_lo &&
+        double r[3];
+        for (int k = 0; k < 3; ++k) r[k] = ((part[k][0] + part[k][1]) + part[k][2]) + part[k][3];
+        const double pn = sqrt(r[1]), gn = sqrt(r[2]);
+        const bool ok = pn > 0.0 && gn > 0.0 && r[0] / (pn * gn) >= (double)cos_min && pn / gn >= (double)ratio_lo &&
                         pn / gn <= (double)ratio_hi;
         keep[img] = ok ? 1 : 0;
     }
 }
 
-// out[i][y][x] = keep_i ? pred[i][y][x][0] * scale_i : g[i][y][x]  (physical rows only).
-// kept images: g + alpha (p - g), with alpha = 1 giving p exactly
+// out[i][y][x] = keep_i ? g + alpha (p - g) : g, p = pred[i][y][x][0] * scale_i (physical
+// rows only); alpha = 1 gives p exactly
 __global__ void k_guard_write(const float *__restrict__ pred, int C, const float *__restrict__ scale,
                               const float *__restrict__ g, int nimg, int h, int w, int hp, float alpha,
                               const int32_t *__restrict__ keep, float *__restrict__ out)

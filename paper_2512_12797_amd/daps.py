@@ -119,7 +119,7 @@ class Denoiser:
         self.h, self.w, self.hp = h, w, hp
         self.v_lo, self.v_hi = v_lo, v_hi
         self.dev = device
-        self.net = UNet(chans=(32, 64, 128, 256), seed=seed, device=device)
+        self.net = UNet(chans=(32, 64, 128, 256), seed=seed, device=device, in_used=2)  # model, noise level
 
     def inputs(self, x, level):
         """x: normalised models (device f32 [S, h, w]); level: device f32 [S]."""

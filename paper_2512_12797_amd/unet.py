@@ -51,16 +51,19 @@ class Conv:
 
 
 class UNet:
-    def __init__(self, chans=(32, 64, 128, 256), seed=0, device="cuda"):
-        assert all(c % 32 == 0 for c in chans)
+    def __init__(self, chans=(32, 64, 128, 256), seed=0, device="cuda", in_used=IN_USED):
+        """in_used: input channels that carry data (the first layer's initial weights on
+        the others are zero)."""
+        assert all(c % 32 == 0 for c in chans) and 1 <= in_used <= IN_CH
         self.chans = tuple(chans)
+        self.in_used = in_used
         self.L = len(chans)
         self.device = device
         rng = np.random.default_rng(seed)
         self.enc = []
         for i, c in enumerate(chans):
             cin = IN_CH if i == 0 else chans[i - 1]
-            cin_real = IN_USED if i == 0 else chans[i - 1]
+            cin_real = in_used if i == 0 else chans[i - 1]
             self.enc.append((Conv(cin, c, cin_real, c, rng, device), Conv(c, c, c, c, rng, device)))
         self.dec = [None] * (self.L - 1)
         for i in range(self.L - 2, -1, -1):
@@ -81,7 +84,8 @@ class UNet:
         return ls
 
     def nparams(self):
-        return sum(l.cout_real * 9 * (l.cin if l is not self.enc[0][0] else IN_USED) + l.cout_real for l in self.layers())
+        return sum(l.cout_real * 9 * (l.cin if l is not self.enc[0][0] else self.in_used) + l.cout_real
+                   for l in self.layers())
 
     # ------------------------------------------------------------ forward
     def forward(self, x16, res, n, h, w, keep=False):

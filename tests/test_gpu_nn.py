@@ -232,7 +232,7 @@ def _oracle_weights(net):
     out = []
     order = [l for pair in net.enc for l in pair] + [l for i in range(L - 2, -1, -1) for l in net.dec[i]] + [net.out]
     for k, l in enumerate(order):
-        cin_real = 2 if l is net.enc[0][0] else l.cin
+        cin_real = net.in_used if l is net.enc[0][0] else l.cin
         w = l.wf.double().cpu().numpy()[:l.cout_real, :, :cin_real]
         b = l.b.double().cpu().numpy()[:l.cout_real]
         out.append((w, b))
@@ -243,7 +243,7 @@ def _oracle_weights(net):
 def test_network_forward_backward_vs_oracle(N, chans, hw):
     from paper_2512_12797_amd.unet import UNet
     say("case network %s %dx%d" % (chans, hw, hw))
-    net = UNet(chans=chans, seed=1)
+    net = UNet(chans=chans, seed=1, in_used=2)  # two input channels carry data here
     # give the zero-initialised output layer weights so that every gradient is non-trivial
     r = np.random.default_rng(7)
     o = net.out
@@ -276,7 +276,7 @@ def test_network_forward_backward_vs_oracle(N, chans, hw):
     assert e_out < 2e-3 and abs(loss.item() / Lr - 1) < 2e-3
     errs = []
     for k, (l, (gw, gb)) in enumerate(zip(order, grads)):
-        cin_real = 2 if l is net.enc[0][0] else l.cin
+        cin_real = net.in_used if l is net.enc[0][0] else l.cin
         ew = rel(f64(l.dw)[:l.cout_real, :, :cin_real], gw)
         eb = rel(f64(l.db)[:l.cout_real], gb)
         errs += [ew, eb]
