@@ -394,6 +394,11 @@ def uneven_bench(torch, fwi, problems, args):
     mis = torch.empty(batch.nsim, dtype=torch.float64, device=dev)
     kappa = [g[2] for g in groups]
     fwi.fwi_set_time_blocking(args.fwd_steps, args.adj_steps)
+    # the library's default tile height unless --tile forces one (the tuner's timing of a
+    # lone adjoint step mispredicts this checkpointed batch: it picks one step per adjoint
+    # launch, 125 ms per gradient against 118 ms with two)
+    if args.tile:
+        fwi.fwi_set_tile(2, args.tile)
     bz, wx = fwi.fwi_tile_shape(batch, time_ax)
     stream = torch.cuda.Stream()
     prev_stream = torch.cuda.current_stream()

@@ -326,7 +326,7 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override, int wx_override)
                 return;
             }
     }
-    // default: the tallest tile that still gives >= 4 tiles per CU (256 CUs)
+    // default (3D): the tallest tile that still gives >= 4 tiles per CU (256 CUs)
     auto count = [&](int bz) {
         int64_t n = 0;
         for (int s = 0; s < b->nsim; ++s) {
@@ -337,12 +337,10 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override, int wx_override)
         return n;
     };
     if (p.ndim == 2) {
+        // 8 rows: the fastest forward on the 400x150 workload (the tuner's choice) and on
+        // the uneven 32-sample batch (16.1 us per launch against 16.8 and 19.8 us for 16
+        // and 32 rows); taller strips leave fewer wavefronts per compute unit
         p.bz = 8;
-        for (int c : {32, 16, 8})
-            if (count(c) >= 1024) {
-                p.bz = c;
-                break;
-            }
     } else {
         p.bz = 16;
         for (int c : {32, 16})
