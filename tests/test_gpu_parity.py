@@ -305,6 +305,41 @@ def test_3d_uneven_batch_per_sample_imaging(F):
         assert e < TOL
 
 
+@pytest.mark.parametrize("nx", [56, 57])
+def test_3d_row_pitch(F, nx):
+    """Rows of the padded 3D grid are stored 32 cells apart: nx = 56 with a 4-cell sponge
+    pads to exactly 64 cells (no pitch columns), nx = 57 to 65 (31 pitch columns, a second
+    row of 64-wide tiles that holds one grid column).  Sources and receivers sit on the
+    last grid column; data, misfits and the gradient against the oracle."""
+    say("case 3d row pitch, nx %d" % nx)
+    ny, nz = 10, 12
+    g = F.Grid(nz=nz, ny=ny, nx=nx, dz=20.0, dy=20.0, dx=20.0, nb=4, v_ref=3500.0, v_max=3600.0, ndim=3)
+    r = np.random.default_rng(nx)
+    m = f32(r.uniform(1800, 3400, g.nphys))
+    truth = f32(m * 0.9)
+
+    def cell(z, y, x):
+        return (z * ny + y) * nx + x
+
+    srcs = [([cell(1, 5, nx - 1), cell(6, 0, 0)], [1.0, -1.0]), ([cell(1, 9, nx // 2)], [1.0])]
+    rec = np.array([cell(1, y, x) for y in range(0, ny, 3) for x in sorted(set(range(0, nx, 5)) | {nx - 1})],
+                   dtype=np.int32)
+    nt, R = 80, 1
+    batch = F.Batch([g], [0, 0], srcs, [rec, rec], W.ricker(8.0, 2e-3, nt))
+    time = F.time_axis(2e-3, nt, R, 7)
+    dobs = [f32(0.5 * d) for d in oracle_forward_sims(batch, 2e-3, nt, R, [truth], coef_fp32=False)]
+    dp, mis, gr, _ = run_gradient(F, batch, time, [m], np.concatenate([d.ravel() for d in dobs]), 1.0, [1.0])
+    odp, omis, ogr = oracle_batch_gradient(batch, 2e-3, nt, R, [m], dobs, 1.0, [1.0])
+    gdp = split_data(dp, batch, nt // R)
+    for s in range(batch.nsim):
+        e = rel(gdp[s], odp[s])
+        say("  sim %d data rel %.2e misfit rel %.2e" % (s, e, abs(mis[s] / omis[s] - 1)))
+        assert e < TOL and abs(mis[s] / omis[s] - 1) < TOL
+    e = rel(gr, ogr[0])
+    say("  gradient rel %.2e" % e)
+    assert e < TOL
+
+
 @pytest.mark.parametrize("wx", [32, 64])
 def test_3d_launch_order_groups(F, wx):
     """3D batch of two samples with 5 and 2 supergathers on different grids: the forward's
