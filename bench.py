@@ -165,18 +165,15 @@ def gradient_bench(torch, fwi, problems, args, cfg, steps, warmup, with_cpu):
     torch.cuda.empty_cache()
     free, total = torch.cuda.mem_get_info()
     if args.ckpt == "auto":
-        ckpt = 0
-        for k in (0, 10, 15, 20, 30, 50, 100):
-            need = fwi.fwi_workspace_size(batch0, fwi.time_axis(cfg.dt, nt, R, k))
-            if need < free - (8 << 30):
-                ckpt = k
-                break
+        # the schedule with the fewest forward steps whose workspace fits: every imaging
+        # operand kept, else checkpoints plus as long a kept tail as the memory holds
+        time_ax = fwi.fwi_schedule(batch0, fwi.time_axis(cfg.dt, nt, R), free - (8 << 30))
     else:
-        ckpt = int(args.ckpt)
-    time_ax = fwi.time_axis(cfg.dt, nt, R, ckpt)
+        time_ax = fwi.time_axis(cfg.dt, nt, R, int(args.ckpt), int(args.keep_tail))
+    ckpt, tail = time_ax.ckpt_every, time_ax.keep_tail
     ws = fwi.alloc_workspace(batch0, time_ax)
-    log("[%s] setup %.1f s; workspace %.1f GB (ckpt_every=%d); free %.1f of %.1f GB" % (
-        cfg.name, time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, free / 1e9, total / 1e9))
+    log("[%s] setup %.1f s; workspace %.1f GB (ckpt_every=%d, keep_tail=%d); free %.1f of %.1f GB" % (
+        cfg.name, time.perf_counter() - t_setup, ws.numel() / 1e9, ckpt, tail, free / 1e9, total / 1e9))
 
     fwi.fwi_set_tile_width(args.tile_width)
     tuned = None
@@ -259,11 +256,23 @@ def gradient_bench(torch, fwi, problems, args, cfg, steps, warmup, with_cpu):
     width = fwi.fwi_tile_shape(batch0, time_ax)[1] if cfg.ndim == 3 else None
 
     # ---- roofline of the dominant kernel (algorithmic bytes per launch / live duration)
-    # forward step (all imaging operands kept): u^n, u^{n-1} read, u^{n+1}, W^n write =
-    # 16 B per simulation cell, plus c once per sample cell; with checkpoints the forward
-    # sweeps (first pass: 12 B plus a checkpoint pair every K steps, 8/K B; recomputation:
-    # 16 B) average to 14 + 4/K B per simulation cell
-    fwd_bytes = pad_cells * (16 if ckpt == 0 else 14 + 4.0 / ckpt) + samp_cells * 4
+    # forward step: u^n, u^{n-1} read and u^{n+1} written = 12 B per simulation cell, plus
+    # c once per sample cell; W^n written where the imaging operand is kept or recomputed
+    # (+4 B), the pair u^{n+1}, u^n where a checkpoint is taken (+8 B).  Launch counts per
+    # gradient: keep-all: nt imaging launches; checkpoints every K over the first head =
+    # nt - T steps with the last T kept: first pass head - (nseg - 1) plain, nseg - 1
+    # checkpoint and T imaging launches, then head imaging launches (recomputation)
+    if ckpt == 0:
+        modes = {"plain": 0, "checkpoint": 0, "imaging": nt}
+    else:
+        head = nt - tail
+        kk = min(ckpt, max(head, 1))
+        nseg = (head + kk - 1) // kk
+        nck = max(nseg - 1, 0)
+        modes = {"plain": head - nck, "checkpoint": nck, "imaging": tail + head}
+    n_fwd_launch = sum(modes.values())
+    fwd_bytes = (pad_cells * (12 * n_fwd_launch + 8 * modes["checkpoint"] + 4 * modes["imaging"]) / n_fwd_launch
+                 + samp_cells * 4)
     # adjoint + imaging: lt^{k+1}, lt^{k+2}, W^{k-1} read and lt^k written per simulation
     # cell; c read and the FP64 per-sample accumulator read + written per sample cell
     adj_bytes = pad_cells * 16 + samp_cells * 20
@@ -299,6 +308,10 @@ def gradient_bench(torch, fwi, problems, args, cfg, steps, warmup, with_cpu):
             if (tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name
                     and rows is not None and tj.get("tile_rows") == rows):
                 traffic = tj.get("bytes_per_launch")
+                pm = tj.get("per_mode")
+                if pm and name == fwd_name:  # forward: weighted by this schedule's launches
+                    traffic = int(round(1e6 * sum(modes[m] * (pm[m]["fetch_mb"] + pm[m]["write_mb"])
+                                                  for m in modes) / n_fwd_launch))
         except (ValueError, OSError):
             traffic = None
     copy_gbs = copy_probe(torch, fwi, dev)
@@ -327,7 +340,9 @@ def gradient_bench(torch, fwi, problems, args, cfg, steps, warmup, with_cpu):
                    "padded": [cfg.nz + 2 * cfg.nb, ny_pad, cfg.nx + 2 * cfg.nb] if cfg.ndim == 3 else
                              [cfg.nz + 2 * cfg.nb, cfg.nx + 2 * cfg.nb],
                    "nsim": nsim, "nsample": cfg.nsample, "internal_steps": nt, "recorded": nt_rec,
-                   "schedule": "all imaging operands kept" if ckpt == 0 else "checkpoint every %d" % ckpt,
+                   "schedule": "all imaging operands kept" if ckpt == 0 else
+                               "checkpoint every %d, last %d steps kept" % (ckpt, tail),
+                   "forward_launches": modes,
                    "tile_rows": tuned[0] if tuned else None, "tile_width": width, "graphs": bool(args.graphs),
                    "time_steps_per_launch": {"forward": 2 if two_fwd else 1, "adjoint": 2 if two_adj else 1},
                    "graph_captures_replays": list(gstats),
@@ -833,6 +848,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nt", type=int, default=0, help="override internal steps (profiling runs only)")
     ap.add_argument("--ckpt", default="auto", help="auto | 0 (keep all imaging operands) | K (checkpoint)")
+    ap.add_argument("--keep-tail", type=int, default=0, help="with --ckpt K: imaging operands of the last steps kept")
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graphs", type=int, default=1, help="replay each gradient as a captured HIP graph")

@@ -87,6 +87,11 @@ typedef struct {
     int32_t ckpt_every;    /* 0: keep every step's imaging operand (no recomputation);
                               K >= 1: checkpoint every K steps and recompute per segment;
                               -1: forward only (no adjoint state; smallest workspace) */
+    int32_t keep_tail;     /* with K >= 1: the forward also keeps the imaging operands of
+                              the last keep_tail steps (0 <= keep_tail <= nt), which the
+                              adjoint then reads without recomputing them; checkpoints
+                              cover the first nt - keep_tail steps.  Must be 0 when
+                              ckpt_every <= 0.  Results are identical for every value. */
 } fwi_time;
 
 /* A batch of simulations.  Every array here is HOST memory. */
@@ -122,6 +127,20 @@ fwi_status fwi_check(const fwi_batch *b, const fwi_time *t, double *worst_couran
 
 /* Workspace bytes needed by fwi_forward / fwi_adjoint / fwi_gradient for (b, t). */
 fwi_status fwi_workspace_size(const fwi_batch *b, const fwi_time *t, size_t *bytes);
+
+/*
+ * Schedule of the adjoint state for a workspace budget (host-only).  Reads t->dt, nt and
+ * rec_every and sets t->ckpt_every and t->keep_tail to the schedule whose workspace fits
+ * in budget_bytes with the fewest forward time steps per gradient (nt plus the
+ * recomputed ones): every imaging operand kept (ckpt_every 0) if that fits, else the
+ * checkpoint interval K and kept tail T with the largest T, then the smallest workspace.
+ * The checkpoint/recompute schedule is the adjoint-state method's memory/compute trade
+ * (the gradient stated after Eq. 5 needs every forward state in reverse order).  Follows
+ * the process-wide settings that change workspace sizes (fwi_set_overlap).
+ * FWI_E_WORKSPACE if not even the smallest checkpointed schedule fits; *t is then
+ * unchanged.
+ */
+fwi_status fwi_schedule(const fwi_batch *b, fwi_time *t, size_t budget_bytes);
 
 /*
  * Forward solve of every sim (F~(x) of Eq. 4 for each supergather).

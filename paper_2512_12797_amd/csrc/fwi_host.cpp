@@ -102,6 +102,8 @@ fwi_status check_all(const fwi_batch *b, const fwi_time *t, double *worst)
     if (t->nt < 1) return fail(FWI_E_ARG, "nt must be >= 1");
     if (t->rec_every < 1 || t->nt % t->rec_every != 0) return fail(FWI_E_ARG, "nt must be a multiple of rec_every >= 1");
     if (t->ckpt_every < -1) return fail(FWI_E_ARG, "ckpt_every must be >= -1");
+    if (t->keep_tail < 0 || t->keep_tail > t->nt) return fail(FWI_E_ARG, "keep_tail must be in [0, nt]");
+    if (t->keep_tail > 0 && t->ckpt_every < 1) return fail(FWI_E_ARG, "keep_tail needs ckpt_every >= 1");
     if (b->nsim < 1 || b->nsample < 1) return fail(FWI_E_ARG, "nsim and nsample must be >= 1");
     if (b->nsim > 65535 || b->nsample > 65535) return fail(FWI_E_UNSUPPORTED, "more than 65535 sims or samples");
     if (!b->grid || !b->model_off || !b->sample_of || !b->src_ptr || !b->rec_ptr || !b->wavelet)
@@ -193,6 +195,8 @@ struct Plan {
     int64_t gcells = 0;      // imaging accumulator cells
     // layout
     int nlev = 2, K = 0, nseg = 1;
+    int head = 0, tail = 0;  // checkpoints: steps [0, head) recomputed per segment, [head, nt) kept
+    int64_t ring = 0;        // imaging levels of the recomputation ring (two rings with overlap)
     bool fwd_only = false;  // ckpt_every == -1: no adjoint state is kept
     bool overlap = false;   // checkpoints: recompute the next segment beside the current adjoint
     int64_t wst_levels = 0, ck_slots = 0;
@@ -686,8 +690,14 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     // workspace layout
     p.fwd_only = t->ckpt_every < 0;
     p.K = p.fwd_only ? 0 : t->ckpt_every;
-    if (p.K > t->nt) p.K = t->nt;
-    p.nseg = p.K > 0 ? (t->nt + p.K - 1) / p.K : 1;
+    p.tail = p.K > 0 ? t->keep_tail : 0;
+    p.head = t->nt - p.tail;
+    if (p.K > 0) {
+        p.K = std::min(p.K, std::max(p.head, 1));
+        p.nseg = (p.head + p.K - 1) / p.K;  // 0 when every step is kept
+    } else {
+        p.nseg = 1;
+    }
     // levels: 2 (u^n, u^{n-1} updated in place), 4 with checkpoints (recomputation and
     // adjoint), and in 2D two more for the output levels of two-step launches
     p.nlev = (p.K > 0 ? 4 : 2) + (p.ndim == 2 ? 2 : 0);
@@ -704,9 +714,10 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     }
     // with overlap the recomputation writes one of two rings of K imaging levels while the
     // adjoint reads the other
-    p.overlap = !p.fwd_only && p.K > 0 && p.K < t->nt && !no_overlap && g_overlap.load();
-    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? (p.overlap ? 2 * p.K : p.K) : t->nt);
-    p.ck_slots = p.K > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
+    p.overlap = !p.fwd_only && p.K > 0 && p.nseg >= 2 && !no_overlap && g_overlap.load();
+    p.ring = p.K > 0 && p.nseg > 0 ? (p.overlap ? 2 * p.K : p.K) : 0;
+    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.ring + p.tail : t->nt);
+    p.ck_slots = p.K > 0 && p.nseg > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
     int64_t maxdata = 0;
     for (auto &S : p.sims) maxdata = std::max(maxdata, (int64_t)p.nt_rec * S.nrec);
     p.nchunk_res = (int)std::min<int64_t>(64, std::max<int64_t>(1, maxdata / 4096));
@@ -942,6 +953,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
 {
     k.add(p.ndim); k.add(p.bz); k.add(p.ty); k.add(p.wx); k.add(p.per_xcd); k.add(p.cells); k.add(p.coefs); k.add(p.data);
     k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
+    k.add(p.head); k.add(p.tail); k.add(p.ring); k.add(p.overlap);
     k.add(p.nchunk_res); k.add(p.nchunk_fin);
     k.add(p.grouped); k.add(p.bzg); k.add(p.nw); k.add(p.per_xcd_g); k.add(p.gcells);
     k.add(p.two); k.add(p.two_adj); k.add(p.nw2); k.add(p.sg2); k.add(p.per_xcd2); k.add(p.per_xcd_g2);
@@ -956,7 +968,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
                            p.o_part, p.o_npart, p.o_mis, p.total};
     k.bytes(offs, sizeof offs);
     k.add(b->nsim); k.add(b->nsample);
-    k.add(t->dt); k.add(t->nt); k.add(t->rec_every); k.add(t->ckpt_every);
+    k.add(t->dt); k.add(t->nt); k.add(t->rec_every); k.add(t->ckpt_every); k.add(t->keep_tail);
     k.bytes(b->wavelet, sizeof(float) * t->nt);
 }
 
@@ -1151,7 +1163,8 @@ fwi_status prologue(const fwi_batch *b, const fwi_time *t, const double *kappa, 
 }
 
 // forward sweep n = 0..nt-1; records data into `dat`; stores imaging operands (store-all)
-// or checkpoints (K >= 1)
+// or checkpoints every K steps over steps [0, head) and the imaging operands of the kept
+// tail [head, nt) (K >= 1)
 fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fwi_time *t, const float *v,
                        float *dat, hipStream_t st)
 {
@@ -1207,7 +1220,11 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         a.next = prev;  // in place over u^{n-1}
         a.fn = b->wavelet[n];
         a.rec_j = slot(n);
-        a.wst = (p.K == 0 && !p.fwd_only) ? d.wst + (size_t)n * p.cells : nullptr;
+        a.wst = nullptr;
+        if (!p.fwd_only && p.K == 0)
+            a.wst = d.wst + (size_t)n * p.cells;
+        else if (p.K > 0 && n >= p.head)  // the kept tail, after the recomputation ring(s)
+            a.wst = d.wst + (size_t)(p.ring + n - p.head) * p.cells;
         a.cka = a.ckb = nullptr;
         if (p.K > 0 && (n + 1) % p.K == 0 && (n + 1) / p.K < p.nseg) {
             const int slot = (n + 1) / p.K;
@@ -1292,7 +1309,8 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         fwi_status s = sweep(t->nt, 0, [&](int k) { return (const float *)(d.wst + (size_t)(k - 1) * p.cells); });
         if (s) return s;
     } else {
-        // checkpoint segments, last to first: recompute the segment from its checkpoint (its
+        // the kept tail first (its imaging operands are stored), then the checkpoint segments
+        // of steps [0, head), last to first: recompute the segment from its checkpoint (its
         // imaging operands into a ring of K levels), then sweep the adjoint over it.  With
         // overlap, segment sg - 1 is recomputed on the side stream into the other ring while
         // the adjoint of segment sg runs on `st`; events order each ring's writes after the
@@ -1309,7 +1327,7 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         }
         auto ring = [&](int sg) { return d.wst + (size_t)(p.overlap ? (sg & 1) * p.K : 0) * p.cells; };
         auto recompute = [&](int sg) -> fwi_status {
-            const int ns = sg * p.K, ne = std::min(ns + p.K, t->nt);
+            const int ns = sg * p.K, ne = std::min(ns + p.K, p.head);
             float *W = ring(sg);
             const float *cur, *prev;
             if (sg == 0) {
@@ -1341,10 +1359,18 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
             if (p.overlap) HIP_TRY(hipEventRecord(ev[1 + (sg & 1)], rs));
             return FWI_OK;
         };
-        fwi_status s = recompute(p.nseg - 1);
-        if (s) return s;
+        fwi_status s = FWI_OK;
+        if (p.nseg > 0) {
+            s = recompute(p.nseg - 1);
+            if (s) return s;
+        }
+        if (p.tail > 0) {
+            const float *Wt = d.wst + (size_t)p.ring * p.cells;
+            s = sweep(t->nt, p.head, [&](int k) { return Wt + (size_t)(k - 1 - p.head) * p.cells; });
+            if (s) return s;
+        }
         for (int sg = p.nseg - 1; sg >= 0; --sg) {
-            const int ns = sg * p.K, ne = std::min(ns + p.K, t->nt);
+            const int ns = sg * p.K, ne = std::min(ns + p.K, p.head);
             if (p.overlap) {
                 if (sg >= 1) {
                     // ring (sg - 1) & 1 was last read by the adjoint of segment sg + 1
@@ -1446,6 +1472,66 @@ fwi_status fwi_workspace_size(const fwi_batch *b, const fwi_time *t, size_t *byt
     if (s) return s;
     *bytes = p.total;
     return FWI_OK;
+}
+
+fwi_status fwi_schedule(const fwi_batch *b, fwi_time *t, size_t budget_bytes)
+{
+    if (!t) return fail(FWI_E_ARG, "null time");
+    fwi_time q = *t;
+    q.ckpt_every = 0;
+    q.keep_tail = 0;
+    fwi_status s = check_all(b, &q, nullptr);
+    if (s) return s;
+    Plan p;
+    s = build_plan(b, &q, nullptr, p);
+    if (s) return s;
+    if (p.total <= budget_bytes) {  // every imaging operand kept: one forward pass
+        *t = q;
+        return FWI_OK;
+    }
+    // checkpointed layouts differ only in the imaging levels (ring + kept tail) and the
+    // checkpoint slots; everything else is the same for every K and T
+    const int nt = q.nt;
+    q.ckpt_every = 1;
+    q.keep_tail = nt;
+    p = Plan();  // build_plan appends to the plan's tables
+    s = build_plan(b, &q, nullptr, p);
+    if (s) return s;
+    const size_t lev = (size_t)p.cells * 4;
+    const size_t fixed = p.total - align_up((size_t)p.wst_levels * lev) - align_up((size_t)p.ck_slots * lev);
+    const bool ovl = g_overlap.load() != 0;
+    auto bytes_of = [&](int K, int T) {
+        const int head = nt - T;
+        const int k = std::min(K, std::max(head, 1));
+        const int nseg = (head + k - 1) / k;
+        const int64_t ring = nseg > 0 ? ((ovl && nseg >= 2) ? 2 * k : k) : 0;
+        const int64_t ck = nseg > 0 ? 2 * (int64_t)(nseg - 1) : 0;
+        return fixed + align_up((size_t)(ring + T) * lev) + align_up((size_t)ck * lev);
+    };
+    // fewest forward steps = longest kept tail; then the smallest workspace
+    for (int T = nt; T >= 0; --T) {
+        const int head = nt - T;
+        int best = 0;
+        size_t best_bytes = 0;
+        for (int K = 1; K <= std::max(head, 1); ++K) {
+            const size_t by = bytes_of(K, T);
+            if (by <= budget_bytes && (best == 0 || by < best_bytes)) {
+                best = K;
+                best_bytes = by;
+            }
+        }
+        if (best) {
+            q.ckpt_every = best;
+            q.keep_tail = T;
+            p = Plan();
+            s = build_plan(b, &q, nullptr, p);
+            if (s) return s;
+            if (p.total != best_bytes) return fail(FWI_E_UNSUPPORTED, "schedule size model disagrees with the plan");
+            *t = q;
+            return FWI_OK;
+        }
+    }
+    return fail(FWI_E_WORKSPACE, "no checkpointed schedule fits in %zu bytes", budget_bytes);
 }
 
 fwi_status fwi_forward(const fwi_batch *b, const fwi_time *t, const float *v, float *d_pred, void *ws,

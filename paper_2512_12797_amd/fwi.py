@@ -31,7 +31,8 @@ class FwiGrid(C.Structure):
 
 
 class FwiTime(C.Structure):
-    _fields_ = [("dt", C.c_double), ("nt", C.c_int32), ("rec_every", C.c_int32), ("ckpt_every", C.c_int32)]
+    _fields_ = [("dt", C.c_double), ("nt", C.c_int32), ("rec_every", C.c_int32), ("ckpt_every", C.c_int32),
+                ("keep_tail", C.c_int32)]
 
 
 class FwiBatch(C.Structure):
@@ -60,6 +61,8 @@ def lib():
             getattr(L, name).restype = C.c_int32
         L.fwi_check.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.POINTER(C.c_double)]
         L.fwi_workspace_size.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.POINTER(C.c_size_t)]
+        L.fwi_schedule.restype = C.c_int32
+        L.fwi_schedule.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_size_t]
         L.fwi_forward.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_size_t, C.c_void_p]
         L.fwi_adjoint.argtypes = [C.POINTER(FwiBatch), C.POINTER(FwiTime), C.c_void_p, C.c_void_p,
@@ -188,8 +191,8 @@ class Batch:
         return int(self.model_off[-1])
 
 
-def time_axis(dt, nt, rec_every=1, ckpt_every=0):
-    return FwiTime(float(dt), int(nt), int(rec_every), int(ckpt_every))
+def time_axis(dt, nt, rec_every=1, ckpt_every=0, keep_tail=0):
+    return FwiTime(float(dt), int(nt), int(rec_every), int(ckpt_every), int(keep_tail))
 
 
 # ----------------------------------------------------------- device helpers
@@ -234,6 +237,13 @@ def fwi_workspace_size(batch: Batch, time: FwiTime) -> int:
     n = C.c_size_t(0)
     _ok(lib().fwi_workspace_size(batch.c, C.byref(time), C.byref(n)))
     return n.value
+
+
+def fwi_schedule(batch: Batch, time: FwiTime, budget_bytes: int) -> FwiTime:
+    """A copy of ``time`` with ckpt_every and keep_tail chosen for the budget."""
+    t = FwiTime(time.dt, time.nt, time.rec_every, time.ckpt_every, time.keep_tail)
+    _ok(lib().fwi_schedule(batch.c, C.byref(t), C.c_size_t(int(budget_bytes))))
+    return t
 
 
 def alloc_workspace(batch: Batch, time: FwiTime, device="cuda"):

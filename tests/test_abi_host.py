@@ -97,6 +97,45 @@ def test_workspace_sizes(F):
     assert ck >= (10 + 2 * 9) * cells * 4
 
 
+def test_kept_tail_validation_and_sizes(F):
+    """keep_tail: range and schedule checks; the workspace holds the recomputation ring,
+    the kept tail and the checkpoints of the first nt - keep_tail steps."""
+    g, rec, wav = small(F)
+    b = F.Batch([g], [0, 0], [([31], [1.0]), ([40], [-1.0])], [rec, rec], wav)
+    for K, T in ((10, -1), (10, 101), (0, 5), (-1, 5)):
+        expect(F, F.FWI_E_ARG, F.fwi_check, b, F.time_axis(1e-3, 100, 2, K, T))
+    lev = 2 * (28 * 38) * 4  # one level of both sims (bytes)
+    size = lambda K, T: F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, K, T))
+    base = size(10, 0)  # ring 10 + 2 x 9 checkpoint levels = 28
+    # tail 30: head 70 -> 7 segments: ring 10 + tail 30 + 2 x 6 checkpoint levels = 52
+    assert abs(size(10, 30) - base - 24 * lev) <= 512
+    # tail 95: head 5 -> a ring of 5 levels, one segment, no checkpoint: 100
+    assert abs(size(10, 95) - base - 72 * lev) <= 512
+    # every step kept through the tail: no ring, no checkpoint: 100
+    assert abs(size(10, 100) - base - 72 * lev) <= 512
+    assert size(10, 100) > F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, 0))  # two more field levels
+
+
+def test_schedule_for_a_budget(F):
+    g, rec, wav = small(F)
+    b = F.Batch([g], [0, 0], [([31], [1.0]), ([40], [-1.0])], [rec, rec], wav)
+    t = F.time_axis(1e-3, 100, 2)
+    full = F.fwi_workspace_size(b, t)
+    s = F.fwi_schedule(b, t, full)
+    assert (s.ckpt_every, s.keep_tail) == (0, 0) and (s.dt, s.nt, s.rec_every) == (t.dt, 100, 2)
+    lev = 2 * (28 * 38) * 4
+    for budget in (full - 1, full - 30 * lev, full - 60 * lev):
+        s = F.fwi_schedule(b, t, budget)
+        K, T = s.ckpt_every, s.keep_tail
+        assert K >= 1 and 0 <= T < 100
+        assert F.fwi_workspace_size(b, s) <= budget
+        # no schedule keeps a longer tail within the budget (fewer forward steps)
+        for K2 in range(1, 101 - (T + 1)):
+            assert F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, K2, T + 1)) > budget
+    small_budget = F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, 10, 0)) - 30 * lev
+    expect(F, F.FWI_E_WORKSPACE, F.fwi_schedule, b, t, small_budget)
+
+
 def test_null_workspace_rejected_before_any_device_work(F):
     g, rec, wav = small(F)
     b = F.Batch([g], [0], [([31], [1.0])], [rec], wav)

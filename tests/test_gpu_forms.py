@@ -362,16 +362,12 @@ def _run(F, batch, time, v, dobs, kappa, ws, stream=None):
     return dpred.cpu().numpy(), mis.cpu().numpy(), grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("ndim", [2, 3])
-def test_overlapped_recomputation_is_bitwise_sequential(F, ndim):
-    """Checkpointed schedules with the recomputation of segment s - 1 beside the adjoint of
-    segment s (side stream, two imaging rings) give the sequential schedule's results bit
-    for bit, directly and as a replayed graph, and match the oracle.  nt = 97 with
-    checkpoints every 6 steps leaves a short last segment."""
-    say("case overlapped recomputation %dD" % ndim)
+def _overlap_problem(F, ndim):
+    """97-step problems of the checkpoint-schedule tests (2D: uneven two-sample batch; 3D:
+    one sample, three supergathers)."""
     if ndim == 2:
         batch, groups, _, models = _edge_batch(F, 3, 6, nt=97, R=1)
-        time = F.time_axis(1e-3, 97, 1, 6)
+        dt = 1e-3
     else:
         g = F.Grid(nz=14, ny=11, nx=30, dz=20.0, dy=20.0, dx=20.0, nb=3, v_ref=3500.0, v_max=3850.0, ndim=3)
         r0 = np.random.default_rng(5)
@@ -380,7 +376,19 @@ def test_overlapped_recomputation_is_bitwise_sequential(F, ndim):
         batch = F.Batch([g], [0, 0, 0], srcs, [rec] * 3, W.ricker(9.0, 2e-3, 97))
         groups = [(None, None, 1.0)]
         models = [f32(r0.uniform(1800, 3400, g.nphys))]
-        time = F.time_axis(2e-3, 97, 1, 6)
+        dt = 2e-3
+    return batch, groups, models, dt
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_overlapped_recomputation_is_bitwise_sequential(F, ndim):
+    """Checkpointed schedules with the recomputation of segment s - 1 beside the adjoint of
+    segment s (side stream, two imaging rings) give the sequential schedule's results bit
+    for bit, directly and as a replayed graph, and match the oracle.  nt = 97 with
+    checkpoints every 6 steps leaves a short last segment."""
+    say("case overlapped recomputation %dD" % ndim)
+    batch, groups, models, dt = _overlap_problem(F, ndim)
+    time = F.time_axis(dt, 97, 1, 6)
     kappa = [gr[2] for gr in groups]
     r = np.random.default_rng(2)
     dobs_np = [f32(1e-3 * r.standard_normal((97, batch.nrec[s]))) for s in range(batch.nsim)]
@@ -402,13 +410,64 @@ def test_overlapped_recomputation_is_bitwise_sequential(F, ndim):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
-    dt = 1e-3 if ndim == 2 else 2e-3
     _, omis, ogr = oracle_batch_gradient(batch, dt, 97, 1, models, dobs_np, 2.0, kappa)
     gg = split_model(outs[0][2].astype(np.float64), batch)
     for k in range(batch.nsample):
         e = rel(gg[k], ogr[k])
         say("  sample %d gradient rel %.2e" % (k, e))
         assert e < TOL
+
+
+# (ckpt_every, keep_tail, overlap): segments of 6 under a kept tail of 20 (77 = 12 x 6 + 5),
+# a tail that leaves one checkpointed step, every step kept, an interval longer than the
+# checkpointed part, and a kept tail beside the overlapped recomputation
+TAIL_SCHEDULES = [(6, 0, False), (6, 20, False), (6, 96, False), (6, 97, False), (50, 60, False), (4, 31, True)]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_kept_tail_schedules_are_bitwise_checkpointed(F, ndim):
+    """A forward that also keeps the imaging operands of the last steps, so the adjoint
+    recomputes only the checkpointed part, gives the keep-all schedule's results bit for
+    bit (one adjoint step per launch, so every schedule adds the per-sample products in
+    the same order), and the default two-step 2D adjoint matches the oracle."""
+    say("case kept-tail schedules %dD" % ndim)
+    batch, groups, models, dt = _overlap_problem(F, ndim)
+    kappa = [gr[2] for gr in groups]
+    r = np.random.default_rng(2)
+    dobs_np = [f32(1e-3 * r.standard_normal((97, batch.nrec[s]))) for s in range(batch.nsim)]
+    dobs = dev(np.concatenate([d.ravel() for d in dobs_np]))
+    v = dev(np.concatenate(models))
+    ref = None
+    try:
+        F.fwi_set_time_blocking(0, 1)
+        for K, T, ov in [(0, 0, False)] + TAIL_SCHEDULES:
+            F.fwi_set_overlap(ov)
+            time = F.time_axis(dt, 97, 1, K, T)
+            ws = F.alloc_workspace(batch, time)
+            out = _run(F, batch, time, v, dobs, kappa, ws)
+            F.fwi_poll_status(ws)
+            del ws
+            if ref is None:
+                ref = out
+                continue
+            say("  K=%d T=%d overlap=%d: identical" % (K, T, ov))
+            for a, b in zip(ref, out):
+                assert np.array_equal(a, b), (K, T, ov)
+    finally:
+        F.fwi_set_overlap(False)
+        F.fwi_set_time_blocking(0, 0)
+    _, omis, ogr = oracle_batch_gradient(batch, dt, 97, 1, models, dobs_np, 2.0, kappa)
+    for K, T, ov in TAIL_SCHEDULES[1:3]:  # default time blocking: two-step 2D adjoint launches
+        time = F.time_axis(dt, 97, 1, K, T)
+        ws = F.alloc_workspace(batch, time)
+        _, mis, gr = _run(F, batch, time, v, dobs, kappa, ws)
+        del ws
+        gg = split_model(gr.astype(np.float64), batch)
+        for k in range(batch.nsample):
+            e = rel(gg[k], ogr[k])
+            say("  K=%d T=%d sample %d gradient rel %.2e" % (K, T, k, e))
+            assert e < TOL
+        assert np.allclose(mis, omis, rtol=TOL, atol=0)
 
 
 @pytest.mark.parametrize("ckpt", [0, 6])
