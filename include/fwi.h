@@ -284,8 +284,8 @@ fwi_status fwi_graphs_enable(int32_t on);
 fwi_status fwi_graphs_stats(int64_t *captures, int64_t *replays);
 
 /*
- * Tile height of the step kernels: rows per 2D tile (8, 16, 32) or planes per 3D tile
- * (16, 32); the one-step 2D adjoint sweeps strips of 8 rows when the tile height is 8 and
+ * Tile height of the step kernels: rows per 2D tile (8, 16, 32) or planes per 3D forward
+ * tile (16, 24, 32, 40; the 3D adjoint's tiles are 16 planes high); the one-step 2D adjoint sweeps strips of 8 rows when the tile height is 8 and
  * of 16 rows otherwise.  fwi_set_tile forces one for every batch of that dimensionality
  * (0 returns to automatic choice).  fwi_tune times one forward and one adjoint step of
  * every candidate on the caller's batch, model v (device) and workspace (>=

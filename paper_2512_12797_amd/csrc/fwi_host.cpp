@@ -222,7 +222,7 @@ void stencil_weights(const fwi_grid &g, float w[3][5], double gmax[3], float &in
 
 // Tile heights the kernels are instantiated for (rows per 2D tile, planes per 3D tile).
 const int kBz2[] = {8, 16, 32};
-const int kBz3[] = {16, 32};
+const int kBz3[] = {16, 24, 32, 40};
 
 // Process-wide tile choices: forced per dimensionality (fwi_set_tile) or tuned per batch
 // shape (fwi_tune): the tile height and, for 2D keep-all batches, the adjoint's time steps
@@ -286,7 +286,7 @@ std::string shape_signature(const fwi_batch *b)
 bool valid_bz(int ndim, int bz)
 {
     if (ndim == 2) return bz == 8 || bz == 16 || bz == 32;
-    return bz == 16 || bz == 32;
+    return bz == 16 || bz == 24 || bz == 32 || bz == 40;
 }
 
 // 3D tile width: 64 cells (8 rows per tile) unless 32-wide tiles (two rows per wavefront,
@@ -346,11 +346,23 @@ void pick_tiles(Plan &p, const fwi_batch *b, int bz_override, int wx_override)
         // and 32 rows); taller strips leave fewer wavefronts per compute unit
         p.bz = 8;
     } else {
+        // the height with the fewest planes read per tile column (its planes plus the
+        // 8-plane z halo, over the tiles that cover the depth) among those that still give
+        // >= 4 tiles per CU (256 CUs); ties go to the taller tile
+        auto planes = [&](int bz) {
+            int64_t n = 0;
+            for (int s = 0; s < b->nsim; ++s) {
+                const fwi_grid &g = b->grid[b->sample_of[s]];
+                n += (int64_t)((g.nz + 2 * g.nb + bz - 1) / bz) * (bz + 2 * kHalo);
+            }
+            return n;
+        };
         p.bz = 16;
-        for (int c : {32, 16})
-            if (count(c) >= 1024) {
+        int64_t best = planes(16);
+        for (int c : kBz3)
+            if (count(c) >= 1024 && (planes(c) < best || (planes(c) == best && c > p.bz))) {
                 p.bz = c;
-                break;
+                best = planes(c);
             }
     }
 }
@@ -612,6 +624,11 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
                     G.y0 = iy * TYt;
                     G.z0 = z0;
                     G.tix = ((z0 / p.bz) * nty + iy) * ntx + ix;
+                    // a forward tile height that is not a multiple of this tile's (3D: 24, 40)
+                    // splits some of these tiles between two forward tiles
+                    const int iz2 = z0 / p.bz + 1;
+                    G.tix2 = (z0 + p.bzg > iz2 * p.bz && iz2 < (Sm.N[0] + p.bz - 1) / p.bz)
+                                 ? (iz2 * nty + iy) * ntx + ix : -1;
                     p.gtiles.push_back(G);
                 }
     }

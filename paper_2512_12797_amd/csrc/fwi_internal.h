@@ -78,8 +78,9 @@ struct Tile {
 struct GTile {
     int32_t sample;
     int32_t x0, y0, z0;
-    int32_t tix;
-    int32_t pad0, pad1, pad2;
+    int32_t tix;   // the forward tile (of every sim of the sample) that holds plane / row z0
+    int32_t tix2;  // 3D: the next forward tile in z where this tile reaches into it, else -1
+    int32_t pad1, pad2;
 };
 
 // One row (2D: a grid row; 3D: an xy plane) of a tile that holds receivers.  vec_off

@@ -1346,6 +1346,10 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
 
     __shared__ float V[2][G::LY][G::LX];
     __shared__ double red[BZ][G::TY][WX];
+    // c of the tile's planes, read once for all of the sample's supergathers
+    float cr[BZ];
+#pragma unroll
+    for (int r = 0; r < BZ; ++r) cr[r] = bload(rC, poff(z0 + r) + g.cb);
 
     for (int j = 0; j < sim_cnt; ++j) {
         const int sim = sim_beg + j;
@@ -1366,25 +1370,32 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
         const int d_hi = __builtin_amdgcn_readfirstlane((int)(d_off >> 32));
         const int64_t d_off_u = (int64_t)(((uint64_t)(uint32_t)d_hi << 32) | (uint32_t)d_lo);
         const float *Rho = rec_j >= 0 ? A.rho + d_off_u + (int64_t)rec_j * nrec : nullptr;
-        // receiver event planes of the sim tile that holds this tile, from plane z0 on (a
-        // sim tile may be taller than BZ)
-        int ev = 0, ev_end = 0, ev_z = -1, ev_off = 0;
+        // receiver event planes of the sim tile that holds plane z0, from plane z0 on (a
+        // sim tile may be taller than BZ), then those of the next sim tile in z where this
+        // tile reaches into it (event planes are in increasing z within a sim tile)
+        int ev = 0, ev_end = 0, ev_z = -1, ev_off = 0, ev2 = 0, ev2_end = 0;
         if (rec_j >= 0) {
             const Tile &T = A.tiles[tile0 + GT.tix];
             ev = __builtin_amdgcn_readfirstlane(T.ev_beg);
             ev_end = ev + __builtin_amdgcn_readfirstlane(T.ev_cnt);
-            while (ev < ev_end) {
-                ev_z = __builtin_amdgcn_readfirstlane(evrows[ev].z);
-                if (ev_z >= z0) break;
-                ++ev;
+            if (GT.tix2 >= 0) {
+                const Tile &T2 = A.tiles[tile0 + GT.tix2];
+                ev2 = __builtin_amdgcn_readfirstlane(T2.ev_beg);
+                ev2_end = ev2 + __builtin_amdgcn_readfirstlane(T2.ev_cnt);
             }
-            if (ev < ev_end)
+            while (ev < ev_end && __builtin_amdgcn_readfirstlane(evrows[ev].z) < z0) ++ev;
+            if (ev == ev_end) {
+                ev = ev2;
+                ev_end = ev2_end;
+                ev2 = ev2_end;
+            }
+            if (ev < ev_end) {
+                ev_z = __builtin_amdgcn_readfirstlane(evrows[ev].z);
                 ev_off = __builtin_amdgcn_readfirstlane(evrows[ev].vec_off);
-            else
-                ev_z = -1;
+            }
         }
 
-        float q[BZ + 12], cq[BZ + PF], pq[BZ + PF], wq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
+        float q[BZ + 12], pq[BZ + PF], wq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
 #pragma unroll
         for (int k = 0; k < 12; ++k) q[k] = bload(rU, poff(z0 - kHalo + k) + cbs);
 #pragma unroll
@@ -1392,7 +1403,6 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
             const uint32_t pz = poff(z0 + k);
             hyq[k] = bload(rU, pz + hybs);
             hxq[k] = bload(rU, pz + hxbs);
-            cq[k] = bload(rC, pz + cbs);
             pq[k] = bload(rP, pz + cbs);
             wq[k] = bload(rW, pz + cbs);
         }
@@ -1406,7 +1416,6 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
                 const uint32_t pz = poff(z + PF);
                 hyq[r + PF] = bload(rU, pz + hybs);
                 hxq[r + PF] = bload(rU, pz + hxbs);
-                cq[r + PF] = bload(rC, pz + cbs);
                 pq[r + PF] = bload(rP, pz + cbs);
                 wq[r + PF] = bload(rW, pz + cbs);
             }
@@ -1429,11 +1438,15 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
             if (z == ev_z) {  // uniform
                 const int rid = evvec[ev_off + threadIdx.x];
                 if (rid >= 0) wv += Rho[rid];
-                ++ev;
+                if (++ev == ev_end) {
+                    ev = ev2;
+                    ev_end = ev2_end;
+                    ev2 = ev2_end;
+                }
                 ev_z = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].z) : -1;
                 ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
             }
-            const float un = a * qq[4] - b * pq[r] + cq[r] * wv;
+            const float un = a * qq[4] - b * pq[r] + cr[r] * wv;
             bstore(rN, poff(z) + sbs, g.in ? un : 0.0f);  // whole lines, as in the forward
             const double pr = (double)un * (double)wq[r];  // the product of two floats is exact in FP64
             red[r][g.ry][g.lc] = j == 0 ? pr : red[r][g.ry][g.lc] + pr;
@@ -1686,16 +1699,18 @@ static hipError_t fwd3d_dispatch(const StepArgs &a, int bz, int wx, hipStream_t 
 {
     dim3 grid(8 * a.per_xcd);
     if (a.cka && a.wst) return hipErrorInvalidValue;  // one extra store kind per launch
-    if (wx == 64 && bz == 16)
-        fwd3d_mode<64, 16>(a, grid, st);
-    else if (wx == 64 && bz == 32)
-        fwd3d_mode<64, 32>(a, grid, st);
-    else if (wx == 32 && bz == 16)
-        fwd3d_mode<32, 16>(a, grid, st);
-    else if (wx == 32 && bz == 32)
-        fwd3d_mode<32, 32>(a, grid, st);
-    else
-        return hipErrorInvalidValue;
+    // heights 24 and 40 divide depths that 16 and 32 do not (120 padded planes = 3 x 40)
+    switch (wx * 100 + bz) {
+    case 6416: fwd3d_mode<64, 16>(a, grid, st); break;
+    case 6424: fwd3d_mode<64, 24>(a, grid, st); break;
+    case 6432: fwd3d_mode<64, 32>(a, grid, st); break;
+    case 6440: fwd3d_mode<64, 40>(a, grid, st); break;
+    case 3216: fwd3d_mode<32, 16>(a, grid, st); break;
+    case 3224: fwd3d_mode<32, 24>(a, grid, st); break;
+    case 3232: fwd3d_mode<32, 32>(a, grid, st); break;
+    case 3240: fwd3d_mode<32, 40>(a, grid, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -520,7 +520,7 @@ def test_results_identical_for_every_tile_height(F, ndim):
         time = F.time_axis(2e-3, 80, 1, 0)
         models = [f32(np.random.default_rng(1).uniform(1800, 3000, g.nphys))]
         groups = [(None, None, 1.0)]
-        cands = [16, 32]
+        cands = [16, 24, 32, 40]
     nd = batch.data_size(time.nt // time.rec_every)
     v = dev(np.concatenate(models))
     dobs = dev(1e-4 * np.random.default_rng(2).standard_normal(nd))

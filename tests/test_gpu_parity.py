@@ -246,11 +246,11 @@ def test_3d_parity(F, ckpt, wx):
 
 def test_3d_uneven_batch_per_sample_imaging(F):
     """Two 3D samples of different grid sizes with 3 and 1 supergathers, receivers on planes
-    through the whole depth, against the oracle, with 16- and 32-plane forward tiles (the
-    adjoint sweeps 16-plane tiles of each sample's grid for all of its supergathers; under
-    32-plane forward tiles it skips the receiver events above its first plane) and tiles
-    64 and 32 cells wide (one and two rows per wavefront) -- and all four tile shapes
-    bit-identical."""
+    through the whole depth, against the oracle, with 16-, 24-, 32- and 40-plane forward
+    tiles (the adjoint sweeps 16-plane tiles of each sample's grid for all of its
+    supergathers; under taller forward tiles it skips the receiver events above its first
+    plane, and a 40-plane tile is taller than either grid) and tiles 64 and 32 cells wide
+    (one and two rows per wavefront) -- and all eight tile shapes bit-identical."""
     say("case 3d uneven batch")
     grids = [F.Grid(nz=30, ny=9, nx=40, dz=20.0, dy=22.0, dx=25.0, nb=4, v_ref=3500.0, v_max=3600.0, ndim=3),
              F.Grid(nz=20, ny=12, nx=70, dz=20.0, dy=22.0, dx=25.0, nb=3, v_ref=3500.0, v_max=3600.0, ndim=3)]
@@ -279,7 +279,7 @@ def test_3d_uneven_batch_per_sample_imaging(F):
     kappa = [1.5, 1.0]
     outs = []
     try:
-        for bz in (16, 32):
+        for bz in (16, 24, 32, 40):
             for wx in (64, 32):
                 F.fwi_set_tile(3, bz)
                 F.fwi_set_tile_width(wx)
