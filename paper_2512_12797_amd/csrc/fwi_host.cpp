@@ -1858,28 +1858,41 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
     auto wlev = [&](const Plan &p, const Dev &d, int r) {
         return d.wst + (size_t)(r % std::max<int64_t>(1, p.wst_levels)) * p.cells;
     };
+    // every candidate's plan (the workspace layout is the same for all of them: its table
+    // region holds the largest); the candidates are timed in turn, round after round, so
+    // that drift of the clocks or of the caches affects them alike; round 0 warms up and
+    // each candidate keeps its best later round
+    std::vector<Plan> plans(cand.size());
+    for (size_t c = 0; c < cand.size(); ++c) {
+        s = build_plan(b, t, nullptr, plans[c], cand[c]);
+        if (s) return s;
+    }
+    const Plan &pl = plans.back();  // its two-step tables serve every tile height
+    {
+        Dev d = carve(pl, ws);
+        s = upload_tables(pl, d.base + pl.o_tables, st);
+        if (s) return s;
+        HIP_TRY(launch_prep(d.samples, b->nsample, pl.max_cell, v, d.cf, d.status, st));
+        HIP_TRY(launch_fill_f32(d.lev[0], 2 * pl.cells, 0.0f, st));
+        if (!pl.fwd_only) HIP_TRY(launch_fill_f64(d.gacc, pl.gcells, 0.0, st));
+    }
     hipEvent_t e0, e1, e2;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventCreate(&e2));
-    std::vector<double> fwd_ms(cand.size(), 0.0), adj_ms(cand.size(), 0.0);
-    Plan pl;  // plan of the last candidate: its two-step tables serve every tile height
-    for (size_t c = 0; c < cand.size(); ++c) {
-        Plan &p = pl;
-        p = Plan();
-        s = build_plan(b, t, nullptr, p, cand[c]);
-        if (s) return s;
-        Dev d = carve(p, ws);
-        s = upload_tables(p, d.base + p.o_tables, st);
-        if (s) return s;
-        HIP_TRY(launch_prep(d.samples, b->nsample, p.max_cell, v, d.cf, d.status, st));
-        HIP_TRY(launch_fill_f32(d.lev[0], 2 * p.cells, 0.0f, st));
-        if (!p.fwd_only) HIP_TRY(launch_fill_f64(d.gacc, p.gcells, 0.0, st));
-        StepArgs a = base_args(p, d);
-        a.fn = 0.0f;
-        a.gacc = d.gacc;
-        a.rho = d.rho;
-        for (int pass = 0; pass < 2; ++pass) {  // first pass warms the caches
+    std::vector<double> fwd_ms(cand.size(), 1e30), adj_ms(cand.size(), 1e30);
+    double adj2_ms = 1e30;  // the two-step adjoint, per time step
+    const int rounds = 4;
+    for (int round = 0; round < rounds && s == FWI_OK; ++round) {
+        for (size_t c = 0; c < cand.size() && s == FWI_OK; ++c) {
+            const Plan &p = plans[c];
+            Dev d = carve(p, ws);
+            s = upload_tables(p, d.base + p.o_tables, st);
+            if (s) break;
+            StepArgs a = base_args(p, d);
+            a.fn = 0.0f;
+            a.gacc = d.gacc;
+            a.rho = d.rho;
             float *cur = d.lev[0], *prev = d.lev[1];
             HIP_TRY(hipEventRecord(e0, st));
             for (int r = 0; r < reps; ++r) {
@@ -1899,22 +1912,22 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
                     std::swap(cur, prev);
                 }
             HIP_TRY(hipEventRecord(e2, st));
+            HIP_TRY(hipEventSynchronize(e2));
+            float fms = 0, ams = 0;
+            HIP_TRY(hipEventElapsedTime(&fms, e0, e1));
+            HIP_TRY(hipEventElapsedTime(&ams, e1, e2));
+            if (round > 0) {
+                fwd_ms[c] = std::min(fwd_ms[c], (double)fms / reps);
+                adj_ms[c] = std::min(adj_ms[c], (double)ams / reps);
+            }
         }
-        HIP_TRY(hipEventSynchronize(e2));
-        float fms = 0, ams = 0;
-        HIP_TRY(hipEventElapsedTime(&fms, e0, e1));
-        HIP_TRY(hipEventElapsedTime(&ams, e1, e2));
-        fwd_ms[c] = fms / reps;
-        adj_ms[c] = ams / reps;
-    }
-    // the two-step adjoint: reps launches of two steps, per time step
-    double adj2_ms = 1e30;
-    if (try_two) {
-        Dev d = carve(pl, ws);
-        StepArgs a = base_args2(pl, d);
-        a.rho = d.rho;
-        a.gacc = d.gacc;
-        for (int pass = 0; pass < 2; ++pass) {
+        if (try_two && s == FWI_OK) {  // reps launches of two steps
+            Dev d = carve(pl, ws);
+            s = upload_tables(pl, d.base + pl.o_tables, st);
+            if (s) break;
+            StepArgs a = base_args2(pl, d);
+            a.rho = d.rho;
+            a.gacc = d.gacc;
             float *cur = d.lev[0], *prev = d.lev[1], *o0 = d.lev[2], *o1 = d.lev[3];
             HIP_TRY(hipEventRecord(e0, st));
             for (int r = 0; r < reps; ++r) {
@@ -1929,20 +1942,23 @@ fwi_status fwi_tune(const fwi_batch *b, const fwi_time *t, const float *v, void 
                 std::swap(cur, o1);
             }
             HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms2 = 0;
+            HIP_TRY(hipEventElapsedTime(&ms2, e0, e1));
+            if (round > 0) adj2_ms = std::min(adj2_ms, ms2 / (2.0 * reps));
         }
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms2 = 0;
-        HIP_TRY(hipEventElapsedTime(&ms2, e0, e1));
-        adj2_ms = ms2 / (2.0 * reps);  // reps launches of two steps
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
-    // cost of one gradient time step: forward sweeps (two with recomputation) + adjoint
+    if (s) return s;
+    // cost of one gradient time step: forward sweeps (recomputation included: nt + head
+    // forward steps per nt with checkpoints) + adjoint
+    const double fwd_per_step = p0.K > 0 ? (double)(t->nt + p0.head) / t->nt : 1.0;
     int best = 0, best_adj = 0;
     double best_ms = 1e30;
     for (size_t c = 0; c < cand.size(); ++c) {
-        const double f = fwd_ms[c] * (p0.K > 0 ? 2.0 : 1.0);
+        const double f = fwd_ms[c] * fwd_per_step;
         if (f + adj_ms[c] < best_ms) {
             best_ms = f + adj_ms[c];
             best = cand[c];
