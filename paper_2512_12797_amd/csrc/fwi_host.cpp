@@ -1525,12 +1525,17 @@ fwi_status fwi_schedule(const fwi_batch *b, fwi_time *t, size_t budget_bytes)
         const int64_t ck = nseg > 0 ? 2 * (int64_t)(nseg - 1) : 0;
         return fixed + align_up((size_t)(ring + T) * lev) + align_up((size_t)ck * lev);
     };
-    // fewest forward steps = longest kept tail; then the smallest workspace
+    // fewest forward steps = longest kept tail; then the smallest workspace.  For a
+    // checkpointed part of h steps the levels are r K + 2 ceil(h / K) - 2 (ring factor r = 1,
+    // or 2 with overlap), at most 4 sqrt(h) + 4 at K = ceil(sqrt(2h / r)); so only intervals
+    // with r K and 2 h / K below that bound can be smallest: sqrt(h) / 4 - 1 <= K <= 4 sqrt(h) + 5
     for (int T = nt; T >= 0; --T) {
         const int head = nt - T;
         int best = 0;
         size_t best_bytes = 0;
-        for (int K = 1; K <= std::max(head, 1); ++K) {
+        const int khi = std::min(std::max(head, 1), 3 * (int)std::sqrt(2.0 * head) + 4);
+        const int klo = head > 0 ? std::max(1, head / khi - 1) : 1;
+        for (int K = klo; K <= khi; ++K) {
             const size_t by = bytes_of(K, T);
             if (by <= budget_bytes && (best == 0 || by < best_bytes)) {
                 best = K;
