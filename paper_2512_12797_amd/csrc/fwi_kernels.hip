@@ -827,9 +827,13 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
     const uint32_t rowb = 4u * (uint32_t)Nx;
     auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
 
-    __shared__ float rows[8][2][kTileX + 2 * kHalo];
-    __shared__ float rows1[8][2][kTileX + 2 * kHalo];
-    __shared__ double red[2][BZ][kTileX];
+    // LDS sized by the launch (adj2d2_lds_bytes): the strips' wave sums when a strip has
+    // several waves, then each wave's x rows of the two steps
+    extern __shared__ __align__(16) unsigned char dsm[];
+    double(*red)[BZ][kTileX] = reinterpret_cast<double(*)[BZ][kTileX]>(dsm);
+    float(*rows)[2][kTileX + 2 * kHalo] =
+        reinterpret_cast<float(*)[2][kTileX + 2 * kHalo]>(dsm + (wps > 1 ? (size_t)sg * BZ * kTileX * sizeof(double) : 0));
+    float(*rows1)[2][kTileX + 2 * kHalo] = rows + nw;
     __shared__ float2 abt[2][R1][kTileX];  // leapfrog a, b of each strip's first-step cells
 
     for (int r = wl; r < R1 && active; r += wps) {
@@ -1746,6 +1750,15 @@ hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int wx
     return adjoint ? adj3d_dispatch(a, wx, st) : fwd3d_dispatch(a, bz, wx, st);
 }
 
+// dynamic LDS of the two-step adjoint for nw waves on sg strips: the FP64 wave sums of
+// each strip (kRows2 x 64) when a strip has several waves, and every wave's x rows of both
+// steps (2 x 2 x (64 + 8) floats)
+static size_t adj2d2_lds_bytes(int nw, int sg)
+{
+    const size_t red = nw / sg > 1 ? (size_t)sg * kRows2 * kTileX * sizeof(double) : 0;
+    return red + (size_t)nw * 4 * (kTileX + 2 * kHalo) * sizeof(float);
+}
+
 hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st)
 {
     if (a.ntiles <= 0) return hipSuccess;
@@ -1755,7 +1768,7 @@ hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st)
     if (adjoint) {
         if (a.nw < 1 || a.nw > 8 || (a.sg != 1 && a.sg != 2) || a.nw % a.sg || !a.wimg || !a.wimg2)
             return hipErrorInvalidValue;
-        k_adj2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd_g), 64 * a.nw, 0, st>>>(a);
+        k_adj2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd_g), 64 * a.nw, adj2d2_lds_bytes(a.nw, a.sg), st>>>(a);
     } else {
         k_fwd2d2<kRows2, kPf2><<<dim3(8 * a.per_xcd), 256, 0, st>>>(a);  // 4 strips per workgroup
     }
