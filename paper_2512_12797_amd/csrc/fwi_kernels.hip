@@ -828,13 +828,13 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
     auto roff = [&](int zz) -> uint32_t { return (uint32_t)zz * rowb; };  // zz < 0 wraps out of range
 
     // LDS sized by the launch (adj2d2_lds_bytes): the strips' wave sums when a strip has
-    // several waves, then each wave's x rows of the two steps
+    // several waves, each wave's x rows of the two steps, each strip's a, b
     extern __shared__ __align__(16) unsigned char dsm[];
     double(*red)[BZ][kTileX] = reinterpret_cast<double(*)[BZ][kTileX]>(dsm);
     float(*rows)[2][kTileX + 2 * kHalo] =
         reinterpret_cast<float(*)[2][kTileX + 2 * kHalo]>(dsm + (wps > 1 ? (size_t)sg * BZ * kTileX * sizeof(double) : 0));
     float(*rows1)[2][kTileX + 2 * kHalo] = rows + nw;
-    __shared__ float2 abt[2][R1][kTileX];  // leapfrog a, b of each strip's first-step cells
+    float2(*abt)[R1][kTileX] = reinterpret_cast<float2(*)[R1][kTileX]>(rows1 + nw);  // a, b per strip
 
     for (int r = wl; r < R1 && active; r += wps) {
         double gam = 0.0;
@@ -1751,12 +1751,13 @@ hipError_t launch_step(const StepArgs &a, int ndim, bool adjoint, int bz, int wx
 }
 
 // dynamic LDS of the two-step adjoint for nw waves on sg strips: the FP64 wave sums of
-// each strip (kRows2 x 64) when a strip has several waves, and every wave's x rows of both
-// steps (2 x 2 x (64 + 8) floats)
+// each strip (kRows2 x 64) when a strip has several waves, every wave's x rows of both
+// steps (2 x 2 x (64 + 8) floats) and each strip's leapfrog a, b ((kRows2 + 8) x 64 pairs)
 static size_t adj2d2_lds_bytes(int nw, int sg)
 {
     const size_t red = nw / sg > 1 ? (size_t)sg * kRows2 * kTileX * sizeof(double) : 0;
-    return red + (size_t)nw * 4 * (kTileX + 2 * kHalo) * sizeof(float);
+    return red + (size_t)nw * 4 * (kTileX + 2 * kHalo) * sizeof(float) +
+           (size_t)sg * (kRows2 + 2 * kHalo) * kTileX * 2 * sizeof(float);
 }
 
 hipError_t launch_step2(const StepArgs &a, bool adjoint, hipStream_t st)
