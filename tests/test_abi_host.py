@@ -134,6 +134,16 @@ def test_schedule_for_a_budget(F):
             assert F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, K2, T + 1)) > budget
     small_budget = F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, 10, 0)) - 30 * lev
     expect(F, F.FWI_E_WORKSPACE, F.fwi_schedule, b, t, small_budget)
+    # with the recomputation beside the adjoint the ring is doubled: the pick still fits
+    F.fwi_set_overlap(True)
+    try:
+        for budget in (full - 1, full - 30 * lev):
+            s = F.fwi_schedule(b, t, budget)
+            assert s.ckpt_every >= 1 and F.fwi_workspace_size(b, s) <= budget
+            for K2 in range(1, 100 - s.keep_tail):
+                assert F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, K2, s.keep_tail + 1)) > budget
+    finally:
+        F.fwi_set_overlap(False)
 
 
 def test_null_workspace_rejected_before_any_device_work(F):
