@@ -197,6 +197,8 @@ struct Plan {
     int nlev = 2, K = 0, nseg = 1;
     int head = 0, tail = 0;  // checkpoints: steps [0, head) recomputed per segment, [head, nt) kept
     int64_t ring = 0;        // imaging levels of the recomputation ring (two rings with overlap)
+    int64_t tail_lev0 = 0;   // first imaging level of the kept tail (0: the ring reuses the tail's
+                             // levels, which the adjoint has read before it recomputes)
     bool fwd_only = false;  // ckpt_every == -1: no adjoint state is kept
     bool overlap = false;   // checkpoints: recompute the next segment beside the current adjoint
     int64_t wst_levels = 0, ck_slots = 0;
@@ -733,7 +735,10 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
     // adjoint reads the other
     p.overlap = !p.fwd_only && p.K > 0 && p.nseg >= 2 && !no_overlap && g_overlap.load();
     p.ring = p.K > 0 && p.nseg > 0 ? (p.overlap ? 2 * p.K : p.K) : 0;
-    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.ring + p.tail : t->nt);
+    // without overlap the adjoint sweeps the kept tail before its first recomputation, so a
+    // tail at least as long as the ring lends it its levels
+    p.tail_lev0 = (!p.overlap && p.tail >= p.ring) ? 0 : p.ring;
+    p.wst_levels = p.fwd_only ? 0 : (p.K > 0 ? p.tail_lev0 + p.tail : t->nt);
     p.ck_slots = p.K > 0 && p.nseg > 0 ? 2 * (int64_t)(p.nseg - 1) : 0;
     int64_t maxdata = 0;
     for (auto &S : p.sims) maxdata = std::max(maxdata, (int64_t)p.nt_rec * S.nrec);
@@ -970,7 +975,7 @@ void hash_plan(KeyHash &k, const Plan &p, const fwi_batch *b, const fwi_time *t)
 {
     k.add(p.ndim); k.add(p.bz); k.add(p.ty); k.add(p.wx); k.add(p.per_xcd); k.add(p.cells); k.add(p.coefs); k.add(p.data);
     k.add(p.max_cell); k.add(p.nt_rec); k.add(p.nlev); k.add(p.K); k.add(p.nseg); k.add(p.fwd_only);
-    k.add(p.head); k.add(p.tail); k.add(p.ring); k.add(p.overlap);
+    k.add(p.head); k.add(p.tail); k.add(p.ring); k.add(p.tail_lev0); k.add(p.overlap);
     k.add(p.nchunk_res); k.add(p.nchunk_fin);
     k.add(p.grouped); k.add(p.bzg); k.add(p.nw); k.add(p.per_xcd_g); k.add(p.gcells);
     k.add(p.two); k.add(p.two_adj); k.add(p.nw2); k.add(p.sg2); k.add(p.per_xcd2); k.add(p.per_xcd_g2);
@@ -1241,7 +1246,7 @@ fwi_status run_forward(const Plan &p, const Dev &d, const fwi_batch *b, const fw
         if (!p.fwd_only && p.K == 0)
             a.wst = d.wst + (size_t)n * p.cells;
         else if (p.K > 0 && n >= p.head)  // the kept tail, after the recomputation ring(s)
-            a.wst = d.wst + (size_t)(p.ring + n - p.head) * p.cells;
+            a.wst = d.wst + (size_t)(p.tail_lev0 + n - p.head) * p.cells;
         a.cka = a.ckb = nullptr;
         if (p.K > 0 && (n + 1) % p.K == 0 && (n + 1) / p.K < p.nseg) {
             const int slot = (n + 1) / p.K;
@@ -1377,13 +1382,19 @@ fwi_status run_adjoint(const Plan &p, const Dev &d, const fwi_batch *b, const fw
             return FWI_OK;
         };
         fwi_status s = FWI_OK;
-        if (p.nseg > 0) {
+        // with overlap the last segment is recomputed on the side stream while the tail is
+        // swept; without, the tail goes first (the ring may reuse its levels)
+        if (p.overlap && p.nseg > 0) {
             s = recompute(p.nseg - 1);
             if (s) return s;
         }
         if (p.tail > 0) {
-            const float *Wt = d.wst + (size_t)p.ring * p.cells;
+            const float *Wt = d.wst + (size_t)p.tail_lev0 * p.cells;
             s = sweep(t->nt, p.head, [&](int k) { return Wt + (size_t)(k - 1 - p.head) * p.cells; });
+            if (s) return s;
+        }
+        if (!p.overlap && p.nseg > 0) {
+            s = recompute(p.nseg - 1);
             if (s) return s;
         }
         for (int sg = p.nseg - 1; sg >= 0; --sg) {
@@ -1521,27 +1532,35 @@ fwi_status fwi_schedule(const fwi_batch *b, fwi_time *t, size_t budget_bytes)
         const int head = nt - T;
         const int k = std::min(K, std::max(head, 1));
         const int nseg = (head + k - 1) / k;
-        const int64_t ring = nseg > 0 ? ((ovl && nseg >= 2) ? 2 * k : k) : 0;
+        const bool o = ovl && nseg >= 2;
+        const int64_t ring = nseg > 0 ? (o ? 2 * k : k) : 0;
+        const int64_t imaging = (!o && T >= ring) ? T : ring + T;  // the ring may reuse the tail's levels
         const int64_t ck = nseg > 0 ? 2 * (int64_t)(nseg - 1) : 0;
-        return fixed + align_up((size_t)(ring + T) * lev) + align_up((size_t)ck * lev);
+        return fixed + align_up((size_t)imaging * lev) + align_up((size_t)ck * lev);
     };
     // fewest forward steps = longest kept tail; then the smallest workspace.  For a
-    // checkpointed part of h steps the levels are r K + 2 ceil(h / K) - 2 (ring factor r = 1,
-    // or 2 with overlap), at most 4 sqrt(h) + 4 at K = ceil(sqrt(2h / r)); so only intervals
-    // with r K and 2 h / K below that bound can be smallest: sqrt(h) / 4 - 1 <= K <= 4 sqrt(h) + 5
+    // checkpointed part of h steps with a separate ring the levels are r K + 2 ceil(h / K) - 2
+    // (ring factor r = 1, or 2 with overlap), at most 4 sqrt(h) + 4 at K = ceil(sqrt(2h / r));
+    // so only intervals with r K and 2 h / K below that bound can be smallest:
+    // sqrt(h) / 4 - 1 <= K <= 4 sqrt(h) + 5.  A ring that reuses the tail's levels (K <= T,
+    // no overlap) costs nothing, and the checkpoints are fewest at the longest such interval,
+    // K = min(T, h), which is tried as well.
     for (int T = nt; T >= 0; --T) {
         const int head = nt - T;
         int best = 0;
         size_t best_bytes = 0;
         const int khi = std::min(std::max(head, 1), 3 * (int)std::sqrt(2.0 * head) + 4);
         const int klo = head > 0 ? std::max(1, head / khi - 1) : 1;
-        for (int K = klo; K <= khi; ++K) {
+        const int kalias = std::max(1, std::min(T, head));
+        auto consider = [&](int K) {
             const size_t by = bytes_of(K, T);
             if (by <= budget_bytes && (best == 0 || by < best_bytes)) {
                 best = K;
                 best_bytes = by;
             }
-        }
+        };
+        for (int K = klo; K <= khi; ++K) consider(K);
+        if (kalias > khi) consider(kalias);
         if (best) {
             q.ckpt_every = best;
             q.keep_tail = T;

@@ -99,7 +99,8 @@ def test_workspace_sizes(F):
 
 def test_kept_tail_validation_and_sizes(F):
     """keep_tail: range and schedule checks; the workspace holds the recomputation ring,
-    the kept tail and the checkpoints of the first nt - keep_tail steps."""
+    the kept tail and the checkpoints of the first nt - keep_tail steps, the ring inside the
+    tail's levels when the tail is at least as long (the adjoint reads the tail first)."""
     g, rec, wav = small(F)
     b = F.Batch([g], [0, 0], [([31], [1.0]), ([40], [-1.0])], [rec, rec], wav)
     for K, T in ((10, -1), (10, 101), (0, 5), (-1, 5)):
@@ -107,10 +108,12 @@ def test_kept_tail_validation_and_sizes(F):
     lev = 2 * (28 * 38) * 4  # one level of both sims (bytes)
     size = lambda K, T: F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, K, T))
     base = size(10, 0)  # ring 10 + 2 x 9 checkpoint levels = 28
-    # tail 30: head 70 -> 7 segments: ring 10 + tail 30 + 2 x 6 checkpoint levels = 52
-    assert abs(size(10, 30) - base - 24 * lev) <= 512
-    # tail 95: head 5 -> a ring of 5 levels, one segment, no checkpoint: 100
-    assert abs(size(10, 95) - base - 72 * lev) <= 512
+    # tail 30: head 70 -> 7 segments: tail 30 (holding the ring) + 2 x 6 checkpoint levels = 42
+    assert abs(size(10, 30) - base - 14 * lev) <= 512
+    # tail 6, shorter than the ring: head 94 -> 10 segments: ring 10 + tail 6 + 2 x 9 = 34
+    assert abs(size(10, 6) - base - 6 * lev) <= 512
+    # tail 95: head 5 -> a ring of 5 levels inside the tail, one segment, no checkpoint: 95
+    assert abs(size(10, 95) - base - 67 * lev) <= 512
     # every step kept through the tail: no ring, no checkpoint: 100
     assert abs(size(10, 100) - base - 72 * lev) <= 512
     assert size(10, 100) > F.fwi_workspace_size(b, F.time_axis(1e-3, 100, 2, 0))  # two more field levels

@@ -418,10 +418,12 @@ def test_overlapped_recomputation_is_bitwise_sequential(F, ndim):
         assert e < TOL
 
 
-# (ckpt_every, keep_tail, overlap): segments of 6 under a kept tail of 20 (77 = 12 x 6 + 5),
-# a tail that leaves one checkpointed step, every step kept, an interval longer than the
-# checkpointed part, and a kept tail beside the overlapped recomputation
-TAIL_SCHEDULES = [(6, 0, False), (6, 20, False), (6, 96, False), (6, 97, False), (50, 60, False), (4, 31, True)]
+# (ckpt_every, keep_tail, overlap): segments of 6 under a kept tail of 20 (77 = 12 x 6 + 5;
+# the ring inside the tail's levels), a tail that leaves one checkpointed step, every step
+# kept, an interval longer than the checkpointed part, a tail shorter than the ring (its own
+# levels), and a kept tail beside the overlapped recomputation (two rings of their own)
+TAIL_SCHEDULES = [(6, 0, False), (6, 20, False), (6, 96, False), (6, 97, False), (50, 60, False),
+                  (10, 5, False), (4, 31, True)]
 
 
 @pytest.mark.parametrize("ndim", [2, 3])
