@@ -227,7 +227,9 @@ def test_3d_configuration_full_size_properties(F):
     * linearity in the encoding: sample 0's first supergather's data equal the +-1-weighted
       sum of its 16 shots simulated one by one (rel L2 <= 1e-5);
     * the checkpoint schedule does not change the arithmetic: the gradients with
-      checkpoints every 50 and every 30 steps are identical bit for bit;
+      checkpoints every 50 and every 30 steps, and with the bench's schedule (the kept
+      tail and checkpoint interval fwi_schedule picks for the free memory), are identical
+      bit for bit;
     * the gradient is finite and nonzero, and the per-sample norms match it."""
     from paper_2512_12797_amd import problems
     cfg = W.C5
@@ -244,8 +246,16 @@ def test_3d_configuration_full_size_properties(F):
     dobs = dev(1e-3 * np.random.default_rng(3).standard_normal(batch.data_size(nt_rec)))
     kappa = [g[2] for g in groups]
     outs = []
-    for k in (50, 30):
-        time = F.time_axis(cfg.dt, cfg.nt, cfg.rec_every, k)
+    for k in (50, 30, "schedule"):
+        if k == "schedule":
+            torch.cuda.empty_cache()
+            free, _ = torch.cuda.mem_get_info()
+            time = F.fwi_schedule(batch, F.time_axis(cfg.dt, cfg.nt, cfg.rec_every), free - (8 << 30))
+            say("  schedule for %.1f GB: checkpoints every %d, last %d steps kept" % (
+                (free - (8 << 30)) / 1e9, time.ckpt_every, time.keep_tail))
+            assert time.ckpt_every >= 1 and time.keep_tail > 0
+        else:
+            time = F.time_axis(cfg.dt, cfg.nt, cfg.rec_every, k)
         ws = F.alloc_workspace(batch, time)
         dpred = torch.zeros(batch.data_size(nt_rec), device="cuda")
         mis = torch.zeros(batch.nsim, dtype=torch.float64, device="cuda")
@@ -254,11 +264,12 @@ def test_3d_configuration_full_size_properties(F):
         F.fwi_gradient(batch, time, v, dobs, 1.0, kappa, dpred, mis, grad, gn, ws)
         F.fwi_poll_status(ws)
         outs.append((dpred.cpu().numpy(), mis.cpu().numpy(), grad.cpu().numpy(), gn.cpu().numpy()))
-        say("  checkpoints every %d: |grad| %.3e" % (k, float(grad.double().norm())))
+        say("  checkpoints %s: |grad| %.3e" % (k, float(grad.double().norm())))
         del ws, dpred, mis, grad, gn
         torch.cuda.empty_cache()
-    for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(a, b)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
     dpred, mis, grad, gn = outs[0]
     assert np.all(np.isfinite(grad)) and np.abs(grad).max() > 0
     per = split_model(grad.astype(np.float64), batch)
