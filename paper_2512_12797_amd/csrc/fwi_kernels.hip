@@ -854,6 +854,13 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
     double acc[BZ];
 #pragma unroll
     for (int r = 0; r < BZ; ++r) acc[r] = 0.0;
+    // c of the strip's first-step rows, read once for all of the wave's sims
+    float cr[R1];
+    {
+        const uint32_t cb0 = xin ? xo : kPoison;
+#pragma unroll
+        for (int i = 0; i < R1; ++i) cr[i] = bload(rC, roff(z0 - kHalo + i) + cb0);
+    }
 
     for (int j = wl; j < sim_cnt && active; j += wps) {
         const int sim = sim_beg + j;
@@ -881,14 +888,13 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
         const int d_hi = __builtin_amdgcn_readfirstlane((int)(d_off >> 32));
         const int64_t d_off_u = (int64_t)(((uint64_t)(uint32_t)d_hi << 32) | (uint32_t)d_lo);
 
-        float q[R1 + 8 + PF], hq[R1 + PF], cq[R1 + PF], pq[R1 + PF], s1[R1], wq1[BZ], wq2[BZ];
+        float q[R1 + 8 + PF], hq[R1 + PF], pq[R1 + PF], s1[R1], wq1[BZ], wq2[BZ];
 #pragma unroll
         for (int k = 0; k < 8 + PF; ++k) q[k] = bload(rU, coff(zs - 2 * kHalo + k));
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int zz = zs - kHalo + k;
             hq[k] = bload(rU, hoff(zz));
-            cq[k] = bload(rC, coff(zz));
             pq[k] = bload(rP, coff(zz));
         }
         const float *Rho1 = rec_j1 >= 0 ? A.rho + d_off_u + (int64_t)rec_j1 * nrec : nullptr;
@@ -921,7 +927,6 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
             const int z1 = zs - kHalo + i;
             q[i + 8 + PF] = bload(rU, coff(z1 + kHalo + PF));
             hq[i + PF] = bload(rU, hoff(z1 + PF));
-            cq[i + PF] = bload(rC, coff(z1 + PF));
             pq[i + PF] = bload(rP, coff(z1 + PF));
             // W^{k-1} of own row z0 + r is used at i = r + 4, W^{k-2} at i = r + 8: both are
             // fetched 4 rows ahead, by the strip's own lanes only (the margin lanes' products
@@ -959,7 +964,7 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
                     ez1 = e1 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e1].z) : kNoRow;
                     eo1 = e1 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e1].vec_off) : 0;
                 }
-                const float un = ab.x * q[i + 4] - ab.y * pq[i] + cq[i] * wv;
+                const float un = ab.x * q[i + 4] - ab.y * pq[i] + cr[i] * wv;
                 s1[i] = un;
                 if (i >= kHalo && i < BZ + kHalo) {
                     bstore(rN, soff(z1), un);
@@ -988,7 +993,7 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
                     ez2 = e2 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e2].z) : kNoRow;
                     eo2 = e2 < ev_end ? __builtin_amdgcn_readfirstlane(evrows[e2].vec_off) : 0;
                 }
-                const float un = ab.x * s1[i - 4] - ab.y * q[i] + cq[i - 4] * wv;
+                const float un = ab.x * s1[i - 4] - ab.y * q[i] + cr[i - 4] * wv;
                 bstore(rN2, soff(z2), un);
                 acc[i - 2 * kHalo] += (double)un * (double)wq2[i - 2 * kHalo];
             }
