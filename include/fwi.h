@@ -90,8 +90,11 @@ typedef struct {
     int32_t keep_tail;     /* with K >= 1: the forward also keeps the imaging operands of
                               the last keep_tail steps (0 <= keep_tail <= nt), which the
                               adjoint then reads without recomputing them; checkpoints
-                              cover the first nt - keep_tail steps.  Must be 0 when
-                              ckpt_every <= 0.  Results are identical for every value. */
+                              cover the first nt - keep_tail steps.  A tail at least
+                              as long as the recomputation ring (K levels; overlap off)
+                              also holds the ring once the adjoint has read it.  Must be
+                              0 when ckpt_every <= 0.  Results are identical for every
+                              value. */
 } fwi_time;
 
 /* A batch of simulations.  Every array here is HOST memory. */
