@@ -5,7 +5,8 @@ Default workload (one "step" = one Langevin refinement of every posterior sample
 200 x 200 x 100 grid at 25 m (220 x 220 x 120 with the 10-cell sponge), 64 surface shots
 of a 4 Hz Ricker wavelet on an 8 x 8 lattice and 2500 receivers, 1500 steps of 2 ms; 8
 posterior samples, each drawing 4 supergathers of 16 shots with +-1 polarity per step (32
-simulations in one launch per time step), checkpoints every 10 steps.  Per step: draw
+simulations in one launch per time step), with the checkpoint interval and kept tail that
+fwi_schedule picks for the free memory.  Per step: draw
 encodings (host), encode observed data, forward + misfit + adjoint-state gradient,
 Langevin update.  Inputs are seeded synthetic (dipping layers with a salt body, smoothed
 start, 1 % Gaussian noise) and resident in HBM before the timed region.  The 2D encoded
