@@ -651,6 +651,7 @@ fwi_status build_plan(const fwi_batch *b, const fwi_time *t, const double *kappa
                     G.x0 = ix * kStrip2;
                     G.z0 = iz * kRows2;
                     G.tix = iz * ntx + ix;  // the same strip in each of the sample's sims
+                    G.tix2 = -1;
                     p.gtiles2.push_back(G);
                 }
         }
