@@ -306,8 +306,8 @@ fwi_status fwi_set_tile(int32_t ndim, int32_t bz);
 /*
  * Width of the 3D step kernels' tiles, process-wide: 64 cells (8 rows per tile, one row
  * per wavefront) or 32 cells (16 rows per tile, two rows per wavefront); 0 (the default)
- * picks 64 unless 32-wide tiles would run fewer than half the lanes over the batch's
- * padded grids (x extent rounded up to the width, y extent to the tile's rows).  Results
+ * picks 32 where 32-wide tiles run fewer lanes over the batch's padded grids (x extent
+ * rounded up to the width, y extent to the tile's rows) than 64-wide ones.  Results
  * are identical for both widths; only the speed differs.  The workspace size covers
  * either width.
  */

@@ -291,10 +291,11 @@ bool valid_bz(int ndim, int bz)
     return bz == 16 || bz == 24 || bz == 32 || bz == 40;
 }
 
-// 3D tile width: 64 cells (8 rows per tile) unless 32-wide tiles (two rows per wavefront,
-// 16 rows per tile) would run fewer than half the lanes over the batch's grids, or a width
-// is forced.  (On the 220 x 220 x 120 padded grid 32-wide tiles run 12 % fewer lanes but
-// measured 11 % slower: a 64-wide row segment is two whole 128-byte lines.)
+// 3D tile width: 32 cells (two rows per wavefront, 16 rows per tile) where that runs fewer
+// lanes over the batch's grids than 64-wide tiles (8 rows per tile), else 64, unless a width
+// is forced.  With rows stored at a 32-cell pitch both widths write whole lines; on the
+// 220 x 220 x 120 padded grid 32-wide tiles run 12 % fewer lanes and took 649 / 902 us per
+// forward / adjoint launch against 653 / 927 us (40-plane forward tiles).
 int pick_width3(const fwi_batch *b)
 {
     const int forced = g_width3.load();
@@ -308,7 +309,7 @@ int pick_width3(const fwi_batch *b)
             lanes[i] += ((Nx + wx - 1) / wx) * wx * ((Ny + ty - 1) / ty) * ty;
         }
     }
-    return 2 * lanes[1] < lanes[0] ? 32 : 64;
+    return lanes[1] < lanes[0] ? 32 : 64;
 }
 
 void pick_tiles(Plan &p, const fwi_batch *b, int bz_override, int wx_override)
