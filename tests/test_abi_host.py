@@ -186,6 +186,23 @@ def test_langevin_argument_checks(F):
     assert F.lib().fwi_status_string(F.FWI_E_CFL)
 
 
+def test_3d_tile_shape_defaults(F):
+    """Default 3D tiles: 32 cells wide where that runs fewer lanes than 64 (the bench grid's
+    220-cell rows: 7 x 32 against 4 x 64), else 64; the height with the fewest planes read
+    per tile column (120 padded planes: three 40-plane tiles)."""
+    from paper_2512_12797_amd import problems
+    cfg = W.C5
+    grid = problems.grid_of(cfg)
+    wav = W.ricker(cfg.freq, cfg.dt, 20)
+    b, _ = problems.encoded_batch(cfg, [grid] * cfg.nsample, wav, 0, 0)
+    assert F.fwi_tile_shape(b, F.time_axis(cfg.dt, 20, 1, 10)) == (40, 32)
+    # 128 x 24 rows (no sponge): 64-wide tiles run 128 x 24 lanes, 32-wide 128 x 32
+    g = F.Grid(nz=20, ny=24, nx=128, dz=10, dy=10, dx=10, nb=0, v_ref=2000, v_max=2000, ndim=3)
+    b2 = F.Batch([g] * 64, list(range(64)), [([5], [1.0])] * 64, [np.array([7], dtype=np.int32)] * 64,
+                 W.ricker(10.0, 1e-3, 20))
+    assert F.fwi_tile_shape(b2, F.time_axis(1e-3, 20, 1, 0))[1] == 64
+
+
 def test_time_blocking_values(F):
     # 0 (automatic), 1 or 2 time steps per launch for each sweep; anything else is rejected
     # on the host
