@@ -164,6 +164,14 @@ __device__ __forceinline__ float bload(rsrc_t r, uint32_t off)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
+// The same with the non-temporal cache policy, for fields a launch reads once and no launch
+// reads again soon (the 3D forward's u^{n-1}, the 3D adjoint's lt^{k+2} and W^{k-1}, the 2D
+// two-step adjoint's imaging operands): they then displace less of what is reused from L2
+// (c, halo rows, the per-sample accumulator).
+__device__ __forceinline__ float bload_nt(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 2));
+}
 __device__ __forceinline__ double bload64(rsrc_t r, uint32_t off)
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
@@ -931,8 +939,8 @@ __global__ __launch_bounds__(512) void k_adj2d2(const StepArgs A)
             // W^{k-1} of own row z0 + r is used at i = r + 4, W^{k-2} at i = r + 8: both are
             // fetched 4 rows ahead, by the strip's own lanes only (the margin lanes' products
             // are never used, so their loads are poisoned and fetch nothing)
-            if (i < BZ) wq1[i] = bload(rW, roff(zs + i) + sb);
-            if (i >= kHalo && i - kHalo < BZ) wq2[i - kHalo] = bload(rW2, roff(zs + i - kHalo) + sb);
+            if (i < BZ) wq1[i] = bload_nt(rW, roff(zs + i) + sb);
+            if (i >= kHalo && i - kHalo < BZ) wq2[i - kHalo] = bload_nt(rW2, roff(zs + i - kHalo) + sb);
 
             // both steps' x rows go to LDS before one wave-scope fence
             float *row = rows[wave][i & 1];
@@ -1221,7 +1229,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
         hyq[k] = bload(rU, pz + hyb);
         hxq[k] = bload(rU, pz + hxb);
         cq[k] = bload(rC, pz + cb);
-        pq[k] = bload(rP, pz + cb);
+        pq[k] = bload_nt(rP, pz + cb);
     }
     int ev = T.ev_beg;
     const int ev_end = T.ev_beg + T.ev_cnt;
@@ -1241,7 +1249,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
             hyq[r + PF] = bload(rU, pz + hyb);
             hxq[r + PF] = bload(rU, pz + hxb);
             cq[r + PF] = bload(rC, pz + cb);
-            pq[r + PF] = bload(rP, pz + cb);
+            pq[r + PF] = bload_nt(rP, pz + cb);
         }
         // ---- plane z into LDS
         float(*L)[G::LX] = V[r & 1];
@@ -1412,8 +1420,8 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
             const uint32_t pz = poff(z0 + k);
             hyq[k] = bload(rU, pz + hybs);
             hxq[k] = bload(rU, pz + hxbs);
-            pq[k] = bload(rP, pz + cbs);
-            wq[k] = bload(rW, pz + cbs);
+            pq[k] = bload_nt(rP, pz + cbs);
+            wq[k] = bload_nt(rW, pz + cbs);
         }
         // planes below the grid are swept too: their loads read 0 and their stores fall
         // outside the buffers
@@ -1425,8 +1433,8 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
                 const uint32_t pz = poff(z + PF);
                 hyq[r + PF] = bload(rU, pz + hybs);
                 hxq[r + PF] = bload(rU, pz + hxbs);
-                pq[r + PF] = bload(rP, pz + cbs);
-                wq[r + PF] = bload(rW, pz + cbs);
+                pq[r + PF] = bload_nt(rP, pz + cbs);
+                wq[r + PF] = bload_nt(rW, pz + cbs);
             }
             float(*L)[G::LX] = V[r & 1];
             L[ly][lx] = q[r + 4];
