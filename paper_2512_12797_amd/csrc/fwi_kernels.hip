@@ -180,6 +180,13 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
 }
+// Store with the non-temporal cache policy: the 3D forward's imaging operand, which only
+// the adjoint reads, many launches later, so that it displaces less of the halo rows and
+// coefficients the sweep reuses from L2.
+__device__ __forceinline__ void bstore_nt(rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 2);
+}
 __device__ __forceinline__ void bstore64(rsrc_t r, uint32_t off, double v)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r,
@@ -1219,6 +1226,11 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
     const bool has_src = __syncthreads_or(sz >= 0);
     const bool multi = __syncthreads_or(smulti);
 
+    // z-sponge gamma of the tile's planes, one lane per plane: a sponge plane reads it
+    // instead of every lane dividing by nb again (same value, same rounding)
+    __shared__ double gzs[BZ];
+    if (threadIdx.x < BZ) gzs[threadIdx.x] = sponge_of_depth(sponge_depth(z0 + threadIdx.x, nz_phys, nb), nb, gmz);
+
     // queues indexed by plane (the plane loop is fully unrolled)
     float q[BZ + 12], cq[BZ + PF], pq[BZ + PF], hyq[BZ + PF], hxq[BZ + PF];
 #pragma unroll
@@ -1263,7 +1275,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
         float a = a_col, b = b_col;
         if ((unsigned)(z - nb) >= (unsigned)nz_phys) {  // uniform: a z-sponge plane
             double gam = 0.0;
-            gam = gam + sponge_of_depth(sponge_depth(z, nz_phys, nb), nb, gmz);
+            gam = gam + gzs[r];  // written before the plane loop's first barrier
             gam = gam + gy;
             gam = gam + gx;
             sponge_ab(gam, dt, a, b);
@@ -1285,7 +1297,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
         const uint32_t o = poff(z) + sb;
         const float un = g.in ? a * qq[4] - b * pq[r] + cq[r] * wv : 0.0f;
         bstore(rN, o, un);
-        if (MODE == kStoreImage) bstore(rW, o, g.in ? wv : 0.0f);
+        if (MODE == kStoreImage) bstore_nt(rW, o, g.in ? wv : 0.0f);
         if (MODE == kStoreCkpt) {
             bstore(rKa, o, un);
             bstore(rKb, o, qq[4]);  // 0 past the grid (its loads are poisoned)
