@@ -180,9 +180,11 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
 }
-// Store with the non-temporal cache policy: the 3D forward's imaging operand, which only
-// the adjoint reads, many launches later, so that it displaces less of the halo rows and
-// coefficients the sweep reuses from L2.
+// Store with the non-temporal cache policy, for what a 3D sweep writes and no workgroup of
+// the same launch reads (u^{n+1}, the imaging operand and the checkpoint pair in the
+// forward, lt^k in the adjoint): the next reads come in later launches, after a whole
+// level has streamed through L2, so caching these lines would only displace the halo rows
+// and coefficients the sweep reuses.
 __device__ __forceinline__ void bstore_nt(rsrc_t r, uint32_t off, float v)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 2);
@@ -1296,11 +1298,11 @@ __global__ __launch_bounds__(64 * kWaves3) void k_fwd3d(const StepArgs A)
         // line is written whole
         const uint32_t o = poff(z) + sb;
         const float un = g.in ? a * qq[4] - b * pq[r] + cq[r] * wv : 0.0f;
-        bstore(rN, o, un);
+        bstore_nt(rN, o, un);
         if (MODE == kStoreImage) bstore_nt(rW, o, g.in ? wv : 0.0f);
         if (MODE == kStoreCkpt) {
-            bstore(rKa, o, un);
-            bstore(rKb, o, qq[4]);  // 0 past the grid (its loads are poisoned)
+            bstore_nt(rKa, o, un);
+            bstore_nt(rKb, o, qq[4]);  // 0 past the grid (its loads are poisoned)
         }
         if (z == ev_z) {  // uniform
             if (Dat) {
@@ -1476,7 +1478,7 @@ __global__ __launch_bounds__(64 * kWaves3) void k_adj3d(const StepArgs A)
                 ev_off = ev < ev_end ? __builtin_amdgcn_readfirstlane(evrows[ev].vec_off) : 0;
             }
             const float un = a * qq[4] - b * pq[r] + cr[r] * wv;
-            bstore(rN, poff(z) + sbs, g.in ? un : 0.0f);  // whole lines, as in the forward
+            bstore_nt(rN, poff(z) + sbs, g.in ? un : 0.0f);  // whole lines, as in the forward
             const double pr = (double)un * (double)wq[r];  // the product of two floats is exact in FP64
             red[r][g.ry][g.lc] = j == 0 ? pr : red[r][g.ry][g.lc] + pr;
             // keep each plane's loads in its own plane (prefetch distance PF planes)
