@@ -306,10 +306,12 @@ def gradient_bench(torch, fwi, problems, args, cfg, steps, warmup, with_cpu):
             # counters are valid for the measured kernel sources, kernel and tile height only
             two = two_adj if name == adj_name else two_fwd
             rows = 16 if two else (tuned[0] if tuned is not None else None)
+            # a record may hold counters for several tile heights (the tuner's pick varies)
+            ent = tj.get("by_tile_rows", {}).get(str(rows), tj if tj.get("tile_rows") == rows else None)
             if (tj.get("kernel_source") == kernel_source_hash() and tj.get("kernel") == name
-                    and rows is not None and tj.get("tile_rows") == rows):
-                traffic = tj.get("bytes_per_launch")
-                pm = tj.get("per_mode")
+                    and rows is not None and ent is not None):
+                traffic = ent.get("bytes_per_launch")
+                pm = ent.get("per_mode")
                 if pm and name == fwd_name:  # forward: weighted by this schedule's launches
                     traffic = int(round(1e6 * sum(modes[m] * (pm[m]["fetch_mb"] + pm[m]["write_mb"])
                                                   for m in modes) / n_fwd_launch))
